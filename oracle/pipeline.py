@@ -1,0 +1,130 @@
+"""The CSQRP-LSQR solve (Alg. 1) and the quantities Sec. 4.1 reports.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Steps, in the paper's order:
+  1. s = gamma n sketch rows (chosen by the caller)
+  2. SA by the count sketch (countsketch.sketch_dense)
+  3. R from the QR of SA (qr.r_factor)
+  4. the preconditioned operator B = A R^{-1}, applied implicitly (Remark 3.2)
+     or, for comparison only, formed explicitly as a dense matrix
+  5. LSQR on min ||B y - b|| from y = 0 (Sec. 4.1)
+  6. x = R^{-1} y
+Remark 3.3 observes that the implicit operator loses accuracy on ill-conditioned
+problems; the reading adopted here recovers it with iterative refinement: after
+a sweep, the true residual r = b - A x is recomputed and the same preconditioned
+LSQR solves min ||A d - r||, x <- x + d (`refine` extra sweeps, default 1).
+
+Reported: iterations, the true residual ||b - A x|| / ||b|| recomputed from x,
+the normal-equation residual ||A^T r|| / (||A||_F ||r||), and ||r||^2/||b||^2
+(the paper's squared "relative least squares error", Sec. 4.1).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import countsketch, qr
+from .lsqr import lsqr
+
+
+def csr(row_ptr, col, val, m, n):
+    return sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col, np.int64),
+                          np.asarray(row_ptr, np.int64)), shape=(m, n))
+
+
+def precondition(row_ptr, col, val, m, n, s, seed, qr_dtype="f64", r_store="f64", b=None,
+                 hash_in=None):
+    """Steps 1-3: returns dict(h, sign, SA, Sb, R) with R as a float64 array holding the
+    stored preconditioner (rounded to float32 first when r_store == 'f32')."""
+    if hash_in is None:
+        h, sign = countsketch.hash_sign(m, s, seed)
+    else:
+        h, sign = hash_in
+    SA, Sb = countsketch.sketch_dense(row_ptr, col, val, h, sign, s, n, b=b)
+    if qr_dtype == "f32":
+        R = qr.r_factor(SA.astype(np.float32), check_rank=False).astype(np.float64)
+    else:
+        R = qr.r_factor(SA)
+    if r_store == "f32":
+        R = R.astype(np.float32).astype(np.float64)
+    return dict(h=h, sign=sign, SA=SA, Sb=Sb, R=R)
+
+
+def lsqr_on_preconditioned(A, R, b, atol=1e-10, btol=1e-10, conlim=1e8, itmax=None,
+                           operator="implicit", keep_history=False):
+    """Steps 4-6 for one right-hand side; returns (x, LSQRResult)."""
+    m, n = A.shape
+    if operator == "implicit":
+        AT = A.T.tocsr()
+
+        def apply_B(v):
+            return A @ sla.solve_triangular(R, v, lower=False)
+
+        def apply_Bt(u):
+            return sla.solve_triangular(R, AT @ u, lower=False, trans="T")
+    elif operator == "explicit":
+        # B = A R^{-1}: solve B R = A row-wise, i.e. R^T B^T = A^T.
+        Bd = sla.solve_triangular(R, A.toarray().T, lower=False, trans="T").T
+
+        def apply_B(v):
+            return Bd @ v
+
+        def apply_Bt(u):
+            return Bd.T @ u
+    else:
+        raise ValueError(operator)
+    res = lsqr(apply_B, apply_Bt, b, n, atol=atol, btol=btol, conlim=conlim, itmax=itmax,
+               keep_history=keep_history)
+    x = sla.solve_triangular(R, res.y, lower=False)
+    return x, res
+
+
+def residual_metrics(A, x, b):
+    r = b - A @ x
+    nb = float(np.linalg.norm(b))
+    nr = float(np.linalg.norm(r))
+    afro = float(sp.linalg.norm(A)) if sp.issparse(A) else float(np.linalg.norm(A))
+    nar = float(np.linalg.norm(A.T @ r))
+    return dict(normr=nr, relres=nr / nb if nb else 0.0,
+                normal_relres=nar / (afro * nr) if nr else 0.0,
+                rel_ls_error_sq=(nr / nb) ** 2 if nb else 0.0)
+
+
+def l2_error(E, x, u_exact):
+    uh = E @ x
+    return float(np.linalg.norm(uh - u_exact) / np.linalg.norm(u_exact))
+
+
+def refined_lsqr(A, R, b, refine=1, **kw):
+    """LSQR sweeps with iterative refinement on the true residual; returns (x, [results])."""
+    b = np.asarray(b, np.float64)
+    x = np.zeros(A.shape[1])
+    r = b.copy()
+    results = []
+    for sweep in range(1 + refine):
+        dx, res = lsqr_on_preconditioned(A, R, r, **kw)
+        results.append(res)
+        x = x + dx
+        r = b - A @ x
+        if res.itn == 0:
+            break
+    return x, results
+
+
+def solve(row_ptr, col, val, b, m, n, s, seed, atol=1e-10, btol=1e-10, conlim=1e8, itmax=None,
+          qr_dtype="f64", r_store="f64", operator="implicit", refine=1, keep_history=False):
+    """Full CSQRP-LSQR for one right-hand side; returns a dict of results."""
+    pre = precondition(row_ptr, col, val, m, n, s, seed, qr_dtype=qr_dtype, r_store=r_store)
+    A = csr(row_ptr, col, val, m, n)
+    x, results = refined_lsqr(A, pre["R"], b, refine=refine, atol=atol, btol=btol, conlim=conlim,
+                              itmax=itmax, operator=operator, keep_history=keep_history)
+    res = results[0]
+    out = dict(x=x, itn=sum(r.itn for r in results), itn_sweeps=[r.itn for r in results],
+               istop=res.istop, est_normr=res.normr, est_normar=res.normar, anorm=res.anorm,
+               acond=res.acond, R=pre["R"], h=pre["h"], sign=pre["sign"],
+               history=[r.history for r in results])
+    out.update(residual_metrics(A, x, np.asarray(b, np.float64)))
+    return out
