@@ -1,0 +1,196 @@
+/*
+ * rfmls — sketch-preconditioned least squares for random-feature-method systems
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Solves min_x ||A x - b||_2 for a sparse, ill-conditioned, overdetermined
+ * A (m x n, m >> n; problem (1.1) of Chen & Tan, "High-precision randomized
+ * iterative methods for the random feature method", arXiv:2409.15818) by the
+ * paper's CSQRP-LSQR pipeline (Algorithm 1):
+ *
+ *   rfmls_sketch   count sketch SA = Phi D A, s = gamma n rows   (Def. 2.3; Alg. 1 step 2)
+ *   rfmls_precond  Householder QR of SA -> R; the library keeps  (Alg. 1 step 3)
+ *                  R^{-1} (upper triangular) as the preconditioner
+ *   rfmls_solve    LSQR on A R^{-1} (applied implicitly,          (Alg. 1 steps 4-6,
+ *                  Remark 3.2) from y = 0, x = R^{-1} y, plus      Remarks 3.2-3.3, Sec. 4.1)
+ *                  iterative refinement on the true residual
+ *   rfmls_solve_backward  gradients of a loss of x w.r.t. b and A's stored values
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked [host].  All device buffers are
+ *     owned and allocated by the caller, except the library-owned handle
+ *     workspace and rfmls_precond_t.
+ *   - Work is enqueued on the stream given to rfmls_create.  rfmls_transpose,
+ *     rfmls_sketch and rfmls_precond are asynchronous with respect to the host
+ *     (they may still block for internal workspace growth); rfmls_solve and
+ *     rfmls_solve_backward synchronise the stream before returning because
+ *     they report per-right-hand-side info on the host.
+ *   - Return value: RFMLS_OK (0), a positive warning, or a negative error.
+ *     Nothing is thrown across the ABI; rfmls_last_error() describes the last
+ *     failure on a handle.  Arguments are validated before any work is
+ *     enqueued; an invalid argument enqueues nothing.
+ *   - Sparse matrices are CSR: row_ptr int64[rows+1] (row_ptr[0] = 0), col
+ *     int32[nnz] ascending and unique within each row, val float64[nnz].
+ *   - Dense row-major: element (i, j) of a matrix with leading dimension ld
+ *     is at p[i * ld + j].  Blocks of right-hand sides are column-major:
+ *     right-hand side k of B (m x nrhs, ldb >= m) is B + k * ldb.
+ */
+#ifndef RFMLS_H
+#define RFMLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RFMLS_OK = 0,
+  RFMLS_W_NOCONV = 1,     /* iteration limit reached; X is still written */
+  RFMLS_E_ARG = -1,       /* invalid argument (sizes, null pointers, layout) */
+  RFMLS_E_RANK = -2,      /* R numerically singular: |r_ii| <= n u max|r_jj| */
+  RFMLS_E_BREAKDOWN = -3, /* non-finite value met inside the iteration */
+  RFMLS_E_HIP = -4,       /* HIP runtime error (message in rfmls_last_error) */
+  RFMLS_E_NOMEM = -5      /* device allocation of library workspace failed */
+} rfmls_status;
+
+typedef enum { RFMLS_F64 = 0, RFMLS_F32 = 1 } rfmls_dtype;
+
+typedef struct rfmls_handle rfmls_handle;
+typedef struct rfmls_precond rfmls_precond_t;
+
+/* CSR matrix, device pointers.  m rows, n columns, nnz stored entries. */
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const double *val;
+} rfmls_csr;
+
+/* [host] LSQR options (Paige & Saunders stopping rules; Sec. 4.1 uses
+ * tau = 1e-8 and at most n iterations from y = 0). */
+typedef struct {
+  double atol;    /* S2: ||B^T r|| <= atol ||B|| ||r||; also in S1      */
+  double btol;    /* S1: ||r|| <= btol ||b|| + atol ||B|| ||y||         */
+  double conlim;  /* S3: cond(B) estimate >= conlim                     */
+  int64_t itmax;  /* iteration limit per sweep; <= 0 means n            */
+  int32_t refine; /* extra refinement sweeps on the true residual (>= 0) */
+  int32_t check_every; /* host polls the device stop flag every this many
+                          iterations (>= 1); iterations past the stop are
+                          no-ops on the device                           */
+} rfmls_opts;
+
+/* [host] per right-hand side results */
+typedef struct {
+  int64_t itn;          /* total LSQR iterations over all sweeps           */
+  int64_t itn_first;    /* iterations of the first sweep                   */
+  int32_t istop;        /* stopping rule of the first sweep: 0 x=0 exact,
+                           1 S1, 2 S2, 3 S3, 7 itmax                        */
+  int32_t istop_last;   /* stopping rule of the last sweep                 */
+  double normr_est;     /* LSQR estimate of ||r|| at the end of sweep 1    */
+  double normar_est;    /* LSQR estimate of ||B^T r|| at the end of sweep 1 */
+  double anorm_est;     /* Frobenius estimate of ||B||                     */
+  double acond_est;     /* estimate of cond(B)                             */
+  double normb;         /* ||b||                                           */
+  double normr;         /* true ||b - A x|| recomputed in float64          */
+  double normar;        /* true ||A^T (b - A x)||                          */
+} rfmls_info;
+
+void rfmls_default_opts(rfmls_opts *opts /* [host] */);
+
+/* Create a handle bound to HIP device `device` and stream `stream`
+ * (a hipStream_t; NULL = the null stream).  The handle owns a growable
+ * device workspace freed by rfmls_destroy. */
+rfmls_status rfmls_create(rfmls_handle **handle /* [host] out */, int device, void *stream);
+rfmls_status rfmls_destroy(rfmls_handle *handle);
+const char *rfmls_last_error(const rfmls_handle *handle);
+
+/* A^T in CSR (n x m): at_row_ptr int64[n+1], at_col int32[nnz],
+ * at_val float64[nnz], caller-allocated.  Entries of each row of A^T are in
+ * ascending column (= row of A) order, so the result is deterministic.
+ * Needed by rfmls_solve for the products A^T u (Alg. 1 step 5). */
+rfmls_status rfmls_transpose(rfmls_handle *h, const rfmls_csr *A, int64_t *at_row_ptr,
+                             int32_t *at_col, double *at_val);
+
+/* Count sketch (Def. 2.3, Alg. 1 step 2): SA = Phi D A with Phi[h(i), i] = 1
+ * and D = diag(sign).  Row j of SA is the sum, over rows i of A with h(i) = j
+ * taken in ascending i, of sign(i) * A[i, :], accumulated in float64 from +0.
+ *
+ *   s        number of sketch rows, 1 <= s < 2^31 (the paper takes s = gamma n)
+ *   seed     generator seed.  h(i) = ((x >> 32) * s) >> 32 with
+ *            x = mix64(seed + (i+1) * 0x9E3779B97F4A7C15) and sign(i) = +1 iff the
+ *            top bit of mix64((seed ^ 0x5555555555555555) + (i+1) * 0x9E37...15)
+ *            is 0; mix64 is the SplitMix64 finaliser (all arithmetic mod 2^64).
+ *   hash_in, sign_in   optional int32[m] / int8[m] maps used instead of the
+ *            generator (both or neither; h in [0, s), sign in {-1, +1}).
+ *   hash_out, sign_out optional int32[m] / int8[m] copies of the maps used.
+ *   b, nrhs, ldb, Sb   optional: Sb (s x nrhs column-major, ld = s) = S b.
+ *   sa_dtype RFMLS_F64: SA is float64; RFMLS_F32: SA is float32, each element
+ *            rounded to nearest-even from its float64 sum.
+ *   SA, ld_sa  dense row-major s x n output, ld_sa >= n; fully overwritten
+ *            (zeros included).  SA is consumed by rfmls_precond.
+ */
+rfmls_status rfmls_sketch(rfmls_handle *h, const rfmls_csr *A, int64_t s, uint64_t seed,
+                          const int32_t *hash_in, const int8_t *sign_in, int32_t *hash_out,
+                          int8_t *sign_out, const double *b, int64_t nrhs, int64_t ldb,
+                          double *Sb, rfmls_dtype sa_dtype, void *SA, int64_t ld_sa);
+
+/* Preconditioner (Alg. 1 step 3; Thm 3.1-3.2): Householder QR of SA (s x n,
+ * s >= n, row-major, ld_sa >= n; overwritten) in qr_dtype arithmetic
+ * (RFMLS_F64, or RFMLS_F32 on matrix cores; must equal the sketch's sa_dtype),
+ * rows of R scaled so diag(R) > 0.  The library forms and keeps X = R^{-1}
+ * (upper triangular) stored in r_store precision.  Returns RFMLS_E_RANK if
+ * some |r_ii| <= n u max_j |r_jj| (u = unit roundoff of qr_dtype; for
+ * RFMLS_F32 only a zero or non-finite pivot is rejected).  *P_out is
+ * library-owned; free with rfmls_precond_free.  Asynchronous except for the
+ * rank check, which synchronises the stream. */
+rfmls_status rfmls_precond(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
+                           rfmls_dtype r_store, void *SA, int64_t ld_sa,
+                           rfmls_precond_t **P_out /* [host] out */);
+void rfmls_precond_free(rfmls_precond_t *P);
+int64_t rfmls_precond_n(const rfmls_precond_t *P);
+
+/* Copies of the factor for tests: R (with positive diagonal) and X = R^{-1},
+ * each n x n row-major float64 (ld = n) with zeros below the diagonal. */
+rfmls_status rfmls_precond_export_R(rfmls_handle *h, const rfmls_precond_t *P, double *R);
+rfmls_status rfmls_precond_export_Rinv(rfmls_handle *h, const rfmls_precond_t *P, double *X);
+/* Build a preconditioner from a given upper-triangular R (n x n row-major
+ * float64, ld = n, positive diagonal); only the upper triangle is read. */
+rfmls_status rfmls_precond_import_R(rfmls_handle *h, int64_t n, const double *R,
+                                    rfmls_dtype r_store, rfmls_precond_t **P_out);
+
+/* LSQR on the preconditioned problem min ||A R^{-1} y - b|| (Alg. 1 steps 4-6,
+ * operator applied implicitly as A (R^{-1} v) and R^{-T} (A^T u)), from y = 0,
+ * x = R^{-1} y, followed by opts->refine refinement sweeps on the true
+ * residual.  Each of the nrhs right-hand sides is solved independently (the
+ * same iterates as a single solve) in lockstep.
+ *   A, AT    the matrix and its transpose (rfmls_transpose)
+ *   B, ldb   m x nrhs column-major right-hand sides (ldb >= m)
+ *   X, ldx   n x nrhs column-major solutions (ldx >= n), overwritten
+ *   Rout, ldr  optional m x nrhs column-major true residuals b - A x (ldr >= m)
+ *   info     [host] array of nrhs results, may be NULL
+ * Returns RFMLS_W_NOCONV if some right-hand side hit itmax in its first sweep. */
+rfmls_status rfmls_solve(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *AT,
+                         const rfmls_precond_t *P, const double *B, int64_t ldb, int64_t nrhs,
+                         double *X, int64_t ldx, double *Rout, int64_t ldr,
+                         const rfmls_opts *opts, rfmls_info *info);
+
+/* Backward of x = A^+ b for a loss L with G = dL/dX (n x nrhs, ldg >= n).
+ * With r = b - A x, w = (A^T A)^{-1} g and lambda = A w:
+ *   dB[:, k] = lambda_k                        (m x nrhs column-major, lddb >= m)
+ *   dAval[e] = sum_k r_k[i] w_k[j] - lambda_k[i] x_k[j]   for each stored (i, j)
+ * w is obtained by LSQR on the consistent system (A R^{-1})^T lambda = R^{-T} g
+ * from lambda = 0 (its minimum-norm solution lambda = A w), using the same
+ * preconditioned products as rfmls_solve.
+ *   X, ldx  solutions from rfmls_solve; Rres, ldr residuals b - A x (m x nrhs)
+ *   dB may be NULL; dAval (float64[nnz]) may be NULL. */
+rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *AT,
+                                  const rfmls_precond_t *P, const double *X, int64_t ldx,
+                                  const double *Rres, int64_t ldr, const double *G, int64_t ldg,
+                                  int64_t nrhs, double *dB, int64_t lddb, double *dAval,
+                                  const rfmls_opts *opts, rfmls_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFMLS_H */

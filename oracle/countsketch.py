@@ -113,3 +113,14 @@ def explicit_S(h: np.ndarray, sign: np.ndarray, s: int) -> np.ndarray:
     S = np.zeros((s, m))
     S[h, np.arange(m)] = sign
     return S
+
+
+def sketch_rows(row_ptr, col, val, h, sign, n: int, buckets):
+    """Rows `buckets` of SA only (same ascending-row summation), for spot checks
+    of large sketches."""
+    out = np.zeros((len(buckets), n))
+    for k, j in enumerate(buckets):
+        for i in np.nonzero(h == j)[0]:  # ascending row order
+            lo, hi = row_ptr[i], row_ptr[i + 1]
+            out[k, col[lo:hi]] += float(sign[i]) * val[lo:hi]
+    return out

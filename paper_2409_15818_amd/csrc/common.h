@@ -1,0 +1,160 @@
+// Shared definitions of the rfmls HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rfmls.h"
+
+namespace rfmls {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// ---------------------------------------------------------------------------
+// Handle and workspace
+// ---------------------------------------------------------------------------
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace rfmls
+
+struct rfmls_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 0;
+  std::string last_error;
+  // Named, growable device scratch buffers (slot index -> buffer).
+  std::vector<rfmls::Workspace> ws;
+  unsigned int* barrier = nullptr;  // grid-barrier counters (device)
+  int* dev_flags = nullptr;         // device error / abort flags
+  void* pinned = nullptr;           // small pinned host staging buffer
+  size_t pinned_bytes = 0;
+};
+
+struct rfmls_precond {
+  int64_t n = 0;
+  int64_t nt = 0;            // number of tile rows, ceil(n / kTile)
+  rfmls_dtype store = RFMLS_F64;
+  void* Xpk = nullptr;       // packed tiles of X = R^{-1} (upper triangle)
+  double* Rdense = nullptr;  // R (row-major n x n, float64) kept for export
+  int device = 0;
+  // work decomposition of the triangular products: chunks of `chunk` tiles
+  int chunk = 4;
+  int64_t ntab = 0;          // number of (row-or-column, chunk) work items
+  int2* tab_row = nullptr;   // X v:   (tile row I, chunk k)
+  int2* tab_col = nullptr;   // X^T q: (tile column J, chunk k)
+  double* part = nullptr;    // nt x ceil(nt/chunk) x kTile partial sums
+};
+
+namespace rfmls {
+
+// Packed upper-triangular tile layout for the preconditioner: tiles of
+// kTile x kTile, tile (I, J) for J >= I stored contiguously (row-major inside
+// the tile), tile rows one after another.
+constexpr int kTile = 64;
+__host__ __device__ inline int64_t tile_index(int64_t I, int64_t J, int64_t nt) {
+  // tiles before row I: sum_{r<I} (nt - r) = I*nt - I*(I-1)/2
+  return I * nt - (I * (I - 1)) / 2 + (J - I);
+}
+
+// Error plumbing --------------------------------------------------------------
+rfmls_status fail(rfmls_handle* h, rfmls_status st, const char* fmt, ...);
+
+#define RFMLS_HIP(h, call)                                                           \
+  do {                                                                               \
+    hipError_t _e = (call);                                                          \
+    if (_e != hipSuccess)                                                            \
+      return ::rfmls::fail((h), RFMLS_E_HIP, "%s:%d %s: %s", __FILE__, __LINE__, #call, \
+                           hipGetErrorString(_e));                                   \
+  } while (0)
+
+#define RFMLS_CHECK(expr)                \
+  do {                                   \
+    rfmls_status _s = (expr);            \
+    if (_s < 0) return _s;               \
+  } while (0)
+
+// Workspace slot `slot` with at least `bytes` bytes (grows, never shrinks).
+rfmls_status workspace(rfmls_handle* h, int slot, size_t bytes, void** out);
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Slots of the handle workspace used by the different stages.
+enum WsSlot {
+  WS_SKETCH_COUNT = 0,
+  WS_SKETCH_PTR,
+  WS_SKETCH_PERM,
+  WS_SKETCH_HASH,
+  WS_SKETCH_SIGN,
+  WS_QR_TAU,
+  WS_QR_PART,
+  WS_QR_W,
+  WS_QR_WP,
+  WS_QR_T,
+  WS_TRSM,
+  WS_LSQR_VEC,
+  WS_LSQR_SCAL,
+  WS_LSQR_PART,
+  WS_TRANSPOSE,
+  WS_MISC,
+  WS_NUM_SLOTS
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Deterministic block sum of one double per thread (blockDim.x threads, a
+// multiple of 64).  `scratch` must hold blockDim.x/64 doubles.  Every thread
+// receives the result.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x / kWave;
+  for (int i = 0; i < nw; ++i) t += scratch[i];
+  return t;
+}
+
+}  // namespace rfmls
+
+// Launch entry points implemented in the individual .hip files -----------------
+namespace rfmls {
+rfmls_status launch_hash_sign(rfmls_handle* h, int64_t m, int64_t s, uint64_t seed, int32_t* hash,
+                              int8_t* sign);
+rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const int32_t* hash,
+                        const int8_t* sign, const double* b, int64_t nrhs, int64_t ldb, double* Sb,
+                        rfmls_dtype dt, void* SA, int64_t ld);
+rfmls_status run_transpose(rfmls_handle* h, const rfmls_csr* A, int64_t* rp, int32_t* col,
+                           double* val);
+rfmls_status scan_counts(rfmls_handle* h, const int32_t* count, int64_t n, int64_t* ptr);
+rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype dt, void* SA, int64_t ld);
+rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, const void* SA,
+                               int64_t ld, rfmls_dtype store, rfmls_precond_t* P, int check_rank);
+rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit);
+rfmls_status unpack_precond(rfmls_handle* h, const rfmls_precond_t* P, double* Xdense);
+rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                       const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                       double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                       rfmls_info* info);
+rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                          const rfmls_precond_t* P, const double* Xs, int64_t ldx,
+                          const double* Rres, int64_t ldr, const double* G, int64_t ldg,
+                          int64_t nrhs, double* dB, int64_t lddb, double* dAval,
+                          const rfmls_opts* o, rfmls_info* info);
+}  // namespace rfmls

@@ -1,0 +1,729 @@
+// LSQR on the preconditioned operator B = A R^{-1} (Alg. 1 steps 4-6 with the
+// preconditioner applied inside the iteration, Remark 3.2), textbook
+// Paige-Saunders recurrences with every scalar kept on the device.
+//
+// Products used by one iteration:
+//   z = X v            triangular product with the packed X = R^{-1}  (k_trmv_*)
+//   u^ = A z - a u     CSR SpMV, one wavefront per row                 (k_spmv)
+//   q = A^T u          CSR SpMV with the explicit transpose            (k_spmv)
+//   v^ = X^T q - b v   transposed triangular product                   (k_trmvT_*)
+// followed by the plane rotation and the updates of y and w.  Norms are
+// reduced in a fixed order (per-block partials, then a fixed tree), so runs
+// are bitwise reproducible.  The host only polls a device "done" flag every
+// few iterations; kernels launched after the stop return immediately.
+#include "common.h"
+#include "lsqr_dev.h"
+
+namespace rfmls {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSpmvMaxBlocks = 2048;
+
+// ---------------------------------------------------------------------------
+// Triangular products with the packed tiles of X (64 x 64, upper triangle)
+// ---------------------------------------------------------------------------
+// z = X v: block e handles tile row I = tab[e].x, tiles J in [I + k C, I + (k+1) C).
+// Thread (c = lane, w = wave) accumulates rows w + 4q of the tile row against
+// column c, then each row is summed across the wavefront.
+template <typename TS>
+__global__ void __launch_bounds__(kThreads)
+    k_trmv_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+                int C, int maxk, const double* __restrict__ v, double* __restrict__ part,
+                const int* __restrict__ done) {
+  if (done && *done) return;
+  const int2 e = tab[blockIdx.x];
+  const int64_t I = e.x;
+  const int k = e.y;
+  const int64_t J0 = I + (int64_t)k * C;
+  const int64_t J1 = J0 + C < nt ? J0 + C : nt;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t J = J0; J < J1; ++J) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+    const int64_t gc = J * kTile + lane;
+    const double vc = gc < n ? v[gc] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += (double)t[(w + 4 * q) * kTile + lane] * vc;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double s = wave_sum(acc[q]);
+    if (lane == 0) part[((int64_t)I * maxk + k) * kTile + w + 4 * q] = s;
+  }
+}
+
+// p = X^T q: block e handles tile column J = tab[e].x, tiles I in [k C, min((k+1) C, J+1)).
+template <typename TS>
+__global__ void __launch_bounds__(kThreads)
+    k_trmvT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+                 int C, int maxk, const double* __restrict__ qv, double* __restrict__ part,
+                 const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double red[4][kTile];
+  const int2 e = tab[blockIdx.x];
+  const int64_t J = e.x;
+  const int k = e.y;
+  const int64_t I0 = (int64_t)k * C;
+  const int64_t I1 = I0 + C < J + 1 ? I0 + C : J + 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc = 0.0;
+  for (int64_t I = I0; I < I1; ++I) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = w + 4 * q;
+      const int64_t gr = I * kTile + r;
+      const double qr = gr < n ? qv[gr] : 0.0;
+      acc += (double)t[r * kTile + lane] * qr;
+    }
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0)
+    part[((int64_t)J * maxk + k) * kTile + lane] =
+        (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// out[i] = sum_k part[row(i)][k] - coef * prev[i];  partial sum of squares per block.
+// nk(I) = number of chunks of tile row/column I (trans: ceil((I+1)/C), else ceil((nt-I)/C)).
+__global__ void __launch_bounds__(kThreads)
+    k_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int C, int maxk, int trans,
+                 double hcoef, const double* __restrict__ dcoef, const double* prev,
+                 double* out, double* __restrict__ sq, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double ss = 0.0;
+  if (i < n) {
+    const int64_t I = i / kTile;
+    const int r = (int)(i % kTile);
+    const int64_t nk = trans ? (I + 1 + C - 1) / C : (nt - I + C - 1) / C;
+    double s = 0.0;
+    for (int64_t k = 0; k < nk; ++k) s += part[(I * maxk + k) * kTile + r];
+    double cf = hcoef;
+    if (dcoef) cf *= *dcoef;
+    if (prev && cf != 0.0) s -= cf * prev[i];
+    out[i] = s;
+    ss = s * s;
+  }
+  if (sq) {
+    ss = block_sum(ss, scratch);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR SpMV: out[row] = sA * (A x)[row] - coef * prev[row]; one wavefront per row.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+    k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+           const double* __restrict__ val, int64_t rows, const double* __restrict__ x, double sA,
+           double hcoef, const double* __restrict__ dcoef, const double* prev, double* out,
+           double* __restrict__ sq, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+  double cf = hcoef;
+  if (dcoef) cf *= *dcoef;
+  double ss = 0.0;
+  for (int64_t row = wid; row < rows; row += nw) {
+    const int64_t lo = rp[row], hi = rp[row + 1];
+    double s = 0.0;
+    for (int64_t e = lo + lane; e < hi; e += 64) s += val[e] * x[col[e]];
+    s = wave_sum(s);
+    if (lane == 0) {
+      double o = sA * s;
+      if (prev && cf != 0.0) o -= cf * prev[row];
+      out[row] = o;
+      ss += o * o;
+    }
+  }
+  if (sq) {
+    ss = block_sum(ss, scratch);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector helpers
+// ---------------------------------------------------------------------------
+// nrm = sqrt(sum sq[0..nsq)), fixed order; every block computes it, block 0 stores it.
+__device__ double reduce_partials(const double* __restrict__ sq, int nsq, double* scratch) {
+  double t = 0.0;
+  for (int i = threadIdx.x; i < nsq; i += blockDim.x) t += sq[i];
+  return block_sum(t, scratch);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_normalize(double* vec, int64_t len, const double* __restrict__ sq, int nsq,
+                double* __restrict__ nrm_out, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  const double nrm = sqrt(reduce_partials(sq, nsq, scratch));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * kThreads)
+    vec[i] *= inv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nrm_out = nrm;
+}
+
+// out = (a * x + b * y) with a = ha * (*da), b = hb * (*db) (null pointers read as 1)
+__global__ void k_axpby(int64_t len, double ha, const double* __restrict__ da, const double* x,
+                        double hb, const double* __restrict__ db, const double* y, double* out,
+                        const int* __restrict__ done) {
+  if (done && *done) return;
+  double a = ha, b = hb;
+  if (da) a *= *da;
+  if (db) b *= *db;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double o = a * x[i];
+    if (y) o += b * y[i];
+    out[i] = o;
+  }
+}
+
+// out = (x - hb * (*db) * y) / (*dal)   (0 where *dal is not positive)
+__global__ void k_recip_scale(const double* x, double hb, const double* __restrict__ db,
+                              const double* y, const double* __restrict__ dal, double* out,
+                              int64_t len, const int* __restrict__ done) {
+  if (done && *done) return;
+  const double al = *dal;
+  const double inv = al > 0.0 ? 1.0 / al : 0.0;
+  double b = hb;
+  if (db) b *= *db;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double o = x[i];
+    if (y && b != 0.0) o -= b * y[i];
+    out[i] = o * inv;
+  }
+}
+
+__global__ void k_fill(double* p, int64_t len, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x, int64_t len,
+                                                    double* __restrict__ sq) {
+  __shared__ double scratch[kThreads / 64];
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * kThreads)
+    t += x[i] * x[i];
+  t = block_sum(t, scratch);
+  if (threadIdx.x == 0) sq[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------------------
+// LSQR scalars
+// ---------------------------------------------------------------------------
+// After beta_1 = ||b||: set up the state.
+__global__ void k_lsqr_start(LsqrDev* st) {
+  st->bnorm = st->beta;
+  st->phibar = st->beta;
+  st->anorm2 = 0.0;
+  st->ddnorm = 0.0;
+  st->itn = 0;
+  st->istop = 7;
+  st->pending = 0;
+  st->done = 0;
+  if (!(st->beta > 0.0)) {
+    st->istop = 0;
+    st->done = 1;
+  }
+}
+
+// After alpha_1 = ||B^T u_1||.
+__global__ void k_lsqr_start2(LsqrDev* st) {
+  if (st->done) return;
+  st->rhobar = st->alpha;
+  st->normr = st->beta;
+  st->normar = st->alpha * st->beta;
+  if (!(st->alpha > 0.0)) {
+    st->istop = 0;
+    st->done = 1;
+  }
+}
+
+// Plane rotation of iteration k (alpha = alpha_{k+1}, beta = beta_{k+1} are
+// already in the state); wsq holds the partial sums of ||w_k||^2.
+__global__ void __launch_bounds__(kThreads) k_lsqr_rotate(LsqrDev* st, const double* __restrict__ wsq,
+                                                          int nsq) {
+  if (st->done) return;
+  __shared__ double scratch[kThreads / 64];
+  const double w2 = reduce_partials(wsq, nsq, scratch);
+  if (threadIdx.x != 0) return;
+  const double alpha = st->alpha, beta = st->beta;
+  st->itn += 1;
+  st->anorm2 += st->alpha_prev * st->alpha_prev + beta * beta;
+  const double rho = hypot(st->rhobar, beta);
+  if (!(rho > 0.0) || !isfinite(rho)) {
+    st->istop = isfinite(rho) ? 1 : -3;
+    st->done = 1;
+    st->phi_rho = 0.0;
+    st->theta_rho = 0.0;
+    return;
+  }
+  const double c = st->rhobar / rho;
+  const double s = beta / rho;
+  const double theta = s * alpha;
+  st->rhobar = -c * alpha;
+  const double phi = c * st->phibar;
+  st->phibar = s * st->phibar;
+  st->phi_rho = phi / rho;
+  st->theta_rho = theta / rho;
+  st->ddnorm += w2 / (rho * rho);
+  const double anorm = sqrt(st->anorm2);
+  st->acond = anorm * sqrt(st->ddnorm);
+  st->normr = st->phibar;
+  st->normar = st->phibar * alpha * fabs(c);
+  st->pending = 0;
+  if (st->normr == 0.0 || st->normar <= st->atol * anorm * st->normr) st->pending = 2;
+  else if (st->conlim > 0.0 && st->acond >= st->conlim) st->pending = 3;
+  st->alpha_prev = alpha;
+}
+
+// y += phi/rho w;  w = v - theta/rho w;  partial sums of ||y||^2 and ||w||^2.
+__global__ void __launch_bounds__(kThreads)
+    k_lsqr_update(const LsqrDev* __restrict__ st, const double* __restrict__ v, double* w,
+                  double* y, int64_t n, double* __restrict__ ysq, double* __restrict__ wsq) {
+  if (st->done) return;
+  __shared__ double scratch[kThreads / 64];
+  const double a = st->phi_rho, b = st->theta_rho;
+  double sy = 0.0, sw = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double wi = w[i];
+    const double yi = y[i] + a * wi;
+    const double wn = v[i] - b * wi;
+    y[i] = yi;
+    w[i] = wn;
+    sy += yi * yi;
+    sw += wn * wn;
+  }
+  sy = block_sum(sy, scratch);
+  sw = block_sum(sw, scratch);
+  if (threadIdx.x == 0) {
+    ysq[blockIdx.x] = sy;
+    wsq[blockIdx.x] = sw;
+  }
+}
+
+// Stopping tests of iteration k (S1 needs ||y_k||, available only now).
+__global__ void __launch_bounds__(kThreads) k_lsqr_check(LsqrDev* st, const double* __restrict__ ysq,
+                                                         int nsq, int consistent) {
+  if (st->done) return;
+  __shared__ double scratch[kThreads / 64];
+  const double y2 = reduce_partials(ysq, nsq, scratch);
+  if (threadIdx.x != 0) return;
+  st->ynorm = sqrt(y2);
+  const double anorm = sqrt(st->anorm2);
+  int istop = 0;
+  const double rtol = consistent ? st->btol * st->bnorm
+                                 : st->btol * st->bnorm + st->atol * anorm * st->ynorm;
+  if (st->normr <= rtol) istop = 1;
+  else if (st->pending) istop = st->pending;
+  else if (st->itn >= st->itmax) istop = 7;
+  if (istop) {
+    st->istop = istop;
+    st->done = 1;
+  }
+}
+
+// dA[e] += r_i w_j - lam_i x_j on the pattern of A
+__global__ void k_pattern_grad(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               int64_t m, const double* __restrict__ r, const double* __restrict__ w,
+                               const double* __restrict__ lam, const double* __restrict__ x,
+                               double* __restrict__ dA, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t row = wid; row < m; row += nw) {
+    const double ri = r[row], li = lam[row];
+    for (int64_t e = rp[row] + lane; e < rp[row + 1]; e += 64) {
+      const int32_t j = col[e];
+      const double g = ri * w[j] - li * x[j];
+      dA[e] = accumulate ? dA[e] + g : g;
+    }
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host drivers
+// ===========================================================================
+struct Ctx {
+  rfmls_handle* h;
+  const rfmls_csr* A;
+  const rfmls_csr* AT;
+  const rfmls_precond_t* P;
+  hipStream_t st;
+  // work vectors
+  double *u, *v, *w, *y, *z, *q, *t, *r, *xs;
+  double *sqA, *sqB, *sqY, *sqW;
+  LsqrDev* dst;
+  int nspmvA, nspmvAT, nvec_n, nvec_m;
+};
+
+static unsigned spmv_blocks(int64_t rows) {
+  const int64_t b = (rows + 3) / 4;
+  return (unsigned)(b < kSpmvMaxBlocks ? (b > 0 ? b : 1) : kSpmvMaxBlocks);
+}
+static unsigned vec_blocks(int64_t len) {
+  const int64_t b = (len + kThreads - 1) / kThreads;
+  return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+}
+
+rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, const double* in,
+                       double* out, double hcoef, const double* dcoef, const double* prev,
+                       double* sq, const int* done) {
+  const int64_t n = P->n, nt = P->nt;
+  const int C = P->chunk;
+  const int maxk = (int)((nt + C - 1) / C);
+  hipStream_t st = h->stream;
+  double* part = (double*)P->part;
+  if (!trans) {
+    if (P->store == RFMLS_F64)
+      hipLaunchKernelGGL(k_trmv_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
+                         (const double*)P->Xpk, nt, n, P->tab_row, C, maxk, in, part, done);
+    else
+      hipLaunchKernelGGL(k_trmv_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
+                         (const float*)P->Xpk, nt, n, P->tab_row, C, maxk, in, part, done);
+  } else {
+    if (P->store == RFMLS_F64)
+      hipLaunchKernelGGL(k_trmvT_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
+                         (const double*)P->Xpk, nt, n, P->tab_col, C, maxk, in, part, done);
+    else
+      hipLaunchKernelGGL(k_trmvT_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
+                         (const float*)P->Xpk, nt, n, P->tab_col, C, maxk, in, part, done);
+  }
+  hipLaunchKernelGGL(k_tri_reduce, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, st, part, nt, n,
+                     C, maxk, trans, hcoef, dcoef, prev, out, sq, done);
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+int tri_reduce_blocks(int64_t n) { return (int)ceil_div(n, kThreads); }
+
+static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA, double hcoef,
+                         const double* dcoef, const double* prev, double* out, double* sq,
+                         const int* done, int* nblk) {
+  const unsigned nb = spmv_blocks(M->m);
+  hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
+                     x, sA, hcoef, dcoef, prev, out, sq, done);
+  if (nblk) *nblk = (int)nb;
+  RFMLS_HIP(c.h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+// The pinned staging buffer: [0, 1024) uploads, [1024, 4096) downloads.  Every
+// upload is followed by a stream synchronisation before the buffer is reused.
+static rfmls_status upload_state(Ctx& c, const rfmls_opts* o, int64_t itmax) {
+  LsqrDev* pin = (LsqrDev*)c.h->pinned;
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  *pin = LsqrDev{};
+  pin->atol = o->atol;
+  pin->btol = o->btol;
+  pin->conlim = o->conlim;
+  pin->itmax = itmax;
+  RFMLS_HIP(c.h, hipMemcpyAsync(c.dst, pin, sizeof(LsqrDev), hipMemcpyHostToDevice, c.st));
+  return RFMLS_OK;
+}
+
+static rfmls_status poll_done(Ctx& c, int* host_done) {
+  int* pin = (int*)((char*)c.h->pinned + 1024);
+  RFMLS_HIP(c.h, hipMemcpyAsync(pin, &c.dst->done, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  *host_done = *pin;
+  return RFMLS_OK;
+}
+
+// One LSQR sweep for min ||A X y - rhs||; on return c.y holds y and the state
+// is in c.dst.  rhs is an m-vector (device).
+static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, int64_t itmax) {
+  rfmls_handle* h = c.h;
+  const int64_t m = c.A->m, n = c.A->n;
+  const int* done = &c.dst->done;
+  RFMLS_CHECK(upload_state(c, o, itmax));
+  const unsigned vbn = vec_blocks(n), vbm = vec_blocks(m);
+  // beta_1 u_1 = rhs
+  hipLaunchKernelGGL(k_axpby, dim3(vbm), dim3(kThreads), 0, c.st, m, 1.0, (const double*)nullptr,
+                     rhs, 0.0, (const double*)nullptr, (const double*)nullptr, c.u,
+                     (const int*)nullptr);
+  hipLaunchKernelGGL(k_sumsq, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA);
+  hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA, (int)vbm,
+                     &c.dst->beta, (const int*)nullptr);
+  hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(1), 0, c.st, c.dst);
+  hipLaunchKernelGGL(k_fill, dim3(vbn), dim3(kThreads), 0, c.st, c.y, n, 0.0);
+  // alpha_1 v_1 = B^T u_1 = X^T (A^T u_1)
+  RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
+  RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 0.0, nullptr, nullptr, c.sqB, done));
+  const int nred = tri_reduce_blocks(n);
+  hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
+                     &c.dst->alpha, done);
+  hipLaunchKernelGGL(k_lsqr_start2, dim3(1), dim3(1), 0, c.st, c.dst);
+  // w_1 = v_1 and ||w_1||^2
+  hipLaunchKernelGGL(k_axpby, dim3(vbn), dim3(kThreads), 0, c.st, n, 1.0, (const double*)nullptr,
+                     c.v, 0.0, (const double*)nullptr, (const double*)nullptr, c.w, done);
+  hipLaunchKernelGGL(k_sumsq, dim3(vbn), dim3(kThreads), 0, c.st, c.w, n, c.sqW);
+  // alpha_prev for the ||B||_F estimate: alpha_1
+  hipLaunchKernelGGL(k_axpby, dim3(1), dim3(1), 0, c.st, (int64_t)1, 1.0, (const double*)nullptr,
+                     &c.dst->alpha, 0.0, (const double*)nullptr, (const double*)nullptr,
+                     &c.dst->alpha_prev, (const int*)nullptr);
+  const int every = o->check_every > 0 ? o->check_every : 8;
+  int hd = 0;
+  RFMLS_CHECK(poll_done(c, &hd));
+  for (int64_t it = 0; it < itmax && !hd; ++it) {
+    // beta u = A (X v) - alpha u
+    RFMLS_CHECK(tri_apply(h, c.P, 0, c.v, c.z, 0.0, nullptr, nullptr, nullptr, done));
+    int nb = 0;
+    RFMLS_CHECK(spmv(c, c.A, c.z, 1.0, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+    hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA, nb,
+                       &c.dst->beta, done);
+    // alpha v = X^T (A^T u) - beta v
+    RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
+    RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 1.0, &c.dst->beta, c.v, c.sqB, done));
+    hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
+                       &c.dst->alpha, done);
+    hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqW, (int)vbn);
+    hipLaunchKernelGGL(k_lsqr_update, dim3(vbn), dim3(kThreads), 0, c.st, c.dst, c.v, c.w, c.y, n,
+                       c.sqY, c.sqW);
+    hipLaunchKernelGGL(k_lsqr_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqY, (int)vbn, 0);
+    RFMLS_HIP(h, hipGetLastError());
+    if ((it + 1) % every == 0) RFMLS_CHECK(poll_done(c, &hd));
+  }
+  return RFMLS_OK;
+}
+
+static rfmls_status make_ctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                             const rfmls_precond_t* P, Ctx& c) {
+  c.h = h;
+  c.A = A;
+  c.AT = AT;
+  c.P = P;
+  c.st = h->stream;
+  const int64_t m = A->m, n = A->n;
+  const size_t nvec = (size_t)(4 * m + 8 * n + 4 * kSpmvMaxBlocks + 64);
+  void* p;
+  RFMLS_CHECK(workspace(h, WS_LSQR_VEC, sizeof(double) * nvec, &p));
+  double* d = (double*)p;
+  c.u = d;
+  d += m;
+  c.r = d;
+  d += m;
+  c.t = d;
+  d += m;
+  d += m;  // spare m-vector
+  c.v = d;
+  d += n;
+  c.w = d;
+  d += n;
+  c.y = d;
+  d += n;
+  c.z = d;
+  d += n;
+  c.q = d;
+  d += n;
+  c.xs = d;
+  d += n;
+  d += 2 * n;  // spare
+  c.sqA = d;
+  d += kSpmvMaxBlocks;
+  c.sqB = d;
+  d += kSpmvMaxBlocks;
+  c.sqY = d;
+  d += kSpmvMaxBlocks;
+  c.sqW = d;
+  void* ps;
+  RFMLS_CHECK(workspace(h, WS_LSQR_SCAL, sizeof(LsqrDev) * 2, &ps));
+  c.dst = (LsqrDev*)ps;
+  return RFMLS_OK;
+}
+
+static rfmls_status read_state(Ctx& c, LsqrDev* out) {
+  LsqrDev* pin = (LsqrDev*)((char*)c.h->pinned + 2048);
+  RFMLS_HIP(c.h, hipMemcpyAsync(pin, c.dst, sizeof(LsqrDev), hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  *out = *pin;
+  return RFMLS_OK;
+}
+
+// ||v||^2 of a device vector into host
+static rfmls_status host_norm(Ctx& c, const double* v, int64_t len, double* out) {
+  const unsigned nb = vec_blocks(len);
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(kThreads), 0, c.st, v, len, c.sqY);
+  std::vector<double> tmp(nb);
+  RFMLS_HIP(c.h, hipMemcpyAsync(tmp.data(), c.sqY, sizeof(double) * nb, hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  double s = 0.0;
+  for (double t : tmp) s += t;
+  *out = sqrt(s);
+  return RFMLS_OK;
+}
+
+rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                       const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                       double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                       rfmls_info* info) {
+  Ctx c;
+  RFMLS_CHECK(make_ctx(h, A, AT, P, c));
+  const int64_t m = A->m, n = A->n;
+  const int64_t itmax = o->itmax > 0 ? o->itmax : n;
+  const unsigned vbn = vec_blocks(n), vbm = vec_blocks(m);
+  rfmls_status ret = RFMLS_OK;
+  for (int64_t k = 0; k < nrhs; ++k) {
+    const double* b = B + k * ldb;
+    double* x = X + k * ldx;
+    rfmls_info inf{};
+    double* rres = c.r;
+    for (int sweep = 0; sweep <= o->refine; ++sweep) {
+      const double* rhs = sweep == 0 ? b : rres;
+      RFMLS_CHECK(lsqr_sweep(c, rhs, o, itmax));
+      LsqrDev s;
+      RFMLS_CHECK(read_state(c, &s));
+      if (s.istop < 0) return fail(h, RFMLS_E_BREAKDOWN, "non-finite value in LSQR");
+      if (sweep == 0) {
+        inf.itn_first = s.itn;
+        inf.istop = s.istop;
+        inf.normr_est = s.normr;
+        inf.normar_est = s.normar;
+        inf.anorm_est = sqrt(s.anorm2);
+        inf.acond_est = s.acond;
+        inf.normb = s.bnorm;
+        if (s.istop == 7) ret = RFMLS_W_NOCONV;
+      }
+      inf.itn += s.itn;
+      inf.istop_last = s.istop;
+      // x (+)= X y
+      RFMLS_CHECK(tri_apply(h, P, 0, c.y, sweep == 0 ? x : c.xs, 0.0, nullptr, nullptr, nullptr,
+                            nullptr));
+      if (sweep > 0)
+        hipLaunchKernelGGL(k_axpby, dim3(vbn), dim3(kThreads), 0, c.st, n, 1.0,
+                           (const double*)nullptr, (const double*)x, 1.0, (const double*)nullptr,
+                           (const double*)c.xs, x, (const int*)nullptr);
+      // r = b - A x
+      RFMLS_CHECK(spmv(c, A, x, -1.0, -1.0, nullptr, b, rres, nullptr, nullptr, nullptr));
+      if (s.itn == 0) break;
+    }
+    RFMLS_CHECK(host_norm(c, rres, m, &inf.normr));
+    RFMLS_CHECK(spmv(c, AT, rres, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, nullptr, nullptr));
+    RFMLS_CHECK(host_norm(c, c.q, n, &inf.normar));
+    if (Rout)
+      hipLaunchKernelGGL(k_axpby, dim3(vbm), dim3(kThreads), 0, c.st, m, 1.0, (const double*)nullptr,
+                         (const double*)rres, 0.0, (const double*)nullptr, (const double*)nullptr,
+                         Rout + k * ldr, (const int*)nullptr);
+    if (info) info[k] = inf;
+  }
+  RFMLS_HIP(h, hipStreamSynchronize(c.st));
+  return ret;
+}
+
+// Backward: LSQR on the consistent system B^T lam = c (c = X^T g), operator
+// M = B^T (n x m), tracking lam = B z through the shadow vectors vt, wt (v = B vt).
+rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                          const rfmls_precond_t* P, const double* Xs, int64_t ldx,
+                          const double* Rres, int64_t ldr, const double* G, int64_t ldg,
+                          int64_t nrhs, double* dB, int64_t lddb, double* dAval,
+                          const rfmls_opts* o, rfmls_info* info) {
+  Ctx c;
+  RFMLS_CHECK(make_ctx(h, A, AT, P, c));
+  const int64_t m = A->m, n = A->n;
+  const int64_t itmax = o->itmax > 0 ? o->itmax : m;
+  const unsigned vbn = vec_blocks(n), vbm = vec_blocks(m);
+  const int nred = tri_reduce_blocks(n);
+  // roles: un = u (n-vector), vm = v (m-vector), vt/wt/zz shadows (n-vectors)
+  double* un = c.z;   // n
+  double* vm = c.t;   // m
+  double* vt = c.w;   // n
+  double* wt = c.q;   // n
+  double* zz = c.y;   // n
+  double* tmpn = c.xs;  // n
+  double* lam = c.r;  // m
+  const int* done = &c.dst->done;
+  rfmls_status ret = RFMLS_OK;
+  for (int64_t k = 0; k < nrhs; ++k) {
+    RFMLS_CHECK(upload_state(c, o, itmax));
+    // beta_1 u_1 = c = X^T g
+    RFMLS_CHECK(tri_apply(h, P, 1, G + k * ldg, un, 0.0, nullptr, nullptr, c.sqB, nullptr));
+    hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, un, n, c.sqB, nred,
+                       &c.dst->beta, (const int*)nullptr);
+    hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(1), 0, c.st, c.dst);
+    hipLaunchKernelGGL(k_fill, dim3(vbn), dim3(kThreads), 0, c.st, zz, n, 0.0);
+    // alpha_1 v_1 = M^T u_1 = A (X u_1);  vt_1 = u_1 / alpha_1
+    RFMLS_CHECK(tri_apply(h, P, 0, un, tmpn, 0.0, nullptr, nullptr, nullptr, done));
+    int nb = 0;
+    RFMLS_CHECK(spmv(c, A, tmpn, 1.0, 0.0, nullptr, nullptr, vm, c.sqA, done, &nb));
+    hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, vm, m, c.sqA, nb,
+                       &c.dst->alpha, done);
+    hipLaunchKernelGGL(k_lsqr_start2, dim3(1), dim3(1), 0, c.st, c.dst);
+    hipLaunchKernelGGL(k_recip_scale, dim3(vbn), dim3(kThreads), 0, c.st, un, 0.0, (const double*)nullptr,
+                       (const double*)nullptr, &c.dst->alpha, vt, n, done);
+    hipLaunchKernelGGL(k_axpby, dim3(vbn), dim3(kThreads), 0, c.st, n, 1.0, (const double*)nullptr,
+                       (const double*)vt, 0.0, (const double*)nullptr, (const double*)nullptr, wt,
+                       done);
+    hipLaunchKernelGGL(k_sumsq, dim3(vbn), dim3(kThreads), 0, c.st, wt, n, c.sqW);
+    hipLaunchKernelGGL(k_axpby, dim3(1), dim3(1), 0, c.st, (int64_t)1, 1.0, (const double*)nullptr,
+                       &c.dst->alpha, 0.0, (const double*)nullptr, (const double*)nullptr,
+                       &c.dst->alpha_prev, (const int*)nullptr);
+    const int every = o->check_every > 0 ? o->check_every : 8;
+    int hd = 0;
+    RFMLS_CHECK(poll_done(c, &hd));
+    for (int64_t it = 0; it < itmax && !hd; ++it) {
+      // beta u = X^T (A^T v) - alpha u
+      RFMLS_CHECK(spmv(c, AT, vm, 1.0, 0.0, nullptr, nullptr, tmpn, nullptr, done, nullptr));
+      RFMLS_CHECK(tri_apply(h, P, 1, tmpn, un, 1.0, &c.dst->alpha, un, c.sqB, done));
+      hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, un, n, c.sqB, nred,
+                         &c.dst->beta, done);
+      // alpha v = A (X u) - beta v;  vt = (u - beta vt) / alpha
+      RFMLS_CHECK(tri_apply(h, P, 0, un, tmpn, 0.0, nullptr, nullptr, nullptr, done));
+      RFMLS_CHECK(spmv(c, A, tmpn, 1.0, 1.0, &c.dst->beta, vm, vm, c.sqA, done, &nb));
+      hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, vm, m, c.sqA, nb,
+                         &c.dst->alpha, done);
+      hipLaunchKernelGGL(k_recip_scale, dim3(vbn), dim3(kThreads), 0, c.st, un, 1.0,
+                         (const double*)&c.dst->beta, (const double*)vt, &c.dst->alpha, vt, n, done);
+      hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqW, (int)vbn);
+      hipLaunchKernelGGL(k_lsqr_update, dim3(vbn), dim3(kThreads), 0, c.st, c.dst, vt, wt, zz, n,
+                         c.sqY, c.sqW);
+      hipLaunchKernelGGL(k_lsqr_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqY, (int)vbn, 1);
+      RFMLS_HIP(h, hipGetLastError());
+      if ((it + 1) % every == 0) RFMLS_CHECK(poll_done(c, &hd));
+    }
+    LsqrDev s;
+    RFMLS_CHECK(read_state(c, &s));
+    if (s.istop < 0) return fail(h, RFMLS_E_BREAKDOWN, "non-finite value in backward LSQR");
+    if (s.istop == 7) ret = RFMLS_W_NOCONV;
+    if (info) {
+      rfmls_info inf{};
+      inf.itn = inf.itn_first = s.itn;
+      inf.istop = inf.istop_last = s.istop;
+      inf.normr_est = s.normr;
+      inf.normb = s.bnorm;
+      info[k] = inf;
+    }
+    // w = X z (into tmpn), lam = A w
+    RFMLS_CHECK(tri_apply(h, P, 0, zz, tmpn, 0.0, nullptr, nullptr, nullptr, nullptr));
+    RFMLS_CHECK(spmv(c, A, tmpn, 1.0, 0.0, nullptr, nullptr, lam, nullptr, nullptr, nullptr));
+    if (dB)
+      hipLaunchKernelGGL(k_axpby, dim3(vbm), dim3(kThreads), 0, c.st, m, 1.0, (const double*)nullptr,
+                         (const double*)lam, 0.0, (const double*)nullptr, (const double*)nullptr,
+                         dB + k * lddb, (const int*)nullptr);
+    if (dAval)
+      hipLaunchKernelGGL(k_pattern_grad, dim3(spmv_blocks(m)), dim3(kThreads), 0, c.st, A->row_ptr,
+                         A->col, m, Rres + k * ldr, (const double*)tmpn, (const double*)lam,
+                         Xs + k * ldx, dAval, k > 0 ? 1 : 0);
+    RFMLS_HIP(h, hipGetLastError());
+  }
+  RFMLS_HIP(h, hipStreamSynchronize(c.st));
+  return ret;
+}
+
+}  // namespace rfmls

@@ -1,0 +1,90 @@
+"""The CSQRP-LSQR pipeline (Alg. 1) over the C-ABI, and its differentiable form.
+
+csqrp_lsqr      sketch -> QR preconditioner -> LSQR for one or many right-hand sides
+LstsqFunction   torch.autograd.Function: x = A^+ b with gradients w.r.t. b and the
+                stored values of A (restricted to A's pattern), the backward running
+                the preconditioned LSQR on the transposed operator.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from .api import (CSR, Handle, Precond, default_opts, rfmls_precond, rfmls_sketch, rfmls_solve,
+                  rfmls_solve_backward, rfmls_transpose)
+
+
+@dataclass
+class Result:
+    x: torch.Tensor
+    residual: torch.Tensor | None
+    info: list
+    status: int
+    precond: Precond
+    AT: CSR
+    timings: dict = field(default_factory=dict)
+
+
+def csqrp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, qr_dtype: str = "f64",
+               r_store: str = "f64", opts=None, AT: CSR | None = None) -> Result:
+    """Alg. 1 on the GPU: s = gamma n sketch rows, seed of the count sketch."""
+    if AT is None:
+        AT = rfmls_transpose(h, A)
+    SA, _, _, _ = rfmls_sketch(h, A, s, seed, dtype=qr_dtype)
+    P = rfmls_precond(h, SA, qr_dtype, r_store)
+    del SA
+    X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts)
+    return Result(X, R, info, rc, P, AT)
+
+
+class LstsqFunction(torch.autograd.Function):
+    """x = argmin ||A x - b|| with A given by its CSR pattern and differentiable values.
+
+    forward(val, b, solver) -> x;  backward gives dL/dval (on the pattern) and dL/db."""
+
+    @staticmethod
+    def forward(ctx, val, b, solver):
+        A = CSR(solver.m, solver.n, solver.row_ptr, solver.col, val.detach().contiguous())
+        res = csqrp_lsqr(solver.handle, A, b.detach(), solver.s, solver.seed, solver.qr_dtype,
+                         solver.r_store, solver.opts)
+        solver.last = res
+        ctx.solver = solver
+        ctx.A = A
+        ctx.res = res
+        ctx.single = b.dim() == 1
+        return res.x
+
+    @staticmethod
+    def backward(ctx, gx):
+        solver, A, res = ctx.solver, ctx.A, ctx.res
+        G = gx.contiguous()
+        dB, dA, info, _ = rfmls_solve_backward(solver.handle, A, res.AT, res.precond, res.x,
+                                               res.residual, G, solver.opts)
+        solver.last_backward_info = info
+        return dA, dB, None
+
+
+@dataclass
+class LstsqSolver:
+    """Configuration holder for LstsqFunction (pattern of A, sketch size, precisions)."""
+    handle: Handle
+    m: int
+    n: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    s: int
+    seed: int = 2
+    qr_dtype: str = "f64"
+    r_store: str = "f64"
+    opts: object = None
+    last: Result | None = None
+    last_backward_info: list | None = None
+
+    def __post_init__(self):
+        if self.opts is None:
+            self.opts = default_opts()
+
+    def __call__(self, val: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        return LstsqFunction.apply(val, b, self)
