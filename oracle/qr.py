@@ -7,8 +7,10 @@ matrix with positive diagonal such that R^T R = (SA)^T (SA).  It is computed by
 Householder QR (never from the Gram matrix, whose condition number is the
 square of SA's).  The QR is unique up to the signs of R's rows, so every row
 with a negative diagonal entry is negated.  A rank check follows Sec. 4.4's
-"fails in the preconditioning phase": |r_ii| <= n * u * max_j |r_jj| means SA
-(hence A, by Thm 3.1) is numerically rank deficient.
+"fails in the preconditioning phase", which gives no threshold; the reading used
+here is |r_ii| <= 16 u max_j |r_jj|: a pivot within a few rounding errors of
+the largest one (an exactly dependent column leaves a pivot of a few u) means
+SA, hence A by Thm 3.1, is numerically rank deficient.
 
 Two implementations:
   r_factor           LAPACK's Householder QR (numpy.linalg.qr, a library primitive)
@@ -39,7 +41,7 @@ def rank_ok(R: np.ndarray) -> bool:
         return True
     dg = np.abs(np.diag(R)).astype(np.float64)
     u = np.finfo(R.dtype).eps / 2
-    return bool(dg.min() > n * u * dg.max())
+    return bool(dg.min() > 16.0 * u * dg.max())
 
 
 def r_factor(SA: np.ndarray, check_rank: bool = True) -> np.ndarray:
@@ -50,7 +52,7 @@ def r_factor(SA: np.ndarray, check_rank: bool = True) -> np.ndarray:
     R = np.linalg.qr(SA, mode="r")[:n, :n]
     R = np.triu(_normalise(R))
     if check_rank and not rank_ok(R):
-        raise RankDeficient("R has a pivot below n*u*max|r_jj|")
+        raise RankDeficient("R has a pivot below 16*u*max|r_jj|")
     return R
 
 
