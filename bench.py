@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Time-to-tolerance benchmark of the CSQRP-LSQR pipeline on one MI355X.
+
+One step = the whole path on one synthetic RFM system already resident in HBM:
+A^T build, count sketch, Householder QR + R^{-1}, LSQR to the 1e-10 stopping
+rule with refinement sweeps, final true residual.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload poisson2d_8x8] [--precision f64|f32]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to rel. residual 1e-10 (FP64 vs FP32-precond); SpMV/trsv HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+COMPUTE_KERNELS = ("qr_gemm_update", "qr_gemm_VtC", "inv_gemm", "qr_panel")
+SKETCH_SEED = 2
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(S, s, itn_total, threads):
+    """The oracle, as it stands, on a bounded sample of the workload, scaled to a
+    full time-to-tolerance estimate: the full sketch, the QR of the first n/4
+    columns of SA (scaled by the Householder flop ratio), and two LSQR
+    iterations of the full-size implicit operator (scaled by the iteration count)."""
+    import numpy as np
+    import scipy.linalg as sla
+
+    from oracle import countsketch, pipeline, qr
+    from oracle.lsqr import lsqr
+
+    t0 = time.perf_counter()
+    h, sign = countsketch.hash_sign(S.m, s, SKETCH_SEED)
+    SA, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+    t_sketch = time.perf_counter() - t0
+    ns = max(64, S.n // 4)
+    t0 = time.perf_counter()
+    qr.r_factor(SA[:, :ns], check_rank=False)
+    t_qr_sample = time.perf_counter() - t0
+    del SA
+    ratio = (ns * ns * (s - ns / 3.0)) / (S.n * S.n * (s - S.n / 3.0))
+    A = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    AT = A.T.tocsr()
+    Rt = np.triu(np.ones((S.n, S.n))) + np.eye(S.n) * S.n
+    t0 = time.perf_counter()
+    lsqr(lambda v: A @ sla.solve_triangular(Rt, v),
+         lambda u: sla.solve_triangular(Rt, AT @ u, trans="T"), S.b[0], S.n, atol=0, btol=0,
+         conlim=0, itmax=2)
+    t_it = (time.perf_counter() - t0) / 2.0
+    est = t_sketch + t_qr_sample / ratio + t_it * itn_total
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle on the {S.m}x{S.n} system: full count sketch ({t_sketch:.1f} s), "
+                       f"Householder QR of SA[:, :{ns}] ({t_qr_sample:.1f} s, scaled by the flop "
+                       f"ratio {ratio:.4f}), 2 LSQR iterations ({t_it:.2f} s each, scaled to "
+                       f"{itn_total} iterations)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poisson2d_8x8")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
+                    help="f64: float64 QR and R^-1; f32: float32 QR on matrix cores, float32-stored R^-1")
+    ap.add_argument("--refine", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-trace", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2409_15818_amd as R
+    from oracle import pipeline  # only for the L2 error / residual check of the output
+    from rfmgen import build_config, exact_solution, feature_eval, sample_points
+
+    torch.cuda.set_device(0)
+    log(f"[bench] building {args.workload}")
+    S, s = build_config(args.workload)
+    A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
+    b = torch.tensor(S.b[0], device="cuda")
+    h = R.Handle()
+    opts = R.default_opts(refine=args.refine)
+    qd = args.precision
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        AT = R.rfmls_transpose(h, A)
+        if ev is not None:
+            ev[1].record()
+        SA, _, _, _ = R.rfmls_sketch(h, A, s, SKETCH_SEED, dtype=qd)
+        if ev is not None:
+            ev[2].record()
+        P = R.rfmls_precond(h, SA, qd, qd)
+        del SA
+        if ev is not None:
+            ev[3].record()
+        X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts)
+        if ev is not None:
+            ev[4].record()
+        return X, info, P, AT
+
+    for w in range(args.warmup):
+        log(f"[bench] warmup {w + 1}/{args.warmup}")
+        out = step()
+        del out
+    torch.cuda.synchronize()
+    times, phases = [], []
+    X = info = None
+    for k in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info, P, AT = step(ev)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        phases.append({"transpose": ev[0].elapsed_time(ev[1]), "sketch": ev[1].elapsed_time(ev[2]),
+                       "qr_and_inverse": ev[2].elapsed_time(ev[3]), "lsqr": ev[3].elapsed_time(ev[4])})
+        log(f"[bench] step {k + 1}/{args.steps}: {dt * 1e3:.1f} ms  itn={info[0]['itn']}")
+        del P, AT
+    med = statistics.median(times)
+    ph = {key: statistics.median(p[key] for p in phases) for key in phases[0]}
+
+    kernels, roof = [], None
+    if not args.no_trace:
+        R.rfmls_trace_enable(h, True)
+        _ = step()
+        torch.cuda.synchronize()
+        kernels = R.rfmls_trace_read(h)
+        R.rfmls_trace_enable(h, False)
+        for k in kernels:
+            k["avg_ms"] = k["ms"] / max(k["launches"], 1)
+            k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+            k["tflops"] = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
+        kernels.sort(key=lambda k: -k["ms"])
+        dom = kernels[0]
+        if dom["name"] in COMPUTE_KERNELS:
+            roof = {"kernel": dom["name"], "bound": "mfma", "achieved": round(dom["tflops"], 3),
+                    "peak": MFMA_PEAK_TFLOPS[qd], "unit": "TFLOP/s",
+                    "frac": round(dom["tflops"] / MFMA_PEAK_TFLOPS[qd], 4), "traffic": None}
+        else:
+            roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(dom["gbs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
+                    "traffic": None}
+
+    # accuracy of the measured solve
+    x = X.detach().cpu().numpy()
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    met = pipeline.residual_metrics(Ah, x, S.b[0])
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    l2 = pipeline.l2_error(E, x, exact_solution(pts))
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    vs_oracle = None
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        vs_oracle = {"oracle_normr": gold["normr"], "rel_diff_normr": abs(met["normr"] - gold["normr"]) / gold["normr"],
+                     "oracle_l2_error": gold["l2_error"], "l2_ratio": l2 / gold["l2_error"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        cpu = cpu_baseline(S, s, int(info[0]["itn"]), threads)
+
+    out = {
+        "metric": METRIC, "value": round(med, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * sum(times) / len(times), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": qd,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
+                   "precision": qd, "refine": args.refine, "atol": opts.atol, "btol": opts.btol},
+        "phases_ms": {k: round(v, 3) for k, v in ph.items()},
+        "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),
+                       "istop": int(info[0]["istop"])},
+        "relres": met["relres"], "normal_relres": met["normal_relres"], "l2_error": l2,
+        "vs_oracle": vs_oracle,
+        "roofline": roof,
+        "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
+                    for k in kernels[:12]],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -48,7 +48,7 @@ typedef enum {
   RFMLS_OK = 0,
   RFMLS_W_NOCONV = 1,     /* iteration limit reached; X is still written */
   RFMLS_E_ARG = -1,       /* invalid argument (sizes, null pointers, layout) */
-  RFMLS_E_RANK = -2,      /* R numerically singular: |r_ii| <= n u max|r_jj| */
+  RFMLS_E_RANK = -2,      /* R numerically singular: |r_ii| <= 16 u max|r_jj| */
   RFMLS_E_BREAKDOWN = -3, /* non-finite value met inside the iteration */
   RFMLS_E_HIP = -4,       /* HIP runtime error (message in rfmls_last_error) */
   RFMLS_E_NOMEM = -5      /* device allocation of library workspace failed */
@@ -140,7 +140,7 @@ rfmls_status rfmls_sketch(rfmls_handle *h, const rfmls_csr *A, int64_t s, uint64
  * (RFMLS_F64, or RFMLS_F32 on matrix cores; must equal the sketch's sa_dtype),
  * rows of R scaled so diag(R) > 0.  The library forms and keeps X = R^{-1}
  * (upper triangular) stored in r_store precision.  Returns RFMLS_E_RANK if
- * some |r_ii| <= n u max_j |r_jj| (u = unit roundoff of qr_dtype; for
+ * some |r_ii| <= 16 u max_j |r_jj| (u = unit roundoff of qr_dtype; for
  * RFMLS_F32 only a zero or non-finite pivot is rejected).  *P_out is
  * library-owned; free with rfmls_precond_free.  Asynchronous except for the
  * rank check, which synchronises the stream. */
@@ -189,6 +189,24 @@ rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfm
                                   const double *Rres, int64_t ldr, const double *G, int64_t ldg,
                                   int64_t nrhs, double *dB, int64_t lddb, double *dAval,
                                   const rfmls_opts *opts, rfmls_info *info);
+
+/* ---- Kernel tracing (measurement support; not part of the numerical path) ----
+ * While enabled, every launch of the library's kernels is bracketed by HIP
+ * events on the handle's stream and tagged with the algorithmic bytes moved and
+ * flops performed by that launch (what the method must read/write/compute, not
+ * what the hardware happened to fetch).  rfmls_trace_read synchronises the
+ * stream and returns one aggregate per kernel name, then clears the records. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;     /* summed event time of all launches        */
+  double bytes;  /* summed algorithmic bytes                 */
+  double flops;  /* summed algorithmic floating-point ops    */
+} rfmls_trace_entry;
+
+rfmls_status rfmls_trace_enable(rfmls_handle *h, int enable);
+/* Writes up to cap entries to out [host]; *count [host] receives the number written. */
+rfmls_status rfmls_trace_read(rfmls_handle *h, rfmls_trace_entry *out, int cap, int *count);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ EXPORTED = [
     "rfmls_default_opts", "rfmls_create", "rfmls_destroy", "rfmls_last_error", "rfmls_transpose",
     "rfmls_sketch", "rfmls_precond", "rfmls_precond_free", "rfmls_precond_n",
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
-    "rfmls_solve", "rfmls_solve_backward",
+    "rfmls_solve", "rfmls_solve_backward", "rfmls_trace_enable", "rfmls_trace_read",
 ]
 
 
@@ -47,6 +47,11 @@ class rfmls_info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rfmls_trace_entry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 _lib = None
@@ -87,6 +92,8 @@ def load():
                                 P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_solve_backward.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, vp,
                                          i64, i64, vp, i64, vp, P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_trace_enable.argtypes = [vp, C.c_int]
+    lib.rfmls_trace_read.argtypes = [vp, P(rfmls_trace_entry), C.c_int, P(C.c_int)]
     for name in EXPORTED:
         if name not in ("rfmls_default_opts", "rfmls_precond_free", "rfmls_last_error",
                         "rfmls_precond_n"):

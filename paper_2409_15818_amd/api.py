@@ -119,6 +119,20 @@ class Precond:
             pass
 
 
+def rfmls_trace_enable(h: Handle, enable: bool = True):
+    h.check(h._lib.rfmls_trace_enable(h._h, int(bool(enable))))
+
+
+def rfmls_trace_read(h: Handle) -> list:
+    """Per-kernel aggregates since the last read: name, launches, ms, bytes, flops."""
+    cap = 64
+    buf = (_lib.rfmls_trace_entry * cap)()
+    cnt = C.c_int(0)
+    h.check(h._lib.rfmls_trace_read(h._h, buf, cap, C.byref(cnt)))
+    return [dict(name=buf[k].name.decode(), launches=buf[k].launches, ms=buf[k].ms,
+                 bytes=buf[k].bytes, flops=buf[k].flops) for k in range(cnt.value)]
+
+
 def rfmls_transpose(h: Handle, A: CSR) -> CSR:
     dev = A.row_ptr.device
     rp = torch.empty(A.n + 1, dtype=torch.int64, device=dev)

@@ -43,6 +43,17 @@ rfmls_status workspace(rfmls_handle* h, int slot, size_t bytes, void** out) {
   return RFMLS_OK;
 }
 
+hipEvent_t trace_event(rfmls_handle* h) {
+  hipEvent_t e = nullptr;
+  if (!h->event_pool.empty()) {
+    e = h->event_pool.back();
+    h->event_pool.pop_back();
+  } else {
+    hipEventCreate(&e);
+  }
+  return e;
+}
+
 static bool csr_ok(const rfmls_csr* A) {
   return A && A->m >= 0 && A->n >= 1 && A->nnz >= 0 && A->row_ptr && (A->nnz == 0 || (A->col && A->val)) &&
          A->nnz < ((int64_t)1 << 31) && A->m < ((int64_t)1 << 31) && A->n < ((int64_t)1 << 31);
@@ -105,6 +116,11 @@ rfmls_status rfmls_destroy(rfmls_handle* h) {
   if (!h) return RFMLS_OK;
   hipSetDevice(h->device);
   hipStreamSynchronize(h->stream);
+  for (auto& r : h->trace_recs) {
+    hipEventDestroy(r.beg);
+    hipEventDestroy(r.end);
+  }
+  for (auto e : h->event_pool) hipEventDestroy(e);
   for (auto& w : h->ws)
     if (w.ptr) hipFree(w.ptr);
   if (h->barrier) hipFree(h->barrier);
@@ -291,6 +307,42 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
   if (nrhs == 0) return RFMLS_OK;
   RFMLS_CHECK(set_device(h));
   return run_backward(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
+}
+
+rfmls_status rfmls_trace_enable(rfmls_handle* h, int enable) {
+  if (!h) return RFMLS_E_ARG;
+  h->trace = enable != 0;
+  return RFMLS_OK;
+}
+
+rfmls_status rfmls_trace_read(rfmls_handle* h, rfmls_trace_entry* out, int cap, int* count) {
+  if (!h || (!out && cap > 0) || !count) return RFMLS_E_ARG;
+  RFMLS_CHECK(set_device(h));
+  RFMLS_HIP(h, hipStreamSynchronize(h->stream));
+  std::vector<rfmls_trace_entry> agg;
+  for (auto& r : h->trace_recs) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.beg, r.end);
+    size_t k = 0;
+    for (; k < agg.size(); ++k)
+      if (strncmp(agg[k].name, r.name, sizeof(agg[k].name)) == 0) break;
+    if (k == agg.size()) {
+      rfmls_trace_entry e{};
+      strncpy(e.name, r.name, sizeof(e.name) - 1);
+      agg.push_back(e);
+    }
+    agg[k].launches += 1;
+    agg[k].ms += ms;
+    agg[k].bytes += r.bytes;
+    agg[k].flops += r.flops;
+    h->event_pool.push_back(r.beg);
+    h->event_pool.push_back(r.end);
+  }
+  h->trace_recs.clear();
+  int n = 0;
+  for (size_t k = 0; k < agg.size() && n < cap; ++k) out[n++] = agg[k];
+  *count = n;
+  return RFMLS_OK;
 }
 
 }  // extern "C"

@@ -24,8 +24,19 @@ struct Workspace {
 
 }  // namespace rfmls
 
+namespace rfmls {
+struct TraceRec {
+  const char* name;
+  hipEvent_t beg, end;
+  double bytes, flops;
+};
+}  // namespace rfmls
+
 struct rfmls_handle {
   int device = 0;
+  bool trace = false;
+  std::vector<rfmls::TraceRec> trace_recs;
+  std::vector<hipEvent_t> event_pool;
   hipStream_t stream = nullptr;
   int num_cus = 0;
   std::string last_error;
@@ -131,6 +142,30 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;
 }
 
+}  // namespace rfmls
+
+// Tracing: bracket the launches issued inside the scope with events when the
+// handle's trace flag is set.  name must be a string literal.
+namespace rfmls {
+hipEvent_t trace_event(rfmls_handle* h);
+struct Trace {
+  rfmls_handle* h;
+  TraceRec rec;
+  Trace(rfmls_handle* hh, const char* name, double bytes, double flops) : h(hh) {
+    if (!h->trace) return;
+    rec.name = name;
+    rec.bytes = bytes;
+    rec.flops = flops;
+    rec.beg = trace_event(h);
+    rec.end = trace_event(h);
+    hipEventRecord(rec.beg, h->stream);
+  }
+  ~Trace() {
+    if (!h->trace) return;
+    hipEventRecord(rec.end, h->stream);
+    h->trace_recs.push_back(rec);
+  }
+};
 }  // namespace rfmls
 
 // Launch entry points implemented in the individual .hip files -----------------

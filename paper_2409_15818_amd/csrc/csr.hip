@@ -87,6 +87,7 @@ rfmls_status run_transpose(rfmls_handle* h, const rfmls_csr* A, int64_t* rp, int
   RFMLS_CHECK(workspace(h, WS_SKETCH_COUNT, sizeof(int32_t) * (size_t)(n + 1), &p_count));
   int32_t* hist = (int32_t*)p_hist;
   int32_t* count = (int32_t*)p_count;
+  Trace tr(h, "transpose", 2.0 * (12.0 * (double)A->nnz) + 8.0 * (double)(m + n + 2), 0.0);
   if (nchunk > 0) {
     hipLaunchKernelGGL(k_tr_hist, dim3((unsigned)nchunk), dim3(256), 0, h->stream, A->row_ptr,
                        A->col, m, n, rc, hist);

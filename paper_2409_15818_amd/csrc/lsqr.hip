@@ -391,6 +391,13 @@ rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, con
   const int maxk = (int)((nt + C - 1) / C);
   hipStream_t st = h->stream;
   double* part = (double*)P->part;
+  const double esz = P->store == RFMLS_F64 ? 8.0 : 4.0;
+  const double tiles = (double)nt * (double)(nt + 1) / 2.0;
+  const double tri_elems = (double)n * (double)(n + 1) / 2.0;
+  {
+  // algorithmic: the n(n+1)/2 stored entries of X once, the input vector, the output
+  Trace tr(h, trans ? "trmv_Xt" : "trmv_X", esz * tri_elems + 16.0 * (double)n, 2.0 * tri_elems);
+  (void)tiles;
   if (!trans) {
     if (P->store == RFMLS_F64)
       hipLaunchKernelGGL(k_trmv_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
@@ -406,6 +413,8 @@ rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, con
       hipLaunchKernelGGL(k_trmvT_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
                          (const float*)P->Xpk, nt, n, P->tab_col, C, maxk, in, part, done);
   }
+  }
+  Trace tr2(h, "tri_reduce", 8.0 * (double)nt * maxk * kTile + 16.0 * (double)n, 0.0);
   hipLaunchKernelGGL(k_tri_reduce, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, st, part, nt, n,
                      C, maxk, trans, hcoef, dcoef, prev, out, sq, done);
   RFMLS_HIP(h, hipGetLastError());
@@ -418,6 +427,12 @@ static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA,
                          const double* dcoef, const double* prev, double* out, double* sq,
                          const int* done, int* nblk) {
   const unsigned nb = spmv_blocks(M->m);
+  // algorithmic: values and column indices once, row pointers, x gathered once,
+  // out written (and prev read when used)
+  Trace tr(c.h, M == c.A ? "spmv_A" : "spmv_At",
+           12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) + 8.0 * (double)M->n +
+               8.0 * (double)M->m * (prev ? 2.0 : 1.0),
+           2.0 * (double)M->nnz);
   hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
                      x, sA, hcoef, dcoef, prev, out, sq, done);
   if (nblk) *nblk = (int)nb;

@@ -255,8 +255,13 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     args[4] = (void*)&rpw_i;
     RFMLS_HIP(h, hipFuncSetAttribute((const void*)k_qr_panel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    {
+    // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
+    const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
+    Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
     RFMLS_HIP(h, hipLaunchCooperativeKernel((const void*)k_qr_panel<T>, dim3((unsigned)G),
                                             dim3(kPanelThreads), args, (unsigned)lds, st));
+    }
     const int64_t ntr = n - k0 - jb;  // trailing columns
     if (ntr <= 0) continue;
     const int64_t ncols = n - k0;     // [V | C]
@@ -278,11 +283,18 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     g1.beta = T(0);
     g1.ksplit = ksplit_rows;
     g1.c_zstride = (int64_t)jb * ncols;
-    RFMLS_HIP(h, gemm<T>(g1, st));
+    {
+      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M * ncols + (double)nsplit * jb * ncols),
+               2.0 * (double)jb * ncols * M);
+      RFMLS_HIP(h, gemm<T>(g1, st));
+    }
+    {
+    Trace tr(h, "qr_buildT_Wp", sizeof(T) * (double)(nsplit + 1) * jb * ncols, 2.0 * (double)jb * jb * ntr);
     hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, W, (int64_t)jb * ncols,
                        (int)nsplit, ncols, jb, tau, Tm);
     hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(ntr, 64)), dim3(256), 0, st, W,
                        (int64_t)jb * ncols, (int)nsplit, ncols, jb, ntr, Tm, Wp, ntr);
+    }
     GemmArgs<T> g2;
     g2.M = M;
     g2.N = ntr;
@@ -297,7 +309,11 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     g2.ldc = ld;
     g2.alpha = T(-1);
     g2.beta = T(1);
-    RFMLS_HIP(h, gemm<T>(g2, st));
+    {
+      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M * ntr + (double)M * jb + (double)jb * ntr),
+               2.0 * (double)M * ntr * jb);
+      RFMLS_HIP(h, gemm<T>(g2, st));
+    }
     RFMLS_HIP(h, hipGetLastError());
   }
   return RFMLS_OK;

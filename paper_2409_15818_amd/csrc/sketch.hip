@@ -189,6 +189,7 @@ __global__ void k_sketch_rhs(const double* __restrict__ b, int64_t nrhs, int64_t
 rfmls_status launch_hash_sign(rfmls_handle* h, int64_t m, int64_t s, uint64_t seed, int32_t* hash,
                               int8_t* sign) {
   if (m == 0) return RFMLS_OK;
+  Trace tr(h, "hash_sign", 5.0 * (double)m, 0.0);
   hipLaunchKernelGGL(k_hash_sign, dim3(ceil_div(m, 256)), dim3(256), 0, h->stream, m, (uint64_t)s,
                      seed, hash, sign);
   RFMLS_HIP(h, hipGetLastError());
@@ -201,6 +202,7 @@ rfmls_status launch_hash_sign(rfmls_handle* h, int64_t m, int64_t s, uint64_t se
 rfmls_status bucket_sort(rfmls_handle* h, const int32_t* key, int64_t m, int64_t nb, int64_t* ptr,
                          int32_t* perm, int32_t* scratch_count, int32_t* scratch_tmp) {
   hipStream_t st = h->stream;
+  Trace tr(h, "bucket_sort", 4.0 * (double)m * 4.0 + 8.0 * (double)nb * 3.0, 0.0);
   hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(nb, 256) < 4096 ? ceil_div(nb, 256) : 4096),
                      dim3(256), 0, st, scratch_count, nb, 0);
   if (m > 0)
@@ -235,12 +237,20 @@ rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const in
   int64_t* bptr = (int64_t*)p_ptr;
   int32_t* perm = (int32_t*)p_perm;
   RFMLS_CHECK(bucket_sort(h, hash, A->m, s, bptr, perm, (int32_t*)p_count, (int32_t*)p_tmp));
+  {
+  // algorithmic bytes: CSR read once, bucket list and signs, dense SA written once
+  const double esz = dt == RFMLS_F64 ? 8.0 : 4.0;
+  Trace tr(h, "sketch_rows",
+           12.0 * (double)A->nnz + 8.0 * (double)(A->m + 1) + 5.0 * (double)A->m +
+               8.0 * (double)(s + 1) + esz * (double)s * (double)A->n,
+           (double)A->nnz);
   if (dt == RFMLS_F64)
     hipLaunchKernelGGL(k_sketch_rows<double>, dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
                        A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (double*)SA, ld);
   else
     hipLaunchKernelGGL(k_sketch_rows<float>, dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
                        A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (float*)SA, ld);
+  }
   RFMLS_HIP(h, hipGetLastError());
   if (b != nullptr && Sb != nullptr && nrhs > 0) {
     hipLaunchKernelGGL(k_sketch_rhs, dim3(ceil_div(s, 256)), dim3(256), 0, h->stream, b, nrhs, ldb,

@@ -1,0 +1,56 @@
+"""Write the oracle's reference values for the full-size workloads.
+
+Calls only the CPU oracle (oracle/) on inputs from the seeded generator
+(rfmgen/); the GPU path is never involved.  Usage:
+    python tests/golden/make_golden.py poisson2d_8x8 [poisson3d_4x4x4 ...]
+writes tests/golden/<name>.json.
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import countsketch, pipeline, qr  # noqa: E402
+from rfmgen import build_config, exact_solution, feature_eval, sample_points  # noqa: E402
+
+SKETCH_SEED = 2
+
+
+def main(name: str, refine: int = 2):
+    t0 = time.time()
+    S, s = build_config(name)
+    h, sign = countsketch.hash_sign(S.m, s, SKETCH_SEED)
+    SA, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+    t1 = time.time()
+    R = qr.r_factor(SA, check_rank=False)
+    del SA
+    t2 = time.time()
+    A = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    x, results = pipeline.refined_lsqr(A, R, S.b[0], refine=refine)
+    t3 = time.time()
+    met = pipeline.residual_metrics(A, x, S.b[0])
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    out = dict(
+        workload=name, m=S.m, n=S.n, nnz=S.nnz, s=s, sketch_seed=SKETCH_SEED, refine=refine,
+        itn_sweeps=[r.itn for r in results], istop_sweeps=[r.istop for r in results],
+        normb=float(np.linalg.norm(S.b[0])), normr=met["normr"], relres=met["relres"],
+        normal_relres=met["normal_relres"], l2_error=pipeline.l2_error(E, x, exact_solution(pts)),
+        rdiag_min=float(np.abs(np.diag(R)).min()), rdiag_max=float(np.abs(np.diag(R)).max()),
+        seconds=dict(sketch=t1 - t0, qr=t2 - t1, lsqr=t3 - t2),
+    )
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:]:
+        main(nm)
