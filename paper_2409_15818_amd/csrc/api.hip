@@ -99,14 +99,14 @@ rfmls_status rfmls_create(rfmls_handle** out, int device, void* stream) {
     return RFMLS_E_HIP;
   }
   h->num_cus = prop.multiProcessorCount;
-  if (hipMalloc(&h->barrier, 64 * sizeof(unsigned)) != hipSuccess ||
+  if (hipMalloc(&h->barrier, kBarrierWords * sizeof(unsigned)) != hipSuccess ||
       hipMalloc(&h->dev_flags, 64 * sizeof(int)) != hipSuccess ||
       hipHostMalloc(&h->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     rfmls_destroy(h);
     return RFMLS_E_NOMEM;
   }
   h->pinned_bytes = 4096;
-  hipMemset(h->barrier, 0, 64 * sizeof(unsigned));
+  hipMemset(h->barrier, 0, kBarrierWords * sizeof(unsigned));
   hipMemset(h->dev_flags, 0, 64 * sizeof(int));
   *out = h;
   return RFMLS_OK;

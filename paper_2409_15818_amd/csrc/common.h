@@ -13,6 +13,9 @@
 namespace rfmls {
 
 constexpr int kWave = 64;  // CDNA wavefront width
+// grid-reduction counters of the QR panel kernel: one 256-byte line per counter
+constexpr int kBarrierStride = 64;     // unsigned words between counters
+constexpr int kBarrierWords = 64 * kBarrierStride;
 
 // ---------------------------------------------------------------------------
 // Handle and workspace
@@ -108,6 +111,9 @@ enum WsSlot {
   WS_QR_W,
   WS_QR_WP,
   WS_QR_T,
+  WS_QR_WR,
+  WS_QR_Y,
+  WS_QR_TI,
   WS_TRSM,
   WS_LSQR_VEC,
   WS_LSQR_SCAL,

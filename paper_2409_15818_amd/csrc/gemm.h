@@ -10,14 +10,15 @@
 //     coordinates reads 0 for r < c, 1 for r == c and the stored value for
 //     r > c.  For A the panel coordinates are (r, c) = (i, k) (no transpose) or
 //     (k, i) (transpose); for B they are (k, j) for the first b_vcols columns.
-//   - triangular skipping: op(A) upper triangular (k >= i only) and/or B upper
-//     triangular (k <= j only); whole zero K-tiles are skipped.
+//   - triangular operands: op(A) upper (k >= i only) or lower (k <= i only)
+//     triangular and/or B upper triangular (k <= j only); zero K-tiles are
+//     skipped and the zero triangle is never read (it may hold anything).
 // Split-K: blockIdx.z selects the K range [z*ksplit, (z+1)*ksplit) and output
 // C + z*c_zstride (each slice writes its own partial result, no atomics).
 //
-// Block: 256 threads = 4 waves in a 2 x 2 grid; a block computes a 64 x 64
-// tile of C, each wave a 32 x 32 sub-tile as 2 x 2 MFMA 16 x 16 tiles.  K is
-// staged through LDS in steps of 16.
+// Block: 256 threads = 4 waves in a 2 x 2 grid computing a 128 x 128 (or 64-
+// wide) tile of C, each wave a quarter of it as 16 x 16 MFMA tiles.  K is
+// staged through LDS in steps of 16, the next step prefetched into registers.
 #pragma once
 
 #include "common.h"
@@ -38,6 +39,7 @@ struct GemmArgs {
   int a_vmask = 0;      // A is V (Householder mask)
   int64_t b_vcols = 0;  // first b_vcols columns of B are V (Householder mask)
   int a_upper = 0;      // op(A) upper triangular
+  int a_lower = 0;      // op(A) lower triangular
   int b_upper = 0;      // B upper triangular
   int64_t ksplit = 0;   // 0 = no split
   int64_t c_zstride = 0;
@@ -78,105 +80,138 @@ __device__ __forceinline__ T vmask(int64_t r, int64_t c, T v) {
   return r < c ? T(0) : (r == c ? T(1) : v);
 }
 
+// Tile load helpers: element (i, k) of op(A) and (k, j) of B with masks and bounds.
 template <typename T>
+__device__ __forceinline__ T load_a(const GemmArgs<T>& g, int64_t gi, int64_t gk, int64_t kend) {
+  T v = T(0);
+  if (gi < g.M && gk < kend && !(g.a_upper && gk < gi) && !(g.a_lower && gk > gi)) {
+    if (!g.transA) {
+      v = g.A[gi * g.lda + gk];
+      if (g.a_vmask) v = vmask<T>(gi, gk, v);
+    } else {
+      v = g.A[gk * g.lda + gi];
+      if (g.a_vmask) v = vmask<T>(gk, gi, v);
+    }
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T load_b(const GemmArgs<T>& g, int64_t gk, int64_t gj, int64_t kend) {
+  T v = T(0);
+  if (gj < g.N && gk < kend && !(g.b_upper && gk > gj)) {
+    v = g.B[gk * g.ldb + gj];
+    if (gj < g.b_vcols) v = vmask<T>(gk, gj, v);
+  }
+  return v;
+}
+
+// Block tile BM x BN (BM, BN in {64, 128}); 4 waves in a 2 x 2 grid, each wave
+// (BM/2) x (BN/2) made of 16 x 16 MFMA tiles.  The next K chunk is fetched
+// from global memory into registers while the current one is consumed from
+// LDS, so the loads overlap the matrix-core work.
+template <typename T, int BMt, int BNt>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  constexpr int TM = BMt / 32, TN = BNt / 32;   // MFMA tiles per wave per dim
+  constexpr int EA = BMt * BK / 256;             // A elements per thread per chunk
+  constexpr int EB = BNt * BK / 256;             // B elements per thread per chunk
+  __shared__ T As[BK][BMt + PAD];
+  __shared__ T Bs[BK][BNt + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wy = wave >> 1, wx = wave & 1;
-  const int64_t i0 = (int64_t)blockIdx.y * BM;
-  const int64_t j0 = (int64_t)blockIdx.x * BN;
+  const int64_t i0 = (int64_t)blockIdx.y * BMt;
+  const int64_t j0 = (int64_t)blockIdx.x * BNt;
   int64_t kbeg = 0, kend = g.K;
   if (g.ksplit > 0) {
     kbeg = (int64_t)blockIdx.z * g.ksplit;
     kend = kbeg + g.ksplit < g.K ? kbeg + g.ksplit : g.K;
   }
-  if (g.a_upper && i0 > kbeg) kbeg = i0 - (i0 % BK) > kbeg ? i0 - (i0 % BK) : kbeg;
+  if (g.a_upper && i0 > kbeg) kbeg = i0;
+  if (g.a_lower) {
+    const int64_t lim = i0 + BMt;
+    if (lim < kend) kend = lim;
+  }
   if (g.b_upper) {
-    const int64_t lim = j0 + BN;
+    const int64_t lim = j0 + BNt;
     if (lim < kend) kend = lim;
   }
   T* C = g.C + (int64_t)blockIdx.z * g.c_zstride;
 
-  typename Mfma<T>::acc_t acc[2][2];
+  typename Mfma<T>::acc_t acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    for (int b = 0; b < TN; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- stage op(A) tile (BM x BK) into As[k][i] ----
+  // thread -> element mapping of the staging loads (contiguous runs in memory)
+  // op(A) not transposed: row r = tid / (256/BMt), k run of EA starting at ka
+  // op(A) transposed / B: k = tid / (BMt/EA) (resp. BNt/EB), run along i (resp. j)
+  T ra[EA], rb[EB];
+  auto fetch = [&](int64_t k0) {
     if (!g.transA) {
-      const int r = tid >> 2;          // 0..63
-      const int kk = (tid & 3) * 4;    // 0,4,8,12
-      const int64_t gi = i0 + r;
+      const int r = tid / (BK / EA);
+      const int ka = (tid % (BK / EA)) * EA;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gk = k0 + kk + q;
-        T v = T(0);
-        if (gi < g.M && gk < kend) {
-          v = g.A[gi * g.lda + gk];
-          if (g.a_vmask) v = vmask<T>(gi, gk, v);
-        }
-        As[kk + q][r] = v;
-      }
+      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + r, k0 + ka + q, kend);
     } else {
-      const int kk = tid >> 4;         // 0..15
-      const int r = (tid & 15) * 4;    // 0..60
-      const int64_t gk = k0 + kk;
+      const int kk = tid / (BMt / EA);
+      const int r = (tid % (BMt / EA)) * EA;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gi = i0 + r + q;
-        T v = T(0);
-        if (gi < g.M && gk < kend) {
-          v = g.A[gk * g.lda + gi];
-          if (g.a_vmask) v = vmask<T>(gk, gi, v);
-        }
-        As[kk][r + q] = v;
-      }
+      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + r + q, k0 + kk, kend);
     }
-    // ---- stage B tile (BK x BN) into Bs[k][j] ----
-    {
-      const int kk = tid >> 4;
-      const int c = (tid & 15) * 4;
-      const int64_t gk = k0 + kk;
+    const int kk = tid / (BNt / EB);
+    const int c = (tid % (BNt / EB)) * EB;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gj = j0 + c + q;
-        T v = T(0);
-        if (gj < g.N && gk < kend) {
-          v = g.B[gk * g.ldb + gj];
-          if (gj < g.b_vcols) v = vmask<T>(gk, gj, v);
-        }
-        Bs[kk][c + q] = v;
-      }
+    for (int q = 0; q < EB; ++q) rb[q] = load_b(g, k0 + kk, j0 + c + q, kend);
+  };
+  auto stash = [&]() {
+    if (!g.transA) {
+      const int r = tid / (BK / EA);
+      const int ka = (tid % (BK / EA)) * EA;
+#pragma unroll
+      for (int q = 0; q < EA; ++q) As[ka + q][r] = ra[q];
+    } else {
+      const int kk = tid / (BMt / EA);
+      const int r = (tid % (BMt / EA)) * EA;
+#pragma unroll
+      for (int q = 0; q < EA; ++q) As[kk][r + q] = ra[q];
     }
+    const int kk = tid / (BNt / EB);
+    const int c = (tid % (BNt / EB)) * EB;
+#pragma unroll
+    for (int q = 0; q < EB; ++q) Bs[kk][c + q] = rb[q];
+  };
+
+  if (kbeg < kend) fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
-      T a0 = As[kr][wy * 32 + (lane & 15)];
-      T a1 = As[kr][wy * 32 + 16 + (lane & 15)];
-      T b0 = Bs[kr][wx * 32 + (lane & 15)];
-      T b1 = Bs[kr][wx * 32 + 16 + (lane & 15)];
-      acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[kr][wy * (BMt / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[kr][wx * (BNt / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
     }
-    __syncthreads();
   }
   // ---- epilogue: register r of each 16x16 tile is element (Mfma::row(lane, r), lane % 16) ----
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wy * 32 + a * 16 + Mfma<T>::row(lane, r);
-        const int64_t gj = j0 + wx * 32 + b * 16 + (lane & 15);
+        const int64_t gi = i0 + wy * (BMt / 2) + a * 16 + Mfma<T>::row(lane, r);
+        const int64_t gj = j0 + wx * (BNt / 2) + b * 16 + (lane & 15);
         if (gi < g.M && gj < g.N) {
           T v = g.alpha * acc[a][b][r];
           if (g.beta != T(0)) v += g.beta * C[gi * g.ldc + gj];
@@ -193,9 +228,21 @@ inline hipError_t gemm(const GemmArgs<T>& g, hipStream_t st) {
   unsigned gz = 1;
   if (g.ksplit > 0) gz = (unsigned)((g.K + g.ksplit - 1) / g.ksplit);
   if (gz == 0) gz = 1;
-  dim3 grid((unsigned)((g.N + gemm_detail::BN - 1) / gemm_detail::BN),
-            (unsigned)((g.M + gemm_detail::BM - 1) / gemm_detail::BM), gz);
-  hipLaunchKernelGGL(gemm_detail::k_gemm<T>, grid, dim3(256), 0, st, g);
+  // 128 x 128 tiles for large outputs, 64-wide tiles where a dimension is small
+  const bool bigM = g.M > 64, bigN = g.N > 64;
+  if (bigM && bigN) {
+    dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), gz);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 128>), grid, dim3(256), 0, st, g);
+  } else if (bigN) {
+    dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 63) / 64), gz);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 128>), grid, dim3(256), 0, st, g);
+  } else if (bigM) {
+    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 127) / 128), gz);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 64>), grid, dim3(256), 0, st, g);
+  } else {
+    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), gz);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 64>), grid, dim3(256), 0, st, g);
+  }
   return hipGetLastError();
 }
 

@@ -1,20 +1,25 @@
 // Blocked Householder QR of the sketch SA (s x n, row-major, in place):
 // Alg. 1 step 3.  Only R is needed; Q is never formed.
 //
-// For each panel of nb columns starting at k0 (M = s - k0 rows):
-//   1. k_qr_panel   unblocked Householder on the s x nb panel.  The panel is
-//                   spread over G co-resident workgroups (rows held in LDS);
-//                   every column needs one grid-wide reduction: the partial
-//                   sums  sigma = sum_{i>j} a_ij^2  and  d_c = sum_{i>j} a_ij a_ic
-//                   plus the pivot row, after which every workgroup forms the
-//                   same reflector (LAPACK dlarfg convention: beta = -sign(alpha)
-//                   ||(alpha, x)||, tau = (beta - alpha) / beta, v = [1; x/(alpha-beta)])
-//                   and applies it to its rows.
-//   2. k_gemm       W_z = V^T [V | C] over row slices z (split-K partials)
-//   3. k_qr_buildT  sum the V^T V partials and build the compact-WY factor T
-//                   (I - V T V^T = H_1 ... H_nb; LAPACK dlarft, forward, columnwise)
-//   4. k_qr_wp      W' = T^T sum_z W_z for the trailing columns
-//   5. k_gemm       C <- C - V W'
+// Two levels of blocking.  Outer blocks of kOuter = 256 columns are factored
+// panel by panel (kMaxNb = 64 columns each); the trailing matrix right of an
+// outer block is then updated once, with K = 256, which keeps that update --
+// most of the flops -- on the matrix cores instead of bound by HBM traffic.
+//
+// Inner panel at column p0 (M = s - p0 rows):
+//   k_qr_panel   unblocked Householder on the M x 64 panel, spread over G
+//                co-resident workgroups (rows held in LDS); each column needs one
+//                grid-wide reduction of sigma = sum_{i>j} a_ij^2, d_c = sum_{i>j}
+//                a_ij a_ic and the pivot row, after which every workgroup forms
+//                the same reflector (LAPACK dlarfg convention: beta = -sign(alpha)
+//                ||(alpha, x)||, tau = (beta - alpha)/beta, v = [1; x/(alpha-beta)])
+//                and applies it to its rows;
+//   inside the outer block: W = V^T [V | C] (split-K GEMM), T from V^T V
+//                (dlarft, forward, columnwise), C <- C - V (T^T W).
+// Outer block at column k0 (M0 = s - k0 rows, V_o = its 256 Householder vectors):
+//   W = V_o^T [V_o | C] (split-K GEMM; the first 256 columns are the Gram V_o^T V_o),
+//   T_o from the Gram: diagonal 64-blocks by dlarft, off-diagonal blocks by
+//   T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
 // All reductions run in a fixed order, so the factorisation is deterministic.
 #include "common.h"
 #include "gemm.h"
@@ -22,18 +27,85 @@
 namespace rfmls {
 namespace {
 
-constexpr int kPanelThreads = 256;
 constexpr int kMaxNb = 64;
-constexpr int kPartStride = 2 * kMaxNb;  // per slot: [c] sums (c in [j, nb)), [64 + c] pivot row
 
-__device__ __forceinline__ bool grid_barrier(unsigned* counter, unsigned target, int* err) {
-  __syncthreads();
+// Grid-wide sum of one payload vector per block, returned to every block.
+// Two levels keep both the serialised atomics and the reads short: blocks are
+// grouped in clusters of kCluster; the last block to arrive in a cluster sums
+// its cluster's payloads (in block order) and arrives at the global counter;
+// the last cluster leader sums the cluster sums (in cluster order), publishes
+// the result and bumps a generation word that every block waits for.  All
+// sums run in a fixed order, so every block receives bit-identical values.
+//   pw   [G][kPayload]      block payloads (written by the caller before the call)
+//   cw   [nclus][kPayload]  cluster sums
+//   out  [2][kPayload]      published result, double-buffered by epoch parity
+//   cnt  [(nclus + 2) * kBarrierStride]  cluster counters, global counter and
+//                           generation word, each on its own cache line
+// Counters only grow; epoch e (0, 1, ...) numbers the calls within one launch.
+constexpr int kCluster = 16;
+constexpr int kPayload = 2 * kMaxNb;
+
+__device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsigned* cnt, int lo,
+                               int hi, unsigned epoch, double* red, int* err) {
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  const int nclus = (G + kCluster - 1) / kCluster;
+  const int cl = g / kCluster;
+  const int csize = (cl == nclus - 1) ? G - cl * kCluster : kCluster;
+  unsigned* gcount = cnt + (int64_t)nclus * kBarrierStride;
+  unsigned* gen = cnt + (int64_t)(nclus + 1) * kBarrierStride;
+  __shared__ int role;  // 0: wait, 1: cluster leader, 2: global leader
   __shared__ int ok;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    int spins = 0;
     ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    const unsigned old =
+        __hip_atomic_fetch_add(&cnt[(int64_t)cl * kBarrierStride], 1u, __ATOMIC_ACQ_REL,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    role = (old == (epoch + 1) * (unsigned)csize - 1u) ? 1 : 0;
+  }
+  __syncthreads();
+  if (role == 1) {
+    for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
+      // issue all loads before summing (one memory round trip, not kCluster)
+      double v[kCluster];
+#pragma unroll
+      for (int q = 0; q < kCluster; ++q)
+        v[q] = q < csize ? pw[(int64_t)(cl * kCluster + q) * kPayload + k] : 0.0;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kCluster; ++q) s += v[q];
+      cw[(int64_t)cl * kPayload + k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned old =
+          __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == (epoch + 1) * (unsigned)nclus - 1u) role = 2;
+    }
+    __syncthreads();
+    if (role == 2) {
+      double* o = out + (int64_t)(epoch & 1u) * kPayload;
+      for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
+        double s = 0.0;
+        for (int c0 = 0; c0 < nclus; c0 += kCluster) {
+          double v[kCluster];
+#pragma unroll
+          for (int q = 0; q < kCluster; ++q)
+            v[q] = c0 + q < nclus ? cw[(int64_t)(c0 + q) * kPayload + k] : 0.0;
+#pragma unroll
+          for (int q = 0; q < kCluster; ++q) s += v[q];
+        }
+        o[k] = s;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(gen, epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch + 1u) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1 << 26)) {
         ok = 0;
@@ -43,71 +115,96 @@ __device__ __forceinline__ bool grid_barrier(unsigned* counter, unsigned target,
     }
   }
   __syncthreads();
-  return ok != 0;
+  if (!ok) return false;
+  const double* o = out + (int64_t)(epoch & 1u) * kPayload;
+  for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) red[k] = o[k];
+  __syncthreads();
+  return true;
 }
 
-// part layout: part[slot][c][g], c in [0, 2*kMaxNb), g in [0, G)
-template <typename T>
+// Payload of column j (length 2 (nb - j)): entry c - j for c in [j, nb) holds
+// sigma (c == j) or d_c (c > j); entry (nb - j) + (c - j) holds the pivot row
+// value a_jc (only the block owning row j contributes, the others add 0).
+//
+// Each block owns rpw <= 8 Q consecutive panel rows and keeps them in
+// registers: thread (c = lane, rg = wavefront) holds a[q] = P[r0 + rg + 8 q][c].
+// All threads of a wavefront hold the same rows, so column j reaches every
+// lane of the wavefront by v_readlane from lane j (scalar registers, no LDS).
+// Few, large blocks keep the per-column grid reduction short (its cost grows
+// with the number of blocks).
+constexpr int kPanelThreads = 512;
+constexpr int kPanelGroups = kPanelThreads / 64;
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double lane_value(float v, int lane) {
+  return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <typename T, int Q>
 __global__ void __launch_bounds__(kPanelThreads)
     k_qr_panel(T* __restrict__ P, int64_t ld, int64_t M, int nb, int rpw, T* __restrict__ tau,
-               double* __restrict__ part, unsigned* __restrict__ bar, int* __restrict__ err) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);          // rpw x nb
-  __shared__ double red[2 * kMaxNb];                 // reduced sums / pivot row
-  __shared__ double grp[4][kMaxNb];                  // per row-group partials
+               double* __restrict__ ws, unsigned* __restrict__ cnt, int* __restrict__ err) {
+  __shared__ double red[kPayload];              // reduced payload
+  __shared__ double grp[kPanelGroups][kMaxNb];  // per row-group partials
+  __shared__ double piv[kMaxNb];                // pivot row (owner block)
   const int G = gridDim.x;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
-  const int c = tid & 63;    // column handled by this thread
-  const int rg = tid >> 6;   // row group 0..3
+  const int c = tid & 63;
+  const int rg = tid >> 6;  // wavefront index: uniform within a wavefront
   const int64_t r0 = (int64_t)g * rpw;
   const int nr = (int)(M - r0 < rpw ? (M - r0 > 0 ? M - r0 : 0) : rpw);
+  const int nclus = (G + kCluster - 1) / kCluster;
+  double* pw = ws;                               // [G][kPayload]
+  double* cw = ws + (int64_t)G * kPayload;       // [nclus][kPayload]
+  double* out = cw + (int64_t)nclus * kPayload;  // [2][kPayload]
 
-  for (int e = tid; e < nr * nb; e += kPanelThreads) {
-    const int i = e / nb, cc = e % nb;
-    tile[e] = P[(r0 + i) * ld + cc];
+  // rows beyond the panel are held as zeros and contribute nothing
+  T a[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int li = rg + kPanelGroups * q;
+    a[q] = (li < nr && c < nb) ? P[(r0 + li) * ld + c] : T(0);
   }
-  __syncthreads();
 
   for (int j = 0; j < nb; ++j) {
-    const int slot = j & 1;
-    double* pw = part + (int64_t)slot * kPartStride * G;
-    // ---- local partials over rows i > j (global panel row index) ----
+    // Only block 0 (rows 0 .. rpw-1, rpw >= 128 >= nb) holds rows i <= j; in
+    // every other block all rows take part.  li > j is uniform per wavefront.
+    const bool top = (g == 0);
+    if (top && rg == (j % kPanelGroups)) {  // pivot row j lives in this wavefront
+      const int qj = j / kPanelGroups;
+      double pv = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) pv = (q == qj) ? (double)a[q] : pv;
+      piv[c] = pv;
+    }
+    // ---- local partials over rows i > j: sum_i a_ij a_ic ----
     double s = 0.0;
-    if (c >= j && c < nb) {
-      for (int i = rg; i < nr; i += 4) {
-        const int64_t gi = r0 + i;
-        if (gi > j) s += (double)tile[i * nb + j] * (double)tile[i * nb + c];
-      }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int li = rg + kPanelGroups * q;
+      if (!top || li > j) s += lane_value(a[q], j) * (double)a[q];
     }
     grp[rg][c] = s;
     __syncthreads();
+    const int L = nb - j;
     if (tid < 64 && c >= j && c < nb) {
-      const double t = (grp[0][c] + grp[1][c]) + (grp[2][c] + grp[3][c]);
-      pw[(int64_t)c * G + g] = t;
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPanelGroups; ++q) t += grp[q][c];
+      double* my = pw + (int64_t)g * kPayload;
+      my[c - j] = t;
+      my[L + c - j] = top ? piv[c] : 0.0;
     }
-    // pivot row j lives in block j / rpw
-    const bool own_pivot = (j >= r0) && (j < r0 + nr);
-    if (own_pivot && tid < 64 && c >= j && c < nb)
-      pw[(int64_t)(kMaxNb + c) * G + g] = (double)tile[(j - r0) * nb + c];
-    if (!grid_barrier(bar, (unsigned)((j + 1) * G), err)) return;
-    // ---- reduce: wave w handles columns c = w, w+4, ... (coalesced over g) ----
-    {
-      const int lane = tid & 63;
-      const int w = tid >> 6;
-      for (int cc = j + w; cc < nb; cc += 4) {
-        double t = 0.0;
-        for (int gg = lane; gg < G; gg += 64) t += pw[(int64_t)cc * G + gg];
-        t = wave_sum(t);
-        if (lane == 0) red[cc] = t;
-      }
-      const int owner = j / rpw;
-      if (tid < 64 && c >= j && c < nb) red[kMaxNb + c] = pw[(int64_t)(kMaxNb + c) * G + owner];
-    }
-    __syncthreads();
+    if (!grid_allreduce(pw, cw, out, cnt, 0, 2 * L, (unsigned)j, red, err)) return;
     // ---- reflector (identical in every block) ----
-    const double alpha = red[kMaxNb + j];
-    const double sigma = red[j];
+    const double alpha = red[L];
+    const double sigma = red[0];
     double beta, tj, scal;
     if (sigma == 0.0) {
       beta = alpha;
@@ -120,33 +217,28 @@ __global__ void __launch_bounds__(kPanelThreads)
       scal = 1.0 / (alpha - beta);
     }
     if (g == 0 && tid == 0) tau[j] = (T)tj;
-    // ---- apply H_j to this block's rows i >= j, columns c > j ----
-    if (c > j && c < nb && tj != 0.0) {
-      const double wc = red[kMaxNb + c] + scal * red[c];
-      const double f = tj * wc;
-      for (int i = rg; i < nr; i += 4) {
-        const int64_t gi = r0 + i;
-        if (gi > j) {
-          const double vi = scal * (double)tile[i * nb + j];
-          tile[i * nb + c] = (T)((double)tile[i * nb + c] - vi * f);
-        } else if (gi == j) {
-          tile[i * nb + c] = (T)((double)tile[i * nb + c] - f);
-        }
-      }
-    }
-    __syncthreads();
-    if (c == j) {
-      for (int i = rg; i < nr; i += 4) {
-        const int64_t gi = r0 + i;
-        if (gi > j) tile[i * nb + j] = (T)(scal * (double)tile[i * nb + j]);
-        else if (gi == j) tile[i * nb + j] = (T)beta;
+    // ---- apply H_j to rows i >= j of columns c > j; column j becomes v ----
+    const bool upd = (c > j && c < nb && tj != 0.0);
+    const double f = upd ? tj * (red[L + c - j] + scal * red[c - j]) : 0.0;
+    const double sf = scal * f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int li = rg + kPanelGroups * q;
+      const double vj = lane_value(a[q], j);  // read before lane j rewrites it
+      if (!top || li > j) {
+        if (upd) a[q] = (T)((double)a[q] - sf * vj);
+        else if (c == j) a[q] = (T)(scal * vj);
+      } else if (li == j) {
+        if (upd) a[q] = (T)((double)a[q] - f);
+        else if (c == j) a[q] = (T)beta;
       }
     }
     __syncthreads();
   }
-  for (int e = tid; e < nr * nb; e += kPanelThreads) {
-    const int i = e / nb, cc = e % nb;
-    P[(r0 + i) * ld + cc] = tile[e];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int li = rg + kPanelGroups * q;
+    if (li < nr && c < nb) P[(r0 + li) * ld + c] = a[q];
   }
 }
 
@@ -155,7 +247,7 @@ __global__ void __launch_bounds__(kPanelThreads)
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_qr_buildT(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb,
-                const T* __restrict__ tau, T* __restrict__ Tout) {
+                const T* __restrict__ tau, T* __restrict__ Tout, int64_t ldt) {
   __shared__ double Gm[kMaxNb][kMaxNb + 1];
   __shared__ double Tm[kMaxNb][kMaxNb + 1];
   __shared__ double tv[kMaxNb];
@@ -181,7 +273,19 @@ __global__ void __launch_bounds__(256)
     if (tid == 0) Tm[j][j] = tj;
     __syncthreads();
   }
-  for (int e = tid; e < nb * nb; e += 256) Tout[e] = (T)Tm[e / nb][e % nb];
+  for (int e = tid; e < nb * nb; e += 256) Tout[(int64_t)(e / nb) * ldt + e % nb] = (T)Tm[e / nb][e % nb];
+}
+
+// W[e] = sum_z Wz[z * zstride + e] over a contiguous range of len elements
+template <typename T>
+__global__ void k_sum_slices(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t len,
+                             T* __restrict__ W) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < nsplit; ++z) acc += (double)Wz[(int64_t)z * zstride + e];
+    W[e] = (T)acc;
+  }
 }
 
 // W'[:, cols] = T^T * sum_z Wz[:, nb + cols], one block per 64 columns.
@@ -213,106 +317,211 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+constexpr int64_t kOuter = 256;
+
+// largest rows-per-thread of the register-resident panel (float64 needs 2 VGPRs per row)
+// (the largest register-resident configurations that compile without spills)
+template <typename T>
+constexpr int kQmax() { return sizeof(T) == 8 ? 32 : 64; }
+
+template <typename T>
+GemmArgs<T> vt_gemm(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, T* out,
+                    int64_t ksplit) {
+  // out_z = V^T [V | C] over row slices: V = the vcols Householder vectors
+  // stored below the diagonal of P, C the next ncols - vcols columns
+  GemmArgs<T> g;
+  g.M = vcols;
+  g.N = ncols;
+  g.K = M;
+  g.A = P;
+  g.lda = ld;
+  g.transA = 1;
+  g.a_vmask = 1;
+  g.B = P;
+  g.ldb = ld;
+  g.b_vcols = vcols;
+  g.C = out;
+  g.ldc = ncols;
+  g.alpha = T(1);
+  g.beta = T(0);
+  g.ksplit = ksplit;
+  g.c_zstride = vcols * ncols;
+  return g;
+}
+
+template <typename T>
+GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, const T* Wp) {
+  // C <- C - V Wp, C = the ncols columns right of the vcols Householder vectors
+  GemmArgs<T> g;
+  g.M = M;
+  g.N = ncols;
+  g.K = vcols;
+  g.A = P;
+  g.lda = ld;
+  g.a_vmask = 1;
+  g.B = Wp;
+  g.ldb = ncols;
+  g.C = P + vcols;
+  g.ldc = ld;
+  g.alpha = T(-1);
+  g.beta = T(1);
+  return g;
 }
 
 template <typename T>
 rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
   hipStream_t st = h->stream;
-  const int nbmax = kMaxNb;
-  const int64_t ksplit_rows = 4096;
-  const int64_t max_split = (s + ksplit_rows - 1) / ksplit_rows;
-  void *p_tau, *p_part, *p_w, *p_wp, *p_t;
-  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * nbmax, &p_tau));
-  RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(double) * 2 * kPartStride * 1024, &p_part));
-  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * (size_t)max_split * nbmax * (size_t)n, &p_w));
-  RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * (size_t)nbmax * (size_t)n, &p_wp));
-  RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * nbmax * nbmax, &p_t));
+  const int64_t split_in = 512, split_out = 8192;
+  const int64_t nsp_in_max = (s + split_in - 1) / split_in;
+  const int64_t nsp_out_max = (s + split_out - 1) / split_out;
+  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y, *p_ti;
+  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuter, &p_tau));
+  RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(double) * kPayload * (1024 + 1024 / kCluster + 2 + 8),
+                        &p_part));
+  const size_t wz_in = (size_t)nsp_in_max * kMaxNb * kOuter;
+  const size_t wz_out = (size_t)nsp_out_max * kOuter * (size_t)n;
+  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * (wz_in > wz_out ? wz_in : wz_out), &p_wz));
+  RFMLS_CHECK(workspace(h, WS_QR_WR, sizeof(T) * kOuter * (size_t)n, &p_w));
+  RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)n, &p_wp));
+  RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * kOuter * kOuter, &p_to));
+  RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
+  RFMLS_CHECK(workspace(h, WS_QR_TI, sizeof(T) * kMaxNb * kMaxNb, &p_ti));
   T* tau = (T*)p_tau;
+  T* Wz = (T*)p_wz;
   T* W = (T*)p_w;
   T* Wp = (T*)p_wp;
-  T* Tm = (T*)p_t;
-  const size_t lds_budget = 150 * 1024;
-  for (int64_t k0 = 0; k0 < n; k0 += nbmax) {
-    const int jb = (int)(n - k0 < nbmax ? n - k0 : nbmax);
-    const int64_t M = s - k0;
-    // rows per block: at least 64, as many blocks as CUs allow, LDS-limited
-    int64_t G = h->num_cus;
-    int64_t rpw = (M + G - 1) / G;
-    if (rpw < 64) {
-      rpw = 64;
-      G = (M + rpw - 1) / rpw;
+  T* To = (T*)p_to;
+  T* Y = (T*)p_y;
+  T* Ti = (T*)p_ti;
+  for (int64_t k0 = 0; k0 < n; k0 += kOuter) {
+    const int64_t bw = n - k0 < kOuter ? n - k0 : kOuter;
+    // ---------------- inner panels of the outer block ----------------
+    for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
+      const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
+      const int64_t M = s - p0;
+      // rows per block: 8 Q with Q in {16, 32[, 64]}; at most 64 blocks when possible
+      int q = 16;
+      while (q < kQmax<T>() && (M + 8 * q - 1) / (8 * q) > 64) q = (2 * q < kQmax<T>()) ? 2 * q : kQmax<T>();
+      const int64_t rpw = 8 * (int64_t)q;
+      const int64_t G = (M + rpw - 1) / rpw;
+      if (G > 1024)
+        return fail(h, RFMLS_E_ARG, "QR panel of %lld rows needs more than 1024 blocks", (long long)M);
+      T* P = SA + p0 * ld + p0;
+      T* tau_p = tau + (p0 - k0);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, h->barrier, kBarrierWords);
+      int rpw_i = (int)rpw;
+      void* args[] = {(void*)&P, (void*)&ld, (void*)&M, (void*)&jb, (void*)&rpw_i, (void*)&tau_p,
+                      (void*)&p_part, (void*)&h->barrier, (void*)&h->dev_flags};
+      const void* fn = q == 16 ? (const void*)k_qr_panel<T, 16>
+                       : q == 32 ? (const void*)k_qr_panel<T, 32>
+                                 : (const void*)k_qr_panel<T, kQmax<T>()>;
+      {
+        // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
+        const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
+        Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
+        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
+      }
+      const int64_t rem = k0 + bw - (p0 + jb);
+      if (rem <= 0) continue;
+      const int64_t ncols = jb + rem;
+      const int64_t nsp = (M + split_in - 1) / split_in;
+      {
+        Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
+                 2.0 * (double)jb * ncols * M);
+        RFMLS_HIP(h, gemm<T>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, split_in), st));
+        hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(jb * ncols, 256)), dim3(256), 0, st,
+                           (const T*)Wz, (int64_t)jb * ncols, (int)nsp, (int64_t)jb * ncols, W);
+      }
+      {
+        Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)W, (int64_t)0, 1,
+                           ncols, jb, (const T*)tau_p, Ti, (int64_t)jb);
+        hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 64)), dim3(256), 0, st, (const T*)W,
+                           (int64_t)0, 1, ncols, jb, rem, (const T*)Ti, Wp, rem);
+      }
+      {
+        Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
+                 2.0 * (double)M * rem * jb);
+        RFMLS_HIP(h, gemm<T>(v_update<T>(P, ld, M, jb, rem, Wp), st));
+      }
+      RFMLS_HIP(h, hipGetLastError());
     }
-    if ((size_t)rpw * jb * sizeof(T) > lds_budget)
-      return fail(h, RFMLS_E_ARG, "QR panel of %lld rows does not fit the co-resident LDS budget",
-                  (long long)M);
-    T* P = SA + k0 * ld + k0;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, h->barrier, 1);
-    const size_t lds = (size_t)rpw * jb * sizeof(T);
-    void* args[] = {(void*)&P, (void*)&ld, (void*)&M, (void*)&jb, (void*)&rpw, (void*)&tau,
-                    (void*)&p_part, (void*)&h->barrier, (void*)&h->dev_flags};
-    int rpw_i = (int)rpw;
-    args[4] = (void*)&rpw_i;
-    RFMLS_HIP(h, hipFuncSetAttribute((const void*)k_qr_panel<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    {
-    // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
-    const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
-    Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
-    RFMLS_HIP(h, hipLaunchCooperativeKernel((const void*)k_qr_panel<T>, dim3((unsigned)G),
-                                            dim3(kPanelThreads), args, (unsigned)lds, st));
-    }
-    const int64_t ntr = n - k0 - jb;  // trailing columns
+    // ---------------- trailing update with the whole outer block ----------------
+    const int64_t ntr = n - k0 - bw;
     if (ntr <= 0) continue;
-    const int64_t ncols = n - k0;     // [V | C]
-    const int64_t nsplit = (M + ksplit_rows - 1) / ksplit_rows;
-    GemmArgs<T> g1;
-    g1.M = jb;
-    g1.N = ncols;
-    g1.K = M;
-    g1.A = P;
-    g1.lda = ld;
-    g1.transA = 1;
-    g1.a_vmask = 1;
-    g1.B = P;
-    g1.ldb = ld;
-    g1.b_vcols = jb;
-    g1.C = W;
-    g1.ldc = ncols;
-    g1.alpha = T(1);
-    g1.beta = T(0);
-    g1.ksplit = ksplit_rows;
-    g1.c_zstride = (int64_t)jb * ncols;
+    const int64_t M0 = s - k0;
+    T* P0 = SA + k0 * ld + k0;
+    const int64_t ncols = bw + ntr;
+    const int64_t nsp = (M0 + split_out - 1) / split_out;
     {
-      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M * ncols + (double)nsplit * jb * ncols),
-               2.0 * (double)jb * ncols * M);
-      RFMLS_HIP(h, gemm<T>(g1, st));
+      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
+               2.0 * (double)bw * ncols * M0);
+      RFMLS_HIP(h, gemm<T>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, split_out), st));
+      hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ncols, 256) < 4096 ? ceil_div(bw * ncols, 256) : 4096),
+                         dim3(256), 0, st, (const T*)Wz, bw * ncols, (int)nsp, bw * ncols, W);
     }
     {
-    Trace tr(h, "qr_buildT_Wp", sizeof(T) * (double)(nsplit + 1) * jb * ncols, 2.0 * (double)jb * jb * ntr);
-    hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, W, (int64_t)jb * ncols,
-                       (int)nsplit, ncols, jb, tau, Tm);
-    hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(ntr, 64)), dim3(256), 0, st, W,
-                       (int64_t)jb * ncols, (int)nsplit, ncols, jb, ntr, Tm, Wp, ntr);
+      // T_o: diagonal 64-blocks from the Gram's diagonal blocks, then block columns
+      Trace tr(h, "qr_outer_T", sizeof(T) * 4.0 * (double)bw * bw, 2.0 * (double)bw * bw * bw);
+      for (int64_t q0 = 0; q0 < bw; q0 += kMaxNb) {
+        const int jq = (int)(bw - q0 < kMaxNb ? bw - q0 : kMaxNb);
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)(W + q0 * ncols + q0),
+                           (int64_t)0, 1, ncols, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
+                           (int64_t)kOuter);
+      }
+      for (int64_t q0 = kMaxNb; q0 < bw; q0 += kMaxNb) {
+        const int64_t jq = bw - q0 < kMaxNb ? bw - q0 : kMaxNb;
+        GemmArgs<T> ga;  // Y = T_o[:q0, :q0] * Gram[:q0, q0:q0+jq]
+        ga.M = q0;
+        ga.N = jq;
+        ga.K = q0;
+        ga.A = To;
+        ga.lda = kOuter;
+        ga.a_upper = 1;
+        ga.B = W + q0;
+        ga.ldb = ncols;
+        ga.C = Y;
+        ga.ldc = jq;
+        RFMLS_HIP(h, gemm<T>(ga, st));
+        GemmArgs<T> gb;  // T_o[:q0, q0:q0+jq] = -Y * T_qq
+        gb.M = q0;
+        gb.N = jq;
+        gb.K = jq;
+        gb.A = Y;
+        gb.lda = jq;
+        gb.B = To + q0 * kOuter + q0;
+        gb.ldb = kOuter;
+        gb.b_upper = 1;
+        gb.C = To + q0;
+        gb.ldc = kOuter;
+        gb.alpha = T(-1);
+        RFMLS_HIP(h, gemm<T>(gb, st));
+      }
     }
-    GemmArgs<T> g2;
-    g2.M = M;
-    g2.N = ntr;
-    g2.K = jb;
-    g2.A = P;
-    g2.lda = ld;
-    g2.transA = 0;
-    g2.a_vmask = 1;
-    g2.B = Wp;
-    g2.ldb = ntr;
-    g2.C = P + jb;
-    g2.ldc = ld;
-    g2.alpha = T(-1);
-    g2.beta = T(1);
     {
-      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M * ntr + (double)M * jb + (double)jb * ntr),
-               2.0 * (double)M * ntr * jb);
-      RFMLS_HIP(h, gemm<T>(g2, st));
+      // W' = T_o^T W[:, bw:]  (T_o^T lower triangular)
+      Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * ntr, (double)bw * bw * ntr);
+      GemmArgs<T> gt;
+      gt.M = bw;
+      gt.N = ntr;
+      gt.K = bw;
+      gt.A = To;
+      gt.lda = kOuter;
+      gt.transA = 1;
+      gt.a_lower = 1;
+      gt.B = W + bw;
+      gt.ldb = ncols;
+      gt.C = Wp;
+      gt.ldc = ntr;
+      RFMLS_HIP(h, gemm<T>(gt, st));
+    }
+    {
+      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr + (double)M0 * bw + (double)bw * ntr),
+               2.0 * (double)M0 * ntr * bw);
+      RFMLS_HIP(h, gemm<T>(v_update<T>(P0, ld, M0, bw, ntr, Wp), st));
     }
     RFMLS_HIP(h, hipGetLastError());
   }
