@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
                     help="f64: float64 QR and R^-1; f32: float32 QR on matrix cores, float32-stored R^-1")
     ap.add_argument("--refine", type=int, default=2)
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides u_k = sin(k pi x) sin(pi y)..., k = 1..nrhs, solved together")
+    ap.add_argument("--lockstep", type=int, default=1, help="1: lockstep blocks of 32; 0: one at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     args = ap.parse_args()
@@ -95,11 +98,11 @@ def main():
 
     torch.cuda.set_device(0)
     log(f"[bench] building {args.workload}")
-    S, s = build_config(args.workload)
+    S, s = build_config(args.workload, modes=tuple(range(1, args.nrhs + 1)))
     A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
-    b = torch.tensor(S.b[0], device="cuda")
+    b = torch.tensor(S.b[0] if args.nrhs == 1 else S.b, device="cuda")
     h = R.Handle()
-    opts = R.default_opts(refine=args.refine)
+    opts = R.default_opts(refine=args.refine, lockstep=args.lockstep)
     qd = args.precision
 
     def step(ev=None):
@@ -137,7 +140,7 @@ def main():
         times.append(dt)
         phases.append({"transpose": ev[0].elapsed_time(ev[1]), "sketch": ev[1].elapsed_time(ev[2]),
                        "qr_and_inverse": ev[2].elapsed_time(ev[3]), "lsqr": ev[3].elapsed_time(ev[4])})
-        log(f"[bench] step {k + 1}/{args.steps}: {dt * 1e3:.1f} ms  itn={info[0]['itn']}")
+        log(f"[bench] step {k + 1}/{args.steps}: {dt * 1e3:.1f} ms  itn={[i['itn'] for i in info]}")
         del P, AT
     med = statistics.median(times)
     ph = {key: statistics.median(p[key] for p in phases) for key in phases[0]}
@@ -164,13 +167,14 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
                     "traffic": None}
 
-    # accuracy of the measured solve
-    x = X.detach().cpu().numpy()
+    # accuracy of the measured solve (every right-hand side)
+    Xn = X.detach().cpu().numpy().reshape(args.nrhs, S.n)
     Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
-    met = pipeline.residual_metrics(Ah, x, S.b[0])
     pts = sample_points(S.d)
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
-    l2 = pipeline.l2_error(E, x, exact_solution(pts))
+    mets = [pipeline.residual_metrics(Ah, Xn[k], S.b[k]) for k in range(args.nrhs)]
+    l2s = [pipeline.l2_error(E, Xn[k], exact_solution(pts, S.modes[k])) for k in range(args.nrhs)]
+    met, l2, x = mets[0], l2s[0], Xn[0]
     gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
     vs_oracle = None
     if os.path.exists(gold_path):
@@ -182,7 +186,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        cpu = cpu_baseline(S, s, int(info[0]["itn"]), threads)
+        cpu = cpu_baseline(S, s, int(sum(i["itn"] for i in info)), threads)
 
     out = {
         "metric": METRIC, "value": round(med, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -190,11 +194,17 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": qd,
         "data": "synthetic",
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
-                   "precision": qd, "refine": args.refine, "atol": opts.atol, "btol": opts.btol},
+                   "precision": qd, "refine": args.refine, "atol": opts.atol, "btol": opts.btol,
+                   "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1)},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),
-                       "istop": int(info[0]["istop"])},
+                       "istop": int(info[0]["istop"]),
+                       "max_over_rhs": int(max(i["itn"] for i in info))},
         "relres": met["relres"], "normal_relres": met["normal_relres"], "l2_error": l2,
+        "per_rhs": None if args.nrhs == 1 else {
+            "relres_max": max(mm["relres"] for mm in mets),
+            "normal_relres_max": max(mm["normal_relres"] for mm in mets),
+            "l2_error": [float(f"{v:.3e}") for v in l2s]},
         "vs_oracle": vs_oracle,
         "roofline": roof,
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}

@@ -78,6 +78,10 @@ typedef struct {
   int32_t check_every; /* host polls the device stop flag every this many
                           iterations (>= 1); iterations past the stop are
                           no-ops on the device                           */
+  int32_t lockstep; /* nonzero (default): with nrhs > 1, iterate the
+                       right-hand sides in lockstep blocks of 32 that share
+                       every pass over A, A^T and R^{-1}; 0: one at a time */
+  int32_t reserved; /* set to 0 */
 } rfmls_opts;
 
 /* [host] per right-hand side results */

@@ -18,7 +18,8 @@ INCLUDE = PKG.parent / "include"
 LIB = PKG / "librfmls.so"
 OBJDIR = PKG / "_build"
 
-SOURCES = ["api.hip", "sketch.hip", "csr.hip", "qr.hip", "precond.hip", "lsqr.hip"]
+SOURCES = ["api.hip", "sketch.hip", "csr.hip", "qr.hip", "precond.hip", "lsqr.hip",
+           "lsqr_block.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -79,6 +79,8 @@ void rfmls_default_opts(rfmls_opts* o) {
   o->itmax = 0;
   o->refine = 1;
   o->check_every = 8;
+  o->lockstep = 1;
+  o->reserved = 0;
 }
 
 rfmls_status rfmls_create(rfmls_handle** out, int device, void* stream) {
@@ -288,6 +290,8 @@ rfmls_status rfmls_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* A
     return fail(h, RFMLS_E_ARG, "rfmls_solve: invalid B / X / leading dimensions");
   if (nrhs == 0) return RFMLS_OK;
   RFMLS_CHECK(set_device(h));
+  if (o->lockstep && nrhs > 1)
+    return run_solve_block(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
   return run_solve(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
 }
 

@@ -118,6 +118,8 @@ enum WsSlot {
   WS_LSQR_VEC,
   WS_LSQR_SCAL,
   WS_LSQR_PART,
+  WS_LSQR_BLK,
+  WS_LSQR_BSTATE,
   WS_TRANSPOSE,
   WS_MISC,
   WS_NUM_SLOTS
@@ -193,6 +195,10 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                        const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
                        double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
                        rfmls_info* info);
+rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                             const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                             double* X, int64_t ldx, double* Rout, int64_t ldr,
+                             const rfmls_opts* o, rfmls_info* info);
 rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                           const rfmls_precond_t* P, const double* Xs, int64_t ldx,
                           const double* Rres, int64_t ldr, const double* G, int64_t ldg,

@@ -1,0 +1,697 @@
+// Lockstep LSQR for a block of right-hand sides (up to kBlk = 32 at a time).
+//
+// Each column runs exactly the single-right-hand-side recurrences of lsqr.hip
+// (its own alpha, beta, rotation, stopping test); the columns only share the
+// passes over the matrices:
+//   Z = X V        triangular product with the packed X = R^{-1}: each 64 x 64
+//                  tile of X meets a 64 x 32 block of V on the matrix cores
+//                  (v_mfma_f64_16x16x4f64), so X is streamed once per
+//                  iteration for all 32 columns instead of 32 times
+//   U = A Z - U a  CSR SpMM: one wavefront per row, lanes over (column, entry)
+//   Q = A^T U      the same with the transpose
+//   V = X^T Q - V b
+// Vectors are interleaved row-major blocks (element (i, c) at i * 32 + c).
+// A column that has stopped keeps its y and x; the host polls one
+// "all columns done" flag every few iterations.
+#include "common.h"
+#include "lsqr_dev.h"
+
+namespace rfmls {
+
+constexpr int kBlk = 32;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSpmmMaxBlocks = 2048;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct BlockState {
+  LsqrDev col[kBlk];
+  int all_done;
+  int pad[15];
+};
+
+__device__ __forceinline__ bool all_done(const BlockState* st) { return st->all_done != 0; }
+
+// ---------------------------------------------------------------------------
+// Triangular products with 64 x 32 blocks on the matrix cores.
+// Wave w computes rows 16 w .. 16 w + 15 of the 64-row output block, both
+// 16-column halves.  Operand layout of v_mfma_f64_16x16x4f64: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r holds
+// D[l / 16 + 4 r][l % 16].
+// ---------------------------------------------------------------------------
+template <typename TS>
+__global__ void __launch_bounds__(kThreads)
+    k_trmm_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+                int C, int maxk, const double* __restrict__ V, double* __restrict__ part,
+                const BlockState* __restrict__ st) {
+  if (st && all_done(st)) return;
+  const int2 e = tab[blockIdx.x];
+  const int64_t I = e.x;
+  const int k = e.y;
+  const int64_t J0 = I + (int64_t)k * C;
+  const int64_t J1 = J0 + C < nt ? J0 + C : nt;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int64_t J = J0; J < J1; ++J) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile) + (16 * w + lr) * kTile;
+#pragma unroll 4
+    for (int s = 0; s < kTile / 4; ++s) {
+      const int kk = 4 * s + lk;
+      const double a = (double)t[kk];
+      const int64_t vr = J * kTile + kk;
+      const double b0 = vr < n ? V[vr * kBlk + lr] : 0.0;
+      const double b1 = vr < n ? V[vr * kBlk + 16 + lr] : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    }
+  }
+  double* o = part + ((int64_t)I * maxk + k) * (kTile * kBlk);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * w + lk + 4 * r;
+    o[row * kBlk + lr] = acc0[r];
+    o[row * kBlk + 16 + lr] = acc1[r];
+  }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(kThreads)
+    k_trmmT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+                 int C, int maxk, const double* __restrict__ Qv, double* __restrict__ part,
+                 const BlockState* __restrict__ st) {
+  if (st && all_done(st)) return;
+  const int2 e = tab[blockIdx.x];
+  const int64_t J = e.x;
+  const int k = e.y;
+  const int64_t I0 = (int64_t)k * C;
+  const int64_t I1 = I0 + C < J + 1 ? I0 + C : J + 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int64_t I = I0; I < I1; ++I) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile) + 16 * w + lr;
+#pragma unroll 4
+    for (int s = 0; s < kTile / 4; ++s) {
+      const int kk = 4 * s + lk;  // row of the X tile = column of X^T
+      const double a = (double)t[kk * kTile];
+      const int64_t qr = I * kTile + kk;
+      const double b0 = qr < n ? Qv[qr * kBlk + lr] : 0.0;
+      const double b1 = qr < n ? Qv[qr * kBlk + 16 + lr] : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    }
+  }
+  double* o = part + ((int64_t)J * maxk + k) * (kTile * kBlk);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * w + lk + 4 * r;
+    o[row * kBlk + lr] = acc0[r];
+    o[row * kBlk + 16 + lr] = acc1[r];
+  }
+}
+
+// out[i][c] = sum_k part[...][i][c] - coef_c prev[i][c]; per-column partial sums of squares.
+// coef_c = hcoef * coef[c * cstride] (coef may be null).  Thread (i, c) with c = tid % 32.
+__global__ void __launch_bounds__(kThreads)
+    k_blk_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int C, int maxk,
+                     int trans, double hcoef, const double* __restrict__ coef, int cstride,
+                     const double* prev, double* out, double* __restrict__ sq,
+                     const BlockState* __restrict__ st) {
+  if (st && all_done(st)) return;
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk;
+  const int rsub = threadIdx.x / kBlk;
+  double cf = hcoef;
+  if (coef) cf *= coef[c * cstride];
+  const bool act = !st || !st->col[c].done;
+  double ss = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / kBlk) + rsub; i < n;
+       i += (int64_t)gridDim.x * (kThreads / kBlk)) {
+    const int64_t I = i / kTile;
+    const int r = (int)(i % kTile);
+    const int64_t nk = trans ? (I + 1 + C - 1) / C : (nt - I + C - 1) / C;
+    double s = 0.0;
+    for (int64_t kq = 0; kq < nk; ++kq) s += part[((I * maxk + kq) * kTile + r) * kBlk + c];
+    if (prev && cf != 0.0) s -= cf * prev[i * kBlk + c];
+    if (act) out[i * kBlk + c] = s;
+    ss += s * s;
+  }
+  if (sq) {
+    red[rsub][c] = ss;
+    __syncthreads();
+    if (rsub == 0) {
+      double t = 0.0;
+      for (int q = 0; q < kThreads / kBlk; ++q) t += red[q][c];
+      sq[blockIdx.x * kBlk + c] = t;
+    }
+  }
+}
+
+// CSR SpMM: out[row][c] = sA (M Xin)[row][c] - coef_c prev[row][c]; one wavefront per row,
+// lane l works on column l % 32 and every other entry (l / 32); per-column partial sums of squares.
+__global__ void __launch_bounds__(kThreads)
+    k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+           const double* __restrict__ val, int64_t rows, const double* __restrict__ Xin, double sA,
+           double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
+           double* out, double* __restrict__ sq, const BlockState* __restrict__ st) {
+  if (st && all_done(st)) return;
+  __shared__ double red[kThreads / 64][kBlk];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = lane & (kBlk - 1), half = lane >> 5;
+  const int64_t wid = (int64_t)blockIdx.x * (kThreads / 64) + wv;
+  const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+  double cf = hcoef;
+  if (coef) cf *= coef[c * cstride];
+  const bool act = !st || !st->col[c].done;
+  double ss = 0.0;
+  for (int64_t row = wid; row < rows; row += nw) {
+    const int64_t lo = rp[row], hi = rp[row + 1];
+    double s = 0.0;
+    for (int64_t e = lo + half; e < hi; e += 2) s += val[e] * Xin[(int64_t)col[e] * kBlk + c];
+    s += __shfl_xor(s, 32, 64);
+    if (half == 0) {
+      double o = sA * s;
+      if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
+      if (act) out[row * kBlk + c] = o;
+      ss += o * o;
+    }
+  }
+  if (sq) {
+    if (half == 0) red[wv][c] = ss;
+    __syncthreads();
+    if (threadIdx.x < kBlk) {
+      double t = 0.0;
+      for (int q = 0; q < kThreads / 64; ++q) t += red[q][threadIdx.x];
+      sq[blockIdx.x * kBlk + threadIdx.x] = t;
+    }
+  }
+}
+
+// Per-column norms from partial sums: nrm_c = sqrt(sum_b sq[b][c]) -> state field
+// (field = 0: beta, 1: alpha).  Columns already stopped keep their state.
+__global__ void __launch_bounds__(kThreads) k_blk_norms(const double* __restrict__ sq, int nsq,
+                                                        BlockState* st, int field, int force) {
+  if (!force && all_done(st)) return;
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  double t = 0.0;
+  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += sq[b * kBlk + c];
+  red[rsub][c] = t;
+  __syncthreads();
+  if (rsub == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / kBlk; ++q) s += red[q][c];
+    LsqrDev& d = st->col[c];
+    if (force || !d.done) {
+      if (field == 0) d.beta = sqrt(s);
+      else d.alpha = sqrt(s);
+    }
+  }
+}
+
+// vec[i][c] *= 1 / state_c (beta or alpha) for active columns
+__global__ void k_blk_scale(double* vec, int64_t len, const BlockState* __restrict__ st, int field,
+                            int force) {
+  if (!force && all_done(st)) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const LsqrDev& d = st->col[e % kBlk];
+    if (!force && d.done) continue;
+    const double nv = field == 0 ? d.beta : d.alpha;
+    vec[e] = nv > 0.0 ? vec[e] / nv : 0.0;
+  }
+}
+
+// out = x (copy) for active columns
+__global__ void k_blk_copy(const double* x, double* out, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = x[e];
+}
+
+__global__ void k_blk_fill(double* p, int64_t len, double v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// per-column sums of squares of a len x 32 block
+__global__ void __launch_bounds__(kThreads) k_blk_sumsq(const double* __restrict__ x, int64_t len,
+                                                        double* __restrict__ sq) {
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / kBlk) + rsub; i < len;
+       i += (int64_t)gridDim.x * (kThreads / kBlk))
+    t += x[i * kBlk + c] * x[i * kBlk + c];
+  red[rsub][c] = t;
+  __syncthreads();
+  if (rsub == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / kBlk; ++q) s += red[q][c];
+    sq[blockIdx.x * kBlk + c] = s;
+  }
+}
+
+__device__ void all_done_update(BlockState* st) {
+  int all = 1;
+  for (int c = 0; c < kBlk; ++c) all &= st->col[c].done != 0;
+  st->all_done = all;
+}
+
+__global__ void k_blk_start(BlockState* st, double atol, double btol, double conlim, int64_t itmax) {
+  const int c = threadIdx.x;
+  if (c < kBlk) {
+    LsqrDev& d = st->col[c];
+    const double beta = d.beta;
+    d = LsqrDev{};
+    d.beta = beta;
+    d.atol = atol;
+    d.btol = btol;
+    d.conlim = conlim;
+    d.itmax = itmax;
+    d.bnorm = beta;
+    d.phibar = beta;
+    d.istop = 7;
+    if (!(beta > 0.0)) {
+      d.istop = 0;
+      d.done = 1;
+    }
+  }
+  __syncthreads();
+  if (c == 0) all_done_update(st);
+}
+
+__global__ void k_blk_start2(BlockState* st) {
+  const int c = threadIdx.x;
+  if (c < kBlk) {
+    LsqrDev& d = st->col[c];
+    if (!d.done) {
+      d.rhobar = d.alpha;
+      d.alpha_prev = d.alpha;
+      d.normr = d.beta;
+      d.normar = d.alpha * d.beta;
+      if (!(d.alpha > 0.0)) {
+        d.istop = 0;
+        d.done = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (c == 0) all_done_update(st);
+}
+
+// plane rotation per active column (same arithmetic as the single-column kernel)
+__global__ void __launch_bounds__(kThreads) k_blk_rotate(BlockState* st, const double* __restrict__ wsq,
+                                                         int nsq) {
+  if (all_done(st)) return;
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  double t = 0.0;
+  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += wsq[b * kBlk + c];
+  red[rsub][c] = t;
+  __syncthreads();
+  if (rsub != 0) return;
+  double w2 = 0.0;
+  for (int q = 0; q < kThreads / kBlk; ++q) w2 += red[q][c];
+  LsqrDev& d = st->col[c];
+  if (d.done) {
+    d.phi_rho = 0.0;
+    d.theta_rho = 0.0;
+    return;
+  }
+  const double alpha = d.alpha, beta = d.beta;
+  d.itn += 1;
+  d.anorm2 += d.alpha_prev * d.alpha_prev + beta * beta;
+  const double rho = hypot(d.rhobar, beta);
+  if (!(rho > 0.0) || !isfinite(rho)) {
+    d.istop = isfinite(rho) ? 1 : -3;
+    d.done = 1;
+    d.phi_rho = 0.0;
+    d.theta_rho = 0.0;
+    return;
+  }
+  const double cs = d.rhobar / rho;
+  const double sn = beta / rho;
+  const double theta = sn * alpha;
+  d.rhobar = -cs * alpha;
+  const double phi = cs * d.phibar;
+  d.phibar = sn * d.phibar;
+  d.phi_rho = phi / rho;
+  d.theta_rho = theta / rho;
+  d.ddnorm += w2 / (rho * rho);
+  const double anorm = sqrt(d.anorm2);
+  d.acond = anorm * sqrt(d.ddnorm);
+  d.normr = d.phibar;
+  d.normar = d.phibar * alpha * fabs(cs);
+  d.pending = 0;
+  if (d.normr == 0.0 || d.normar <= d.atol * anorm * d.normr) d.pending = 2;
+  else if (d.conlim > 0.0 && d.acond >= d.conlim) d.pending = 3;
+  d.alpha_prev = alpha;
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_blk_update(const BlockState* __restrict__ st, const double* __restrict__ v, double* w, double* y,
+                 int64_t n, double* __restrict__ ysq, double* __restrict__ wsq) {
+  if (all_done(st)) return;
+  __shared__ double ry[kThreads / kBlk][kBlk], rw[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  const LsqrDev& d = st->col[c];
+  const bool act = !d.done;
+  const double a = d.phi_rho, b = d.theta_rho;
+  double sy = 0.0, sw = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / kBlk) + rsub; i < n;
+       i += (int64_t)gridDim.x * (kThreads / kBlk)) {
+    const int64_t e = i * kBlk + c;
+    double yi = y[e], wn = w[e];
+    if (act) {
+      const double wi = w[e];
+      yi = yi + a * wi;
+      wn = v[e] - b * wi;
+      y[e] = yi;
+      w[e] = wn;
+    }
+    sy += yi * yi;
+    sw += wn * wn;
+  }
+  ry[rsub][c] = sy;
+  rw[rsub][c] = sw;
+  __syncthreads();
+  if (rsub == 0) {
+    double ty = 0.0, tw = 0.0;
+    for (int q = 0; q < kThreads / kBlk; ++q) {
+      ty += ry[q][c];
+      tw += rw[q][c];
+    }
+    ysq[blockIdx.x * kBlk + c] = ty;
+    wsq[blockIdx.x * kBlk + c] = tw;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_blk_check(BlockState* st, const double* __restrict__ ysq,
+                                                        int nsq) {
+  if (all_done(st)) return;
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  double t = 0.0;
+  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += ysq[b * kBlk + c];
+  red[rsub][c] = t;
+  __syncthreads();
+  if (rsub == 0) {
+    double y2 = 0.0;
+    for (int q = 0; q < kThreads / kBlk; ++q) y2 += red[q][c];
+    LsqrDev& d = st->col[c];
+    if (!d.done) {
+      d.ynorm = sqrt(y2);
+      const double anorm = sqrt(d.anorm2);
+      int istop = 0;
+      if (d.normr <= d.btol * d.bnorm + d.atol * anorm * d.ynorm) istop = 1;
+      else if (d.pending) istop = d.pending;
+      else if (d.itn >= d.itmax) istop = 7;
+      if (istop) {
+        d.istop = istop;
+        d.done = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) all_done_update(st);
+}
+
+// column-major (ld) <-> interleaved block conversions
+__global__ void k_gather_block(const double* __restrict__ B, int64_t ldb, int64_t k0, int64_t nb,
+                               int64_t len, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / kBlk, c = e % kBlk;
+    out[e] = c < nb ? B[(k0 + c) * ldb + i] : 0.0;
+  }
+}
+__global__ void k_scatter_block(const double* __restrict__ in, int64_t len, int64_t k0, int64_t nb,
+                                double* __restrict__ X, int64_t ldx) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / kBlk, c = e % kBlk;
+    if (c < nb) X[(k0 + c) * ldx + i] = in[e];
+  }
+}
+__global__ void k_blk_axpy(double* x, const double* __restrict__ dx, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] += dx[e];
+}
+
+unsigned grid_for(int64_t elems) {
+  const int64_t b = (elems + kThreads - 1) / kThreads;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+unsigned rows_grid(int64_t rows) {  // blocks of 8 rows x 32 columns
+  const int64_t b = (rows + (kThreads / kBlk) - 1) / (kThreads / kBlk);
+  return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
+}
+unsigned spmm_grid(int64_t rows) {
+  const int64_t b = (rows + 3) / 4;
+  return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
+}
+
+struct BCtx {
+  rfmls_handle* h;
+  const rfmls_csr* A;
+  const rfmls_csr* AT;
+  const rfmls_precond_t* P;
+  hipStream_t st;
+  double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX;
+  double *sqA, *sqB, *sqY, *sqW, *part;
+  BlockState* dst;
+};
+
+double* state_field(BlockState* s, int which) {
+  // pointer to col[0].<field>; stride between columns in doubles
+  LsqrDev* d = &s->col[0];
+  return which == 0 ? &d->beta : &d->alpha;
+}
+constexpr int kStride = (int)(sizeof(LsqrDev) / sizeof(double));
+static_assert(sizeof(LsqrDev) % sizeof(double) == 0, "LsqrDev must be a whole number of doubles");
+
+rfmls_status tri_block(BCtx& c, int trans, const double* in, double* out, double hcoef,
+                       const double* coef, const double* prev, double* sq, const BlockState* stp) {
+  const rfmls_precond_t* P = c.P;
+  const int64_t n = P->n, nt = P->nt;
+  const int C = P->chunk;
+  const int maxk = (int)((nt + C - 1) / C);
+  const double esz = P->store == RFMLS_F64 ? 8.0 : 4.0;
+  const double tri = (double)n * (double)(n + 1) / 2.0;
+  {
+    Trace tr(c.h, trans ? "trmm_Xt" : "trmm_X", esz * tri + 2.0 * 8.0 * kBlk * (double)n,
+             2.0 * tri * kBlk);
+    if (!trans) {
+      if (P->store == RFMLS_F64)
+        hipLaunchKernelGGL(k_trmm_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
+                           (const double*)P->Xpk, nt, n, P->tab_row, C, maxk, in, c.part, stp);
+      else
+        hipLaunchKernelGGL(k_trmm_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
+                           (const float*)P->Xpk, nt, n, P->tab_row, C, maxk, in, c.part, stp);
+    } else {
+      if (P->store == RFMLS_F64)
+        hipLaunchKernelGGL(k_trmmT_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
+                           (const double*)P->Xpk, nt, n, P->tab_col, C, maxk, in, c.part, stp);
+      else
+        hipLaunchKernelGGL(k_trmmT_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
+                           (const float*)P->Xpk, nt, n, P->tab_col, C, maxk, in, c.part, stp);
+    }
+  }
+  hipLaunchKernelGGL(k_blk_tri_reduce, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)c.part,
+                     nt, n, C, maxk, trans, hcoef, coef, kStride, prev, out, sq, stp);
+  RFMLS_HIP(c.h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+rfmls_status spmm(BCtx& c, const rfmls_csr* M, const double* x, double sA, double hcoef,
+                  const double* coef, const double* prev, double* out, double* sq,
+                  const BlockState* stp, int* nblk) {
+  const unsigned nb = spmm_grid(M->m);
+  Trace tr(c.h, M == c.A ? "spmm_A" : "spmm_At",
+           12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) +
+               8.0 * kBlk * ((double)M->n + (double)M->m * (prev ? 2.0 : 1.0)),
+           2.0 * kBlk * (double)M->nnz);
+  hipLaunchKernelGGL(k_spmm, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, x,
+                     sA, hcoef, coef, kStride, prev, out, sq, stp);
+  if (nblk) *nblk = (int)nb;
+  RFMLS_HIP(c.h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+rfmls_status poll_all(BCtx& c, int* done) {
+  int* pin = (int*)((char*)c.h->pinned + 1024);
+  RFMLS_HIP(c.h, hipMemcpyAsync(pin, &c.dst->all_done, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  *done = *pin;
+  return RFMLS_OK;
+}
+
+// One lockstep sweep for min ||A X y - rhs|| over the 32 columns of rhs (m x 32).
+rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_t itmax) {
+  const int64_t m = c.A->m, n = c.A->n;
+  const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
+  // beta_1 u_1 = rhs
+  hipLaunchKernelGGL(k_blk_copy, dim3(gm), dim3(kThreads), 0, c.st, rhs, c.U, m);
+  hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(m)), dim3(kThreads), 0, c.st, (const double*)c.U, m,
+                     c.sqA);
+  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA,
+                     (int)rows_grid(m), c.dst, 0, 1);
+  hipLaunchKernelGGL(k_blk_start, dim3(1), dim3(64), 0, c.st, c.dst, o->atol, o->btol, o->conlim, itmax);
+  hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, c.U, m, (const BlockState*)c.dst, 0, 1);
+  hipLaunchKernelGGL(k_blk_fill, dim3(gn), dim3(kThreads), 0, c.st, c.Y, n * kBlk, 0.0);
+  // alpha_1 v_1 = X^T (A^T u_1)
+  RFMLS_CHECK(spmm(c, c.AT, c.U, 1.0, 0.0, nullptr, nullptr, c.Q, nullptr, nullptr, nullptr));
+  RFMLS_CHECK(tri_block(c, 1, c.Q, c.V, 0.0, nullptr, nullptr, c.sqB, nullptr));
+  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+                     (int)rows_grid(n), c.dst, 1, 0);
+  hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, c.V, n, (const BlockState*)c.dst, 1, 0);
+  hipLaunchKernelGGL(k_blk_start2, dim3(1), dim3(64), 0, c.st, c.dst);
+  hipLaunchKernelGGL(k_blk_copy, dim3(gn), dim3(kThreads), 0, c.st, (const double*)c.V, c.W, n);
+  hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)c.W, n,
+                     c.sqW);
+  RFMLS_HIP(c.h, hipGetLastError());
+  const int every = o->check_every > 0 ? o->check_every : 8;
+  int hd = 0;
+  RFMLS_CHECK(poll_all(c, &hd));
+  const BlockState* cst = c.dst;
+  for (int64_t it = 0; it < itmax && !hd; ++it) {
+    RFMLS_CHECK(tri_block(c, 0, c.V, c.Z, 0.0, nullptr, nullptr, nullptr, cst));
+    int nb = 0;
+    RFMLS_CHECK(spmm(c, c.A, c.Z, 1.0, 1.0, state_field(c.dst, 1), c.U, c.U, c.sqA, cst, &nb));
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nb, c.dst, 0, 0);
+    hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, c.U, m, cst, 0, 0);
+    RFMLS_CHECK(spmm(c, c.AT, c.U, 1.0, 0.0, nullptr, nullptr, c.Q, nullptr, cst, nullptr));
+    RFMLS_CHECK(tri_block(c, 1, c.Q, c.V, 1.0, state_field(c.dst, 0), c.V, c.sqB, cst));
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+                       (int)rows_grid(n), c.dst, 1, 0);
+    hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, c.V, n, cst, 1, 0);
+    hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqW,
+                       (int)rows_grid(n));
+    hipLaunchKernelGGL(k_blk_update, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, cst,
+                       (const double*)c.V, c.W, c.Y, n, c.sqY, c.sqW);
+    hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqY,
+                       (int)rows_grid(n));
+    RFMLS_HIP(c.h, hipGetLastError());
+    if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
+  }
+  return RFMLS_OK;
+}
+
+rfmls_status read_block_state(BCtx& c, BlockState* out) {
+  RFMLS_HIP(c.h, hipMemcpyAsync(out, c.dst, sizeof(BlockState), hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
+  return RFMLS_OK;
+}
+
+}  // namespace
+
+rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                             const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                             double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                             rfmls_info* info) {
+  const int64_t m = A->m, n = A->n;
+  const int64_t itmax = o->itmax > 0 ? o->itmax : n;
+  BCtx c;
+  c.h = h;
+  c.A = A;
+  c.AT = AT;
+  c.P = P;
+  c.st = h->stream;
+  const int64_t maxk = (P->nt + P->chunk - 1) / P->chunk;
+  const size_t nvec = (size_t)kBlk * (size_t)(5 * m + 8 * n) + 4 * (size_t)kSpmmMaxBlocks * kBlk +
+                      (size_t)P->nt * maxk * kTile * kBlk;
+  void* p;
+  RFMLS_CHECK(workspace(h, WS_LSQR_BLK, sizeof(double) * nvec, &p));
+  double* d = (double*)p;
+  auto take = [&](int64_t len) {
+    double* r = d;
+    d += len;
+    return r;
+  };
+  c.U = take(m * kBlk);
+  c.Rr = take(m * kBlk);
+  c.Bb = take(m * kBlk);
+  c.T = take(m * kBlk);
+  take(m * kBlk);
+  c.V = take(n * kBlk);
+  c.W = take(n * kBlk);
+  c.Y = take(n * kBlk);
+  c.Z = take(n * kBlk);
+  c.Q = take(n * kBlk);
+  c.Xb = take(n * kBlk);
+  c.DX = take(n * kBlk);
+  take(n * kBlk);
+  c.sqA = take(kSpmmMaxBlocks * kBlk);
+  c.sqB = take(kSpmmMaxBlocks * kBlk);
+  c.sqY = take(kSpmmMaxBlocks * kBlk);
+  c.sqW = take(kSpmmMaxBlocks * kBlk);
+  c.part = take(P->nt * maxk * kTile * kBlk);
+  void* ps;
+  RFMLS_CHECK(workspace(h, WS_LSQR_BSTATE, sizeof(BlockState), &ps));
+  c.dst = (BlockState*)ps;
+  const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
+  rfmls_status ret = RFMLS_OK;
+  std::vector<BlockState> hs(1);
+  for (int64_t k0 = 0; k0 < nrhs; k0 += kBlk) {
+    const int64_t nb = nrhs - k0 < kBlk ? nrhs - k0 : kBlk;
+    std::vector<rfmls_info> inf(nb);
+    hipLaunchKernelGGL(k_gather_block, dim3(gm), dim3(kThreads), 0, c.st, B, ldb, k0, nb, m, c.Bb);
+    for (int sweep = 0; sweep <= o->refine; ++sweep) {
+      RFMLS_CHECK(block_sweep(c, sweep == 0 ? c.Bb : c.Rr, o, itmax));
+      RFMLS_CHECK(read_block_state(c, hs.data()));
+      int64_t itn_max = 0;
+      for (int64_t q = 0; q < nb; ++q) {
+        const LsqrDev& s = hs[0].col[q];
+        if (s.istop < 0) return fail(h, RFMLS_E_BREAKDOWN, "non-finite value in LSQR (column %lld)", (long long)(k0 + q));
+        if (sweep == 0) {
+          inf[q].itn_first = s.itn;
+          inf[q].istop = s.istop;
+          inf[q].normr_est = s.normr;
+          inf[q].normar_est = s.normar;
+          inf[q].anorm_est = sqrt(s.anorm2);
+          inf[q].acond_est = s.acond;
+          inf[q].normb = s.bnorm;
+          if (s.istop == 7) ret = RFMLS_W_NOCONV;
+        }
+        inf[q].itn += s.itn;
+        inf[q].istop_last = s.istop;
+        if (s.itn > itn_max) itn_max = s.itn;
+      }
+      // x (+)= X y ; r = b - A x
+      RFMLS_CHECK(tri_block(c, 0, c.Y, sweep == 0 ? c.Xb : c.DX, 0.0, nullptr, nullptr, nullptr, nullptr));
+      if (sweep > 0)
+        hipLaunchKernelGGL(k_blk_axpy, dim3(gn), dim3(kThreads), 0, c.st, c.Xb, (const double*)c.DX, n);
+      RFMLS_CHECK(spmm(c, A, c.Xb, -1.0, -1.0, nullptr, c.Bb, c.Rr, nullptr, nullptr, nullptr));
+      if (itn_max == 0) break;
+    }
+    // true residual norms per column
+    hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(m)), dim3(kThreads), 0, c.st, (const double*)c.Rr, m, c.sqA);
+    RFMLS_CHECK(spmm(c, AT, c.Rr, 1.0, 0.0, nullptr, nullptr, c.Q, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)c.Q, n, c.sqB);
+    std::vector<double> sa((size_t)rows_grid(m) * kBlk), sb((size_t)rows_grid(n) * kBlk);
+    RFMLS_HIP(h, hipMemcpyAsync(sa.data(), c.sqA, sizeof(double) * sa.size(), hipMemcpyDeviceToHost, c.st));
+    RFMLS_HIP(h, hipMemcpyAsync(sb.data(), c.sqB, sizeof(double) * sb.size(), hipMemcpyDeviceToHost, c.st));
+    hipLaunchKernelGGL(k_scatter_block, dim3(gn), dim3(kThreads), 0, c.st, (const double*)c.Xb, n, k0, nb, X, ldx);
+    if (Rout)
+      hipLaunchKernelGGL(k_scatter_block, dim3(gm), dim3(kThreads), 0, c.st, (const double*)c.Rr, m, k0, nb, Rout, ldr);
+    RFMLS_HIP(h, hipStreamSynchronize(c.st));
+    for (int64_t q = 0; q < nb; ++q) {
+      double ra = 0.0, rb = 0.0;
+      for (size_t b = 0; b < sa.size() / kBlk; ++b) ra += sa[b * kBlk + q];
+      for (size_t b = 0; b < sb.size() / kBlk; ++b) rb += sb[b * kBlk + q];
+      inf[q].normr = sqrt(ra);
+      inf[q].normar = sqrt(rb);
+      if (info) info[k0 + q] = inf[q];
+    }
+  }
+  return ret;
+}
+
+}  // namespace rfmls

@@ -126,14 +126,13 @@ __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsign
 // sigma (c == j) or d_c (c > j); entry (nb - j) + (c - j) holds the pivot row
 // value a_jc (only the block owning row j contributes, the others add 0).
 //
-// Each block owns rpw <= 8 Q consecutive panel rows and keeps them in
-// registers: thread (c = lane, rg = wavefront) holds a[q] = P[r0 + rg + 8 q][c].
+// Each block (NT threads, NG = NT / 64 wavefronts) owns rpw <= NG Q consecutive
+// panel rows and keeps them in registers: thread (c = lane, rg = wavefront)
+// holds a[q] = P[r0 + rg + NG q][c].
 // All threads of a wavefront hold the same rows, so column j reaches every
 // lane of the wavefront by v_readlane from lane j (scalar registers, no LDS).
 // Few, large blocks keep the per-column grid reduction short (its cost grows
 // with the number of blocks).
-constexpr int kPanelThreads = 512;
-constexpr int kPanelGroups = kPanelThreads / 64;
 
 __device__ __forceinline__ double lane_value(double v, int lane) {
   const long long x = __double_as_longlong(v);
@@ -145,10 +144,11 @@ __device__ __forceinline__ double lane_value(float v, int lane) {
   return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <typename T, int Q>
-__global__ void __launch_bounds__(kPanelThreads)
+template <typename T, int Q, int NT>
+__global__ void __launch_bounds__(NT)
     k_qr_panel(T* __restrict__ P, int64_t ld, int64_t M, int nb, int rpw, T* __restrict__ tau,
                double* __restrict__ ws, unsigned* __restrict__ cnt, int* __restrict__ err) {
+  constexpr int kPanelGroups = NT / 64;
   __shared__ double red[kPayload];              // reduced payload
   __shared__ double grp[kPanelGroups][kMaxNb];  // per row-group partials
   __shared__ double piv[kMaxNb];                // pivot row (owner block)
@@ -322,10 +322,31 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 
 constexpr int64_t kOuter = 256;
 
-// largest rows-per-thread of the register-resident panel (float64 needs 2 VGPRs per row)
-// (the largest register-resident configurations that compile without spills)
+// Panel launch shapes in increasing rows per block; a float64 row entry takes
+// two VGPRs.  The largest shapes are the largest that compile without spills
+// (NT / 256 wavefronts per SIMD).
+struct PanelShape {
+  int nt, q;
+  const void* fn;
+  int64_t rpw() const { return (int64_t)(nt / 64) * q; }
+};
 template <typename T>
-constexpr int kQmax() { return sizeof(T) == 8 ? 32 : 64; }
+const PanelShape* panel_shapes();
+template <>
+const PanelShape* panel_shapes<double>() {
+  static const PanelShape s[] = {{512, 16, (const void*)k_qr_panel<double, 16, 512>},
+                                 {512, 32, (const void*)k_qr_panel<double, 32, 512>},
+                                 {0, 0, nullptr}};
+  return s;
+}
+template <>
+const PanelShape* panel_shapes<float>() {
+  static const PanelShape s[] = {{512, 16, (const void*)k_qr_panel<float, 16, 512>},
+                                 {512, 32, (const void*)k_qr_panel<float, 32, 512>},
+                                 {512, 64, (const void*)k_qr_panel<float, 64, 512>},
+                                 {0, 0, nullptr}};
+  return s;
+}
 
 template <typename T>
 GemmArgs<T> vt_gemm(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, T* out,
@@ -402,10 +423,13 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
       const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
       const int64_t M = s - p0;
-      // rows per block: 8 Q with Q in {16, 32[, 64]}; at most 64 blocks when possible
-      int q = 16;
-      while (q < kQmax<T>() && (M + 8 * q - 1) / (8 * q) > 64) q = (2 * q < kQmax<T>()) ? 2 * q : kQmax<T>();
-      const int64_t rpw = 8 * (int64_t)q;
+      // rows per block rpw = (NT / 64) Q: the smallest shape that needs at most
+      // 64 blocks, else the largest one (register-resident rows, no spills)
+      const PanelShape* shapes = panel_shapes<T>();
+      int si = 0;
+      while (shapes[si + 1].q != 0 && (M + shapes[si].rpw() - 1) / shapes[si].rpw() > 64) ++si;
+      const PanelShape sh = shapes[si];
+      const int64_t rpw = sh.rpw();
       const int64_t G = (M + rpw - 1) / rpw;
       if (G > 1024)
         return fail(h, RFMLS_E_ARG, "QR panel of %lld rows needs more than 1024 blocks", (long long)M);
@@ -415,14 +439,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       int rpw_i = (int)rpw;
       void* args[] = {(void*)&P, (void*)&ld, (void*)&M, (void*)&jb, (void*)&rpw_i, (void*)&tau_p,
                       (void*)&p_part, (void*)&h->barrier, (void*)&h->dev_flags};
-      const void* fn = q == 16 ? (const void*)k_qr_panel<T, 16>
-                       : q == 32 ? (const void*)k_qr_panel<T, 32>
-                                 : (const void*)k_qr_panel<T, kQmax<T>()>;
+      const void* fn = sh.fn;
       {
         // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
         const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
         Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
-        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
+        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(sh.nt), args, 0, st));
       }
       const int64_t rem = k0 + bw - (p0 + jb);
       if (rem <= 0) continue;

@@ -222,11 +222,82 @@ def test_solve_deterministic_and_multi_rhs(handle):
     P = R.rfmls_precond(handle, SA)
     rng = np.random.default_rng(4)
     B = torch.tensor(np.stack([S.b[0], rng.standard_normal(S.m), S.b[0] * 2.0]), device="cuda")
-    X, Rr, info, rc = R.rfmls_solve(handle, A, AT, P, B)
+    serial = R.default_opts(lockstep=0)
+    X, Rr, info, rc = R.rfmls_solve(handle, A, AT, P, B, serial)
     for k in range(3):
         x1, _, _, _ = R.rfmls_solve(handle, A, AT, P, B[k])
         assert torch.equal(x1, X[k])
     assert torch.allclose(X[2], 2.0 * X[0], rtol=1e-9, atol=0)
+    # the lockstep path is deterministic too
+    X1, _, _, _ = R.rfmls_solve(handle, A, AT, P, B)
+    X2, _, _, _ = R.rfmls_solve(handle, A, AT, P, B)
+    assert torch.equal(X1, X2)
+
+
+def _lockstep_rhs(S, A_sp, nrhs, seed):
+    """Right-hand sides with different convergence: the PDE load, noise, a zero
+    column (stops before the first iteration), a consistent b = A x0 and a scaled copy."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((nrhs, S.m))
+    B[0] = S.b[0]
+    B[min(5, nrhs - 1)] = 0.0
+    if nrhs > 7:
+        B[7] = A_sp @ rng.standard_normal(S.n)
+        B[nrhs - 1] = 2.0 * S.b[0]
+    return B
+
+
+@pytest.mark.parametrize("nrhs", [2, 32, 35])
+def test_lockstep_multi_rhs_matches_oracle(handle, nrhs):
+    """Lockstep blocks of 32 (ragged last block) against the float64 oracle, per column."""
+    S, s, A = system("poisson2d_3x3")
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    AT = R.rfmls_transpose(handle, A)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, s, SEED)[0])
+    pre = pipeline.precondition(S.row_ptr, S.col, S.val, S.m, S.n, s, SEED)
+    Bn = _lockstep_rhs(S, Ah, nrhs, 11)
+    X, Rr, info, rc = R.rfmls_solve(handle, A, AT, P, torch.tensor(Bn, device="cuda"))
+    Xs, _, info_s, _ = R.rfmls_solve(handle, A, AT, P, torch.tensor(Bn, device="cuda"),
+                                     R.default_opts(lockstep=0))
+    Xn, Rn = X.cpu().numpy(), Rr.cpu().numpy()
+    for k in range(nrhs):
+        b = Bn[k]
+        if not b.any():
+            assert info[k]["itn"] == 0 and info[k]["istop"] == 0 and not Xn[k].any()
+            continue
+        nb = np.linalg.norm(b)
+        if nrhs > 7 and k == 7:  # consistent: both reach the S1 floor btol ||b||
+            assert info[k]["normr"] <= 1e-9 * nb and info_s[k]["normr"] <= 1e-9 * nb
+            continue
+        xo, res = pipeline.refined_lsqr(Ah, pre["R"], b, refine=1)
+        met = pipeline.residual_metrics(Ah, xo, b)
+        assert abs(info[k]["normr"] - met["normr"]) <= 1e-10 * met["normr"], k
+        assert abs(info[k]["normr"] - info_s[k]["normr"]) <= 1e-10 * met["normr"], k
+        assert abs(info[k]["itn_first"] - res[0].itn) <= 2, (k, info[k]["itn_first"], res[0].itn)
+        assert info[k]["istop"] == info_s[k]["istop"]
+        # returned residual is b - A x of the returned x, to the rounding of that product
+        # (forward error of a length-L dot product: L u sum |a_ij x_j| per row)
+        L = int(np.diff(S.row_ptr).max())
+        fe = 2 * L * np.finfo(float).eps * np.linalg.norm(abs(Ah) @ np.abs(Xn[k]))
+        assert np.linalg.norm(Rn[k] - (b - Ah @ Xn[k])) <= fe, k
+    assert _l2(S, Xn[0]) <= 1.1 * _l2(S, Xs[0].cpu().numpy())
+
+
+def test_lockstep_column_independent_of_companions(handle):
+    """Each column of a lockstep block runs its own recurrences: changing the
+    other columns leaves it bitwise unchanged."""
+    S, s, A = system("poisson2d_2x2")
+    AT = R.rfmls_transpose(handle, A)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, s, SEED)[0])
+    rng = np.random.default_rng(12)
+    B1 = rng.standard_normal((6, S.m))
+    B1[2] = S.b[0]
+    B2 = rng.standard_normal((6, S.m)) * 1e3
+    B2[2] = S.b[0]
+    B2[4] = 0.0
+    X1, _, i1, _ = R.rfmls_solve(handle, A, AT, P, torch.tensor(B1, device="cuda"))
+    X2, _, i2, _ = R.rfmls_solve(handle, A, AT, P, torch.tensor(B2, device="cuda"))
+    assert torch.equal(X1[2], X2[2]) and i1[2]["itn"] == i2[2]["itn"]
 
 
 def test_degenerate_right_hand_sides(handle):
