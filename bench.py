@@ -74,8 +74,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson2d_8x8")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
-                    help="f64: float64 QR and R^-1; f32: float32 QR on matrix cores, float32-stored R^-1")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f64f32"],
+                    help="f64: float64 QR and R^-1; f32: float32 QR on matrix cores, float32-stored "
+                         "R^-1; f64f32: float64 QR, float32-stored R^-1")
+    ap.add_argument("--itmax", type=int, default=0, help="LSQR iteration limit per sweep (0: n)")
     ap.add_argument("--refine", type=int, default=2)
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides u_k = sin(k pi x) sin(pi y)..., k = 1..nrhs, solved together")
@@ -102,8 +104,8 @@ def main():
     A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
     b = torch.tensor(S.b[0] if args.nrhs == 1 else S.b, device="cuda")
     h = R.Handle()
-    opts = R.default_opts(refine=args.refine, lockstep=args.lockstep)
-    qd = args.precision
+    opts = R.default_opts(refine=args.refine, lockstep=args.lockstep, itmax=args.itmax)
+    qd, rd = {"f64": ("f64", "f64"), "f32": ("f32", "f32"), "f64f32": ("f64", "f32")}[args.precision]
 
     def step(ev=None):
         if ev is not None:
@@ -114,7 +116,7 @@ def main():
         SA, _, _, _ = R.rfmls_sketch(h, A, s, SKETCH_SEED, dtype=qd)
         if ev is not None:
             ev[2].record()
-        P = R.rfmls_precond(h, SA, qd, qd)
+        P = R.rfmls_precond(h, SA, qd, rd)
         del SA
         if ev is not None:
             ev[3].record()
@@ -194,7 +196,7 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": qd,
         "data": "synthetic",
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
-                   "precision": qd, "refine": args.refine, "atol": opts.atol, "btol": opts.btol,
+                   "precision": args.precision, "refine": args.refine, "itmax": args.itmax, "atol": opts.atol, "btol": opts.btol,
                    "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1)},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),

@@ -16,9 +16,10 @@
 // Split-K: blockIdx.z selects the K range [z*ksplit, (z+1)*ksplit) and output
 // C + z*c_zstride (each slice writes its own partial result, no atomics).
 //
-// Block: 256 threads = 4 waves in a 2 x 2 grid computing a 128 x 128 (or 64-
-// wide) tile of C, each wave a quarter of it as 16 x 16 MFMA tiles.  K is
-// staged through LDS in steps of 16, the next step prefetched into registers.
+// Block: 256 threads = 4 waves in a 2 x 2 grid computing a 64 x 64 (float64)
+// or up to 128 x 128 (float32) tile of C, each wave a quarter of it as 16 x 16
+// MFMA tiles.  K is staged through LDS in steps of 16, the next step
+// prefetched into registers.
 #pragma once
 
 #include "common.h"
@@ -47,7 +48,7 @@ struct GemmArgs {
 
 namespace gemm_detail {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
+constexpr int PAD = 4;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -105,17 +106,21 @@ __device__ __forceinline__ T load_b(const GemmArgs<T>& g, int64_t gk, int64_t gj
   return v;
 }
 
-// Block tile BM x BN (BM, BN in {64, 128}); 4 waves in a 2 x 2 grid, each wave
-// (BM/2) x (BN/2) made of 16 x 16 MFMA tiles.  The next K chunk is fetched
-// from global memory into registers while the current one is consumed from
-// LDS, so the loads overlap the matrix-core work.
-template <typename T, int BMt, int BNt>
+// Block tile BMt x BNt (each 64 or 128) with K chunks of BKt; 4 waves in a
+// 2 x 2 grid, each wave (BMt/2) x (BNt/2) made of 16 x 16 MFMA tiles.  The
+// next K chunk is fetched from global memory into registers while the current
+// one is consumed from LDS, so the loads overlap the matrix-core work.
+// A chunk whose operand tiles lie inside the matrices and clear of every mask
+// and triangle ("clean", decided per block, so the branch is uniform) is read
+// through precomputed pointers with no per-element tests; only chunks on a
+// border, diagonal or ragged edge take the element-wise path.
+template <typename T, int BMt, int BNt, int BKt>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
   constexpr int TM = BMt / 32, TN = BNt / 32;   // MFMA tiles per wave per dim
-  constexpr int EA = BMt * BK / 256;             // A elements per thread per chunk
-  constexpr int EB = BNt * BK / 256;             // B elements per thread per chunk
-  __shared__ T As[BK][BMt + PAD];
-  __shared__ T Bs[BK][BNt + PAD];
+  constexpr int EA = BMt * BKt / 256;            // A elements per thread per chunk
+  constexpr int EB = BNt * BKt / 256;            // B elements per thread per chunk
+  __shared__ T As[BKt][BMt + PAD];
+  __shared__ T Bs[BKt][BNt + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -145,52 +150,70 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
     for (int b = 0; b < TN; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 
   // thread -> element mapping of the staging loads (contiguous runs in memory)
-  // op(A) not transposed: row r = tid / (256/BMt), k run of EA starting at ka
-  // op(A) transposed / B: k = tid / (BMt/EA) (resp. BNt/EB), run along i (resp. j)
+  // op(A) not transposed: row ra_i = tid / (BKt/EA), k run of EA starting at ra_k
+  // op(A) transposed:     k = ra_k, run of EA along i starting at ra_i
+  // B:                    k = rb_k, run of EB along j starting at rb_j
+  const int ra_i = g.transA ? (tid % (BMt / EA)) * EA : tid / (BKt / EA);
+  const int ra_k = g.transA ? tid / (BMt / EA) : (tid % (BKt / EA)) * EA;
+  const int rb_k = tid / (BNt / EB);
+  const int rb_j = (tid % (BNt / EB)) * EB;
+  // pointers for the clean path (only dereferenced for clean chunks)
+  const T* pa = g.transA ? g.A + (int64_t)ra_k * g.lda + (i0 + ra_i) : g.A + (i0 + ra_i) * g.lda + ra_k;
+  const T* pb = g.B + (int64_t)rb_k * g.ldb + (j0 + rb_j);
+  // block-uniform parts of the clean test
+  const bool a_rows_in = i0 + BMt <= g.M;
+  const bool b_cols_in = j0 + BNt <= g.N;
+  auto clean = [&](int64_t k0) {
+    if (k0 + BKt > kend || !a_rows_in || !b_cols_in) return false;
+    const int64_t klast = k0 + BKt - 1, ilast = i0 + BMt - 1, jlast = j0 + BNt - 1;
+    if (g.a_upper && k0 < ilast) return false;
+    if (g.a_lower && klast > i0) return false;
+    if (g.a_vmask && (g.transA ? !(k0 > ilast) : !(i0 > klast))) return false;
+    if (g.b_upper && klast > j0) return false;
+    if (j0 < g.b_vcols && !(k0 > jlast)) return false;
+    return true;
+  };
   T ra[EA], rb[EB];
   auto fetch = [&](int64_t k0) {
-    if (!g.transA) {
-      const int r = tid / (BK / EA);
-      const int ka = (tid % (BK / EA)) * EA;
+    if (clean(k0)) {
+      const T* a = g.transA ? pa + k0 * g.lda : pa + k0;
+      const T* b = pb + k0 * g.ldb;
 #pragma unroll
-      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + r, k0 + ka + q, kend);
-    } else {
-      const int kk = tid / (BMt / EA);
-      const int r = (tid % (BMt / EA)) * EA;
+      for (int q = 0; q < EA; ++q) ra[q] = a[q];
 #pragma unroll
-      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + r + q, k0 + kk, kend);
+      for (int q = 0; q < EB; ++q) rb[q] = b[q];
+      return;
     }
-    const int kk = tid / (BNt / EB);
-    const int c = (tid % (BNt / EB)) * EB;
+    if (!g.transA) {
 #pragma unroll
-    for (int q = 0; q < EB; ++q) rb[q] = load_b(g, k0 + kk, j0 + c + q, kend);
+      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + ra_i, k0 + ra_k + q, kend);
+    } else {
+#pragma unroll
+      for (int q = 0; q < EA; ++q) ra[q] = load_a(g, i0 + ra_i + q, k0 + ra_k, kend);
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) rb[q] = load_b(g, k0 + rb_k, j0 + rb_j + q, kend);
   };
   auto stash = [&]() {
     if (!g.transA) {
-      const int r = tid / (BK / EA);
-      const int ka = (tid % (BK / EA)) * EA;
 #pragma unroll
-      for (int q = 0; q < EA; ++q) As[ka + q][r] = ra[q];
+      for (int q = 0; q < EA; ++q) As[ra_k + q][ra_i] = ra[q];
     } else {
-      const int kk = tid / (BMt / EA);
-      const int r = (tid % (BMt / EA)) * EA;
 #pragma unroll
-      for (int q = 0; q < EA; ++q) As[kk][r + q] = ra[q];
+      for (int q = 0; q < EA; ++q) As[ra_k][ra_i + q] = ra[q];
     }
-    const int kk = tid / (BNt / EB);
-    const int c = (tid % (BNt / EB)) * EB;
 #pragma unroll
-    for (int q = 0; q < EB; ++q) Bs[kk][c + q] = rb[q];
+    for (int q = 0; q < EB; ++q) Bs[rb_k][rb_j + q] = rb[q];
   };
 
   if (kbeg < kend) fetch(kbeg);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BKt) {
     __syncthreads();
     stash();
     __syncthreads();
-    if (k0 + BK < kend) fetch(k0 + BK);
+    if (k0 + BKt < kend) fetch(k0 + BKt);
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
+    for (int ks = 0; ks < BKt; ks += 4) {
       const int kr = ks + (lane >> 4);
       T av[TM], bv[TN];
 #pragma unroll
@@ -228,20 +251,19 @@ inline hipError_t gemm(const GemmArgs<T>& g, hipStream_t st) {
   unsigned gz = 1;
   if (g.ksplit > 0) gz = (unsigned)((g.K + g.ksplit - 1) / g.ksplit);
   if (gz == 0) gz = 1;
-  // 128 x 128 tiles for large outputs, 64-wide tiles where a dimension is small
+  // Tiles measured fastest at the QR's shapes on gfx950: float64 64 x 64
+  // (higher occupancy beats larger register tiles), float32 128 x 128 where
+  // both dimensions allow it.
   const bool bigM = g.M > 64, bigN = g.N > 64;
-  if (bigM && bigN) {
+  if (sizeof(T) == 4 && bigM && bigN) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 128>), grid, dim3(256), 0, st, g);
-  } else if (bigN) {
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 128, 16>), grid, dim3(256), 0, st, g);
+  } else if (sizeof(T) == 4 && bigN) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 63) / 64), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 128>), grid, dim3(256), 0, st, g);
-  } else if (bigM) {
-    dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 127) / 128), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 64>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 128, 16>), grid, dim3(256), 0, st, g);
   } else {
     dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 64>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 64, 16>), grid, dim3(256), 0, st, g);
   }
   return hipGetLastError();
 }

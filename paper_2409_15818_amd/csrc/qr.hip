@@ -42,8 +42,25 @@ constexpr int kMaxNb = 64;
 //   cnt  [(nclus + 2) * kBarrierStride]  cluster counters, global counter and
 //                           generation word, each on its own cache line
 // Counters only grow; epoch e (0, 1, ...) numbers the calls within one launch.
+//
+// Memory ordering: every word that crosses blocks (payloads, cluster sums, the
+// result, counters) is written and read with relaxed agent-scope atomics,
+// which are coherent across the XCDs' separate L2 caches; each writer waits
+// for its stores to complete (s_waitcnt) before the counter update or flag
+// store that publishes them.  Release/acquire fences would do the same but
+// also write back and invalidate the whole L2 of the XCD at every step, which
+// made the reduction cost grow linearly with the number of blocks.
 constexpr int kCluster = 16;
 constexpr int kPayload = 2 * kMaxNb;
+
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until every memory operation this thread issued has completed
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsigned* cnt, int lo,
                                int hi, unsigned epoch, double* red, int* err) {
@@ -56,12 +73,12 @@ __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsign
   unsigned* gen = cnt + (int64_t)(nclus + 1) * kBarrierStride;
   __shared__ int role;  // 0: wait, 1: cluster leader, 2: global leader
   __shared__ int ok;
+  wait_stores();  // this block's payload stores (st_coh by the caller) are complete
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    const unsigned old =
-        __hip_atomic_fetch_add(&cnt[(int64_t)cl * kBarrierStride], 1u, __ATOMIC_ACQ_REL,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(&cnt[(int64_t)cl * kBarrierStride], 1u,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     role = (old == (epoch + 1) * (unsigned)csize - 1u) ? 1 : 0;
   }
   __syncthreads();
@@ -71,16 +88,17 @@ __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsign
       double v[kCluster];
 #pragma unroll
       for (int q = 0; q < kCluster; ++q)
-        v[q] = q < csize ? pw[(int64_t)(cl * kCluster + q) * kPayload + k] : 0.0;
+        v[q] = q < csize ? ld_coh(&pw[(int64_t)(cl * kCluster + q) * kPayload + k]) : 0.0;
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < kCluster; ++q) s += v[q];
-      cw[(int64_t)cl * kPayload + k] = s;
+      st_coh(&cw[(int64_t)cl * kPayload + k], s);
     }
+    wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned old =
-          __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old == (epoch + 1) * (unsigned)nclus - 1u) role = 2;
     }
     __syncthreads();
@@ -92,20 +110,21 @@ __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsign
           double v[kCluster];
 #pragma unroll
           for (int q = 0; q < kCluster; ++q)
-            v[q] = c0 + q < nclus ? cw[(int64_t)(c0 + q) * kPayload + k] : 0.0;
+            v[q] = c0 + q < nclus ? ld_coh(&cw[(int64_t)(c0 + q) * kPayload + k]) : 0.0;
 #pragma unroll
           for (int q = 0; q < kCluster; ++q) s += v[q];
         }
-        o[k] = s;
+        st_coh(&o[k], s);
       }
+      wait_stores();
       __syncthreads();
       if (threadIdx.x == 0)
-        __hip_atomic_store(gen, epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gen, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (threadIdx.x == 0) {
     int spins = 0;
-    while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch + 1u) {
+    while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch + 1u) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1 << 26)) {
         ok = 0;
@@ -117,7 +136,7 @@ __device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsign
   __syncthreads();
   if (!ok) return false;
   const double* o = out + (int64_t)(epoch & 1u) * kPayload;
-  for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) red[k] = o[k];
+  for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) red[k] = ld_coh(&o[k]);
   __syncthreads();
   return true;
 }
@@ -198,8 +217,8 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int q = 0; q < kPanelGroups; ++q) t += grp[q][c];
       double* my = pw + (int64_t)g * kPayload;
-      my[c - j] = t;
-      my[L + c - j] = top ? piv[c] : 0.0;
+      st_coh(&my[c - j], t);
+      st_coh(&my[L + c - j], top ? piv[c] : 0.0);
     }
     if (!grid_allreduce(pw, cw, out, cnt, 0, 2 * L, (unsigned)j, red, err)) return;
     // ---- reflector (identical in every block) ----
@@ -424,10 +443,11 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
       const int64_t M = s - p0;
       // rows per block rpw = (NT / 64) Q: the smallest shape that needs at most
-      // 64 blocks, else the largest one (register-resident rows, no spills)
+      // one block per compute unit, else the largest one (register-resident
+      // rows, no spills); the grid reduction costs about the same for any G
       const PanelShape* shapes = panel_shapes<T>();
       int si = 0;
-      while (shapes[si + 1].q != 0 && (M + shapes[si].rpw() - 1) / shapes[si].rpw() > 64) ++si;
+      while (shapes[si + 1].q != 0 && (M + shapes[si].rpw() - 1) / shapes[si].rpw() > h->num_cus) ++si;
       const PanelShape sh = shapes[si];
       const int64_t rpw = sh.rpw();
       const int64_t G = (M + rpw - 1) / rpw;
