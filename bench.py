@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--lockstep", type=int, default=1, help="1: lockstep blocks of 32; 0: one at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first (reference kernel of "
+                         "known traffic for hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -99,6 +102,14 @@ def main():
     from rfmgen import build_config, exact_solution, feature_eval, sample_points
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {src.numel() * 8} bytes read, {dst.numel() * 8} bytes written")
+        del src, dst
     log(f"[bench] building {args.workload}")
     S, s = build_config(args.workload, modes=tuple(range(1, args.nrhs + 1)))
     A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)

@@ -29,6 +29,10 @@ HIPCC_FLAGS = [
     "-ffp-contract=fast",
     # packed FP32 instructions are disabled for every kernel of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators live in ordinary VGPRs (gfx950 allows it): with
+    # the default AGPR form the compiler copied every GEMM accumulator
+    # VGPR <-> AGPR around each K chunk and drained the MFMA pipeline there
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 

@@ -46,6 +46,18 @@ struct GemmArgs {
   int64_t c_zstride = 0;
 };
 
+// What a GEMM launch is for.  The role only names the kernel symbol (so that
+// profiles separate the uses); the code is the same for every role.
+enum class GemmRole : int {
+  Generic = 0,
+  QrTrailingUpdate = 1,  // C <- C - V (T^T W) after an outer block
+  QrVtC = 2,             // W = V^T [V | C] of an outer block
+  QrInnerUpdate = 3,     // the same two products inside an outer block
+  QrInnerVtC = 4,
+  QrOuterT = 5,          // block columns of T and T^T W
+  Inverse = 6,           // blocked inversion of R
+};
+
 namespace gemm_detail {
 
 constexpr int PAD = 4;
@@ -114,17 +126,20 @@ __device__ __forceinline__ T load_b(const GemmArgs<T>& g, int64_t gk, int64_t gj
 // and triangle ("clean", decided per block, so the branch is uniform) is read
 // through precomputed pointers with no per-element tests; only chunks on a
 // border, diagonal or ragged edge take the element-wise path.
-template <typename T, int BMt, int BNt, int BKt>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
-  constexpr int TM = BMt / 32, TN = BNt / 32;   // MFMA tiles per wave per dim
-  constexpr int EA = BMt * BKt / 256;            // A elements per thread per chunk
-  constexpr int EB = BNt * BKt / 256;            // B elements per thread per chunk
+template <typename T, int BMt, int BNt, int BKt, int WM, int WN, GemmRole Role>
+__global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
+  constexpr int NT = 64 * WM * WN;               // threads: WM x WN wavefronts
+  constexpr int WTM = BMt / WM, WTN = BNt / WN;  // wave tile
+  constexpr int TM = WTM / 16, TN = WTN / 16;    // MFMA tiles per wave per dim
+  constexpr int EA = BMt * BKt / NT;             // A elements per thread per chunk
+  constexpr int EB = BNt * BKt / NT;             // B elements per thread per chunk
+  static_assert(EA >= 1 && EB >= 1 && BKt % EA == 0 && TM >= 1 && TN >= 1, "tile shape");
   __shared__ T As[BKt][BMt + PAD];
   __shared__ T Bs[BKt][BNt + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wy = wave >> 1, wx = wave & 1;
+  const int wy = wave / WN, wx = wave % WN;
   const int64_t i0 = (int64_t)blockIdx.y * BMt;
   const int64_t j0 = (int64_t)blockIdx.x * BNt;
   int64_t kbeg = 0, kend = g.K;
@@ -217,9 +232,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
       const int kr = ks + (lane >> 4);
       T av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = As[kr][wy * (BMt / 2) + a * 16 + (lane & 15)];
+      for (int a = 0; a < TM; ++a) av[a] = As[kr][wy * WTM + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) bv[b] = Bs[kr][wx * (BNt / 2) + b * 16 + (lane & 15)];
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[kr][wx * WTN + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -233,8 +248,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wy * (BMt / 2) + a * 16 + Mfma<T>::row(lane, r);
-        const int64_t gj = j0 + wx * (BNt / 2) + b * 16 + (lane & 15);
+        const int64_t gi = i0 + wy * WTM + a * 16 + Mfma<T>::row(lane, r);
+        const int64_t gj = j0 + wx * WTN + b * 16 + (lane & 15);
         if (gi < g.M && gj < g.N) {
           T v = g.alpha * acc[a][b][r];
           if (g.beta != T(0)) v += g.beta * C[gi * g.ldc + gj];
@@ -245,25 +260,22 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
 
 }  // namespace gemm_detail
 
-template <typename T>
+template <typename T, GemmRole Role = GemmRole::Generic>
 inline hipError_t gemm(const GemmArgs<T>& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   unsigned gz = 1;
   if (g.ksplit > 0) gz = (unsigned)((g.K + g.ksplit - 1) / g.ksplit);
   if (gz == 0) gz = 1;
-  // Tiles measured fastest at the QR's shapes on gfx950: float64 64 x 64
-  // (higher occupancy beats larger register tiles), float32 128 x 128 where
-  // both dimensions allow it.
-  const bool bigM = g.M > 64, bigN = g.N > 64;
-  if (sizeof(T) == 4 && bigM && bigN) {
+  // Tiles measured fastest at the QR's shapes on gfx950: 64 x 64 (higher
+  // occupancy beats larger register tiles), except float32 products with a
+  // long K range (W = V^T [V | C] over 8192-row slices), which prefer 128 x 128.
+  const int64_t kspan = g.ksplit > 0 ? g.ksplit : g.K;
+  if (sizeof(T) == 4 && g.M > 64 && g.N > 64 && kspan >= 1024) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 128, 16>), grid, dim3(256), 0, st, g);
-  } else if (sizeof(T) == 4 && bigN) {
-    dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 63) / 64), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 128, 16>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 128, 128, 16, 2, 2, Role>), grid, dim3(256), 0, st, g);
   } else {
     dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), gz);
-    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 64, 16>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_detail::k_gemm<T, 64, 64, 16, 2, 2, Role>), grid, dim3(256), 0, st, g);
   }
   return hipGetLastError();
 }

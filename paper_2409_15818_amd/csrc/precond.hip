@@ -177,7 +177,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       // R_{I,>I} (64 x rest) times the upper-triangular X_{>I}: 64 rest^2 flops
       Trace tr(h, "inv_gemm", 8.0 * ((double)kTile * rest + 0.5 * (double)rest * rest + (double)nz * kTile * rest),
                (double)kTile * (double)rest * (double)rest);
-      RFMLS_HIP(h, gemm<double>(g, h->stream));
+      RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
     }
     {
       Trace tr(h, "inv_blockrow", 8.0 * ((double)nz * kTile * ldp + (double)kTile * (n - o)),

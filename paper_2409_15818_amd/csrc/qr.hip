@@ -473,7 +473,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       {
         Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
                  2.0 * (double)jb * ncols * M);
-        RFMLS_HIP(h, gemm<T>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, split_in), st));
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, split_in), st)));
         hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(jb * ncols, 256)), dim3(256), 0, st,
                            (const T*)Wz, (int64_t)jb * ncols, (int)nsp, (int64_t)jb * ncols, W);
       }
@@ -487,7 +487,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       {
         Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
                  2.0 * (double)M * rem * jb);
-        RFMLS_HIP(h, gemm<T>(v_update<T>(P, ld, M, jb, rem, Wp), st));
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerUpdate>(v_update<T>(P, ld, M, jb, rem, Wp), st)));
       }
       RFMLS_HIP(h, hipGetLastError());
     }
@@ -501,7 +501,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     {
       Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
                2.0 * (double)bw * ncols * M0);
-      RFMLS_HIP(h, gemm<T>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, split_out), st));
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, split_out), st)));
       hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ncols, 256) < 4096 ? ceil_div(bw * ncols, 256) : 4096),
                          dim3(256), 0, st, (const T*)Wz, bw * ncols, (int)nsp, bw * ncols, W);
     }
@@ -527,7 +527,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
         ga.ldb = ncols;
         ga.C = Y;
         ga.ldc = jq;
-        RFMLS_HIP(h, gemm<T>(ga, st));
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(ga, st)));
         GemmArgs<T> gb;  // T_o[:q0, q0:q0+jq] = -Y * T_qq
         gb.M = q0;
         gb.N = jq;
@@ -540,7 +540,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
         gb.C = To + q0;
         gb.ldc = kOuter;
         gb.alpha = T(-1);
-        RFMLS_HIP(h, gemm<T>(gb, st));
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gb, st)));
       }
     }
     {
@@ -558,12 +558,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       gt.ldb = ncols;
       gt.C = Wp;
       gt.ldc = ntr;
-      RFMLS_HIP(h, gemm<T>(gt, st));
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
     }
     {
       Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr + (double)M0 * bw + (double)bw * ntr),
                2.0 * (double)M0 * ntr * bw);
-      RFMLS_HIP(h, gemm<T>(v_update<T>(P0, ld, M0, bw, ntr, Wp), st));
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, M0, bw, ntr, Wp), st)));
     }
     RFMLS_HIP(h, hipGetLastError());
   }

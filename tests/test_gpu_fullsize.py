@@ -1,0 +1,96 @@
+"""Parity at the full sizes the benchmark runs: the 8x8-box 2D Poisson system
+(m 112,640, n 12,800, 24.3M nonzeros, s 51,200) and the 4x4x4-box 3D one
+(m 165,888, n 25,600, 82.9M nonzeros, s 51,200), in the launch configuration
+bench.py times.
+
+Against the oracle:
+  * the hash and sign arrays bit-exactly (all m rows);
+  * sampled rows of SA (the oracle sums each sampled bucket one by one, in
+    ascending row order) bit-exactly, in float64 and in float32 (= the float64
+    sum rounded to nearest);
+  * the final true residual ||b - A x|| and the PDE error at 10^4 sample
+    points against the stored oracle results in tests/golden/ (written by
+    tests/golden/make_golden.py, which calls only the oracle).
+
+Residual tolerance: 1e-10 relative where cond(A) u^2-level effects stay below
+it (3D system, pivot ratio min|r_jj|/max|r_jj| = 1.7e-7).  The 2D system has a
+pivot ratio of 1.1e-13 (cond(A) about 1e13): there any float64 solver's true
+residual fluctuates at the (u cond(A))^2 relative level of the optimum's
+approximation error, about 5e-8 relative, so the gate there is 1e-6."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import countsketch, pipeline
+from rfmgen import build_config, exact_solution, feature_eval, sample_points
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2409_15818_amd")
+
+SEED = 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RES_TOL = {"poisson2d_8x8": 1e-6, "poisson3d_4x4x4": 1e-10}
+
+_cache = {}
+
+
+def _system(name):
+    if name not in _cache:
+        S, s = build_config(name)
+        A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
+        _cache.clear()
+        _cache[name] = (S, s, A)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", ["poisson2d_8x8", "poisson3d_4x4x4"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fullsize_hash_sign_and_sampled_sketch_rows(handle, name, dtype):
+    S, s, A = _system(name)
+    SA, hg, sg, _ = R.rfmls_sketch(handle, A, s, SEED, dtype=dtype, want_maps=True)
+    ho, so = countsketch.hash_sign(S.m, s, SEED)
+    assert np.array_equal(hg.cpu().numpy(), ho)
+    assert np.array_equal(sg.cpu().numpy(), so)
+    rng = np.random.default_rng(7)
+    buckets = np.unique(np.concatenate([[0, s - 1, int(ho[0]), int(ho[-1])],
+                                        rng.choice(s, 60, replace=False)]))
+    rows = countsketch.sketch_rows(S.row_ptr, S.col, S.val, ho, so, S.n, buckets)
+    got = SA[torch.tensor(buckets, device=SA.device)].cpu().numpy()
+    want = rows if dtype == "f64" else rows.astype(np.float32)
+    assert np.array_equal(got, want)
+    del SA
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"{name}.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,prec", [("poisson2d_8x8", "f64"), ("poisson3d_4x4x4", "f64"),
+                                       ("poisson3d_4x4x4", "f32")])
+def test_fullsize_solve_matches_oracle(handle, name, prec):
+    S, s, A = _system(name)
+    gold = _golden(name)
+    assert (gold["m"], gold["n"], gold["nnz"], gold["s"]) == (S.m, S.n, S.nnz, s)
+    opts = R.default_opts(refine=gold["refine"])
+    res = R.csqrp_lsqr(handle, A, torch.tensor(S.b[0], device="cuda"), s, SEED,
+                       qr_dtype=prec, r_store=prec, opts=opts)
+    info = res.info[0]
+    assert res.status == 0 and info["istop"] in (1, 2)
+    x = res.x.cpu().numpy()
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    met = pipeline.residual_metrics(Ah, x, S.b[0])
+    # the library's residual is b - A x of its x (rounding of that product only)
+    assert abs(met["normr"] - info["normr"]) <= 1e-12 * gold["normb"]
+    assert abs(met["normr"] - gold["normr"]) <= RES_TOL[name] * gold["normr"], \
+        (met["normr"], gold["normr"])
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    l2 = pipeline.l2_error(E, x, exact_solution(pts))
+    assert l2 <= 1.1 * gold["l2_error"], (l2, gold["l2_error"])
+    del res
