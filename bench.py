@@ -23,12 +23,39 @@ sys.path.insert(0, ROOT)
 METRIC = "time to rel. residual 1e-10 (FP64 vs FP32-precond); SpMV/trsv HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-COMPUTE_KERNELS = ("qr_gemm_update", "qr_gemm_VtC", "inv_gemm", "qr_panel")
+COMPUTE_KERNELS = ("qr_gemm_update", "qr_gemm_VtC", "inv_gemm", "qr_inner_update", "qr_inner_VtC")
+# vector-ALU kernels (no matrix cores), priced against the vector peak
+ALU_KERNELS = ("qr_panel", "inv_blockrow")
+ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 SKETCH_SEED = 2
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/pmc_hbm_bytes_<workload>_<precision>.md, FETCH_SIZE + WRITE_SIZE scaled by a
+    copy of known size), or None when there is none or the kernel's sources changed since."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"pmc_hbm_bytes_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel") != kernel:
+        return None
+    hsh = hashlib.sha256()
+    for f in rec["source_files"]:
+        hsh.update(open(os.path.join(ROOT, f), "rb").read())
+    if hsh.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(S, s, itn_total, threads):
@@ -171,14 +198,21 @@ def main():
             k["tflops"] = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
         kernels.sort(key=lambda k: -k["ms"])
         dom = kernels[0]
-        if dom["name"] in COMPUTE_KERNELS:
+        traffic = measured_traffic(dom["name"], args.workload, args.precision)
+        if dom["name"] in ALU_KERNELS:
+            roof = {"kernel": dom["name"], "bound": "alu", "achieved": round(dom["tflops"], 3),
+                    "peak": ALU_PEAK_TFLOPS[qd], "unit": "TFLOP/s",
+                    "frac": round(dom["tflops"] / ALU_PEAK_TFLOPS[qd], 4), "traffic": traffic}
+        elif dom["name"] in COMPUTE_KERNELS:
             roof = {"kernel": dom["name"], "bound": "mfma", "achieved": round(dom["tflops"], 3),
                     "peak": MFMA_PEAK_TFLOPS[qd], "unit": "TFLOP/s",
-                    "frac": round(dom["tflops"] / MFMA_PEAK_TFLOPS[qd], 4), "traffic": None}
+                    "frac": round(dom["tflops"] / MFMA_PEAK_TFLOPS[qd], 4), "traffic": traffic}
         else:
             roof = {"kernel": dom["name"], "bound": "hbm", "achieved": round(dom["gbs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
-                    "traffic": None}
+                    "traffic": traffic}
+        roof["algorithmic_bytes_per_launch"] = dom["bytes"] / max(dom["launches"], 1)
+        roof["flops_per_launch"] = dom["flops"] / max(dom["launches"], 1)
 
     # accuracy of the measured solve (every right-hand side)
     Xn = X.detach().cpu().numpy().reshape(args.nrhs, S.n)

@@ -113,7 +113,6 @@ enum WsSlot {
   WS_QR_T,
   WS_QR_WR,
   WS_QR_Y,
-  WS_QR_TI,
   WS_TRSM,
   WS_LSQR_VEC,
   WS_LSQR_SCAL,

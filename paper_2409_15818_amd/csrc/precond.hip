@@ -158,7 +158,15 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
     const int64_t ldp = rest > 0 ? rest : 1;
     const int64_t zstride = (int64_t)kTile * ldp;
     if (rest > 0) {
-      nz = (int)((rest + kslice - 1) / kslice);
+      // K slices: only as many as it takes for about two blocks per compute
+      // unit (the 64 x rest output has rest / 64 tiles); every slice writes a
+      // 64 x rest partial that the block-row kernel reads back
+      const int64_t ntn = (rest + kTile - 1) / kTile;
+      int64_t nzt = (2 * (int64_t)h->num_cus + ntn - 1) / ntn;
+      int64_t ks = (rest + nzt - 1) / nzt;
+      if (ks < kslice) ks = kslice;
+      ks = (ks + 15) / 16 * 16;
+      nz = (int)((rest + ks - 1) / ks);
       GemmArgs<double> g;
       g.M = n - o < kTile ? n - o : kTile;
       g.N = rest;
@@ -172,7 +180,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       g.alpha = 1.0;
       g.beta = 0.0;
       g.b_upper = 1;
-      g.ksplit = kslice;
+      g.ksplit = ks;
       g.c_zstride = zstride;
       // R_{I,>I} (64 x rest) times the upper-triangular X_{>I}: 64 rest^2 flops
       Trace tr(h, "inv_gemm", 8.0 * ((double)kTile * rest + 0.5 * (double)rest * rest + (double)nz * kTile * rest),

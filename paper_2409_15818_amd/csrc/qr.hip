@@ -261,35 +261,53 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-// Build T (nb x nb upper triangular, row-major) from tau and V^T V = sum of
-// nsplit partial slices Wz (each nb x ldw, leading nb columns hold V^T V).
+// Build T (nb x nb upper triangular, row-major) of the compact-WY form
+// H_1 ... H_nb = I - V T V^T from tau and the Gram V^T V = sum of nsplit
+// partial slices Wz (each nb x ldw; its leading nb columns hold V^T V).
+// T is assembled by doubling: starting from T_jj = tau_j, neighbouring
+// diagonal blocks T_1, T_2 (b columns each) are joined by
+//   T_12 = -T_1 (V_1^T V_2) T_2,
+// the block form of the column recursion T[:j, j] = -tau_j T[:j, :j] V_:j^T v_j
+// (Schreiber and Van Loan), with all threads working on each level.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_qr_buildT(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb,
                 const T* __restrict__ tau, T* __restrict__ Tout, int64_t ldt) {
   __shared__ double Gm[kMaxNb][kMaxNb + 1];
   __shared__ double Tm[kMaxNb][kMaxNb + 1];
-  __shared__ double tv[kMaxNb];
+  __shared__ double Ym[kMaxNb][kMaxNb + 1];
   const int tid = threadIdx.x;
   for (int e = tid; e < nb * nb; e += 256) {
     const int i = e / nb, k = e % nb;
     double sacc = 0.0;
     for (int z = 0; z < nsplit; ++z) sacc += (double)Wz[(int64_t)z * zstride + (int64_t)i * ldw + k];
     Gm[i][k] = sacc;
-    Tm[i][k] = 0.0;
+    Tm[i][k] = (i == k) ? (double)tau[i] : 0.0;
   }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double tj = (double)tau[j];
-    // t = T[0:j,0:j] * G[0:j, j]
-    if (tid < j) {
-      double a = 0.0;
-      for (int k = tid; k < j; ++k) a += Tm[tid][k] * Gm[k][j];
-      tv[tid] = a;
+  for (int b = 1; b < nb; b *= 2) {
+    const int npair = (nb + 2 * b - 1) / (2 * b);
+    // Y = T_1 G_12 for every pair (rows of the first block, columns of the second)
+    for (int e = tid; e < npair * b * b; e += 256) {
+      const int pr = e / (b * b), r = e % (b * b);
+      const int f0 = pr * 2 * b, s0 = f0 + b;
+      const int i = f0 + r / b, j = s0 + r % b;
+      if (j >= nb) continue;
+      double acc = 0.0;
+      for (int k = i; k < s0; ++k) acc += Tm[i][k] * Gm[k][j];
+      Ym[i][j] = acc;
     }
     __syncthreads();
-    if (tid < j) Tm[tid][j] = -tj * tv[tid];
-    if (tid == 0) Tm[j][j] = tj;
+    // T_12 = -Y T_2
+    for (int e = tid; e < npair * b * b; e += 256) {
+      const int pr = e / (b * b), r = e % (b * b);
+      const int f0 = pr * 2 * b, s0 = f0 + b;
+      const int i = f0 + r / b, j = s0 + r % b;
+      if (j >= nb) continue;
+      double acc = 0.0;
+      for (int k = s0; k <= j; ++k) acc += Ym[i][k] * Tm[k][j];
+      Tm[i][j] = -acc;
+    }
     __syncthreads();
   }
   for (int e = tid; e < nb * nb; e += 256) Tout[(int64_t)(e / nb) * ldt + e % nb] = (T)Tm[e / nb][e % nb];
@@ -311,12 +329,12 @@ __global__ void k_sum_slices(const T* __restrict__ Wz, int64_t zstride, int nspl
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_qr_wp(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb, int64_t N,
-            const T* __restrict__ Tm, T* __restrict__ Wp, int64_t ldwp) {
+            const T* __restrict__ Tm, int64_t ldt, T* __restrict__ Wp, int64_t ldwp) {
   __shared__ double Ws[kMaxNb][64 + 1];
   __shared__ double Ts[kMaxNb][kMaxNb + 1];
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * 64;
-  for (int e = tid; e < nb * nb; e += 256) Ts[e / nb][e % nb] = (double)Tm[e];
+  for (int e = tid; e < nb * nb; e += 256) Ts[e / nb][e % nb] = (double)Tm[(int64_t)(e / nb) * ldt + e % nb];
   for (int e = tid; e < nb * 64; e += 256) {
     const int i = e / 64, cc = e % 64;
     double sacc = 0.0;
@@ -417,7 +435,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
   const int64_t split_in = 512, split_out = 8192;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
   const int64_t nsp_out_max = (s + split_out - 1) / split_out;
-  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y, *p_ti;
+  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
   RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuter, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(double) * kPayload * (1024 + 1024 / kCluster + 2 + 8),
                         &p_part));
@@ -428,14 +446,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
   RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)n, &p_wp));
   RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * kOuter * kOuter, &p_to));
   RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
-  RFMLS_CHECK(workspace(h, WS_QR_TI, sizeof(T) * kMaxNb * kMaxNb, &p_ti));
   T* tau = (T*)p_tau;
   T* Wz = (T*)p_wz;
   T* W = (T*)p_w;
   T* Wp = (T*)p_wp;
   T* To = (T*)p_to;
   T* Y = (T*)p_y;
-  T* Ti = (T*)p_ti;
   for (int64_t k0 = 0; k0 < n; k0 += kOuter) {
     const int64_t bw = n - k0 < kOuter ? n - k0 : kOuter;
     // ---------------- inner panels of the outer block ----------------
@@ -479,10 +495,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       }
       {
         Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
+        // this panel's T is also the diagonal block of the outer block's T_o
+        T* Tq = To + (p0 - k0) * kOuter + (p0 - k0);
         hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)W, (int64_t)0, 1,
-                           ncols, jb, (const T*)tau_p, Ti, (int64_t)jb);
+                           ncols, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
         hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 64)), dim3(256), 0, st, (const T*)W,
-                           (int64_t)0, 1, ncols, jb, rem, (const T*)Ti, Wp, rem);
+                           (int64_t)0, 1, ncols, jb, rem, (const T*)Tq, (int64_t)kOuter, Wp, rem);
       }
       {
         Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
@@ -506,10 +524,13 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
                          dim3(256), 0, st, (const T*)Wz, bw * ncols, (int)nsp, bw * ncols, W);
     }
     {
-      // T_o: diagonal 64-blocks from the Gram's diagonal blocks, then block columns
+      // T_o: its diagonal 64-blocks are the inner panels' T, written above,
+      // except the last panel's (no inner update follows it), built here from
+      // the Gram's diagonal block; then the block columns
       Trace tr(h, "qr_outer_T", sizeof(T) * 4.0 * (double)bw * bw, 2.0 * (double)bw * bw * bw);
-      for (int64_t q0 = 0; q0 < bw; q0 += kMaxNb) {
-        const int jq = (int)(bw - q0 < kMaxNb ? bw - q0 : kMaxNb);
+      {
+        const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
+        const int jq = (int)(bw - q0);
         hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)(W + q0 * ncols + q0),
                            (int64_t)0, 1, ncols, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
                            (int64_t)kOuter);
