@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--lockstep", type=int, default=1, help="1: lockstep blocks of 32; 0: one at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time the backward pass (gradients w.r.t. b and A's values) of "
+                         "L = 1/2 sum_k ||E x_k - u_k||^2 at 10^4 sample points")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel of "
                          "known traffic for hardware byte counters)")
@@ -161,7 +164,7 @@ def main():
         X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts)
         if ev is not None:
             ev[4].record()
-        return X, info, P, AT
+        return X, info, P, AT, Rres
 
     for w in range(args.warmup):
         log(f"[bench] warmup {w + 1}/{args.warmup}")
@@ -174,14 +177,15 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, info, P, AT = step(ev)
+        X, info, P, AT, Rres = step(ev)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
         phases.append({"transpose": ev[0].elapsed_time(ev[1]), "sketch": ev[1].elapsed_time(ev[2]),
                        "qr_and_inverse": ev[2].elapsed_time(ev[3]), "lsqr": ev[3].elapsed_time(ev[4])})
         log(f"[bench] step {k + 1}/{args.steps}: {dt * 1e3:.1f} ms  itn={[i['itn'] for i in info]}")
-        del P, AT
+        if k + 1 < args.steps:
+            del P, AT, Rres
     med = statistics.median(times)
     ph = {key: statistics.median(p[key] for p in phases) for key in phases[0]}
 
@@ -229,6 +233,30 @@ def main():
         vs_oracle = {"oracle_normr": gold["normr"], "rel_diff_normr": abs(met["normr"] - gold["normr"]) / gold["normr"],
                      "oracle_l2_error": gold["l2_error"], "l2_ratio": l2 / gold["l2_error"]}
 
+    bwd = None
+    if args.backward:
+        # dL/dx_k = E^T (E x_k - u_k) (the loss's own gradient, host side, untimed)
+        Gn = np.stack([E.T @ (E @ Xn[k] - exact_solution(pts, S.modes[k])) for k in range(args.nrhs)])
+        G = torch.tensor(Gn[0] if args.nrhs == 1 else Gn, device="cuda")
+        Xd = X.reshape(args.nrhs, S.n) if args.nrhs > 1 else X
+        bt = []
+        for k in range(args.steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dB, dAv, binfo, brc = R.rfmls_solve_backward(h, A, AT, P, Xd, Rres, G, opts)
+            torch.cuda.synchronize()
+            if k > 0:
+                bt.append(time.perf_counter() - t0)
+        # adjoint identity for the first right-hand side: <dL/db, db> = g . (A^+ db)
+        db = torch.tensor(np.random.default_rng(9).standard_normal(S.m), device="cuda")
+        xd, _, _, _ = R.rfmls_solve(h, A, AT, P, db, opts)
+        lhs = float((dB if dB.dim() == 1 else dB[0]) @ db)
+        rhs = float(np.dot(Gn[0], xd.cpu().numpy()))
+        bwd = {"ms": round(1e3 * statistics.median(bt), 3), "nrhs": args.nrhs,
+               "iterations_max": int(max(i["itn"] for i in binfo)),
+               "adjoint_identity_rel_err": abs(lhs - rhs) / abs(rhs)}
+        log(f"[bench] backward {bwd}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
@@ -253,6 +281,7 @@ def main():
             "normal_relres_max": max(mm["normal_relres"] for mm in mets),
             "l2_error": [float(f"{v:.3e}") for v in l2s]},
         "vs_oracle": vs_oracle,
+        "backward": bwd,
         "roofline": roof,
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kernels[:12]],

@@ -310,6 +310,8 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
     return fail(h, RFMLS_E_ARG, "rfmls_solve_backward: invalid arguments");
   if (nrhs == 0) return RFMLS_OK;
   RFMLS_CHECK(set_device(h));
+  if (o->lockstep && nrhs > 1)
+    return run_backward_block(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
   return run_backward(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
 }
 

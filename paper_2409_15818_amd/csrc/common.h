@@ -198,6 +198,11 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
                              const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
                              double* X, int64_t ldx, double* Rout, int64_t ldr,
                              const rfmls_opts* o, rfmls_info* info);
+rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                const rfmls_precond_t* P, const double* Xs, int64_t ldx,
+                                const double* Rres, int64_t ldr, const double* G, int64_t ldg,
+                                int64_t nrhs, double* dB, int64_t lddb, double* dAval,
+                                const rfmls_opts* o, rfmls_info* info);
 rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                           const rfmls_precond_t* P, const double* Xs, int64_t ldx,
                           const double* Rres, int64_t ldr, const double* G, int64_t ldg,

@@ -392,8 +392,9 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// consistent != 0: the system has an exact solution (backward pass), S1 is ||r|| <= btol ||b||
 __global__ void __launch_bounds__(kThreads) k_blk_check(BlockState* st, const double* __restrict__ ysq,
-                                                        int nsq) {
+                                                        int nsq, int consistent) {
   if (all_done(st)) return;
   __shared__ double red[kThreads / kBlk][kBlk];
   const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
@@ -409,7 +410,8 @@ __global__ void __launch_bounds__(kThreads) k_blk_check(BlockState* st, const do
       d.ynorm = sqrt(y2);
       const double anorm = sqrt(d.anorm2);
       int istop = 0;
-      if (d.normr <= d.btol * d.bnorm + d.atol * anorm * d.ynorm) istop = 1;
+      const double rtol = consistent ? d.btol * d.bnorm : d.btol * d.bnorm + d.atol * anorm * d.ynorm;
+      if (d.normr <= rtol) istop = 1;
       else if (d.pending) istop = d.pending;
       else if (d.itn >= d.itmax) istop = 7;
       if (istop) {
@@ -445,6 +447,46 @@ __global__ void k_blk_axpy(double* x, const double* __restrict__ dx, int64_t len
     x[e] += dx[e];
 }
 
+// out[i][c] = (x[i][c] - hb beta_c prev[i][c]) / alpha_c for active columns (0 where alpha_c <= 0);
+// force: every column (set-up, before the stop flags mean anything)
+__global__ void k_blk_recip_scale(const double* x, double hb, const double* prev, double* out,
+                                  int64_t len, const BlockState* __restrict__ st, int force) {
+  if (!force && all_done(st)) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const LsqrDev& d = st->col[e % kBlk];
+    if (!force && d.done) continue;
+    double o = x[e];
+    if (prev && hb != 0.0) o -= hb * d.beta * prev[e];
+    out[e] = d.alpha > 0.0 ? o / d.alpha : 0.0;
+  }
+}
+
+// dA[e] (+)= sum_c (r[i][c] w[j][c] - lam[i][c] x[j][c]) on the pattern of A; one wavefront
+// per row, lanes over the row's entries; the 32 columns of each block row are contiguous.
+__global__ void __launch_bounds__(kThreads)
+    k_blk_pattern_grad(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t m,
+                       const double* __restrict__ r, const double* __restrict__ w,
+                       const double* __restrict__ lam, const double* __restrict__ x,
+                       double* __restrict__ dA, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+  for (int64_t row = wid; row < m; row += nw) {
+    const double* ri = r + row * kBlk;
+    const double* li = lam + row * kBlk;
+    for (int64_t e = rp[row] + lane; e < rp[row + 1]; e += 64) {
+      const int64_t j = col[e];
+      const double* wj = w + j * kBlk;
+      const double* xj = x + j * kBlk;
+      double g = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < kBlk; ++c) g += ri[c] * wj[c] - li[c] * xj[c];
+      dA[e] = accumulate ? dA[e] + g : g;
+    }
+  }
+}
+
 unsigned grid_for(int64_t elems) {
   const int64_t b = (elems + kThreads - 1) / kThreads;
   return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -464,7 +506,7 @@ struct BCtx {
   const rfmls_csr* AT;
   const rfmls_precond_t* P;
   hipStream_t st;
-  double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX;
+  double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX, *Sm, *Sn;
   double *sqA, *sqB, *sqY, *sqW, *part;
   BlockState* dst;
 };
@@ -577,7 +619,7 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
     hipLaunchKernelGGL(k_blk_update, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, cst,
                        (const double*)c.V, c.W, c.Y, n, c.sqY, c.sqW);
     hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqY,
-                       (int)rows_grid(n));
+                       (int)rows_grid(n), 0);
     RFMLS_HIP(c.h, hipGetLastError());
     if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
   }
@@ -590,15 +632,11 @@ rfmls_status read_block_state(BCtx& c, BlockState* out) {
   return RFMLS_OK;
 }
 
-}  // namespace
-
-rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
-                             const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
-                             double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
-                             rfmls_info* info) {
+// Work blocks (5 of m x 32, 8 of n x 32), partial sums and the triangular-product
+// partials, carved from one workspace slot.
+static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                              const rfmls_precond_t* P, BCtx& c) {
   const int64_t m = A->m, n = A->n;
-  const int64_t itmax = o->itmax > 0 ? o->itmax : n;
-  BCtx c;
   c.h = h;
   c.A = A;
   c.AT = AT;
@@ -619,7 +657,7 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   c.Rr = take(m * kBlk);
   c.Bb = take(m * kBlk);
   c.T = take(m * kBlk);
-  take(m * kBlk);
+  c.Sm = take(m * kBlk);
   c.V = take(n * kBlk);
   c.W = take(n * kBlk);
   c.Y = take(n * kBlk);
@@ -627,7 +665,7 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   c.Q = take(n * kBlk);
   c.Xb = take(n * kBlk);
   c.DX = take(n * kBlk);
-  take(n * kBlk);
+  c.Sn = take(n * kBlk);
   c.sqA = take(kSpmmMaxBlocks * kBlk);
   c.sqB = take(kSpmmMaxBlocks * kBlk);
   c.sqY = take(kSpmmMaxBlocks * kBlk);
@@ -636,6 +674,19 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   void* ps;
   RFMLS_CHECK(workspace(h, WS_LSQR_BSTATE, sizeof(BlockState), &ps));
   c.dst = (BlockState*)ps;
+  return RFMLS_OK;
+}
+
+}  // namespace
+
+rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                             const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                             double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                             rfmls_info* info) {
+  const int64_t m = A->m, n = A->n;
+  const int64_t itmax = o->itmax > 0 ? o->itmax : n;
+  BCtx c;
+  RFMLS_CHECK(make_bctx(h, A, AT, P, c));
   const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
   rfmls_status ret = RFMLS_OK;
   std::vector<BlockState> hs(1);
@@ -691,6 +742,120 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
       if (info) info[k0 + q] = inf[q];
     }
   }
+  return ret;
+}
+
+
+// Backward in lockstep blocks of 32: for each column, LSQR on the consistent
+// system B^T lam = X^T g with operator M = B^T = X^T A^T (n x m), from lam = 0,
+// tracking the shadow vectors vt (v = B vt) and z (lam = B z); then w = X z,
+// lam = A w, dB = lam and dA += r w^T - lam x^T on A's pattern (summed over
+// the right-hand sides).  Same per-column recurrences as the single-column
+// backward.
+rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                const rfmls_precond_t* P, const double* Xs, int64_t ldx,
+                                const double* Rres, int64_t ldr, const double* G, int64_t ldg,
+                                int64_t nrhs, double* dB, int64_t lddb, double* dAval,
+                                const rfmls_opts* o, rfmls_info* info) {
+  const int64_t m = A->m, n = A->n;
+  const int64_t itmax = o->itmax > 0 ? o->itmax : m;
+  BCtx c;
+  RFMLS_CHECK(make_bctx(h, A, AT, P, c));
+  // roles: un (n), vm (m), vt, wt, zz shadows (n), tmp (n), lam (m), gathered blocks
+  double* un = c.V;
+  double* vm = c.U;
+  double* vt = c.W;
+  double* wt = c.Q;
+  double* zz = c.Y;
+  double* tmp = c.Z;
+  double* lam = c.Rr;
+  double* Gb = c.Xb;
+  double* Xg = c.DX;
+  double* Rg = c.Bb;
+  const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
+  const int every = o->check_every > 0 ? o->check_every : 8;
+  const BlockState* cst = c.dst;
+  rfmls_status ret = RFMLS_OK;
+  std::vector<BlockState> hs(1);
+  for (int64_t k0 = 0; k0 < nrhs; k0 += kBlk) {
+    const int64_t nb = nrhs - k0 < kBlk ? nrhs - k0 : kBlk;
+    hipLaunchKernelGGL(k_gather_block, dim3(gn), dim3(kThreads), 0, c.st, G, ldg, k0, nb, n, Gb);
+    // beta_1 u_1 = X^T g
+    RFMLS_CHECK(tri_block(c, 1, Gb, un, 0.0, nullptr, nullptr, c.sqB, nullptr));
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+                       (int)rows_grid(n), c.dst, 0, 1);
+    hipLaunchKernelGGL(k_blk_start, dim3(1), dim3(64), 0, c.st, c.dst, o->atol, o->btol, o->conlim, itmax);
+    hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, un, n, cst, 0, 1);
+    hipLaunchKernelGGL(k_blk_fill, dim3(gn), dim3(kThreads), 0, c.st, zz, n * kBlk, 0.0);
+    // alpha_1 v_1 = A (X u_1);  vt_1 = u_1 / alpha_1;  w_1 = vt_1
+    RFMLS_CHECK(tri_block(c, 0, un, tmp, 0.0, nullptr, nullptr, nullptr, nullptr));
+    int nbk = 0;
+    RFMLS_CHECK(spmm(c, A, tmp, 1.0, 0.0, nullptr, nullptr, vm, c.sqA, nullptr, &nbk));
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
+    hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, vm, m, cst, 1, 0);
+    hipLaunchKernelGGL(k_blk_start2, dim3(1), dim3(64), 0, c.st, c.dst);
+    hipLaunchKernelGGL(k_blk_recip_scale, dim3(gn), dim3(kThreads), 0, c.st, (const double*)un, 0.0,
+                       (const double*)nullptr, vt, n, cst, 1);
+    hipLaunchKernelGGL(k_blk_copy, dim3(gn), dim3(kThreads), 0, c.st, (const double*)vt, wt, n);
+    hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)wt, n, c.sqW);
+    RFMLS_HIP(h, hipGetLastError());
+    int hd = 0;
+    RFMLS_CHECK(poll_all(c, &hd));
+    for (int64_t it = 0; it < itmax && !hd; ++it) {
+      // beta u = X^T (A^T v) - alpha u
+      RFMLS_CHECK(spmm(c, AT, vm, 1.0, 0.0, nullptr, nullptr, tmp, nullptr, cst, nullptr));
+      RFMLS_CHECK(tri_block(c, 1, tmp, un, 1.0, state_field(c.dst, 1), un, c.sqB, cst));
+      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+                         (int)rows_grid(n), c.dst, 0, 0);
+      hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, un, n, cst, 0, 0);
+      // alpha v = A (X u) - beta v;  vt = (u - beta vt) / alpha
+      RFMLS_CHECK(tri_block(c, 0, un, tmp, 0.0, nullptr, nullptr, nullptr, cst));
+      RFMLS_CHECK(spmm(c, A, tmp, 1.0, 1.0, state_field(c.dst, 0), vm, vm, c.sqA, cst, &nbk));
+      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
+      hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, vm, m, cst, 1, 0);
+      hipLaunchKernelGGL(k_blk_recip_scale, dim3(gn), dim3(kThreads), 0, c.st, (const double*)un, 1.0,
+                         (const double*)vt, vt, n, cst, 0);
+      hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqW,
+                         (int)rows_grid(n));
+      hipLaunchKernelGGL(k_blk_update, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, cst,
+                         (const double*)vt, wt, zz, n, c.sqY, c.sqW);
+      hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqY,
+                         (int)rows_grid(n), 1);
+      RFMLS_HIP(h, hipGetLastError());
+      if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
+    }
+    RFMLS_CHECK(read_block_state(c, hs.data()));
+    for (int64_t q = 0; q < nb; ++q) {
+      const LsqrDev& st = hs[0].col[q];
+      if (st.istop < 0)
+        return fail(h, RFMLS_E_BREAKDOWN, "non-finite value in backward LSQR (column %lld)", (long long)(k0 + q));
+      if (st.istop == 7) ret = RFMLS_W_NOCONV;
+      if (info) {
+        rfmls_info inf{};
+        inf.itn = inf.itn_first = st.itn;
+        inf.istop = inf.istop_last = st.istop;
+        inf.normr_est = st.normr;
+        inf.normb = st.bnorm;
+        info[k0 + q] = inf;
+      }
+    }
+    // w = X z, lam = A w
+    RFMLS_CHECK(tri_block(c, 0, zz, tmp, 0.0, nullptr, nullptr, nullptr, nullptr));
+    RFMLS_CHECK(spmm(c, A, tmp, 1.0, 0.0, nullptr, nullptr, lam, nullptr, nullptr, nullptr));
+    if (dB)
+      hipLaunchKernelGGL(k_scatter_block, dim3(gm), dim3(kThreads), 0, c.st, (const double*)lam, m, k0, nb, dB, lddb);
+    if (dAval) {
+      hipLaunchKernelGGL(k_gather_block, dim3(gm), dim3(kThreads), 0, c.st, Rres, ldr, k0, nb, m, Rg);
+      hipLaunchKernelGGL(k_gather_block, dim3(gn), dim3(kThreads), 0, c.st, Xs, ldx, k0, nb, n, Xg);
+      Trace tr(h, "pattern_grad_blk", 16.0 * (double)A->nnz + 8.0 * (double)(m + 1) + 16.0 * kBlk * (double)(m + n),
+               4.0 * kBlk * (double)A->nnz);
+      hipLaunchKernelGGL(k_blk_pattern_grad, dim3(spmm_grid(m)), dim3(kThreads), 0, c.st, A->row_ptr,
+                         A->col, m, (const double*)Rg, (const double*)tmp, (const double*)lam,
+                         (const double*)Xg, dAval, k0 > 0 ? 1 : 0);
+    }
+    RFMLS_HIP(h, hipGetLastError());
+  }
+  RFMLS_HIP(h, hipStreamSynchronize(c.st));
   return ret;
 }
 

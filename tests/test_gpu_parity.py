@@ -341,6 +341,37 @@ def test_backward_matches_dense_gradients(handle):
     assert np.linalg.norm(dA.cpu().numpy() - dAo) <= 1e-7 * np.linalg.norm(dAo)
 
 
+@pytest.mark.parametrize("nrhs", [3, 33])
+def test_lockstep_backward_matches_dense_gradients(handle, nrhs):
+    """Lockstep backward (blocks of 32, ragged tail) against the dense float64 oracle:
+    dB column by column, dA summed over the right-hand sides."""
+    m, n = 400, 30
+    Ad = dense_with_condition(m, n, 1e4, seed=31)
+    rng = np.random.default_rng(33)
+    Bn = rng.standard_normal((nrhs, m))
+    Gn = rng.standard_normal((nrhs, n))
+    Gn[min(2, nrhs - 1)] = 0.0  # a zero cotangent: stops before the first iteration
+    rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+    A = gpu_csr(rp, col, val, m, n)
+    AT = R.rfmls_transpose(handle, A)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, 4 * n, 1)[0])
+    Xg, Rg, _, _ = R.rfmls_solve(handle, A, AT, P, torch.tensor(Bn, device="cuda"))
+    dB, dA, binfo, rc = R.rfmls_solve_backward(handle, A, AT, P, Xg, Rg, torch.tensor(Gn, device="cuda"))
+    dBs, dAs, _, _ = R.rfmls_solve_backward(handle, A, AT, P, Xg, Rg, torch.tensor(Gn, device="cuda"),
+                                            R.default_opts(lockstep=0))
+    dB, dA = dB.cpu().numpy(), dA.cpu().numpy()
+    dAo = np.zeros_like(dA)
+    for k in range(nrhs):
+        x, r, w, lam = backward.dense_gradients(Ad, Bn[k], Gn[k])
+        if not Gn[k].any():
+            assert not dB[k].any() and binfo[k]["itn"] == 0
+        else:
+            assert np.linalg.norm(dB[k] - lam) <= 1e-8 * np.linalg.norm(lam), k
+        dAo += backward.pattern_grad(rp, col, r, w, lam, x)
+    assert np.linalg.norm(dA - dAo) <= 1e-7 * np.linalg.norm(dAo)
+    assert np.linalg.norm(dBs.cpu().numpy() - dB) <= 1e-9 * np.linalg.norm(dB)
+
+
 def test_autograd_function(handle):
     S, s, A = system("poisson2d_2x2")
     solver = R.LstsqSolver(handle, S.m, S.n, A.row_ptr, A.col, s)
@@ -359,3 +390,46 @@ def test_autograd_function(handle):
     xd = solver(val.detach(), db)
     g = (E.T @ (E @ x.detach() - t))
     assert abs(float(b.grad @ db) - float(g @ xd)) <= 1e-6 * abs(float(g @ xd))
+
+
+def test_backward_matches_central_differences_2x2(handle):
+    """dL/db and dL/dA (on A's pattern) of L = 1/2 ||E x - u||^2 at sample points, x = A^+ b
+    from the GPU pipeline, against central differences of L along random directions
+    (each L evaluation is a full GPU sketch -> QR -> LSQR solve).
+
+    x is linear in b, so any step works there (relative 1e-4).  In A the least-squares
+    solution of this system (cond(A) = 7e5) leaves the linear regime quickly: with the
+    float64 oracle, central differences along a random pattern direction match the
+    analytic derivative to 9e-3 / 9e-5 / 1e-6 at relative steps 1e-6 / 1e-7 / 1e-8
+    (quadratic truncation) and the solver's rounding takes over below 1e-9; the test
+    uses 1e-8 and a 1e-4 tolerance."""
+    S, s, A = system("poisson2d_2x2")
+    pts = sample_points(S.d, 2000)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    t = exact_solution(pts)
+    opts = R.default_opts(refine=2)
+
+    def solve(val, b):
+        Av = R.CSR(S.m, S.n, A.row_ptr, A.col, torch.tensor(val, device="cuda"))
+        return R.csqrp_lsqr(handle, Av, torch.tensor(b, device="cuda"), s, SEED, opts=opts)
+
+    def loss(val, b):
+        x = solve(val, b).x.cpu().numpy()
+        return 0.5 * float(np.sum((E @ x - t) ** 2))
+
+    res = solve(S.val, S.b[0])
+    x = res.x.cpu().numpy()
+    g = E.T @ (E @ x - t)
+    dB, dA, info, rc = R.rfmls_solve_backward(handle, A, res.AT, res.precond, res.x, res.residual,
+                                              torch.tensor(g, device="cuda"), opts)
+    dB, dA = dB.cpu().numpy(), dA.cpu().numpy()
+    rng = np.random.default_rng(21)
+    for _ in range(2):
+        db = rng.standard_normal(S.m)
+        h = 1e-4 * np.linalg.norm(S.b[0]) / np.linalg.norm(db)
+        fd = (loss(S.val, S.b[0] + h * db) - loss(S.val, S.b[0] - h * db)) / (2 * h)
+        assert abs(fd - dB @ db) <= 1e-5 * abs(fd), (fd, dB @ db)
+        dv = rng.standard_normal(S.nnz)
+        h = 1e-8 * np.linalg.norm(S.val) / np.linalg.norm(dv)
+        fd = (loss(S.val + h * dv, S.b[0]) - loss(S.val - h * dv, S.b[0])) / (2 * h)
+        assert abs(fd - dA @ dv) <= 1e-4 * abs(fd), (fd, dA @ dv)
