@@ -151,42 +151,139 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// CSR SpMM: out[row][c] = sA (M Xin)[row][c] - coef_c prev[row][c]; one wavefront per row,
-// lane l works on column l % 32 and every other entry (l / 32); per-column partial sums of squares.
+// CSR SpMM with LDS-staged input windows:
+//   out[row][c] = sA (M Xin)[row][c] - coef_c prev[row][c],  c < 32,
+// plus per-column partial sums of squares of out.  A workgroup takes kGroup
+// consecutive rows and walks their (ascending) column indices in windows of
+// kWin input rows: each window's 32-wide input rows are staged in LDS once,
+// with the group's entries that fall in it, and every row of the group then
+// accumulates from LDS.  Rows of one RFM box share their column runs (the
+// transpose's rows even share whole patterns), so a staged window serves the
+// whole group instead of being gathered from L2 once per nonzero.  Entries
+// are accumulated in CSR order, so results are deterministic.
+// Malformed input (columns out of order or out of range) cannot make the
+// kernel read outside Xin or LDS: such entries end a window's prefix early.
+constexpr int kGroup = 16;
+constexpr int kWin = 128;
+
 __global__ void __launch_bounds__(kThreads)
     k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-           const double* __restrict__ val, int64_t rows, const double* __restrict__ Xin, double sA,
-           double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
+           const double* __restrict__ val, int64_t rows, int64_t ncols, const double* __restrict__ Xin,
+           double sA, double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
            double* out, double* __restrict__ sq, const BlockState* __restrict__ st) {
   if (st && all_done(st)) return;
-  __shared__ double red[kThreads / 64][kBlk];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = lane & (kBlk - 1), half = lane >> 5;
-  const int64_t wid = (int64_t)blockIdx.x * (kThreads / 64) + wv;
-  const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+  __shared__ double Xs[kWin][kBlk];
+  __shared__ double Vs[kGroup][kWin];
+  __shared__ int Cs[kGroup][kWin];
+  __shared__ int64_t cur[kGroup], endp[kGroup];
+  __shared__ int cnt[kGroup];
+  __shared__ int wmin[kGroup];
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int tid = threadIdx.x;
+  const int c = tid & (kBlk - 1), slot = tid / kBlk;  // slot 0..7: rows slot, slot + 8
+  const int er = tid / (kThreads / kGroup), el = tid % (kThreads / kGroup);  // entry staging: row er, lane el
   double cf = hcoef;
   if (coef) cf *= coef[c * cstride];
   const bool act = !st || !st->col[c].done;
   double ss = 0.0;
-  for (int64_t row = wid; row < rows; row += nw) {
-    const int64_t lo = rp[row], hi = rp[row + 1];
-    double s = 0.0;
-    for (int64_t e = lo + half; e < hi; e += 2) s += val[e] * Xin[(int64_t)col[e] * kBlk + c];
-    s += __shfl_xor(s, 32, 64);
-    if (half == 0) {
-      double o = sA * s;
-      if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
-      if (act) out[row * kBlk + c] = o;
-      ss += o * o;
+  const int64_t ngroups = (rows + kGroup - 1) / kGroup;
+  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const int64_t r0 = gi * kGroup;
+    if (tid < kGroup) {
+      const int64_t r = r0 + tid;
+      cur[tid] = r < rows ? rp[r] : 0;
+      endp[tid] = r < rows ? rp[r + 1] : 0;
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+    for (;;) {
+      __syncthreads();
+      if (tid < kGroup) wmin[tid] = cur[tid] < endp[tid] ? col[cur[tid]] : INT32_MAX;
+      __syncthreads();
+      int w0 = INT32_MAX;
+#pragma unroll
+      for (int t = 0; t < kGroup; ++t) w0 = wmin[t] < w0 ? wmin[t] : w0;
+      if (w0 == INT32_MAX) break;  // uniform: every thread computed the same w0
+      // stage the input rows [w0, w0 + kWin) (coalesced, 32 doubles per row)
+      for (int e = tid; e < kWin * kBlk; e += kThreads) {
+        const int64_t r = (int64_t)w0 + e / kBlk;
+        Xs[e / kBlk][e % kBlk] = (r >= 0 && r < ncols) ? Xin[r * kBlk + (e % kBlk)] : 0.0;
+      }
+      // stage each row's entries in the window; cnt = length of the in-window prefix
+      if (el == 0) cnt[er] = (int)(endp[er] - cur[er] < kWin ? endp[er] - cur[er] : kWin);
+      __syncthreads();
+      {
+        const int64_t base = cur[er];
+        int first_bad = kWin;
+        for (int j = el; j < kWin; j += kThreads / kGroup) {
+          const int64_t e = base + j;
+          bool ok = e < endp[er];
+          int cc = 0;
+          if (ok) {
+            cc = col[e] - w0;
+            ok = cc >= 0 && cc < kWin;
+          }
+          if (ok) {
+            Vs[er][j] = val[e];
+            Cs[er][j] = cc;
+          } else if (j < first_bad) {
+            first_bad = j;
+          }
+        }
+        atomicMin(&cnt[er], first_bad);
+      }
+      __syncthreads();
+      {
+        // 8 entries of each of the two rows at a time: all LDS loads issued
+        // before the (in-order) accumulation, so the loads overlap
+        const int n0 = cnt[slot], n1 = cnt[slot + 8];
+        const int nn = n0 < n1 ? n0 : n1;
+        int j = 0;
+        for (; j + 8 <= nn; j += 8) {
+          int c0[8], c1[8];
+          double v0[8], v1[8], x0[8], x1[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            c0[q] = Cs[slot][j + q];
+            c1[q] = Cs[slot + 8][j + q];
+            v0[q] = Vs[slot][j + q];
+            v1[q] = Vs[slot + 8][j + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            x0[q] = Xs[c0[q]][c];
+            x1[q] = Xs[c1[q]][c];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            acc0 += v0[q] * x0[q];
+            acc1 += v1[q] * x1[q];
+          }
+        }
+        for (int j0 = j; j0 < n0; ++j0) acc0 += Vs[slot][j0] * Xs[Cs[slot][j0]][c];
+        for (int j1 = j; j1 < n1; ++j1) acc1 += Vs[slot + 8][j1] * Xs[Cs[slot + 8][j1]][c];
+      }
+      __syncthreads();
+      if (tid < kGroup) cur[tid] += cnt[tid];
+    }
+    // write the group's rows
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int64_t row = r0 + slot + 8 * h2;
+      if (row < rows) {
+        double o = sA * (h2 ? acc1 : acc0);
+        if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
+        if (act) out[row * kBlk + c] = o;
+        ss += o * o;
+      }
     }
   }
   if (sq) {
-    if (half == 0) red[wv][c] = ss;
+    red[slot][c] = ss;
     __syncthreads();
-    if (threadIdx.x < kBlk) {
+    if (tid < kBlk) {
       double t = 0.0;
-      for (int q = 0; q < kThreads / 64; ++q) t += red[q][threadIdx.x];
-      sq[blockIdx.x * kBlk + threadIdx.x] = t;
+      for (int q = 0; q < kThreads / kBlk; ++q) t += red[q][tid];
+      sq[blockIdx.x * kBlk + tid] = t;
     }
   }
 }
@@ -496,7 +593,7 @@ unsigned rows_grid(int64_t rows) {  // blocks of 8 rows x 32 columns
   return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
 }
 unsigned spmm_grid(int64_t rows) {
-  const int64_t b = (rows + 3) / 4;
+  const int64_t b = (rows + kGroup - 1) / kGroup;
   return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
 }
 
@@ -560,8 +657,8 @@ rfmls_status spmm(BCtx& c, const rfmls_csr* M, const double* x, double sA, doubl
            12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) +
                8.0 * kBlk * ((double)M->n + (double)M->m * (prev ? 2.0 : 1.0)),
            2.0 * kBlk * (double)M->nnz);
-  hipLaunchKernelGGL(k_spmm, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, x,
-                     sA, hcoef, coef, kStride, prev, out, sq, stp);
+  hipLaunchKernelGGL(k_spmm, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, M->n,
+                     x, sA, hcoef, coef, kStride, prev, out, sq, stp);
   if (nblk) *nblk = (int)nb;
   RFMLS_HIP(c.h, hipGetLastError());
   return RFMLS_OK;
