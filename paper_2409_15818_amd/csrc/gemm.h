@@ -140,8 +140,13 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wy = wave / WN, wx = wave % WN;
-  const int64_t i0 = (int64_t)blockIdx.y * BMt;
-  const int64_t j0 = (int64_t)blockIdx.x * BNt;
+  // Triangular operands make the K range grow with the tile column (B upper:
+  // k <= j) or row (op(A) lower: k <= i); those tiles are issued first (reversed
+  // order) so the longest blocks do not form a tail at the end of the grid.
+  const unsigned bx = g.b_upper ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const unsigned by = g.a_lower ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+  const int64_t i0 = (int64_t)by * BMt;
+  const int64_t j0 = (int64_t)bx * BNt;
   int64_t kbeg = 0, kend = g.K;
   if (g.ksplit > 0) {
     kbeg = (int64_t)blockIdx.z * g.ksplit;

@@ -61,40 +61,61 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
   }
 }
 
-// Block row I of X = R^{-1}: for the 64 columns j = blockIdx.x*64 + t of the
-// range [o, n) (o = 64 I), the right-hand side is e_j restricted to block I
-// minus sum_z P[z][:, j - o - 64] (the split-K partials of R_{I,>I} X_{>I});
-// then R_II x = rhs is solved by back substitution.
-__global__ void __launch_bounds__(64) k_inv_blockrow(const double* __restrict__ R, int64_t n,
-                                                     int64_t I, const double* __restrict__ P,
-                                                     int nz, int64_t ldp, int64_t zstride,
-                                                     double* __restrict__ X) {
-  __shared__ double Rs[kTile][kTile + 1];
-  __shared__ double Xs[kTile][kTile + 1];
+// Block row I of X = R^{-1} (rows [o, o + b), o = 64 I), columns j in [o, n).
+// Right-hand side: e_j restricted to the block row, minus R_{I,>I} X_{>I}, which
+// arrives in two parts (see invert_upper): Pn (b x (n - o - 64), one slice) from
+// the rows of X solved earlier inside the same outer block, and nzf split-K
+// slices of Pf (rows roff .. roff + b of a (rows of the outer block) x (n - e2)
+// partial) from the rows beyond the outer block, for columns j >= e2.  Then
+// R_II x = rhs by back substitution.  One thread per column with its 64 values
+// in registers; the substitution is column-oriented (x_i = rhs_i / r_ii, then
+// every rhs_k, k < i, is updated at once), so each step offers up to 63
+// independent FMAs instead of one dependent dot product per row.
+constexpr int kInvCols = 128;
+
+__global__ void __launch_bounds__(kInvCols)
+    k_inv_blockrow(const double* __restrict__ R, int64_t n, int64_t I, const double* __restrict__ Pn,
+                   int64_t ldn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
+                   int64_t roff, int64_t e2, double* __restrict__ X) {
+  __shared__ double Rs[kTile][kTile];
   const int64_t o = I * kTile;
   const int b = (int)(n - o < kTile ? n - o : kTile);
   const int t = threadIdx.x;
-  for (int i = 0; i < b; ++i) Rs[i][t] = t < b ? R[(o + i) * n + o + t] : 0.0;
-  const int64_t j = o + (int64_t)blockIdx.x * kTile + t;
+  for (int e = t; e < kTile * kTile; e += kInvCols) {
+    const int i = e / kTile, k = e % kTile;
+    Rs[i][k] = (i < b && k < b) ? R[(o + i) * n + o + k] : (i == k ? 1.0 : 0.0);
+  }
+  const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t;
   const bool live = j < n;
-  for (int i = 0; i < b; ++i) {
-    double v = (live && j == o + i) ? 1.0 : 0.0;
-    if (live && j >= o + kTile && nz > 0) {
-      const int64_t jc = j - o - kTile;
-      double acc = 0.0;
-      for (int z = 0; z < nz; ++z) acc += P[(int64_t)z * zstride + (int64_t)i * ldp + jc];
-      v -= acc;
+  double v[kTile];
+#pragma unroll
+  for (int i = 0; i < kTile; ++i) v[i] = (live && j == o + i) ? 1.0 : 0.0;
+  if (live && j >= o + kTile && Pn) {
+    const int64_t jc = j - o - kTile;
+#pragma unroll
+    for (int i = 0; i < kTile; ++i) v[i] = i < b ? -Pn[(int64_t)i * ldn + jc] : 0.0;
+  }
+  if (live && j >= e2) {
+    const int64_t jf = j - e2;
+    for (int z = 0; z < nzf; ++z) {
+      const double* Pz = Pf + (int64_t)z * zsf + roff * ldf + jf;
+#pragma unroll
+      for (int i = 0; i < kTile; ++i)
+        if (i < b) v[i] -= Pz[(int64_t)i * ldf];
     }
-    Xs[i][t] = v;
   }
   __syncthreads();
+  // rows >= b are the identity with v = 0 and stay 0
+#pragma unroll
+  for (int i = kTile - 1; i >= 0; --i) {
+    v[i] = v[i] / Rs[i][i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v[k] -= Rs[k][i] * v[i];
+  }
   if (live) {
-    for (int i = b - 1; i >= 0; --i) {
-      double acc = Xs[i][t];
-      for (int k = i + 1; k < b; ++k) acc -= Rs[i][k] * Xs[k][t];
-      Xs[i][t] = acc / Rs[i][i];
-    }
-    for (int i = 0; i < b; ++i) X[(o + i) * n + j] = Xs[i][t];
+#pragma unroll
+    for (int i = 0; i < kTile; ++i)
+      if (i < b) X[(o + i) * n + j] = v[i];
   }
 }
 
@@ -147,53 +168,83 @@ __global__ void k_unpack_tiles_f32(const float* __restrict__ pk, int64_t n, int6
   }
 }
 
-// X = R^{-1} by blocked back substitution (see the file comment).  P is the
-// split-K workspace (nz slices of kTile x (n - 64) doubles).
-rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P, int64_t n,
-                          int64_t nt, int64_t kslice) {
-  for (int64_t I = nt - 1; I >= 0; --I) {
-    const int64_t o = I * kTile;
-    const int64_t rest = n - o - kTile;  // columns / rows beyond block I
-    int nz = 0;
-    const int64_t ldp = rest > 0 ? rest : 1;
-    const int64_t zstride = (int64_t)kTile * ldp;
-    if (rest > 0) {
-      // K slices: only as many as it takes for about two blocks per compute
-      // unit (the 64 x rest output has rest / 64 tiles); every slice writes a
-      // 64 x rest partial that the block-row kernel reads back
-      const int64_t ntn = (rest + kTile - 1) / kTile;
-      int64_t nzt = (2 * (int64_t)h->num_cus + ntn - 1) / ntn;
-      int64_t ks = (rest + nzt - 1) / nzt;
+// X = R^{-1} by blocked back substitution, two levels: outer blocks of
+// kInvOuter rows (4 tiles), inner block rows of 64.  For block row I inside
+// the outer block [o2, e2):
+//   R_{I,>I} X_{>I} = R_{I,(I,e2)} X_{(I,e2)}  (near: K < 256, one GEMM per row)
+//                   + R_{I,>=e2} X_{>=e2}        (far: computed once per outer
+//                                                 block for all its rows, M = 256)
+// so the dominant n^3/3 flops run as 256-row GEMMs.  Pf holds up to 4 split-K
+// slices of (e2 - o2) x (n - e2); Pn one 64 x n slice.
+constexpr int64_t kInvOuter = 4 * kTile;
+
+rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* Pf, double* Pn,
+                          int64_t n, int64_t nt, int64_t kslice) {
+  const int64_t nt2 = (nt + 3) / 4;
+  for (int64_t I2 = nt2 - 1; I2 >= 0; --I2) {
+    const int64_t o2 = I2 * kInvOuter;
+    const int64_t e2 = o2 + kInvOuter < n ? o2 + kInvOuter : n;
+    const int64_t far = n - e2;
+    int nzf = 0;
+    const int64_t ldf = far > 0 ? far : 1;
+    const int64_t zsf = (e2 - o2) * ldf;
+    if (far > 0) {
+      // K slices only where the (e2 - o2) x far output has too few tiles for
+      // about two blocks per compute unit (at most 4 slices, each >= kslice)
+      const int64_t tiles = ((e2 - o2 + kTile - 1) / kTile) * ((far + kTile - 1) / kTile);
+      int64_t nzt = (2 * (int64_t)h->num_cus + tiles - 1) / tiles;
+      int64_t ks = (far + nzt - 1) / nzt;
       if (ks < kslice) ks = kslice;
+      if ((far + ks - 1) / ks > 4) ks = (far + 3) / 4;
       ks = (ks + 15) / 16 * 16;
-      nz = (int)((rest + ks - 1) / ks);
+      nzf = (int)((far + ks - 1) / ks);
       GemmArgs<double> g;
-      g.M = n - o < kTile ? n - o : kTile;
-      g.N = rest;
-      g.K = rest;
-      g.A = R + o * n + o + kTile;
+      g.M = e2 - o2;
+      g.N = far;
+      g.K = far;
+      g.A = R + o2 * n + e2;
       g.lda = n;
-      g.B = X + (o + kTile) * n + o + kTile;
+      g.B = X + e2 * n + e2;
       g.ldb = n;
-      g.C = P;
-      g.ldc = ldp;
-      g.alpha = 1.0;
-      g.beta = 0.0;
+      g.C = Pf;
+      g.ldc = ldf;
       g.b_upper = 1;
       g.ksplit = ks;
-      g.c_zstride = zstride;
-      // R_{I,>I} (64 x rest) times the upper-triangular X_{>I}: 64 rest^2 flops
-      Trace tr(h, "inv_gemm", 8.0 * ((double)kTile * rest + 0.5 * (double)rest * rest + (double)nz * kTile * rest),
-               (double)kTile * (double)rest * (double)rest);
+      g.c_zstride = zsf;
+      Trace tr(h, "inv_gemm", 8.0 * ((double)(e2 - o2) * far + 0.5 * (double)far * far + (double)nzf * (e2 - o2) * far),
+               (double)(e2 - o2) * (double)far * (double)far);
       RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
     }
-    {
-      Trace tr(h, "inv_blockrow", 8.0 * ((double)nz * kTile * ldp + (double)kTile * (n - o)),
-               (double)kTile * kTile * (double)(n - o));
-      hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kTile)), dim3(kTile), 0, h->stream, R,
-                         n, I, (const double*)P, nz, ldp, zstride, X);
+    for (int64_t I = (e2 - 1) / kTile; I >= I2 * 4; --I) {
+      const int64_t o = I * kTile;
+      const int64_t b = n - o < kTile ? n - o : kTile;
+      const int64_t kn = e2 - o - b;  // solved rows of this outer block below row block I
+      const int64_t ldn = n - o - kTile > 0 ? n - o - kTile : 1;
+      if (kn > 0) {
+        GemmArgs<double> g;
+        g.M = b;
+        g.N = n - o - kTile;
+        g.K = kn;
+        g.A = R + o * n + o + kTile;
+        g.lda = n;
+        g.B = X + (o + kTile) * n + o + kTile;
+        g.ldb = n;
+        g.C = Pn;
+        g.ldc = ldn;
+        g.b_upper = 1;
+        Trace tr(h, "inv_gemm_near", 8.0 * ((double)b * kn + (double)kn * g.N + (double)b * g.N),
+                 2.0 * (double)b * kn * (double)g.N);
+        RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
+      }
+      {
+        Trace tr(h, "inv_blockrow", 8.0 * ((double)(nzf + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
+                 (double)kTile * kTile * (double)(n - o));
+        hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols), 0, h->stream, R,
+                           n, I, kn > 0 ? (const double*)Pn : (const double*)nullptr, ldn, (const double*)Pf,
+                           nzf, ldf, zsf, o - o2, e2, X);
+      }
+      RFMLS_HIP(h, hipGetLastError());
     }
-    RFMLS_HIP(h, hipGetLastError());
   }
   return RFMLS_OK;
 }
@@ -220,10 +271,11 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   void* p_w;
   RFMLS_CHECK(workspace(h, WS_TRSM, sizeof(double) * (size_t)n * (size_t)n, &p_x));
   const int64_t kslice = 512;
-  const int64_t nzmax = (n + kslice - 1) / kslice;
-  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)nzmax * kTile * (size_t)n, &p_w));
+  // 4 far slices of kInvOuter x n and one near slice of 64 x n
+  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + kTile) * (size_t)n, &p_w));
   double* X = (double*)p_x;
-  RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, n, P->nt, kslice));
+  RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
+                           P->nt, kslice));
   const int64_t ntiles = P->nt * (P->nt + 1) / 2;
   const size_t esz = P->store == RFMLS_F64 ? sizeof(double) : sizeof(float);
   // work tables of the triangular products

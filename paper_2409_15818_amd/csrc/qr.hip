@@ -458,12 +458,18 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
       const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
       const int64_t M = s - p0;
-      // rows per block rpw = (NT / 64) Q: the smallest shape that needs at most
-      // one block per compute unit, else the largest one (register-resident
-      // rows, no spills); the grid reduction costs about the same for any G
+      // rows per block rpw = (NT / 64) Q: the smallest shape whose grid is
+      // co-resident (fewer rows per thread = less arithmetic per column; the
+      // grid reduction costs about the same for any G), else the largest one
       const PanelShape* shapes = panel_shapes<T>();
       int si = 0;
-      while (shapes[si + 1].q != 0 && (M + shapes[si].rpw() - 1) / shapes[si].rpw() > h->num_cus) ++si;
+      for (;; ++si) {
+        if (shapes[si + 1].q == 0) break;
+        int per_cu = 0;
+        RFMLS_HIP(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shapes[si].fn, shapes[si].nt, 0));
+        const int64_t gmax = (int64_t)per_cu * h->num_cus < 1024 ? (int64_t)per_cu * h->num_cus : 1024;
+        if ((M + shapes[si].rpw() - 1) / shapes[si].rpw() <= gmax) break;
+      }
       const PanelShape sh = shapes[si];
       const int64_t rpw = sh.rpw();
       const int64_t G = (M + rpw - 1) / rpw;
