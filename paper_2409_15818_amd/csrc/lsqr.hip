@@ -89,25 +89,38 @@ __global__ void __launch_bounds__(kThreads)
 
 // out[i] = sum_k part[row(i)][k] - coef * prev[i];  partial sum of squares per block.
 // nk(I) = number of chunks of tile row/column I (trans: ceil((I+1)/C), else ceil((nt-I)/C)).
+// A block handles tile rows I (64 outputs each, grid-stride); its four
+// wavefronts sum every fourth partial of each output (independent loads in
+// flight), and the four quarter sums are added in a fixed order.
+constexpr int kRedMaxBlocks = 2048;
+
 __global__ void __launch_bounds__(kThreads)
     k_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int C, int maxk, int trans,
                  double hcoef, const double* __restrict__ dcoef, const double* prev,
                  double* out, double* __restrict__ sq, const int* __restrict__ done) {
   if (done && *done) return;
   __shared__ double scratch[kThreads / 64];
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  __shared__ double quarter[kThreads / 64][kTile];
+  const int r = threadIdx.x & (kTile - 1);
+  const int q = threadIdx.x / kTile;
+  double cf = hcoef;
+  if (dcoef) cf *= *dcoef;
   double ss = 0.0;
-  if (i < n) {
-    const int64_t I = i / kTile;
-    const int r = (int)(i % kTile);
+  for (int64_t I = blockIdx.x; I < nt; I += gridDim.x) {
+    const int64_t i = I * kTile + r;
     const int64_t nk = trans ? (I + 1 + C - 1) / C : (nt - I + C - 1) / C;
     double s = 0.0;
-    for (int64_t k = 0; k < nk; ++k) s += part[(I * maxk + k) * kTile + r];
-    double cf = hcoef;
-    if (dcoef) cf *= *dcoef;
-    if (prev && cf != 0.0) s -= cf * prev[i];
-    out[i] = s;
-    ss = s * s;
+    if (i < n)
+      for (int64_t k = q; k < nk; k += kThreads / kTile) s += part[(I * maxk + k) * kTile + r];
+    quarter[q][r] = s;
+    __syncthreads();
+    if (q == 0 && i < n) {
+      double t = (quarter[0][r] + quarter[1][r]) + (quarter[2][r] + quarter[3][r]);
+      if (prev && cf != 0.0) t -= cf * prev[i];
+      out[i] = t;
+      ss += t * t;
+    }
+    __syncthreads();
   }
   if (sq) {
     ss = block_sum(ss, scratch);
@@ -383,6 +396,11 @@ static unsigned vec_blocks(int64_t len) {
   return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
 
+int tri_reduce_blocks(int64_t n) {
+  const int64_t b = ceil_div(n, kTile);
+  return (int)(b < kRedMaxBlocks ? (b > 0 ? b : 1) : kRedMaxBlocks);
+}
+
 rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, const double* in,
                        double* out, double hcoef, const double* dcoef, const double* prev,
                        double* sq, const int* done) {
@@ -415,13 +433,12 @@ rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, con
   }
   }
   Trace tr2(h, "tri_reduce", 8.0 * (double)nt * maxk * kTile + 16.0 * (double)n, 0.0);
-  hipLaunchKernelGGL(k_tri_reduce, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, st, part, nt, n,
+  hipLaunchKernelGGL(k_tri_reduce, dim3((unsigned)tri_reduce_blocks(n)), dim3(kThreads), 0, st, part, nt, n,
                      C, maxk, trans, hcoef, dcoef, prev, out, sq, done);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
 
-int tri_reduce_blocks(int64_t n) { return (int)ceil_div(n, kThreads); }
 
 static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA, double hcoef,
                          const double* dcoef, const double* prev, double* out, double* sq,
