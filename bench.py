@@ -48,14 +48,15 @@ def measured_traffic(kernel, workload, precision):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec.get("kernel") != kernel:
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
         return None
     hsh = hashlib.sha256()
     for f in rec["source_files"]:
         hsh.update(open(os.path.join(ROOT, f), "rb").read())
     if hsh.hexdigest() != rec["source_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return k["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(S, s, itn_total, threads):

@@ -23,7 +23,13 @@ constexpr int kBlk = 32;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSpmmMaxBlocks = 2048;
+constexpr int kSpmmMaxBlocks = 2048;  // capacity of the per-column partial-sum buffers
+// Producers of per-column partial sums use at most these many blocks (grid-
+// stride loops), and the single-block kernels that fold the partials into the
+// column scalars use 1024 threads (32 columns x 32 slices).
+constexpr int kSpmmBlocks = 512;
+constexpr int kRowBlocks = 256;
+constexpr int kRedThreads = 1024;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -290,18 +296,18 @@ __global__ void __launch_bounds__(kThreads)
 
 // Per-column norms from partial sums: nrm_c = sqrt(sum_b sq[b][c]) -> state field
 // (field = 0: beta, 1: alpha).  Columns already stopped keep their state.
-__global__ void __launch_bounds__(kThreads) k_blk_norms(const double* __restrict__ sq, int nsq,
+__global__ void __launch_bounds__(kRedThreads) k_blk_norms(const double* __restrict__ sq, int nsq,
                                                         BlockState* st, int field, int force) {
   if (!force && all_done(st)) return;
-  __shared__ double red[kThreads / kBlk][kBlk];
+  __shared__ double red[kRedThreads / kBlk][kBlk];
   const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
   double t = 0.0;
-  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += sq[b * kBlk + c];
+  for (int b = rsub; b < nsq; b += kRedThreads / kBlk) t += sq[b * kBlk + c];
   red[rsub][c] = t;
   __syncthreads();
   if (rsub == 0) {
     double s = 0.0;
-    for (int q = 0; q < kThreads / kBlk; ++q) s += red[q][c];
+    for (int q = 0; q < kRedThreads / kBlk; ++q) s += red[q][c];
     LsqrDev& d = st->col[c];
     if (force || !d.done) {
       if (field == 0) d.beta = sqrt(s);
@@ -403,18 +409,18 @@ __global__ void k_blk_start2(BlockState* st) {
 }
 
 // plane rotation per active column (same arithmetic as the single-column kernel)
-__global__ void __launch_bounds__(kThreads) k_blk_rotate(BlockState* st, const double* __restrict__ wsq,
+__global__ void __launch_bounds__(kRedThreads) k_blk_rotate(BlockState* st, const double* __restrict__ wsq,
                                                          int nsq) {
   if (all_done(st)) return;
-  __shared__ double red[kThreads / kBlk][kBlk];
+  __shared__ double red[kRedThreads / kBlk][kBlk];
   const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
   double t = 0.0;
-  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += wsq[b * kBlk + c];
+  for (int b = rsub; b < nsq; b += kRedThreads / kBlk) t += wsq[b * kBlk + c];
   red[rsub][c] = t;
   __syncthreads();
   if (rsub != 0) return;
   double w2 = 0.0;
-  for (int q = 0; q < kThreads / kBlk; ++q) w2 += red[q][c];
+  for (int q = 0; q < kRedThreads / kBlk; ++q) w2 += red[q][c];
   LsqrDev& d = st->col[c];
   if (d.done) {
     d.phi_rho = 0.0;
@@ -490,18 +496,18 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // consistent != 0: the system has an exact solution (backward pass), S1 is ||r|| <= btol ||b||
-__global__ void __launch_bounds__(kThreads) k_blk_check(BlockState* st, const double* __restrict__ ysq,
+__global__ void __launch_bounds__(kRedThreads) k_blk_check(BlockState* st, const double* __restrict__ ysq,
                                                         int nsq, int consistent) {
   if (all_done(st)) return;
-  __shared__ double red[kThreads / kBlk][kBlk];
+  __shared__ double red[kRedThreads / kBlk][kBlk];
   const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
   double t = 0.0;
-  for (int b = rsub; b < nsq; b += kThreads / kBlk) t += ysq[b * kBlk + c];
+  for (int b = rsub; b < nsq; b += kRedThreads / kBlk) t += ysq[b * kBlk + c];
   red[rsub][c] = t;
   __syncthreads();
   if (rsub == 0) {
     double y2 = 0.0;
-    for (int q = 0; q < kThreads / kBlk; ++q) y2 += red[q][c];
+    for (int q = 0; q < kRedThreads / kBlk; ++q) y2 += red[q][c];
     LsqrDev& d = st->col[c];
     if (!d.done) {
       d.ynorm = sqrt(y2);
@@ -588,13 +594,13 @@ unsigned grid_for(int64_t elems) {
   const int64_t b = (elems + kThreads - 1) / kThreads;
   return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
-unsigned rows_grid(int64_t rows) {  // blocks of 8 rows x 32 columns
+unsigned rows_grid(int64_t rows) {  // blocks of 8 rows x 32 columns, grid-stride beyond kRowBlocks
   const int64_t b = (rows + (kThreads / kBlk) - 1) / (kThreads / kBlk);
-  return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
+  return (unsigned)(b < kRowBlocks ? (b > 0 ? b : 1) : kRowBlocks);
 }
-unsigned spmm_grid(int64_t rows) {
+unsigned spmm_grid(int64_t rows) {  // row groups of 16, grid-stride beyond kSpmmBlocks
   const int64_t b = (rows + kGroup - 1) / kGroup;
-  return (unsigned)(b < kSpmmMaxBlocks ? (b > 0 ? b : 1) : kSpmmMaxBlocks);
+  return (unsigned)(b < kSpmmBlocks ? (b > 0 ? b : 1) : kSpmmBlocks);
 }
 
 struct BCtx {
@@ -680,7 +686,7 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
   hipLaunchKernelGGL(k_blk_copy, dim3(gm), dim3(kThreads), 0, c.st, rhs, c.U, m);
   hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(m)), dim3(kThreads), 0, c.st, (const double*)c.U, m,
                      c.sqA);
-  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA,
+  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqA,
                      (int)rows_grid(m), c.dst, 0, 1);
   hipLaunchKernelGGL(k_blk_start, dim3(1), dim3(64), 0, c.st, c.dst, o->atol, o->btol, o->conlim, itmax);
   hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, c.U, m, (const BlockState*)c.dst, 0, 1);
@@ -688,7 +694,7 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
   // alpha_1 v_1 = X^T (A^T u_1)
   RFMLS_CHECK(spmm(c, c.AT, c.U, 1.0, 0.0, nullptr, nullptr, c.Q, nullptr, nullptr, nullptr));
   RFMLS_CHECK(tri_block(c, 1, c.Q, c.V, 0.0, nullptr, nullptr, c.sqB, nullptr));
-  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+  hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqB,
                      (int)rows_grid(n), c.dst, 1, 0);
   hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, c.V, n, (const BlockState*)c.dst, 1, 0);
   hipLaunchKernelGGL(k_blk_start2, dim3(1), dim3(64), 0, c.st, c.dst);
@@ -704,18 +710,18 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
     RFMLS_CHECK(tri_block(c, 0, c.V, c.Z, 0.0, nullptr, nullptr, nullptr, cst));
     int nb = 0;
     RFMLS_CHECK(spmm(c, c.A, c.Z, 1.0, 1.0, state_field(c.dst, 1), c.U, c.U, c.sqA, cst, &nb));
-    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nb, c.dst, 0, 0);
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqA, nb, c.dst, 0, 0);
     hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, c.U, m, cst, 0, 0);
     RFMLS_CHECK(spmm(c, c.AT, c.U, 1.0, 0.0, nullptr, nullptr, c.Q, nullptr, cst, nullptr));
     RFMLS_CHECK(tri_block(c, 1, c.Q, c.V, 1.0, state_field(c.dst, 0), c.V, c.sqB, cst));
-    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqB,
                        (int)rows_grid(n), c.dst, 1, 0);
     hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, c.V, n, cst, 1, 0);
-    hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqW,
+    hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqW,
                        (int)rows_grid(n));
     hipLaunchKernelGGL(k_blk_update, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, cst,
                        (const double*)c.V, c.W, c.Y, n, c.sqY, c.sqW);
-    hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqY,
+    hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqY,
                        (int)rows_grid(n), 0);
     RFMLS_HIP(c.h, hipGetLastError());
     if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
@@ -879,7 +885,7 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
     hipLaunchKernelGGL(k_gather_block, dim3(gn), dim3(kThreads), 0, c.st, G, ldg, k0, nb, n, Gb);
     // beta_1 u_1 = X^T g
     RFMLS_CHECK(tri_block(c, 1, Gb, un, 0.0, nullptr, nullptr, c.sqB, nullptr));
-    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqB,
                        (int)rows_grid(n), c.dst, 0, 1);
     hipLaunchKernelGGL(k_blk_start, dim3(1), dim3(64), 0, c.st, c.dst, o->atol, o->btol, o->conlim, itmax);
     hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, un, n, cst, 0, 1);
@@ -888,7 +894,7 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
     RFMLS_CHECK(tri_block(c, 0, un, tmp, 0.0, nullptr, nullptr, nullptr, nullptr));
     int nbk = 0;
     RFMLS_CHECK(spmm(c, A, tmp, 1.0, 0.0, nullptr, nullptr, vm, c.sqA, nullptr, &nbk));
-    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
+    hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
     hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, vm, m, cst, 1, 0);
     hipLaunchKernelGGL(k_blk_start2, dim3(1), dim3(64), 0, c.st, c.dst);
     hipLaunchKernelGGL(k_blk_recip_scale, dim3(gn), dim3(kThreads), 0, c.st, (const double*)un, 0.0,
@@ -902,21 +908,21 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
       // beta u = X^T (A^T v) - alpha u
       RFMLS_CHECK(spmm(c, AT, vm, 1.0, 0.0, nullptr, nullptr, tmp, nullptr, cst, nullptr));
       RFMLS_CHECK(tri_block(c, 1, tmp, un, 1.0, state_field(c.dst, 1), un, c.sqB, cst));
-      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqB,
+      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqB,
                          (int)rows_grid(n), c.dst, 0, 0);
       hipLaunchKernelGGL(k_blk_scale, dim3(gn), dim3(kThreads), 0, c.st, un, n, cst, 0, 0);
       // alpha v = A (X u) - beta v;  vt = (u - beta vt) / alpha
       RFMLS_CHECK(tri_block(c, 0, un, tmp, 0.0, nullptr, nullptr, nullptr, cst));
       RFMLS_CHECK(spmm(c, A, tmp, 1.0, 1.0, state_field(c.dst, 0), vm, vm, c.sqA, cst, &nbk));
-      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
+      hipLaunchKernelGGL(k_blk_norms, dim3(1), dim3(kRedThreads), 0, c.st, (const double*)c.sqA, nbk, c.dst, 1, 0);
       hipLaunchKernelGGL(k_blk_scale, dim3(gm), dim3(kThreads), 0, c.st, vm, m, cst, 1, 0);
       hipLaunchKernelGGL(k_blk_recip_scale, dim3(gn), dim3(kThreads), 0, c.st, (const double*)un, 1.0,
                          (const double*)vt, vt, n, cst, 0);
-      hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqW,
+      hipLaunchKernelGGL(k_blk_rotate, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqW,
                          (int)rows_grid(n));
       hipLaunchKernelGGL(k_blk_update, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, cst,
                          (const double*)vt, wt, zz, n, c.sqY, c.sqW);
-      hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, (const double*)c.sqY,
+      hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqY,
                          (int)rows_grid(n), 1);
       RFMLS_HIP(h, hipGetLastError());
       if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
