@@ -283,6 +283,33 @@ def test_lockstep_multi_rhs_matches_oracle(handle, nrhs):
     assert _l2(S, Xn[0]) <= 1.1 * _l2(S, Xs[0].cpu().numpy())
 
 
+@pytest.mark.parametrize("prec", [("f64", "f32"), ("f32", "f32")])
+def test_lockstep_with_float32_preconditioner(handle, prec):
+    """Lockstep solve and backward with X = R^{-1} stored in float32 (the float32
+    triangular products on the matrix cores): residuals against the float64 oracle,
+    gradients against the one-column path on the same preconditioner."""
+    S, s, A = system("poisson2d_2x2")  # n = 200: three full tiles and a ragged one
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    AT = R.rfmls_transpose(handle, A)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, s, SEED, dtype=prec[0])[0], prec[0], prec[1])
+    pre = pipeline.precondition(S.row_ptr, S.col, S.val, S.m, S.n, s, SEED)
+    Bn = _lockstep_rhs(S, Ah, 5, 13)
+    X, Rr, info, rc = R.rfmls_solve(handle, A, AT, P, torch.tensor(Bn, device="cuda"))
+    for k in range(5):
+        if not Bn[k].any():
+            assert info[k]["itn"] == 0
+            continue
+        xo, _ = pipeline.refined_lsqr(Ah, pre["R"], Bn[k], refine=1)
+        met = pipeline.residual_metrics(Ah, xo, Bn[k])
+        assert abs(info[k]["normr"] - met["normr"]) <= 1e-10 * met["normr"], k
+    Gn = np.random.default_rng(14).standard_normal((5, S.n))
+    G = torch.tensor(Gn, device="cuda")
+    dB, dA, _, _ = R.rfmls_solve_backward(handle, A, AT, P, X, Rr, G)
+    dBs, dAs, _, _ = R.rfmls_solve_backward(handle, A, AT, P, X, Rr, G, R.default_opts(lockstep=0))
+    assert torch.linalg.norm(dB - dBs) <= 1e-8 * torch.linalg.norm(dBs)
+    assert torch.linalg.norm(dA - dAs) <= 1e-6 * torch.linalg.norm(dAs)
+
+
 def test_lockstep_column_independent_of_companions(handle):
     """Each column of a lockstep block runs its own recurrences: changing the
     other columns leaves it bitwise unchanged."""
