@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(kThreads)
 constexpr int kGroup = 16;
 constexpr int kWin = 128;
 
+template <int kGroup = rfmls::kGroup, int kWin = rfmls::kWin>
 __global__ void __launch_bounds__(kThreads)
     k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
            const double* __restrict__ val, int64_t rows, int64_t ncols, const double* __restrict__ Xin,
@@ -186,7 +187,10 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ int wmin[kGroup];
   __shared__ double red[kThreads / kBlk][kBlk];
   const int tid = threadIdx.x;
-  const int c = tid & (kBlk - 1), slot = tid / kBlk;  // slot 0..7: rows slot, slot + 8
+  constexpr int kSlots = kThreads / kBlk;  // 8 row slots of 32 columns
+  constexpr int RPS = kGroup / kSlots;      // rows per slot: slot, slot + 8, ...
+  static_assert(kGroup % kSlots == 0 && kThreads % kGroup == 0, "row group");
+  const int c = tid & (kBlk - 1), slot = tid / kBlk;
   const int er = tid / (kThreads / kGroup), el = tid % (kThreads / kGroup);  // entry staging: row er, lane el
   double cf = hcoef;
   if (coef) cf *= coef[c * cstride];
@@ -200,7 +204,9 @@ __global__ void __launch_bounds__(kThreads)
       cur[tid] = r < rows ? rp[r] : 0;
       endp[tid] = r < rows ? rp[r + 1] : 0;
     }
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[RPS];
+#pragma unroll
+    for (int h2 = 0; h2 < RPS; ++h2) acc[h2] = 0.0;
     for (;;) {
       __syncthreads();
       if (tid < kGroup) wmin[tid] = cur[tid] < endp[tid] ? col[cur[tid]] : INT32_MAX;
@@ -239,44 +245,50 @@ __global__ void __launch_bounds__(kThreads)
       }
       __syncthreads();
       {
-        // 8 entries of each of the two rows at a time: all LDS loads issued
+        // 8 entries of each of the slot's rows at a time: all LDS loads issued
         // before the (in-order) accumulation, so the loads overlap
-        const int n0 = cnt[slot], n1 = cnt[slot + 8];
-        const int nn = n0 < n1 ? n0 : n1;
+        int nr[RPS];
+        int nn = kWin;
+#pragma unroll
+        for (int h2 = 0; h2 < RPS; ++h2) {
+          nr[h2] = cnt[slot + kSlots * h2];
+          nn = nr[h2] < nn ? nr[h2] : nn;
+        }
         int j = 0;
         for (; j + 8 <= nn; j += 8) {
-          int c0[8], c1[8];
-          double v0[8], v1[8], x0[8], x1[8];
+          int cx[RPS][8];
+          double vx[RPS][8], xx[RPS][8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            c0[q] = Cs[slot][j + q];
-            c1[q] = Cs[slot + 8][j + q];
-            v0[q] = Vs[slot][j + q];
-            v1[q] = Vs[slot + 8][j + q];
-          }
+          for (int h2 = 0; h2 < RPS; ++h2)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            x0[q] = Xs[c0[q]][c];
-            x1[q] = Xs[c1[q]][c];
-          }
+            for (int q = 0; q < 8; ++q) {
+              cx[h2][q] = Cs[slot + kSlots * h2][j + q];
+              vx[h2][q] = Vs[slot + kSlots * h2][j + q];
+            }
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            acc0 += v0[q] * x0[q];
-            acc1 += v1[q] * x1[q];
-          }
+          for (int h2 = 0; h2 < RPS; ++h2)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xx[h2][q] = Xs[cx[h2][q]][c];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int h2 = 0; h2 < RPS; ++h2) acc[h2] += vx[h2][q] * xx[h2][q];
         }
-        for (int j0 = j; j0 < n0; ++j0) acc0 += Vs[slot][j0] * Xs[Cs[slot][j0]][c];
-        for (int j1 = j; j1 < n1; ++j1) acc1 += Vs[slot + 8][j1] * Xs[Cs[slot + 8][j1]][c];
+#pragma unroll
+        for (int h2 = 0; h2 < RPS; ++h2) {
+          const int t = slot + kSlots * h2;
+          for (int jj = j; jj < nr[h2]; ++jj) acc[h2] += Vs[t][jj] * Xs[Cs[t][jj]][c];
+        }
       }
       __syncthreads();
       if (tid < kGroup) cur[tid] += cnt[tid];
     }
     // write the group's rows
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      const int64_t row = r0 + slot + 8 * h2;
+    for (int h2 = 0; h2 < RPS; ++h2) {
+      const int64_t row = r0 + slot + kSlots * h2;
       if (row < rows) {
-        double o = sA * (h2 ? acc1 : acc0);
+        double o = sA * acc[h2];
         if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
         if (act) out[row * kBlk + c] = o;
         ss += o * o;
@@ -603,6 +615,21 @@ unsigned spmm_grid(int64_t rows) {  // row groups of 16, grid-stride beyond kSpm
   return (unsigned)(b < kSpmmBlocks ? (b > 0 ? b : 1) : kSpmmBlocks);
 }
 
+// SpMM shape by average row length (measured on gfx950, 32 columns): short
+// rows (the RFM matrix, 200-400 entries) share 64-wide windows among 16 rows;
+// long rows (its transpose, ~2000 entries) run 8 rows per group in 32-wide
+// windows, whose small LDS footprint gives 7 resident blocks per compute unit
+// (the kernel is latency-bound).  Grids stop at about the resident block count.
+struct SpmmShape {
+  const void* fn;
+  int group;
+  unsigned max_blocks;
+};
+SpmmShape spmm_shape(const rfmls_csr* M) {
+  if (M->m > 0 && M->nnz / M->m > 512) return {(const void*)k_spmm<8, 32>, 8, 1792};
+  return {(const void*)k_spmm<16, 64>, 16, 1024};
+}
+
 struct BCtx {
   rfmls_handle* h;
   const rfmls_csr* A;
@@ -658,13 +685,18 @@ rfmls_status tri_block(BCtx& c, int trans, const double* in, double* out, double
 rfmls_status spmm(BCtx& c, const rfmls_csr* M, const double* x, double sA, double hcoef,
                   const double* coef, const double* prev, double* out, double* sq,
                   const BlockState* stp, int* nblk) {
-  const unsigned nb = spmm_grid(M->m);
+  const SpmmShape sh = spmm_shape(M);
+  const int64_t ng = (M->m + sh.group - 1) / sh.group;
+  const unsigned nb = (unsigned)(ng < (int64_t)sh.max_blocks ? (ng > 0 ? ng : 1) : sh.max_blocks);
   Trace tr(c.h, M == c.A ? "spmm_A" : "spmm_At",
            12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) +
                8.0 * kBlk * ((double)M->n + (double)M->m * (prev ? 2.0 : 1.0)),
            2.0 * kBlk * (double)M->nnz);
-  hipLaunchKernelGGL(k_spmm, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, M->n,
-                     x, sA, hcoef, coef, kStride, prev, out, sq, stp);
+  int kStride_v = kStride;
+  void* args[] = {(void*)&M->row_ptr, (void*)&M->col, (void*)&M->val, (void*)&M->m, (void*)&M->n,
+                  (void*)&x, (void*)&sA, (void*)&hcoef, (void*)&coef, (void*)&kStride_v, (void*)&prev,
+                  (void*)&out, (void*)&sq, (void*)&stp};
+  RFMLS_HIP(c.h, hipLaunchKernel(sh.fn, dim3(nb), dim3(kThreads), args, 0, c.st));
   if (nblk) *nblk = (int)nb;
   RFMLS_HIP(c.h, hipGetLastError());
   return RFMLS_OK;
