@@ -48,31 +48,63 @@ __device__ __forceinline__ bool all_done(const BlockState* st) { return st->all_
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r holds
 // D[l / 16 + 4 r][l % 16].
 // ---------------------------------------------------------------------------
+// Z = X V for a 64-row tile row: each 64 x 64 tile of X is staged in LDS with
+// coalesced loads (the next tile prefetched into registers meanwhile), as is
+// the matching 64 x 32 block of V; the MFMA operands are then read from LDS.
+// Reading the A operand (16 rows x 4 columns per instruction) straight from
+// HBM would fetch 32-byte pieces of 16 different rows per load.
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
     k_trmm_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
                 int C, int maxk, const double* __restrict__ V, double* __restrict__ part,
                 const BlockState* __restrict__ st) {
   if (st && all_done(st)) return;
+  constexpr int kPer = kTile * kTile / kThreads;  // 16 X elements per thread per tile
+  __shared__ TS Xs[kTile][kTile + 1];
+  __shared__ double Vs[kTile][kBlk + 1];
   const int2 e = tab[blockIdx.x];
   const int64_t I = e.x;
   const int k = e.y;
   const int64_t J0 = I + (int64_t)k * C;
   const int64_t J1 = J0 + C < nt ? J0 + C : nt;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  TS xr[kPer];
+  double vr[kTile * kBlk / kThreads];  // 8 V elements per thread
+  auto fetch = [&](int64_t J) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) xr[q] = t[tid + q * kThreads];
+#pragma unroll
+    for (int q = 0; q < kTile * kBlk / kThreads; ++q) {
+      const int idx = tid + q * kThreads;  // (row, col) = (idx / 32, idx % 32)
+      const int64_t r = J * kTile + idx / kBlk;
+      vr[q] = r < n ? V[r * kBlk + (idx % kBlk)] : 0.0;
+    }
+  };
+  if (J0 < J1) fetch(J0);
   for (int64_t J = J0; J < J1; ++J) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile) + (16 * w + lr) * kTile;
-#pragma unroll 4
-    for (int s = 0; s < kTile / 4; ++s) {
-      const int kk = 4 * s + lk;
-      const double a = (double)t[kk];
-      const int64_t vr = J * kTile + kk;
-      const double b0 = vr < n ? V[vr * kBlk + lr] : 0.0;
-      const double b1 = vr < n ? V[vr * kBlk + 16 + lr] : 0.0;
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int idx = tid + q * kThreads;
+      Xs[idx / kTile][idx % kTile] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kTile * kBlk / kThreads; ++q) {
+      const int idx = tid + q * kThreads;
+      Vs[idx / kBlk][idx % kBlk] = vr[q];
+    }
+    __syncthreads();
+    if (J + 1 < J1) fetch(J + 1);
+#pragma unroll
+    for (int s4 = 0; s4 < kTile / 4; ++s4) {
+      const int kk = 4 * s4 + lk;
+      const double a = (double)Xs[16 * w + lr][kk];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vs[kk][lr], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vs[kk][16 + lr], acc1, 0, 0, 0);
     }
   }
   double* o = part + ((int64_t)I * maxk + k) * (kTile * kBlk);
@@ -84,31 +116,60 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// P = X^T Q for a 64-column tile column J: tiles I in [k C, min((k+1) C, J+1)),
+// staged in LDS like k_trmm_part (the operand is the tile read transposed).
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
     k_trmmT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
                  int C, int maxk, const double* __restrict__ Qv, double* __restrict__ part,
                  const BlockState* __restrict__ st) {
   if (st && all_done(st)) return;
+  constexpr int kPer = kTile * kTile / kThreads;
+  __shared__ TS Xs[kTile][kTile + 1];
+  __shared__ double Qs[kTile][kBlk + 1];
   const int2 e = tab[blockIdx.x];
   const int64_t J = e.x;
   const int k = e.y;
   const int64_t I0 = (int64_t)k * C;
   const int64_t I1 = I0 + C < J + 1 ? I0 + C : J + 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  TS xr[kPer];
+  double qr[kTile * kBlk / kThreads];
+  auto fetch = [&](int64_t I) {
+    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) xr[q] = t[tid + q * kThreads];
+#pragma unroll
+    for (int q = 0; q < kTile * kBlk / kThreads; ++q) {
+      const int idx = tid + q * kThreads;
+      const int64_t r = I * kTile + idx / kBlk;
+      qr[q] = r < n ? Qv[r * kBlk + (idx % kBlk)] : 0.0;
+    }
+  };
+  if (I0 < I1) fetch(I0);
   for (int64_t I = I0; I < I1; ++I) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile) + 16 * w + lr;
-#pragma unroll 4
-    for (int s = 0; s < kTile / 4; ++s) {
-      const int kk = 4 * s + lk;  // row of the X tile = column of X^T
-      const double a = (double)t[kk * kTile];
-      const int64_t qr = I * kTile + kk;
-      const double b0 = qr < n ? Qv[qr * kBlk + lr] : 0.0;
-      const double b1 = qr < n ? Qv[qr * kBlk + 16 + lr] : 0.0;
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int idx = tid + q * kThreads;
+      Xs[idx / kTile][idx % kTile] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kTile * kBlk / kThreads; ++q) {
+      const int idx = tid + q * kThreads;
+      Qs[idx / kBlk][idx % kBlk] = qr[q];
+    }
+    __syncthreads();
+    if (I + 1 < I1) fetch(I + 1);
+#pragma unroll
+    for (int s4 = 0; s4 < kTile / 4; ++s4) {
+      const int kk = 4 * s4 + lk;  // row of the X tile = column of X^T
+      const double a = (double)Xs[kk][16 * w + lr];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Qs[kk][lr], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Qs[kk][16 + lr], acc1, 0, 0, 0);
     }
   }
   double* o = part + ((int64_t)J * maxk + k) * (kTile * kBlk);
