@@ -327,6 +327,23 @@ def test_lockstep_column_independent_of_companions(handle):
     assert torch.equal(X1[2], X2[2]) and i1[2]["itn"] == i2[2]["itn"]
 
 
+@pytest.mark.parametrize("m,n,s", [(50, 1, 2), (40, 5, 10), (300, 70, 300), (12, 3, 40)])
+def test_solve_small_dense_systems(handle, m, n, s):
+    """The whole pipeline on tiny dense systems (one column; fewer columns than a tile;
+    a 70-column system, one full tile and a ragged one; a sketch with more rows
+    than A) against numpy's least-squares solution."""
+    Ad = dense_with_condition(m, n, 1e3, seed=41)
+    b = np.random.default_rng(42).standard_normal(m)
+    rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+    A = gpu_csr(rp, col, val, m, n)
+    res = R.csqrp_lsqr(handle, A, torch.tensor(b, device="cuda"), s, 1)
+    x_ref = np.linalg.lstsq(Ad, b, rcond=None)[0]
+    r_ref = np.linalg.norm(b - Ad @ x_ref)
+    assert res.status == 0
+    assert abs(res.info[0]["normr"] - r_ref) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(res.x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
 def test_degenerate_right_hand_sides(handle):
     S, s, A = system("poisson2d_2x2")
     AT = R.rfmls_transpose(handle, A)
