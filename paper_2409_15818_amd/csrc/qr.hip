@@ -8,12 +8,10 @@
 //
 // Inner panel at column p0 (M = s - p0 rows):
 //   k_qr_panel   unblocked Householder on the M x 64 panel, spread over G
-//                co-resident workgroups (rows held in LDS); each column needs one
-//                grid-wide reduction of sigma = sum_{i>j} a_ij^2, d_c = sum_{i>j}
-//                a_ij a_ic and the pivot row, after which every workgroup forms
-//                the same reflector (LAPACK dlarfg convention: beta = -sign(alpha)
-//                ||(alpha, x)||, tau = (beta - alpha)/beta, v = [1; x/(alpha-beta)])
-//                and applies it to its rows;
+//                co-resident workgroups (rows held in registers); each column
+//                needs one grid-wide sum of sigma = sum_{i>j} a_ij^2, d_c =
+//                sum_{i>j} a_ij a_ic and the pivot row, after which every
+//                workgroup forms the same reflector and applies it to its rows;
 //   inside the outer block: W = V^T [V | C] (split-K GEMM), T from V^T V
 //                (dlarft, forward, columnwise), C <- C - V (T^T W).
 // Outer block at column k0 (M0 = s - k0 rows, V_o = its 256 Householder vectors):
@@ -29,129 +27,86 @@ namespace {
 
 constexpr int kMaxNb = 64;
 
-// Grid-wide sum of one payload vector per block, returned to every block.
-// Two levels keep both the serialised atomics and the reads short: blocks are
-// grouped in clusters of kCluster; the last block to arrive in a cluster sums
-// its cluster's payloads (in block order) and arrives at the global counter;
-// the last cluster leader sums the cluster sums (in cluster order), publishes
-// the result and bumps a generation word that every block waits for.  All
-// sums run in a fixed order, so every block receives bit-identical values.
-//   pw   [G][kPayload]      block payloads (written by the caller before the call)
-//   cw   [nclus][kPayload]  cluster sums
-//   out  [2][kPayload]      published result, double-buffered by epoch parity
-//   cnt  [(nclus + 2) * kBarrierStride]  cluster counters, global counter and
-//                           generation word, each on its own cache line
-// Counters only grow; epoch e (0, 1, ...) numbers the calls within one launch.
-//
-// Memory ordering: every word that crosses blocks (payloads, cluster sums, the
-// result, counters) is written and read with relaxed agent-scope atomics,
-// which are coherent across the XCDs' separate L2 caches; each writer waits
-// for its stores to complete (s_waitcnt) before the counter update or flag
-// store that publishes them.  Release/acquire fences would do the same but
-// also write back and invalidate the whole L2 of the XCD at every step, which
-// made the reduction cost grow linearly with the number of blocks.
-constexpr int kCluster = 16;
-constexpr int kPayload = 2 * kMaxNb;
-
-__device__ __forceinline__ void st_coh(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Cross-block exchange of the panel kernel.  Every value crosses blocks in a
+// "low-latency" slot: the float64 travels as two 64-bit words (its low or high
+// 32 bits, and a tag in the upper 32 bits), each written and read with one
+// relaxed agent-scope atomic, which is coherent across the XCDs' separate L2
+// caches.  A reader accepts the value once both words carry the tag it
+// expects, so no flag, counter or store-completion wait sits on the critical
+// path: a hand-over costs one store propagation plus one load round trip.
+// Tags are the column index + 1; the slots are zeroed before every launch.
+__device__ __forceinline__ void ll_put(uint64_t* slot, double v, unsigned tag) {
+  const uint64_t x = (uint64_t)__double_as_longlong(v);
+  const uint64_t t = (uint64_t)tag << 32;
+  __hip_atomic_store(&slot[0], (x & 0xffffffffull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&slot[1], (x >> 32) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_coh(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// wait until every memory operation this thread issued has completed
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
-
-__device__ bool grid_allreduce(const double* pw, double* cw, double* out, unsigned* cnt, int lo,
-                               int hi, unsigned epoch, double* red, int* err) {
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
-  const int nclus = (G + kCluster - 1) / kCluster;
-  const int cl = g / kCluster;
-  const int csize = (cl == nclus - 1) ? G - cl * kCluster : kCluster;
-  unsigned* gcount = cnt + (int64_t)nclus * kBarrierStride;
-  unsigned* gen = cnt + (int64_t)(nclus + 1) * kBarrierStride;
-  __shared__ int role;  // 0: wait, 1: cluster leader, 2: global leader
-  __shared__ int ok;
-  wait_stores();  // this block's payload stores (st_coh by the caller) are complete
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    const unsigned old = __hip_atomic_fetch_add(&cnt[(int64_t)cl * kBarrierStride], 1u,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    role = (old == (epoch + 1) * (unsigned)csize - 1u) ? 1 : 0;
-  }
-  __syncthreads();
-  if (role == 1) {
-    for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
-      // issue all loads before summing (one memory round trip, not kCluster)
-      double v[kCluster];
-#pragma unroll
-      for (int q = 0; q < kCluster; ++q)
-        v[q] = q < csize ? ld_coh(&pw[(int64_t)(cl * kCluster + q) * kPayload + k]) : 0.0;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kCluster; ++q) s += v[q];
-      st_coh(&cw[(int64_t)cl * kPayload + k], s);
-    }
-    wait_stores();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned old =
-          __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == (epoch + 1) * (unsigned)nclus - 1u) role = 2;
-    }
-    __syncthreads();
-    if (role == 2) {
-      double* o = out + (int64_t)(epoch & 1u) * kPayload;
-      for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) {
-        double s = 0.0;
-        for (int c0 = 0; c0 < nclus; c0 += kCluster) {
-          double v[kCluster];
-#pragma unroll
-          for (int q = 0; q < kCluster; ++q)
-            v[q] = c0 + q < nclus ? ld_coh(&cw[(int64_t)(c0 + q) * kPayload + k]) : 0.0;
-#pragma unroll
-          for (int q = 0; q < kCluster; ++q) s += v[q];
-        }
-        st_coh(&o[k], s);
-      }
-      wait_stores();
-      __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_store(gen, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  if (threadIdx.x == 0) {
-    int spins = 0;
-    while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch + 1u) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1 << 26)) {
-        ok = 0;
-        atomicExch(err, 1);
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  if (!ok) return false;
-  const double* o = out + (int64_t)(epoch & 1u) * kPayload;
-  for (int k = lo + (int)threadIdx.x; k < hi; k += blockDim.x) red[k] = ld_coh(&o[k]);
-  __syncthreads();
+// Wait (bounded) for the value tagged `tag`; on time-out flag the error, clear
+// the block's `ok` and return 0.
+__device__ __forceinline__ bool ll_try(uint64_t* p, unsigned tag, double* v) {
+  const uint64_t a = __hip_atomic_load(&p[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t b = __hip_atomic_load(&p[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((unsigned)(a >> 32) != tag || (unsigned)(b >> 32) != tag) return false;
+  *v = __longlong_as_double((long long)((a & 0xffffffffull) | (b << 32)));
   return true;
 }
+constexpr int kSpinLimit = 1 << 20;
+__device__ __forceinline__ double ll_wait(const uint64_t* slot, unsigned tag, int* err, int* ok) {
+  uint64_t* p = const_cast<uint64_t*>(slot);
+  double v = 0.0;
+  for (int spins = 0; !ll_try(p, tag, &v); ++spins) {
+    if (spins > kSpinLimit) {
+      atomicExch(err, 1);
+      *ok = 0;
+      return 0.0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return v;
+}
+// Two values polled together (one round trip per attempt for both).
+__device__ __forceinline__ void ll_wait2(const uint64_t* s0, const uint64_t* s1, unsigned tag,
+                                         double* v0, double* v1, int* err, int* ok) {
+  uint64_t* p0 = const_cast<uint64_t*>(s0);
+  uint64_t* p1 = const_cast<uint64_t*>(s1);
+  bool d0 = false, d1 = false;
+  for (int spins = 0;; ++spins) {
+    if (!d0) d0 = ll_try(p0, tag, v0);
+    if (!d1) d1 = ll_try(p1, tag, v1);
+    if (d0 && d1) return;
+    if (spins > kSpinLimit) {
+      atomicExch(err, 1);
+      *ok = 0;
+      *v0 = *v1 = 0.0;
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 
-// Payload of column j (length 2 (nb - j)): entry c - j for c in [j, nb) holds
-// sigma (c == j) or d_c (c > j); entry (nb - j) + (c - j) holds the pivot row
-// value a_jc (only the block owning row j contributes, the others add 0).
+// Unblocked Householder QR of an M x nb panel (nb <= 64) spread over G
+// co-resident workgroups of NT = 1024 threads (16 wavefronts), one per CU.
+// Thread (c = lane, rg = wavefront) of block g holds rows
+// r0 + rg + 16 q (q < Q, r0 = g rpw, rpw = 16 Q) of column c in registers;
+// all lanes of a wavefront hold the same rows, so column j reaches every lane
+// by v_readlane from lane j (no LDS).  Block 0 holds rows 0 .. rpw-1 >= nb-1.
 //
-// Each block (NT threads, NG = NT / 64 wavefronts) owns rpw <= NG Q consecutive
-// panel rows and keeps them in registers: thread (c = lane, rg = wavefront)
-// holds a[q] = P[r0 + rg + NG q][c].
-// All threads of a wavefront hold the same rows, so column j reaches every
-// lane of the wavefront by v_readlane from lane j (scalar registers, no LDS).
-// Few, large blocks keep the per-column grid reduction short (its cost grows
-// with the number of blocks).
+// Column j needs one grid-wide sum: sigma = sum_{i>j} a_ij^2 and
+// d_c = sum_{i>j} a_ij a_ic (c > j), plus the pivot row a_jc from block 0.
+// Each block publishes its partial sums (slots r1[j&1][c][g]) and block 0 the
+// pivot row (rp[j&1][c]).  With G >= 64 blocks, block c sums the G partials of
+// column c (each of its first G threads waits for one, then a fixed-order
+// wavefront tree and an ordered sum of the wavefront results) and publishes
+// the total (r2[j&1][c]); every block then reads the nb - j totals.  With
+// fewer blocks every block sums all G partials itself (16 threads per column,
+// each over blocks p, p + 16, ..., then those 16 partial sums in order).  Every
+// block thus receives bit-identical totals and forms the same reflector (LAPACK
+// dlarfg convention: beta = -sign(alpha) ||(alpha, x)||, tau = (beta -
+// alpha)/beta, v = [1; x/(alpha-beta)]), computed once per block by the thread
+// of column j, and applies it to its rows.  Slots of column j are reused by
+// column j + 2 only: a block can publish column j + 2 only after every block
+// has published column j + 1, which each does after reading column j.
+//   ll  slots, 16 bytes each: r1 [2][64][G], rp [2][64], r2 [2][64]
 
 __device__ __forceinline__ double lane_value(double v, int lane) {
   const long long x = __double_as_longlong(v);
@@ -163,14 +118,22 @@ __device__ __forceinline__ double lane_value(float v, int lane) {
   return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <typename T, int Q, int NT>
-__global__ void __launch_bounds__(NT)
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelGroups = kPanelThreads / 64;  // wavefronts per block
+constexpr int kPanelMaxBlocks = kPanelThreads;    // a reducer thread per block
+__host__ __device__ constexpr int64_t ll_words(int64_t G) { return 2 * (2 * kMaxNb * G + 4 * kMaxNb); }
+
+template <typename T, int Q>
+__global__ void __launch_bounds__(kPanelThreads)
     k_qr_panel(T* __restrict__ P, int64_t ld, int64_t M, int nb, int rpw, T* __restrict__ tau,
-               double* __restrict__ ws, unsigned* __restrict__ cnt, int* __restrict__ err) {
-  constexpr int kPanelGroups = NT / 64;
-  __shared__ double red[kPayload];              // reduced payload
-  __shared__ double grp[kPanelGroups][kMaxNb];  // per row-group partials
-  __shared__ double piv[kMaxNb];                // pivot row (owner block)
+               uint64_t* __restrict__ ll, int* __restrict__ err) {
+  static_assert(kPanelGroups * Q >= kMaxNb, "block 0 must hold the panel's top rows");
+  __shared__ double red[2 * kMaxNb];               // totals, then the pivot row
+  __shared__ double grp[kPanelGroups][kMaxNb];     // per-wavefront partials
+  __shared__ double part[kPanelGroups][kMaxNb];    // partial sums of the totals
+  __shared__ double piv[kMaxNb];                   // pivot row (block 0)
+  __shared__ double refl[3];                       // beta, tau, 1/(alpha - beta)
+  __shared__ int ok;
   const int G = gridDim.x;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
@@ -178,23 +141,29 @@ __global__ void __launch_bounds__(NT)
   const int rg = tid >> 6;  // wavefront index: uniform within a wavefront
   const int64_t r0 = (int64_t)g * rpw;
   const int nr = (int)(M - r0 < rpw ? (M - r0 > 0 ? M - r0 : 0) : rpw);
-  const int nclus = (G + kCluster - 1) / kCluster;
-  double* pw = ws;                               // [G][kPayload]
-  double* cw = ws + (int64_t)G * kPayload;       // [nclus][kPayload]
-  double* out = cw + (int64_t)nclus * kPayload;  // [2][kPayload]
+  uint64_t* r1 = ll;                                // [2][kMaxNb][G] slots
+  uint64_t* rp = ll + 2 * (2 * kMaxNb * (int64_t)G);  // [2][kMaxNb]
+  uint64_t* r2 = rp + 2 * (2 * kMaxNb);               // [2][kMaxNb]
+  if (tid == 0) ok = 1;
 
   // rows beyond the panel are held as zeros and contribute nothing
   T a[Q];
+  const int64_t rstep = (int64_t)kPanelGroups * ld;  // between a thread's rows
+  {
+    const T* pr = P + (r0 + rg) * ld + c;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int li = rg + kPanelGroups * q;
-    a[q] = (li < nr && c < nb) ? P[(r0 + li) * ld + c] : T(0);
+    for (int q = 0; q < Q; ++q, pr += rstep) {
+      const int li = rg + kPanelGroups * q;
+      a[q] = (li < nr && c < nb) ? *pr : T(0);
+    }
   }
 
+  const bool top = (g == 0);
   for (int j = 0; j < nb; ++j) {
-    // Only block 0 (rows 0 .. rpw-1, rpw >= 128 >= nb) holds rows i <= j; in
-    // every other block all rows take part.  li > j is uniform per wavefront.
-    const bool top = (g == 0);
+    const unsigned tag = (unsigned)j + 1u;
+    const int par = j & 1;
+    const int L = nb - j;
+    // Only block 0 holds rows i <= j (li > j is uniform per wavefront).
     if (top && rg == (j % kPanelGroups)) {  // pivot row j lives in this wavefront
       const int qj = j / kPanelGroups;
       double pv = 0.0;
@@ -207,36 +176,74 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int li = rg + kPanelGroups * q;
-      if (!top || li > j) s += lane_value(a[q], j) * (double)a[q];
+      // rows li >= kMaxNb > j always take part (compile-time for large q)
+      if (kPanelGroups * q >= kMaxNb || !top || li > j) s += lane_value(a[q], j) * (double)a[q];
     }
     grp[rg][c] = s;
     __syncthreads();
-    const int L = nb - j;
     if (tid < 64 && c >= j && c < nb) {
       double t = 0.0;
 #pragma unroll
       for (int q = 0; q < kPanelGroups; ++q) t += grp[q][c];
-      double* my = pw + (int64_t)g * kPayload;
-      st_coh(&my[c - j], t);
-      st_coh(&my[L + c - j], top ? piv[c] : 0.0);
+      ll_put(&r1[2 * (((int64_t)par * kMaxNb + c) * G + g)], t, tag);
+      if (top) ll_put(&rp[2 * (par * kMaxNb + c)], piv[c], tag);
     }
-    if (!grid_allreduce(pw, cw, out, cnt, 0, 2 * L, (unsigned)j, red, err)) return;
-    // ---- reflector (identical in every block) ----
-    const double alpha = red[L];
-    const double sigma = red[0];
-    double beta, tj, scal;
-    if (sigma == 0.0) {
-      beta = alpha;
-      tj = 0.0;
-      scal = 0.0;
+    // ---- totals ----
+    double tot = 0.0;  // thread c (< 64): total of column c
+    if (G >= kMaxNb) {
+      if (g >= j && g < nb) {  // this block sums column g (block-uniform branch)
+        double v = 0.0;
+        if (tid < G) v = ll_wait(&r1[2 * (((int64_t)par * kMaxNb + g) * G + tid)], tag, err, &ok);
+        v = wave_sum(v);
+        if (c == 0) part[rg][0] = v;
+        __syncthreads();
+        if (tid == 0) {
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < kPanelGroups; ++q) t += part[q][0];
+          ll_put(&r2[2 * (par * kMaxNb + g)], t, tag);
+        }
+      }
     } else {
-      const double nrm = sqrt(alpha * alpha + sigma);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tj = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
+      if (c >= j && c < nb) {
+        double t = 0.0;
+        for (int gg = rg; gg < G; gg += kPanelGroups)
+          t += ll_wait(&r1[2 * (((int64_t)par * kMaxNb + c) * G + gg)], tag, err, &ok);
+        part[rg][c] = t;
+      }
+      __syncthreads();
+      if (tid < 64 && c >= j && c < nb) {
+#pragma unroll
+        for (int q = 0; q < kPanelGroups; ++q) tot += part[q][c];
+      }
     }
-    if (g == 0 && tid == 0) tau[j] = (T)tj;
+    if (tid < 64 && c >= j && c < nb) {
+      double pc;
+      if (G >= kMaxNb)
+        ll_wait2(&r2[2 * (par * kMaxNb + c)], &rp[2 * (par * kMaxNb + c)], tag, &tot, &pc, err, &ok);
+      else
+        pc = ll_wait(&rp[2 * (par * kMaxNb + c)], tag, err, &ok);
+      red[c - j] = tot;
+      red[L + c - j] = pc;
+      if (c == j) {  // the reflector, once per block
+        const double alpha = pc, sigma = tot;
+        double beta = alpha, tj = 0.0, scal = 0.0;
+        if (sigma != 0.0) {
+          const double nrm = sqrt(alpha * alpha + sigma);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tj = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        refl[0] = beta;
+        refl[1] = tj;
+        refl[2] = scal;
+        if (top) tau[j] = (T)tj;
+      }
+    }
+    __syncthreads();
+    if (!ok) return;  // a partner block did not answer (error flag set)
     // ---- apply H_j to rows i >= j of columns c > j; column j becomes v ----
+    const double beta = refl[0], tj = refl[1], scal = refl[2];
     const bool upd = (c > j && c < nb && tj != 0.0);
     const double f = upd ? tj * (red[L + c - j] + scal * red[c - j]) : 0.0;
     const double sf = scal * f;
@@ -244,7 +251,7 @@ __global__ void __launch_bounds__(NT)
     for (int q = 0; q < Q; ++q) {
       const int li = rg + kPanelGroups * q;
       const double vj = lane_value(a[q], j);  // read before lane j rewrites it
-      if (!top || li > j) {
+      if (kPanelGroups * q >= kMaxNb || !top || li > j) {
         if (upd) a[q] = (T)((double)a[q] - sf * vj);
         else if (c == j) a[q] = (T)(scal * vj);
       } else if (li == j) {
@@ -252,12 +259,17 @@ __global__ void __launch_bounds__(NT)
         else if (c == j) a[q] = (T)beta;
       }
     }
-    __syncthreads();
+    // no barrier here: the next writes of red, refl and part follow the next
+    // column's first __syncthreads, and piv / grp are not read after this point
   }
+  T* pw_row = P + (r0 + rg) * ld + c;
+  // an opaque copy: otherwise the compiler reuses the Q row addresses of the
+  // initial loads here and keeps them alive (spilled) across the whole kernel
+  asm volatile("" : "+v"(pw_row));
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < Q; ++q, pw_row += rstep) {
     const int li = rg + kPanelGroups * q;
-    if (li < nr && c < nb) P[(r0 + li) * ld + c] = a[q];
+    if (li < nr && c < nb) *pw_row = a[q];
   }
 }
 
@@ -353,36 +365,51 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+__global__ void k_zero_u64(uint64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 constexpr int64_t kOuter = 256;
 
-// Panel launch shapes in increasing rows per block; a float64 row entry takes
-// two VGPRs.  The largest shapes are the largest that compile without spills
-// (NT / 256 wavefronts per SIMD).
+// Panel launch shapes (rows per thread Q, rows per block 16 Q), increasing.
+// The largest are the largest that compile without spills at 1024 threads.
 struct PanelShape {
-  int nt, q;
+  int q;
   const void* fn;
-  int64_t rpw() const { return (int64_t)(nt / 64) * q; }
+  int64_t rpw() const { return (int64_t)kPanelGroups * q; }
 };
 template <typename T>
-const PanelShape* panel_shapes();
-template <>
-const PanelShape* panel_shapes<double>() {
-  static const PanelShape s[] = {{512, 16, (const void*)k_qr_panel<double, 16, 512>},
-                                 {512, 32, (const void*)k_qr_panel<double, 32, 512>},
-                                 {0, 0, nullptr}};
+const PanelShape* panel_shapes() {
+  static const PanelShape s[] = {{4, (const void*)k_qr_panel<T, 4>},
+                                 {8, (const void*)k_qr_panel<T, 8>},
+                                 {16, (const void*)k_qr_panel<T, 16>},
+                                 {32, (const void*)k_qr_panel<T, 32>},
+                                 {0, nullptr}};
   return s;
 }
-template <>
-const PanelShape* panel_shapes<float>() {
-  static const PanelShape s[] = {{512, 16, (const void*)k_qr_panel<float, 16, 512>},
-                                 {512, 32, (const void*)k_qr_panel<float, 32, 512>},
-                                 {512, 64, (const void*)k_qr_panel<float, 64, 512>},
-                                 {0, 0, nullptr}};
-  return s;
+
+// The smallest shape whose grid (G = ceil(M / rows per block)) fits one block
+// per CU: fewer rows per thread means less arithmetic per column on the
+// critical path, and one block per CU keeps the SIMDs' shares equal (two
+// blocks on some CUs would double their work per column).
+template <typename T>
+rfmls_status pick_panel_shape(rfmls_handle* h, int64_t M, PanelShape* out, int64_t* G_out) {
+  for (const PanelShape* sh = panel_shapes<T>(); sh->q != 0; ++sh) {
+    int per_cu = 0;
+    RFMLS_HIP(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sh->fn, kPanelThreads, 0));
+    int64_t gmax = per_cu >= 1 ? (int64_t)h->num_cus : 0;
+    if (gmax > kPanelMaxBlocks) gmax = kPanelMaxBlocks;
+    const int64_t G = (M + sh->rpw() - 1) / sh->rpw();
+    if (G <= gmax) {
+      *out = *sh;
+      *G_out = G;
+      return RFMLS_OK;
+    }
+  }
+  return fail(h, RFMLS_E_ARG, "QR panel of %lld rows does not fit one co-resident grid",
+              (long long)M);
 }
 
 template <typename T>
@@ -437,8 +464,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
   const int64_t nsp_out_max = (s + split_out - 1) / split_out;
   void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
   RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuter, &p_tau));
-  RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(double) * kPayload * (1024 + 1024 / kCluster + 2 + 8),
-                        &p_part));
+  RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
   const size_t wz_in = (size_t)nsp_in_max * kMaxNb * kOuter;
   const size_t wz_out = (size_t)nsp_out_max * kOuter * (size_t)n;
   RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * (wz_in > wz_out ? wz_in : wz_out), &p_wz));
@@ -458,35 +484,25 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
     for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
       const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
       const int64_t M = s - p0;
-      // rows per block rpw = (NT / 64) Q: the smallest shape whose grid is
-      // co-resident (fewer rows per thread = less arithmetic per column; the
-      // grid reduction costs about the same for any G), else the largest one
-      const PanelShape* shapes = panel_shapes<T>();
-      int si = 0;
-      for (;; ++si) {
-        if (shapes[si + 1].q == 0) break;
-        int per_cu = 0;
-        RFMLS_HIP(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, shapes[si].fn, shapes[si].nt, 0));
-        const int64_t gmax = (int64_t)per_cu * h->num_cus < 1024 ? (int64_t)per_cu * h->num_cus : 1024;
-        if ((M + shapes[si].rpw() - 1) / shapes[si].rpw() <= gmax) break;
-      }
-      const PanelShape sh = shapes[si];
+      PanelShape sh;
+      int64_t G = 0;
+      RFMLS_CHECK(pick_panel_shape<T>(h, M, &sh, &G));
       const int64_t rpw = sh.rpw();
-      const int64_t G = (M + rpw - 1) / rpw;
-      if (G > 1024)
-        return fail(h, RFMLS_E_ARG, "QR panel of %lld rows needs more than 1024 blocks", (long long)M);
       T* P = SA + p0 * ld + p0;
       T* tau_p = tau + (p0 - k0);
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, h->barrier, kBarrierWords);
+      uint64_t* ll = (uint64_t*)p_part;
+      const int64_t nll = ll_words(G);
+      hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nll, 256) < 512 ? ceil_div(nll, 256) : 512), dim3(256),
+                         0, st, ll, nll);
       int rpw_i = (int)rpw;
-      void* args[] = {(void*)&P, (void*)&ld, (void*)&M, (void*)&jb, (void*)&rpw_i, (void*)&tau_p,
-                      (void*)&p_part, (void*)&h->barrier, (void*)&h->dev_flags};
+      void* args[] = {(void*)&P,     (void*)&ld, (void*)&M,  (void*)&jb,
+                      (void*)&rpw_i, (void*)&tau_p, (void*)&ll, (void*)&h->dev_flags};
       const void* fn = sh.fn;
       {
         // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
         const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
         Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
-        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(sh.nt), args, 0, st));
+        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
       }
       const int64_t rem = k0 + bw - (p0 + jb);
       if (rem <= 0) continue;
