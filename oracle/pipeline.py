@@ -15,6 +15,13 @@ problems; the reading adopted here recovers it with iterative refinement: after
 a sweep, the true residual r = b - A x is recomputed and the same preconditioned
 LSQR solves min ||A d - r||, x <- x + d (`refine` extra sweeps, default 1).
 
+Starting point (Alg. 1 takes y^(0) as an input).  Sec. 4.1 starts from zero;
+Remark 3.1 offers y^(0) = Q^T (S b), obtained by carrying S b through the
+Householder QR as an extra column of [SA | Sb]: the top n entries of that
+column of the triangular factor are Q^T (S b), and x^(0) = R^{-1} y^(0) is the
+minimiser of ||S (A x - b)|| (`sketched_start`).  A sweep from a non-zero x
+solves for the correction from the residual b - A x, as the refinement sweeps do.
+
 Reported: iterations, the true residual ||b - A x|| / ||b|| recomputed from x,
 the normal-equation residual ||A^T r|| / (||A||_F ||r||), and ||r||^2/||b||^2
 (the paper's squared "relative least squares error", Sec. 4.1).
@@ -98,11 +105,29 @@ def l2_error(E, x, u_exact):
     return float(np.linalg.norm(uh - u_exact) / np.linalg.norm(u_exact))
 
 
-def refined_lsqr(A, R, b, refine=1, **kw):
-    """LSQR sweeps with iterative refinement on the true residual; returns (x, [results])."""
+def sketched_start(SA, SB, check_rank=True):
+    """Remark 3.1: Householder QR of [SA | SB] (SB: s x k sketched right-hand
+    sides, in SA's dtype).  Returns (R, Y0, X0): R the n x n factor of SA (diag
+    > 0), Y0 = Q^T SB (its top n x k block of the extended factor, with R's row
+    signs) and X0 = R^{-1} Y0, the minimisers of ||SA x - SB[:, k]||."""
+    SA = np.asarray(SA)
+    SB = np.asarray(SB, SA.dtype).reshape(SA.shape[0], -1)
+    n = SA.shape[1]
+    Rx = qr.r_factor(np.hstack([SA, SB]), check_rank=False)
+    R = Rx[:n, :n].astype(np.float64)
+    if check_rank and not qr.rank_ok(Rx[:n, :n]):
+        raise qr.RankDeficient("R has a pivot below 16*u*max|r_jj|")
+    Y0 = Rx[:n, n:].astype(np.float64)
+    X0 = sla.solve_triangular(R, Y0, lower=False)
+    return R, Y0, X0
+
+
+def refined_lsqr(A, R, b, refine=1, x0=None, **kw):
+    """LSQR sweeps with iterative refinement on the true residual, from x = 0
+    or from x0; returns (x, [results])."""
     b = np.asarray(b, np.float64)
-    x = np.zeros(A.shape[1])
-    r = b.copy()
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
+    r = b.copy() if x0 is None else b - A @ x
     results = []
     for sweep in range(1 + refine):
         dx, res = lsqr_on_preconditioned(A, R, r, **kw)
@@ -115,16 +140,30 @@ def refined_lsqr(A, R, b, refine=1, **kw):
 
 
 def solve(row_ptr, col, val, b, m, n, s, seed, atol=1e-10, btol=1e-10, conlim=1e8, itmax=None,
-          qr_dtype="f64", r_store="f64", operator="implicit", refine=1, keep_history=False):
-    """Full CSQRP-LSQR for one right-hand side; returns a dict of results."""
-    pre = precondition(row_ptr, col, val, m, n, s, seed, qr_dtype=qr_dtype, r_store=r_store)
+          qr_dtype="f64", r_store="f64", operator="implicit", refine=1, keep_history=False,
+          start="zero"):
+    """Full CSQRP-LSQR for one right-hand side (start "zero": y^(0) = 0, Sec. 4.1;
+    "sketch": y^(0) = Q^T (S b), Remark 3.1); returns a dict of results."""
+    pre = precondition(row_ptr, col, val, m, n, s, seed, qr_dtype=qr_dtype, r_store=r_store,
+                       b=np.asarray(b, np.float64) if start == "sketch" else None)
     A = csr(row_ptr, col, val, m, n)
-    x, results = refined_lsqr(A, pre["R"], b, refine=refine, atol=atol, btol=btol, conlim=conlim,
-                              itmax=itmax, operator=operator, keep_history=keep_history)
+    x0 = None
+    if start == "sketch":
+        SA = pre["SA"].astype(np.float32) if qr_dtype == "f32" else pre["SA"]
+        R, _, X0 = sketched_start(SA, pre["Sb"], check_rank=qr_dtype == "f64")
+        if r_store == "f32":
+            R = R.astype(np.float32).astype(np.float64)
+        pre["R"] = R
+        x0 = X0[:, 0]
+    elif start != "zero":
+        raise ValueError(start)
+    x, results = refined_lsqr(A, pre["R"], b, refine=refine, x0=x0, atol=atol, btol=btol,
+                              conlim=conlim, itmax=itmax, operator=operator,
+                              keep_history=keep_history)
     res = results[0]
     out = dict(x=x, itn=sum(r.itn for r in results), itn_sweeps=[r.itn for r in results],
                istop=res.istop, est_normr=res.normr, est_normar=res.normar, anorm=res.anorm,
                acond=res.acond, R=pre["R"], h=pre["h"], sign=pre["sign"],
-               history=[r.history for r in results])
+               history=[r.history for r in results], x0=x0)
     out.update(residual_metrics(A, x, np.asarray(b, np.float64)))
     return out

@@ -239,6 +239,80 @@ def test_refined_solve_reaches_dense_optimum():
     assert out["istop"] in (1, 2)
 
 
+# ------------------------------------------------- starting point (Remark 3.1)
+def _sketch_case(m=300, n=12, s=60, kappa=1e3, seed=4, k=1):
+    A = dense_with_condition(m, n, kappa, seed=seed)
+    B = np.random.default_rng(seed + 1).standard_normal((k, m))
+    rp, col, val = csr_from_dense(A, keep_zeros=True)
+    h, sign = countsketch.hash_sign(m, s, seed + 2)
+    SA, SB = countsketch.sketch_dense(rp, col, val, h, sign, s, n, b=B)
+    return A, B, SA, SB.T  # SB: s x k
+
+
+def test_sketched_start_minimises_the_sketched_residual():
+    A, B, SA, SB = _sketch_case()
+    R, Y0, X0 = pipeline.sketched_start(SA, SB)
+    xs = np.linalg.lstsq(SA, SB[:, 0], rcond=None)[0]
+    assert np.linalg.norm(X0[:, 0] - xs) <= 1e-10 * np.linalg.norm(xs)
+    # the extended factor's last pivot is the sketched residual norm
+    Rx = qr.r_factor(np.hstack([SA, SB]), check_rank=False)
+    assert abs(Rx[-1, -1] - np.linalg.norm(SA @ xs - SB[:, 0])) <= 1e-10 * np.linalg.norm(SB)
+    # R is the sketch's own factor and Y0 = Q^T S b with Q = SA R^{-1}
+    assert np.linalg.norm(R.T @ R - SA.T @ SA) <= 1e-12 * np.linalg.norm(SA) ** 2
+    Q = sla.solve_triangular(R, SA.T, trans="T").T
+    assert np.linalg.norm(Y0[:, 0] - Q.T @ SB[:, 0]) <= 1e-10 * np.linalg.norm(SB)
+
+
+def test_sketched_start_columns_are_independent():
+    A, B, SA, SB = _sketch_case(k=3)
+    _, _, X0 = pipeline.sketched_start(SA, SB)
+    for k in range(3):
+        _, _, xk = pipeline.sketched_start(SA, SB[:, k])
+        assert np.linalg.norm(X0[:, k] - xk[:, 0]) <= 1e-12 * np.linalg.norm(xk)
+
+
+def test_sketched_start_with_injective_sketch_is_the_solution():
+    # s >= m with distinct buckets: ||S (A x - b)|| = ||A x - b||, so x0 is already
+    # the least-squares solution and a sweep from it has nothing left to do
+    A, b = _small_problem(m=80, n=10, kappa=1e6)
+    rp, col, val = csr_from_dense(A)
+    m, n = A.shape
+    h = np.random.default_rng(3).permutation(m).astype(np.int32)
+    sign = np.where(np.arange(m) % 3 == 0, -1, 1).astype(np.int8)
+    SA, Sb = countsketch.sketch_dense(rp, col, val, h, sign, m, n, b=b)
+    R, _, X0 = pipeline.sketched_start(SA, Sb)
+    xs = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert np.linalg.norm(A @ (X0[:, 0] - xs)) <= 1e-10 * np.linalg.norm(b)
+    _, res = pipeline.refined_lsqr(sp.csr_matrix(A), R, b, refine=0, x0=X0[:, 0])
+    assert res[0].itn <= 1
+
+
+def test_sketched_start_recovers_a_consistent_solution():
+    m, n = 400, 15
+    A = dense_with_condition(m, n, 1e4, seed=9)
+    xt = np.random.default_rng(10).standard_normal(n)
+    b = A @ xt
+    rp, col, val = csr_from_dense(A, keep_zeros=True)
+    h, sign = countsketch.hash_sign(m, 4 * n, 7)
+    SA, Sb = countsketch.sketch_dense(rp, col, val, h, sign, 4 * n, n, b=b)
+    _, _, X0 = pipeline.sketched_start(SA, Sb)
+    assert np.linalg.norm(X0[:, 0] - xt) <= 1e-9 * np.linalg.norm(xt)
+
+
+def test_solve_from_sketched_start_reaches_dense_optimum_sooner():
+    S, s = build_config("poisson2d_3x3")
+    Ad = dense_from_csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    Q, RA = np.linalg.qr(Ad)
+    xs = sla.solve_triangular(RA, Q.T @ S.b[0])
+    rstar = np.linalg.norm(S.b[0] - Ad @ xs)
+    cold = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1)
+    warm = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1,
+                          start="sketch")
+    assert abs(warm["normr"] - rstar) <= 1e-10 * rstar
+    assert warm["istop"] in (1, 2)
+    assert warm["itn"] < cold["itn"]
+
+
 # ---------------------------------------------------------------- gradients
 def test_dense_gradients_match_finite_differences():
     rng = np.random.default_rng(8)
