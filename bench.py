@@ -2,10 +2,13 @@
 """Time-to-tolerance benchmark of the CSQRP-LSQR pipeline on one MI355X.
 
 One step = the whole path on one synthetic RFM system already resident in HBM:
-A^T build, count sketch, Householder QR + R^{-1}, LSQR to the 1e-10 stopping
-rule with refinement sweeps, final true residual.  Prints one JSON line.
+A^T build, count sketch (with S b), Householder QR of [SA | Sb] + R^{-1}, LSQR
+from the sketched starting point y0 = Q^T (S b) (Remark 3.1; --start zero for
+y0 = 0) to the 1e-10 stopping rule with refinement sweeps, final true
+residual.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload poisson2d_8x8] [--precision f64|f32]
+                  [--start sketch|zero] [--nrhs K] [--backward]
 """
 
 from __future__ import annotations
@@ -110,6 +113,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides u_k = sin(k pi x) sin(pi y)..., k = 1..nrhs, solved together")
     ap.add_argument("--lockstep", type=int, default=1, help="1: lockstep blocks of 32; 0: one at a time")
+    ap.add_argument("--start", default="sketch", choices=["sketch", "zero"],
+                    help="LSQR starting point: sketch = y0 = Q^T (S b) from the QR of [SA | Sb] "
+                         "(Remark 3.1); zero = y0 = 0 (Sec. 4.1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--backward", action="store_true",
@@ -155,14 +161,22 @@ def main():
         AT = R.rfmls_transpose(h, A)
         if ev is not None:
             ev[1].record()
-        SA, _, _, _ = R.rfmls_sketch(h, A, s, SKETCH_SEED, dtype=qd)
+        if args.start == "sketch":
+            # S b rides along as extra columns of SA through the QR (Remark 3.1)
+            SA = R.sketch_buffer(s, S.n + args.nrhs, qd)
+            SA, _, _, Sb = R.rfmls_sketch(h, A, s, SKETCH_SEED, b=b, dtype=qd, SA=SA)
+        else:
+            SA, _, _, _ = R.rfmls_sketch(h, A, s, SKETCH_SEED, dtype=qd)
         if ev is not None:
             ev[2].record()
-        P = R.rfmls_precond(h, SA, qd, rd)
+        if args.start == "sketch":
+            P, X0 = R.rfmls_precond_x0(h, SA, S.n, Sb if args.nrhs > 1 else Sb[0], qd, rd)
+        else:
+            P, X0 = R.rfmls_precond(h, SA, qd, rd), None
         del SA
         if ev is not None:
             ev[3].record()
-        X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts)
+        X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts, x0=X0)
         if ev is not None:
             ev[4].record()
         return X, info, P, AT, Rres
@@ -271,7 +285,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
                    "precision": args.precision, "refine": args.refine, "itmax": args.itmax, "atol": opts.atol, "btol": opts.btol,
-                   "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1)},
+                   "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1),
+                   "start": args.start},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),
                        "istop": int(info[0]["istop"]),

@@ -10,8 +10,10 @@
  *   rfmls_sketch   count sketch SA = Phi D A, s = gamma n rows   (Def. 2.3; Alg. 1 step 2)
  *   rfmls_precond  Householder QR of SA -> R; the library keeps  (Alg. 1 step 3)
  *                  R^{-1} (upper triangular) as the preconditioner
+ *                  (rfmls_precond_x0 also returns the sketched     (Remark 3.1)
+ *                  solution x^(0) = R^{-1} Q^T S b as a starting point)
  *   rfmls_solve    LSQR on A R^{-1} (applied implicitly,          (Alg. 1 steps 4-6,
- *                  Remark 3.2) from y = 0, x = R^{-1} y, plus      Remarks 3.2-3.3, Sec. 4.1)
+ *                  Remark 3.2) from y = 0 or a given x, x = R^{-1} y, Remarks 3.2-3.3, Sec. 4.1)
  *                  iterative refinement on the true residual
  *   rfmls_solve_backward  gradients of a loss of x w.r.t. b and A's stored values
  *
@@ -81,7 +83,10 @@ typedef struct {
   int32_t lockstep; /* nonzero (default): with nrhs > 1, iterate the
                        right-hand sides in lockstep blocks of 32 that share
                        every pass over A, A^T and R^{-1}; 0: one at a time */
-  int32_t reserved; /* set to 0 */
+  int32_t x_init;   /* nonzero: X holds a starting point on entry (for example
+                       from rfmls_precond_x0) and the first sweep solves for
+                       the correction from b - A X; 0 (default): start from
+                       x = 0 (y^(0) = 0, Sec. 4.1)                        */
 } rfmls_opts;
 
 /* [host] per right-hand side results */
@@ -151,6 +156,26 @@ rfmls_status rfmls_sketch(rfmls_handle *h, const rfmls_csr *A, int64_t s, uint64
 rfmls_status rfmls_precond(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
                            rfmls_dtype r_store, void *SA, int64_t ld_sa,
                            rfmls_precond_t **P_out /* [host] out */);
+/* Preconditioner plus the sketched starting point (Alg. 1 step 3 with the
+ * initial guess y^(0) = Q^T (S b) of Remark 3.1).  The sketched right-hand
+ * sides SB = S B (rfmls_sketch's Sb) are written into SA as columns
+ * n .. n+nrhs-1 and carried through the same Householder QR, so the top n
+ * entries of those columns of the triangular factor are y0_k = Q^T (S b_k)
+ * (with R's row signs).  The library returns X0[:, k] = R^{-1} y0_k, the
+ * minimiser of ||S (A x - b_k)||, for rfmls_solve with opts->x_init = 1.
+ * Otherwise as rfmls_precond: R, its rank check (first n pivots only) and the
+ * stored X = R^{-1} are those of SA alone.
+ *   SA, ld_sa  s x n sketch (row-major, qr_dtype), ld_sa >= n + nrhs, s >= n + nrhs;
+ *              columns n .. ld_sa-1 of every row are overwritten (scratch: the
+ *              right-hand sides, then room that lets the QR's products run on
+ *              whole tiles; ld_sa a multiple of 128 is fastest)
+ *   SB         s x nrhs column-major float64 (ld = s), nrhs >= 1
+ *   X0, ldx0   n x nrhs column-major float64 output, ldx0 >= n
+ * Synchronises the stream (rank check); on error nothing is returned in *P_out. */
+rfmls_status rfmls_precond_x0(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
+                              rfmls_dtype r_store, void *SA, int64_t ld_sa, const double *SB,
+                              int64_t nrhs, double *X0, int64_t ldx0,
+                              rfmls_precond_t **P_out /* [host] out */);
 void rfmls_precond_free(rfmls_precond_t *P);
 int64_t rfmls_precond_n(const rfmls_precond_t *P);
 
@@ -165,12 +190,14 @@ rfmls_status rfmls_precond_import_R(rfmls_handle *h, int64_t n, const double *R,
 
 /* LSQR on the preconditioned problem min ||A R^{-1} y - b|| (Alg. 1 steps 4-6,
  * operator applied implicitly as A (R^{-1} v) and R^{-T} (A^T u)), from y = 0,
- * x = R^{-1} y, followed by opts->refine refinement sweeps on the true
+ * x = R^{-1} y (or, with opts->x_init, on min ||A R^{-1} y - (b - A x_in)||,
+ * x = x_in + R^{-1} y), followed by opts->refine refinement sweeps on the true
  * residual.  Each of the nrhs right-hand sides is solved independently (the
  * same iterates as a single solve) in lockstep.
  *   A, AT    the matrix and its transpose (rfmls_transpose)
  *   B, ldb   m x nrhs column-major right-hand sides (ldb >= m)
- *   X, ldx   n x nrhs column-major solutions (ldx >= n), overwritten
+ *   X, ldx   n x nrhs column-major solutions (ldx >= n), overwritten; read
+ *            first as the starting point when opts->x_init is set
  *   Rout, ldr  optional m x nrhs column-major true residuals b - A x (ldr >= m)
  *   info     [host] array of nrhs results, may be NULL
  * Returns RFMLS_W_NOCONV if some right-hand side hit itmax in its first sweep. */

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "RFMLS_OK", 1: "RFMLS_W_NOCONV", -1: "RFMLS_E_ARG", -2: "RFML
 
 EXPORTED = [
     "rfmls_default_opts", "rfmls_create", "rfmls_destroy", "rfmls_last_error", "rfmls_transpose",
-    "rfmls_sketch", "rfmls_precond", "rfmls_precond_free", "rfmls_precond_n",
+    "rfmls_sketch", "rfmls_precond", "rfmls_precond_x0", "rfmls_precond_free", "rfmls_precond_n",
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
     "rfmls_solve", "rfmls_solve_backward", "rfmls_trace_enable", "rfmls_trace_read",
 ]
@@ -37,7 +37,7 @@ class rfmls_csr(C.Structure):
 class rfmls_opts(C.Structure):
     _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("conlim", C.c_double),
                 ("itmax", C.c_int64), ("refine", C.c_int32), ("check_every", C.c_int32),
-                ("lockstep", C.c_int32), ("reserved", C.c_int32)]
+                ("lockstep", C.c_int32), ("x_init", C.c_int32)]
 
 
 class rfmls_info(C.Structure):
@@ -82,6 +82,7 @@ def load():
     lib.rfmls_sketch.argtypes = [vp, P(rfmls_csr), i64, u64, vp, vp, vp, vp, vp, i64, i64, vp,
                                  C.c_int, vp, i64]
     lib.rfmls_precond.argtypes = [vp, i64, i64, C.c_int, C.c_int, vp, i64, P(vp)]
+    lib.rfmls_precond_x0.argtypes = [vp, i64, i64, C.c_int, C.c_int, vp, i64, vp, i64, vp, i64, P(vp)]
     lib.rfmls_precond_free.argtypes = [vp]
     lib.rfmls_precond_free.restype = None
     lib.rfmls_precond_n.argtypes = [vp]

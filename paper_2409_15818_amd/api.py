@@ -142,13 +142,23 @@ def rfmls_transpose(h: Handle, A: CSR) -> CSR:
     return CSR(A.n, A.m, rp, col[:A.nnz], val[:A.nnz])
 
 
+def sketch_buffer(s: int, cols: int, dtype: str = "f64", device="cuda") -> torch.Tensor:
+    """Row-major s x ld buffer for SA, ld = cols rounded up to 128 elements:
+    aligned rows, and room for the QR's widest tile (rfmls_precond_x0 uses
+    the columns beyond n as scratch)."""
+    ld = (cols + 127) // 128 * 128
+    return torch.empty((s, ld), dtype=torch.float64 if dtype == "f64" else torch.float32,
+                       device=device)
+
+
 def rfmls_sketch(h: Handle, A: CSR, s: int, seed: int, hash_in=None, sign_in=None, b=None,
                  dtype: str = "f64", want_maps: bool = False, SA=None):
-    """Returns (SA [s x n row-major], hash or None, sign or None, Sb or None)."""
+    """Returns (SA [s x n row-major view, rows ld >= n apart], hash or None, sign
+    or None, Sb or None).  SA may be given (any row stride >= n)."""
     dev = A.row_ptr.device
     tdt = torch.float64 if dtype == "f64" else torch.float32
     if SA is None:
-        SA = torch.empty((s, A.n), dtype=tdt, device=dev)
+        SA = sketch_buffer(s, A.n, dtype, dev)[:, :A.n]
     hout = torch.empty(A.m, dtype=torch.int32, device=dev) if want_maps else None
     sout = torch.empty(A.m, dtype=torch.int8, device=dev) if want_maps else None
     Sb = None
@@ -173,6 +183,22 @@ def rfmls_precond(h: Handle, SA: torch.Tensor, qr_dtype: str = "f64", r_store: s
     return Precond(h, p, n)
 
 
+def rfmls_precond_x0(h: Handle, SA: torch.Tensor, n: int, Sb: torch.Tensor, qr_dtype: str = "f64",
+                     r_store: str = "f64"):
+    """Preconditioner and sketched starting points (Remark 3.1).  SA: [s, ld]
+    with ld >= n + nrhs (its columns n.. are scratch); Sb: [nrhs, s] (or [s])
+    from rfmls_sketch.  Returns (Precond, X0 [nrhs, n] or [n])."""
+    s = SA.shape[0]
+    single = Sb.dim() == 1
+    SB = (Sb.reshape(1, -1) if single else Sb).contiguous()
+    nrhs = SB.shape[0]
+    X0 = torch.empty((nrhs, n), dtype=torch.float64, device=SA.device)
+    p = C.c_void_p()
+    h.check(h._lib.rfmls_precond_x0(h._h, s, n, DTYPES[qr_dtype], DTYPES[r_store], _ptr(SA),
+                                    SA.stride(0), _ptr(SB), nrhs, _ptr(X0), n, C.byref(p)))
+    return Precond(h, p, n), (X0[0] if single else X0)
+
+
 def rfmls_precond_import_R(h: Handle, R: torch.Tensor, r_store: str = "f64") -> Precond:
     n = R.shape[0]
     R = R.contiguous()
@@ -194,15 +220,23 @@ def rfmls_precond_export_Rinv(h: Handle, P: Precond) -> torch.Tensor:
 
 
 def rfmls_solve(h: Handle, A: CSR, AT: CSR, P: Precond, B: torch.Tensor, opts: rfmls_opts | None = None,
-                want_residual: bool = True):
-    """B: [nrhs, m] (or [m]) float64.  Returns (X [nrhs, n], Rres [nrhs, m] or None, [info dicts], status)."""
+                want_residual: bool = True, x0: torch.Tensor | None = None):
+    """B: [nrhs, m] (or [m]) float64; x0: optional starting points shaped like
+    the result (sets opts.x_init).  Returns (X [nrhs, n], Rres [nrhs, m] or
+    None, [info dicts], status)."""
     single = B.dim() == 1
     Bm = (B.reshape(1, -1) if single else B).contiguous()
     nrhs = Bm.shape[0]
-    X = torch.empty((nrhs, A.n), dtype=torch.float64, device=B.device)
+    if x0 is None:
+        X = torch.empty((nrhs, A.n), dtype=torch.float64, device=B.device)
+    else:
+        X = x0.reshape(nrhs, A.n).to(dtype=torch.float64, device=B.device).clone()
     R = torch.empty((nrhs, A.m), dtype=torch.float64, device=B.device) if want_residual else None
     infos = (rfmls_info * nrhs)()
     o = opts if opts is not None else default_opts()
+    if x0 is not None:
+        o = rfmls_opts.from_buffer_copy(o)
+        o.x_init = 1
     rc = h.check(h._lib.rfmls_solve(h._h, C.byref(A.c()), C.byref(AT.c()), P._p, _ptr(Bm), A.m, nrhs,
                                     _ptr(X), A.n, _ptr(R), A.m, C.byref(o), infos))
     info = [infos[k].as_dict() for k in range(nrhs)]

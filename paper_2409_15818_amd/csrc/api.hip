@@ -80,7 +80,7 @@ void rfmls_default_opts(rfmls_opts* o) {
   o->refine = 1;
   o->check_every = 8;
   o->lockstep = 1;
-  o->reserved = 0;
+  o->x_init = 0;
 }
 
 rfmls_status rfmls_create(rfmls_handle** out, int device, void* stream) {
@@ -184,6 +184,21 @@ rfmls_status rfmls_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, uint64
   return run_sketch(h, A, s, hash, sign, b, nrhs, ldb, Sb, sa_dtype, SA, ld_sa);
 }
 
+// Householder QR of the s x ncols matrix SA, then a check of the panel kernel's
+// cross-block hand-over (its bounded waits set the device flag on time-out).
+static rfmls_status qr_checked(rfmls_handle* h, int64_t s, int64_t ncols, int64_t n_room,
+                               rfmls_dtype dt, void* SA, int64_t ld) {
+  RFMLS_CHECK(run_qr(h, s, ncols, n_room, dt, SA, ld));
+  int flag = 0;
+  RFMLS_HIP(h, hipMemcpyAsync(&flag, h->dev_flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RFMLS_HIP(h, hipStreamSynchronize(h->stream));
+  if (flag) {
+    hipMemset(h->dev_flags, 0, sizeof(int));
+    return fail(h, RFMLS_E_HIP, "QR panel: a workgroup did not receive its partner's sums in time");
+  }
+  return RFMLS_OK;
+}
+
 rfmls_status rfmls_precond(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
                            rfmls_dtype r_store, void* SA, int64_t ld_sa, rfmls_precond_t** P_out) {
   if (!h) return RFMLS_E_ARG;
@@ -194,18 +209,39 @@ rfmls_status rfmls_precond(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype qr
   if ((qr_dtype != RFMLS_F64 && qr_dtype != RFMLS_F32) || (r_store != RFMLS_F64 && r_store != RFMLS_F32))
     return fail(h, RFMLS_E_ARG, "rfmls_precond: unknown dtype");
   RFMLS_CHECK(set_device(h));
-  RFMLS_CHECK(run_qr(h, s, n, qr_dtype, SA, ld_sa));
-  int flag = 0;
-  RFMLS_HIP(h, hipMemcpyAsync(&flag, h->dev_flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  RFMLS_HIP(h, hipStreamSynchronize(h->stream));
-  if (flag) {
-    hipMemset(h->dev_flags, 0, sizeof(int));
-    return fail(h, RFMLS_E_HIP, "rfmls_precond: QR panel grid barrier timed out");
-  }
+  RFMLS_CHECK(qr_checked(h, s, n, n, qr_dtype, SA, ld_sa));
   rfmls_precond_t* P = new (std::nothrow) rfmls_precond_t();
   if (!P) return fail(h, RFMLS_E_NOMEM, "rfmls_precond: out of host memory");
   P->device = h->device;
   rfmls_status st = run_build_precond(h, n, qr_dtype, SA, ld_sa, r_store, P, qr_dtype == RFMLS_F64);
+  if (st < 0) {
+    rfmls_precond_free(P);
+    return st;
+  }
+  *P_out = P;
+  return RFMLS_OK;
+}
+
+rfmls_status rfmls_precond_x0(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
+                              rfmls_dtype r_store, void* SA, int64_t ld_sa, const double* SB,
+                              int64_t nrhs, double* X0, int64_t ldx0, rfmls_precond_t** P_out) {
+  if (!h) return RFMLS_E_ARG;
+  if (!P_out) return fail(h, RFMLS_E_ARG, "rfmls_precond_x0: P_out is null");
+  *P_out = nullptr;
+  if (n < 1 || nrhs < 1 || s < n + nrhs || !SA || ld_sa < n + nrhs || !SB || !X0 || ldx0 < n)
+    return fail(h, RFMLS_E_ARG,
+                "rfmls_precond_x0: need nrhs >= 1, s >= n + nrhs, ld_sa >= n + nrhs, ldx0 >= n "
+                "and non-null SA, SB, X0");
+  if ((qr_dtype != RFMLS_F64 && qr_dtype != RFMLS_F32) || (r_store != RFMLS_F64 && r_store != RFMLS_F32))
+    return fail(h, RFMLS_E_ARG, "rfmls_precond_x0: unknown dtype");
+  RFMLS_CHECK(set_device(h));
+  RFMLS_CHECK(put_sketched_rhs(h, s, n, nrhs, qr_dtype, SA, ld_sa, SB));
+  RFMLS_CHECK(qr_checked(h, s, n + nrhs, ld_sa, qr_dtype, SA, ld_sa));
+  rfmls_precond_t* P = new (std::nothrow) rfmls_precond_t();
+  if (!P) return fail(h, RFMLS_E_NOMEM, "rfmls_precond_x0: out of host memory");
+  P->device = h->device;
+  rfmls_status st = run_build_precond(h, n, qr_dtype, SA, ld_sa, r_store, P, qr_dtype == RFMLS_F64);
+  if (st >= 0) st = sketched_solution(h, P, nrhs, qr_dtype, SA, ld_sa, X0, ldx0);
   if (st < 0) {
     rfmls_precond_free(P);
     return st;

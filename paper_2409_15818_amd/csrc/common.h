@@ -120,6 +120,7 @@ enum WsSlot {
   WS_LSQR_BLK,
   WS_LSQR_BSTATE,
   WS_TRANSPOSE,
+  WS_X0,
   WS_MISC,
   WS_NUM_SLOTS
 };
@@ -185,10 +186,24 @@ rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const in
 rfmls_status run_transpose(rfmls_handle* h, const rfmls_csr* A, int64_t* rp, int32_t* col,
                            double* val);
 rfmls_status scan_counts(rfmls_handle* h, const int32_t* count, int64_t n, int64_t* ptr);
-rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype dt, void* SA, int64_t ld);
+// Householder QR of SA (s x n); columns n .. n_room-1 (n_room <= ld) may be
+// used as scratch
+rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, rfmls_dtype dt, void* SA,
+                    int64_t ld);
 rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, const void* SA,
                                int64_t ld, rfmls_dtype store, rfmls_precond_t* P, int check_rank);
 rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit);
+rfmls_status put_sketched_rhs(rfmls_handle* h, int64_t s, int64_t n, int64_t nrhs, rfmls_dtype dt,
+                              void* SA, int64_t ld, const double* SB);
+rfmls_status sketched_solution(rfmls_handle* h, const rfmls_precond_t* P, int64_t nrhs,
+                               rfmls_dtype dt, const void* SA, int64_t ld, double* X0,
+                               int64_t ldx0);
+// out = X in (trans 0) or X^T in (trans 1), X = R^{-1} the stored preconditioner,
+// minus hcoef (*dcoef) prev when prev is given; per-block sums of squares of
+// out into sq when given; nothing when *done is set
+rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, const double* in,
+                       double* out, double hcoef, const double* dcoef, const double* prev,
+                       double* sq, const int* done);
 rfmls_status unpack_precond(rfmls_handle* h, const rfmls_precond_t* P, double* Xdense);
 rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                        const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,

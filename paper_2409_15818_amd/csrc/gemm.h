@@ -122,10 +122,11 @@ __device__ __forceinline__ T load_b(const GemmArgs<T>& g, int64_t gk, int64_t gj
 // 2 x 2 grid, each wave (BMt/2) x (BNt/2) made of 16 x 16 MFMA tiles.  The
 // next K chunk is fetched from global memory into registers while the current
 // one is consumed from LDS, so the loads overlap the matrix-core work.
-// A chunk whose operand tiles lie inside the matrices and clear of every mask
-// and triangle ("clean", decided per block, so the branch is uniform) is read
-// through precomputed pointers with no per-element tests; only chunks on a
-// border, diagonal or ragged edge take the element-wise path.
+// A chunk clear of every mask and triangle and inside the K range ("clean",
+// decided per block, so the branch is uniform) is read through precomputed
+// pointers with no per-element tests, or with one bound test per element on
+// a tile over the matrix's last rows or columns; only chunks on a diagonal, a
+// mask border or the end of the K range take the element-wise path.
 template <typename T, int BMt, int BNt, int BKt, int WM, int WN, GemmRole Role>
 __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
   constexpr int NT = 64 * WM * WN;               // threads: WM x WN wavefronts
@@ -183,8 +184,10 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
   // block-uniform parts of the clean test
   const bool a_rows_in = i0 + BMt <= g.M;
   const bool b_cols_in = j0 + BNt <= g.N;
+  // a chunk inside the K range and clear of every mask and triangle (the
+  // bounds of the tile's block of rows or columns aside)
   auto clean = [&](int64_t k0) {
-    if (k0 + BKt > kend || !a_rows_in || !b_cols_in) return false;
+    if (k0 + BKt > kend) return false;
     const int64_t klast = k0 + BKt - 1, ilast = i0 + BMt - 1, jlast = j0 + BNt - 1;
     if (g.a_upper && k0 < ilast) return false;
     if (g.a_lower && klast > i0) return false;
@@ -198,10 +201,34 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
     if (clean(k0)) {
       const T* a = g.transA ? pa + k0 * g.lda : pa + k0;
       const T* b = pb + k0 * g.ldb;
+      if (a_rows_in && b_cols_in) {
 #pragma unroll
-      for (int q = 0; q < EA; ++q) ra[q] = a[q];
+        for (int q = 0; q < EA; ++q) ra[q] = a[q];
 #pragma unroll
-      for (int q = 0; q < EB; ++q) rb[q] = b[q];
+        for (int q = 0; q < EB; ++q) rb[q] = b[q];
+      } else {
+        // a tile over the last rows or columns: a thread's run of EA (EB)
+        // elements inside the matrix is loaded as one run, as on the interior
+        // path (vector loads); a run outside reads zeros, and only a run
+        // across the edge goes element by element
+        const int64_t ia = i0 + ra_i, jb = j0 + rb_j;
+        const int64_t a_in = g.transA ? g.M - ia : (ia < g.M ? EA : 0);  // run elements inside
+        if (a_in >= EA) {
+#pragma unroll
+          for (int q = 0; q < EA; ++q) ra[q] = a[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < EA; ++q) ra[q] = q < a_in ? a[q] : T(0);
+        }
+        const int64_t b_in = g.N - jb;
+        if (b_in >= EB) {
+#pragma unroll
+          for (int q = 0; q < EB; ++q) rb[q] = b[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < EB; ++q) rb[q] = q < b_in ? b[q] : T(0);
+        }
+      }
       return;
     }
     if (!g.transA) {

@@ -628,8 +628,16 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
     double* x = X + k * ldx;
     rfmls_info inf{};
     double* rres = c.r;
+    // from x = 0 the first sweep takes b itself; from a given x every sweep
+    // solves for the correction from the true residual r = b - A x
+    const bool warm = o->x_init != 0;
+    if (warm) {
+      RFMLS_CHECK(host_norm(c, b, m, &inf.normb));
+      RFMLS_CHECK(spmv(c, A, x, -1.0, -1.0, nullptr, b, rres, nullptr, nullptr, nullptr));
+    }
     for (int sweep = 0; sweep <= o->refine; ++sweep) {
-      const double* rhs = sweep == 0 ? b : rres;
+      const bool from_zero = sweep == 0 && !warm;
+      const double* rhs = from_zero ? b : rres;
       RFMLS_CHECK(lsqr_sweep(c, rhs, o, itmax));
       LsqrDev s;
       RFMLS_CHECK(read_state(c, &s));
@@ -641,15 +649,15 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
         inf.normar_est = s.normar;
         inf.anorm_est = sqrt(s.anorm2);
         inf.acond_est = s.acond;
-        inf.normb = s.bnorm;
+        if (!warm) inf.normb = s.bnorm;
         if (s.istop == 7) ret = RFMLS_W_NOCONV;
       }
       inf.itn += s.itn;
       inf.istop_last = s.istop;
       // x (+)= X y
-      RFMLS_CHECK(tri_apply(h, P, 0, c.y, sweep == 0 ? x : c.xs, 0.0, nullptr, nullptr, nullptr,
+      RFMLS_CHECK(tri_apply(h, P, 0, c.y, from_zero ? x : c.xs, 0.0, nullptr, nullptr, nullptr,
                             nullptr));
-      if (sweep > 0)
+      if (!from_zero)
         hipLaunchKernelGGL(k_axpby, dim3(vbn), dim3(kThreads), 0, c.st, n, 1.0,
                            (const double*)nullptr, (const double*)x, 1.0, (const double*)nullptr,
                            (const double*)c.xs, x, (const int*)nullptr);

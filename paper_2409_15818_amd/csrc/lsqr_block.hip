@@ -890,8 +890,29 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
     const int64_t nb = nrhs - k0 < kBlk ? nrhs - k0 : kBlk;
     std::vector<rfmls_info> inf(nb);
     hipLaunchKernelGGL(k_gather_block, dim3(gm), dim3(kThreads), 0, c.st, B, ldb, k0, nb, m, c.Bb);
+    // from x = 0 the first sweep takes B itself; from given starting points
+    // every sweep solves for the correction from the true residual B - A X
+    const bool warm = o->x_init != 0;
+    std::vector<double> bsq;
+    if (warm) {
+      hipLaunchKernelGGL(k_gather_block, dim3(gn), dim3(kThreads), 0, c.st, (const double*)X, ldx, k0, nb,
+                         n, c.Xb);
+      RFMLS_CHECK(spmm(c, A, c.Xb, -1.0, -1.0, nullptr, c.Bb, c.Rr, nullptr, nullptr, nullptr));
+      hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(m)), dim3(kThreads), 0, c.st, (const double*)c.Bb, m,
+                         c.sqA);
+      bsq.assign((size_t)rows_grid(m) * kBlk, 0.0);
+      RFMLS_HIP(h, hipMemcpyAsync(bsq.data(), c.sqA, sizeof(double) * bsq.size(), hipMemcpyDeviceToHost,
+                                  c.st));
+      RFMLS_HIP(h, hipStreamSynchronize(c.st));
+      for (int64_t q = 0; q < nb; ++q) {
+        double t = 0.0;
+        for (size_t b = 0; b < bsq.size() / kBlk; ++b) t += bsq[b * kBlk + q];
+        inf[q].normb = sqrt(t);
+      }
+    }
     for (int sweep = 0; sweep <= o->refine; ++sweep) {
-      RFMLS_CHECK(block_sweep(c, sweep == 0 ? c.Bb : c.Rr, o, itmax));
+      const bool from_zero = sweep == 0 && !warm;
+      RFMLS_CHECK(block_sweep(c, from_zero ? c.Bb : c.Rr, o, itmax));
       RFMLS_CHECK(read_block_state(c, hs.data()));
       int64_t itn_max = 0;
       for (int64_t q = 0; q < nb; ++q) {
@@ -904,7 +925,7 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
           inf[q].normar_est = s.normar;
           inf[q].anorm_est = sqrt(s.anorm2);
           inf[q].acond_est = s.acond;
-          inf[q].normb = s.bnorm;
+          if (!warm) inf[q].normb = s.bnorm;
           if (s.istop == 7) ret = RFMLS_W_NOCONV;
         }
         inf[q].itn += s.itn;
@@ -912,8 +933,8 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
         if (s.itn > itn_max) itn_max = s.itn;
       }
       // x (+)= X y ; r = b - A x
-      RFMLS_CHECK(tri_block(c, 0, c.Y, sweep == 0 ? c.Xb : c.DX, 0.0, nullptr, nullptr, nullptr, nullptr));
-      if (sweep > 0)
+      RFMLS_CHECK(tri_block(c, 0, c.Y, from_zero ? c.Xb : c.DX, 0.0, nullptr, nullptr, nullptr, nullptr));
+      if (!from_zero)
         hipLaunchKernelGGL(k_blk_axpy, dim3(gn), dim3(kThreads), 0, c.st, c.Xb, (const double*)c.DX, n);
       RFMLS_CHECK(spmm(c, A, c.Xb, -1.0, -1.0, nullptr, c.Bb, c.Rr, nullptr, nullptr, nullptr));
       if (itn_max == 0) break;

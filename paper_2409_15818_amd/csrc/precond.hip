@@ -29,6 +29,31 @@ __global__ void k_extract_R(const T* __restrict__ SA, int64_t ld, int64_t n,
     R[i * n + j] = j >= i ? sg * (double)SA[i * ld + j] : 0.0;
 }
 
+// Remark 3.1: the sketched right-hand sides become extra columns of the
+// factored matrix, element (i, n + k) = SB[k s + i] in the QR's precision.
+template <typename T>
+__global__ void k_put_rhs(T* __restrict__ SA, int64_t ld, int64_t s, int64_t n, int64_t nrhs,
+                          const double* __restrict__ SB) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < s * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / s, i = e % s;
+    SA[i * ld + n + k] = (T)SB[k * s + i];
+  }
+}
+
+// y0_k = Q^T (S b_k): the top n entries of the extra columns after the QR,
+// with the row signs that make diag(R) > 0 (as in k_extract_R).
+template <typename T>
+__global__ void k_take_y0(const T* __restrict__ SA, int64_t ld, int64_t n, int64_t nrhs,
+                          double* __restrict__ Y0) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / n, i = e % n;
+    const double sg = (double)SA[i * ld + i] < 0.0 ? -1.0 : 1.0;
+    Y0[k * n + i] = sg * (double)SA[i * ld + n + k];
+  }
+}
+
 // stats[0] = min |r_ii|, stats[1] = max |r_ii|, stats[2] = count of non-finite
 __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R, int64_t n,
                                                     double* __restrict__ stats) {
@@ -314,6 +339,40 @@ rfmls_status unpack_precond(rfmls_handle* h, const rfmls_precond_t* P, double* X
     hipLaunchKernelGGL(k_unpack_tiles_f32, dim3((unsigned)P->n), dim3(256), 0, h->stream,
                        (const float*)P->Xpk, P->n, P->nt, Xdense);
   RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+rfmls_status put_sketched_rhs(rfmls_handle* h, int64_t s, int64_t n, int64_t nrhs, rfmls_dtype dt,
+                              void* SA, int64_t ld, const double* SB) {
+  const unsigned g = ceil_div(s * nrhs, 256) < 4096 ? ceil_div(s * nrhs, 256) : 4096;
+  if (dt == RFMLS_F64)
+    hipLaunchKernelGGL(k_put_rhs<double>, dim3(g), dim3(256), 0, h->stream, (double*)SA, ld, s, n,
+                       nrhs, SB);
+  else
+    hipLaunchKernelGGL(k_put_rhs<float>, dim3(g), dim3(256), 0, h->stream, (float*)SA, ld, s, n,
+                       nrhs, SB);
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+rfmls_status sketched_solution(rfmls_handle* h, const rfmls_precond_t* P, int64_t nrhs,
+                               rfmls_dtype dt, const void* SA, int64_t ld, double* X0,
+                               int64_t ldx0) {
+  const int64_t n = P->n;
+  void* p_y;
+  RFMLS_CHECK(workspace(h, WS_X0, sizeof(double) * (size_t)n * (size_t)nrhs, &p_y));
+  double* Y0 = (double*)p_y;
+  const unsigned g = ceil_div(n * nrhs, 256) < 4096 ? ceil_div(n * nrhs, 256) : 4096;
+  if (dt == RFMLS_F64)
+    hipLaunchKernelGGL(k_take_y0<double>, dim3(g), dim3(256), 0, h->stream, (const double*)SA, ld,
+                       n, nrhs, Y0);
+  else
+    hipLaunchKernelGGL(k_take_y0<float>, dim3(g), dim3(256), 0, h->stream, (const float*)SA, ld, n,
+                       nrhs, Y0);
+  RFMLS_HIP(h, hipGetLastError());
+  // x0_k = R^{-1} y0_k with the stored X
+  for (int64_t k = 0; k < nrhs; ++k)
+    RFMLS_CHECK(tri_apply(h, P, 0, Y0 + k * n, X0 + k * ldx0, 0.0, nullptr, nullptr, nullptr, nullptr));
   return RFMLS_OK;
 }
 

@@ -372,6 +372,7 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
 }
 
 constexpr int64_t kOuter = 256;
+inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
 // Panel launch shapes (rows per thread Q, rows per block 16 Q), increasing.
 // The largest are the largest that compile without spills at 1024 threads.
@@ -414,9 +415,10 @@ rfmls_status pick_panel_shape(rfmls_handle* h, int64_t M, PanelShape* out, int64
 
 template <typename T>
 GemmArgs<T> vt_gemm(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, T* out,
-                    int64_t ksplit) {
+                    int64_t ldo, int64_t ksplit) {
   // out_z = V^T [V | C] over row slices: V = the vcols Householder vectors
-  // stored below the diagonal of P, C the next ncols - vcols columns
+  // stored below the diagonal of P, C the next ncols - vcols columns; rows of
+  // out are ldo apart, slices vcols ldo apart
   GemmArgs<T> g;
   g.M = vcols;
   g.N = ncols;
@@ -429,17 +431,19 @@ GemmArgs<T> vt_gemm(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, T
   g.ldb = ld;
   g.b_vcols = vcols;
   g.C = out;
-  g.ldc = ncols;
+  g.ldc = ldo;
   g.alpha = T(1);
   g.beta = T(0);
   g.ksplit = ksplit;
-  g.c_zstride = vcols * ncols;
+  g.c_zstride = vcols * ldo;
   return g;
 }
 
 template <typename T>
-GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, const T* Wp) {
+GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, const T* Wp,
+                     int64_t ldwp) {
   // C <- C - V Wp, C = the ncols columns right of the vcols Householder vectors
+  // (rows of Wp ldwp apart)
   GemmArgs<T> g;
   g.M = M;
   g.N = ncols;
@@ -448,7 +452,7 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
   g.lda = ld;
   g.a_vmask = 1;
   g.B = Wp;
-  g.ldb = ncols;
+  g.ldb = ldwp;
   g.C = P + vcols;
   g.ldc = ld;
   g.alpha = T(-1);
@@ -456,8 +460,11 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
   return g;
 }
 
+// n_room >= n columns of SA may be written: the big trailing products round
+// their column count up to the tile width inside that room (full tiles, no
+// ragged edge); the extra columns only ever hold values nothing reads.
 template <typename T>
-rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
+rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld) {
   hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 8192;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
@@ -465,11 +472,14 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
   void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
   RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuter, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
+  // rows of the products W, W' are padded to 32 elements (128-byte aligned
+  // rows for every column count)
+  const int64_t npad = pad32(n_room);
   const size_t wz_in = (size_t)nsp_in_max * kMaxNb * kOuter;
-  const size_t wz_out = (size_t)nsp_out_max * kOuter * (size_t)n;
+  const size_t wz_out = (size_t)nsp_out_max * kOuter * (size_t)npad;
   RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * (wz_in > wz_out ? wz_in : wz_out), &p_wz));
-  RFMLS_CHECK(workspace(h, WS_QR_WR, sizeof(T) * kOuter * (size_t)n, &p_w));
-  RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)n, &p_wp));
+  RFMLS_CHECK(workspace(h, WS_QR_WR, sizeof(T) * kOuter * (size_t)npad, &p_w));
+  RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)npad, &p_wp));
   RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * kOuter * kOuter, &p_to));
   RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
   T* tau = (T*)p_tau;
@@ -507,43 +517,47 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       const int64_t rem = k0 + bw - (p0 + jb);
       if (rem <= 0) continue;
       const int64_t ncols = jb + rem;
+      const int64_t ldw = pad32(ncols), ldwp = pad32(rem);
       const int64_t nsp = (M + split_in - 1) / split_in;
       {
         Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
                  2.0 * (double)jb * ncols * M);
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, split_in), st)));
-        hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(jb * ncols, 256)), dim3(256), 0, st,
-                           (const T*)Wz, (int64_t)jb * ncols, (int)nsp, (int64_t)jb * ncols, W);
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, ldw, split_in), st)));
+        hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(jb * ldw, 256)), dim3(256), 0, st,
+                           (const T*)Wz, (int64_t)jb * ldw, (int)nsp, (int64_t)jb * ldw, W);
       }
       {
         Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
         // this panel's T is also the diagonal block of the outer block's T_o
         T* Tq = To + (p0 - k0) * kOuter + (p0 - k0);
         hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)W, (int64_t)0, 1,
-                           ncols, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
+                           ldw, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
         hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 64)), dim3(256), 0, st, (const T*)W,
-                           (int64_t)0, 1, ncols, jb, rem, (const T*)Tq, (int64_t)kOuter, Wp, rem);
+                           (int64_t)0, 1, ldw, jb, rem, (const T*)Tq, (int64_t)kOuter, Wp, ldwp);
       }
       {
         Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
                  2.0 * (double)M * rem * jb);
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerUpdate>(v_update<T>(P, ld, M, jb, rem, Wp), st)));
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerUpdate>(v_update<T>(P, ld, M, jb, rem, Wp, ldwp), st)));
       }
       RFMLS_HIP(h, hipGetLastError());
     }
     // ---------------- trailing update with the whole outer block ----------------
-    const int64_t ntr = n - k0 - bw;
-    if (ntr <= 0) continue;
+    if (n - k0 - bw <= 0) continue;
+    // columns right of the block, rounded up to the widest tile (128) within
+    // the room
+    const int64_t ntr = (n_room < (n + 127) / 128 * 128 ? n_room : (n + 127) / 128 * 128) - k0 - bw;
     const int64_t M0 = s - k0;
     T* P0 = SA + k0 * ld + k0;
     const int64_t ncols = bw + ntr;
+    const int64_t ldw = pad32(ncols), ldwp = pad32(ntr);
     const int64_t nsp = (M0 + split_out - 1) / split_out;
     {
       Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
                2.0 * (double)bw * ncols * M0);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, split_out), st)));
-      hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ncols, 256) < 4096 ? ceil_div(bw * ncols, 256) : 4096),
-                         dim3(256), 0, st, (const T*)Wz, bw * ncols, (int)nsp, bw * ncols, W);
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, ldw, split_out), st)));
+      hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ldw, 256) < 4096 ? ceil_div(bw * ldw, 256) : 4096),
+                         dim3(256), 0, st, (const T*)Wz, bw * ldw, (int)nsp, bw * ldw, W);
     }
     {
       // T_o: its diagonal 64-blocks are the inner panels' T, written above,
@@ -553,8 +567,8 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       {
         const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
         const int jq = (int)(bw - q0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)(W + q0 * ncols + q0),
-                           (int64_t)0, 1, ncols, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)(W + q0 * ldw + q0),
+                           (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
                            (int64_t)kOuter);
       }
       for (int64_t q0 = kMaxNb; q0 < bw; q0 += kMaxNb) {
@@ -567,7 +581,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
         ga.lda = kOuter;
         ga.a_upper = 1;
         ga.B = W + q0;
-        ga.ldb = ncols;
+        ga.ldb = ldw;
         ga.C = Y;
         ga.ldc = jq;
         RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(ga, st)));
@@ -598,15 +612,15 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
       gt.transA = 1;
       gt.a_lower = 1;
       gt.B = W + bw;
-      gt.ldb = ncols;
+      gt.ldb = ldw;
       gt.C = Wp;
-      gt.ldc = ntr;
+      gt.ldc = ldwp;
       RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
     }
     {
       Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr + (double)M0 * bw + (double)bw * ntr),
                2.0 * (double)M0 * ntr * bw);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, M0, bw, ntr, Wp), st)));
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, M0, bw, ntr, Wp, ldwp), st)));
     }
     RFMLS_HIP(h, hipGetLastError());
   }
@@ -615,9 +629,11 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, T* SA, int64_t ld) {
 
 }  // namespace
 
-rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype dt, void* SA, int64_t ld) {
-  if (dt == RFMLS_F64) return qr_impl<double>(h, s, n, (double*)SA, ld);
-  return qr_impl<float>(h, s, n, (float*)SA, ld);
+rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, rfmls_dtype dt, void* SA,
+                    int64_t ld) {
+  if (n_room < n || n_room > ld) n_room = n;
+  if (dt == RFMLS_F64) return qr_impl<double>(h, s, n, n_room, (double*)SA, ld);
+  return qr_impl<float>(h, s, n, n_room, (float*)SA, ld);
 }
 
 }  // namespace rfmls

@@ -12,8 +12,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from .api import (CSR, Handle, Precond, default_opts, rfmls_precond, rfmls_sketch, rfmls_solve,
-                  rfmls_solve_backward, rfmls_transpose)
+from .api import (CSR, Handle, Precond, default_opts, rfmls_precond, rfmls_precond_x0, rfmls_sketch,
+                  rfmls_solve, rfmls_solve_backward, rfmls_transpose, sketch_buffer)
 
 
 @dataclass
@@ -28,14 +28,25 @@ class Result:
 
 
 def csqrp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, qr_dtype: str = "f64",
-               r_store: str = "f64", opts=None, AT: CSR | None = None) -> Result:
-    """Alg. 1 on the GPU: s = gamma n sketch rows, seed of the count sketch."""
+               r_store: str = "f64", opts=None, AT: CSR | None = None,
+               start: str = "zero") -> Result:
+    """Alg. 1 on the GPU: s = gamma n sketch rows, seed of the count sketch.
+    start "zero": y^(0) = 0 (Sec. 4.1); "sketch": y^(0) = Q^T (S b) (Remark 3.1)."""
     if AT is None:
         AT = rfmls_transpose(h, A)
-    SA, _, _, _ = rfmls_sketch(h, A, s, seed, dtype=qr_dtype)
-    P = rfmls_precond(h, SA, qr_dtype, r_store)
+    if start == "zero":
+        SA, _, _, _ = rfmls_sketch(h, A, s, seed, dtype=qr_dtype)
+        P = rfmls_precond(h, SA, qr_dtype, r_store)
+        x0 = None
+    elif start == "sketch":
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        SA = sketch_buffer(s, A.n + nrhs, qr_dtype, b.device)
+        SA, _, _, Sb = rfmls_sketch(h, A, s, seed, b=b, dtype=qr_dtype, SA=SA)
+        P, x0 = rfmls_precond_x0(h, SA, A.n, Sb if b.dim() == 2 else Sb[0], qr_dtype, r_store)
+    else:
+        raise ValueError(f"unknown start {start!r}")
     del SA
-    X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts)
+    X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts, x0=x0)
     return Result(X, R, info, rc, P, AT)
 
 

@@ -10,7 +10,8 @@ Against the oracle:
     sum rounded to nearest);
   * the final true residual ||b - A x|| and the PDE error at 10^4 sample
     points against the stored oracle results in tests/golden/ (written by
-    tests/golden/make_golden.py, which calls only the oracle).
+    tests/golden/make_golden.py, which calls only the oracle), from the zero
+    and from the sketched starting point.
 
 Residual tolerance: 1e-10 relative where cond(A) u^2-level effects stay below
 it (3D system, pivot ratio min|r_jj|/max|r_jj| = 1.7e-7).  The 2D system has a
@@ -71,15 +72,20 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name,prec", [("poisson2d_8x8", "f64"), ("poisson3d_4x4x4", "f64"),
-                                       ("poisson3d_4x4x4", "f32")])
-def test_fullsize_solve_matches_oracle(handle, name, prec):
+# both starting points (y0 = 0, Sec. 4.1; y0 = Q^T S b, Remark 3.1) reach the
+# same least-squares optimum, so both are gated on the same stored oracle result
+@pytest.mark.parametrize("name,prec,start", [("poisson2d_8x8", "f64", "zero"),
+                                             ("poisson2d_8x8", "f64", "sketch"),
+                                             ("poisson3d_4x4x4", "f64", "zero"),
+                                             ("poisson3d_4x4x4", "f32", "zero"),
+                                             ("poisson3d_4x4x4", "f32", "sketch")])
+def test_fullsize_solve_matches_oracle(handle, name, prec, start):
     S, s, A = _system(name)
     gold = _golden(name)
     assert (gold["m"], gold["n"], gold["nnz"], gold["s"]) == (S.m, S.n, S.nnz, s)
     opts = R.default_opts(refine=gold["refine"])
     res = R.csqrp_lsqr(handle, A, torch.tensor(S.b[0], device="cuda"), s, SEED,
-                       qr_dtype=prec, r_store=prec, opts=opts)
+                       qr_dtype=prec, r_store=prec, opts=opts, start=start)
     info = res.info[0]
     assert res.status == 0 and info["istop"] in (1, 2)
     x = res.x.cpu().numpy()

@@ -219,6 +219,108 @@ def test_imported_R_matches_oracle_iteration(handle):
     assert abs(info[0]["normr"] - orc["normr"]) <= 1e-9 * orc["normr"]
 
 
+# ------------------------------------------- sketched starting point (Remark 3.1)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sketched_start_matches_oracle(handle, dtype):
+    # well-conditioned dense system (x0 determined to ~kappa u), 3 right-hand
+    # sides carried through the QR as extra columns, ragged tiles (n = 90)
+    m, n, s, k = 3000, 90, 400, 3
+    Ad = dense_with_condition(m, n, 1e3, seed=12)
+    Bh = np.random.default_rng(13).standard_normal((k, m))
+    rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+    A = gpu_csr(rp, col, val, m, n)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    SA = torch.empty((s, n + k), dtype=tdt, device="cuda")
+    SA, _, _, Sb = R.rfmls_sketch(handle, A, s, SEED, b=torch.tensor(Bh, device="cuda"), dtype=dtype,
+                                  SA=SA)
+    P, X0 = R.rfmls_precond_x0(handle, SA, n, Sb, dtype, dtype)
+    h, sg = countsketch.hash_sign(m, s, SEED)
+    SAo, SBo = countsketch.sketch_dense(rp, col, val, h, sg, s, n, b=Bh)
+    assert np.array_equal(Sb.cpu().numpy(), SBo)
+    SAq = SAo.astype(np.float32) if dtype == "f32" else SAo
+    Ro, _, X0o = pipeline.sketched_start(SAq, SBo.T, check_rank=dtype == "f64")
+    X0g = X0.cpu().numpy().T
+    assert np.abs(X0g - X0o).max() / np.abs(X0o).max() < (1e-11 if dtype == "f64" else 1e-3)
+    # the extra columns leave R (and the stored R^{-1}) as rfmls_precond makes them
+    Rg = R.rfmls_precond_export_R(handle, P).cpu().numpy()
+    assert np.abs(Rg - Ro).max() / np.abs(Ro).max() < (1e-12 if dtype == "f64" else 1e-5)
+    SA2 = R.rfmls_sketch(handle, A, s, SEED, dtype=dtype)[0]
+    Rp = R.rfmls_precond_export_R(handle, R.rfmls_precond(handle, SA2, dtype, dtype)).cpu().numpy()
+    assert np.array_equal(Rg, Rp)
+
+
+def test_sketched_start_injective_sketch_needs_no_iterations(handle):
+    # s >= m with distinct buckets: x0 is already the least-squares solution
+    rng = np.random.default_rng(21)
+    m, n = 120, 15
+    Ad = dense_with_condition(m, n, 1e5, seed=21)
+    b = rng.standard_normal(m)
+    rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+    A = gpu_csr(rp, col, val, m, n)
+    hh = torch.tensor(rng.permutation(m).astype(np.int32), device="cuda")
+    ss = torch.tensor(np.where(np.arange(m) % 2 == 0, 1, -1).astype(np.int8), device="cuda")
+    SA = torch.empty((m, n + 1), dtype=torch.float64, device="cuda")
+    bt = torch.tensor(b, device="cuda")
+    SA, _, _, Sb = R.rfmls_sketch(handle, A, m, SEED, hash_in=hh, sign_in=ss, b=bt, SA=SA)
+    P, x0 = R.rfmls_precond_x0(handle, SA, n, Sb[0])
+    xs = np.linalg.lstsq(Ad, b, rcond=None)[0]
+    assert np.linalg.norm(Ad @ (x0.cpu().numpy() - xs)) <= 1e-10 * np.linalg.norm(b)
+    AT = R.rfmls_transpose(handle, A)
+    x, _, info, _ = R.rfmls_solve(handle, A, AT, P, bt, R.default_opts(refine=0), x0=x0)
+    assert info[0]["itn"] <= 1
+    assert abs(info[0]["normb"] - np.linalg.norm(b)) <= 1e-13 * np.linalg.norm(b)
+    assert np.linalg.norm(Ad @ (x.cpu().numpy() - xs)) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [("f64", "f64"), ("f32", "f32")])
+def test_pipeline_from_sketched_start(handle, name, prec):
+    S, s, A = system(name)
+    b = torch.tensor(S.b[0], device="cuda")
+    res = R.csqrp_lsqr(handle, A, b, s, SEED, qr_dtype=prec[0], r_store=prec[1], start="sketch")
+    info = res.info[0]
+    orc = _oracle(S, s, start="sketch")  # float64 oracle from its own sketched start
+    cold = _oracle(S, s)
+    assert info["istop"] in (1, 2)
+    # the same optimum as from zero, to the same tolerance
+    assert abs(info["normr"] - orc["normr"]) <= 1e-10 * orc["normr"], (info["normr"], orc["normr"])
+    assert abs(info["normr"] - cold["normr"]) <= 1e-10 * cold["normr"]
+    assert abs(info["normb"] - np.linalg.norm(S.b[0])) <= 1e-13 * np.linalg.norm(S.b[0])
+    x = res.x.cpu().numpy()
+    assert _l2(S, x) <= 1.1 * _l2(S, orc["x"])
+    if prec == ("f64", "f64"):
+        assert abs(info["itn_first"] - orc["itn_sweeps"][0]) <= 2
+        assert info["itn"] < cold["itn"]
+
+
+def test_lockstep_from_sketched_starts(handle):
+    """Several right-hand sides through one QR with extra columns, then the
+    lockstep solve from those starting points, per column against the oracle."""
+    S, s, A = system("poisson2d_3x3")
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    nrhs = 5
+    Bh = _lockstep_rhs(S, Ah, 8, 31)[[0, 1, 5, 7, 2]]  # load, noise, zero, twice the load, noise
+    Bt = torch.tensor(Bh, device="cuda")
+    SA = torch.empty((s, S.n + nrhs), dtype=torch.float64, device="cuda")
+    SA, _, _, Sb = R.rfmls_sketch(handle, A, s, SEED, b=Bt, SA=SA)
+    P, X0 = R.rfmls_precond_x0(handle, SA, S.n, Sb)
+    AT = R.rfmls_transpose(handle, A)
+    X, Rr, info, rc = R.rfmls_solve(handle, A, AT, P, Bt, x0=X0)
+    Xs, _, infos, _ = R.rfmls_solve(handle, A, AT, P, Bt, R.default_opts(lockstep=0), x0=X0)
+    for k in range(nrhs):
+        orc = pipeline.solve(S.row_ptr, S.col, S.val, Bh[k], S.m, S.n, s, SEED, start="sketch")
+        nb = np.linalg.norm(Bh[k])
+        assert abs(info[k]["normb"] - nb) <= 1e-13 * max(nb, 1e-300)
+        if nb == 0.0:
+            assert info[k]["normr"] == 0.0 and np.all(X[k].cpu().numpy() == 0.0)
+            continue
+        tol = 1e-10 * orc["normr"] + 2 * 64 * 1.1e-16 * np.linalg.norm(
+            abs(Ah) @ abs(X[k].cpu().numpy()))
+        assert abs(info[k]["normr"] - orc["normr"]) <= tol, (k, info[k]["normr"], orc["normr"])
+        # lockstep and one-at-a-time agree
+        assert abs(info[k]["normr"] - infos[k]["normr"]) <= tol
+
+
 def test_solve_deterministic_and_multi_rhs(handle):
     S, s, A = system("poisson2d_3x3")
     AT = R.rfmls_transpose(handle, A)
