@@ -1,10 +1,11 @@
 // Blocked Householder QR of the sketch SA (s x n, row-major, in place):
 // Alg. 1 step 3.  Only R is needed; Q is never formed.
 //
-// Two levels of blocking.  Outer blocks of kOuter = 256 columns are factored
-// panel by panel (kMaxNb = 64 columns each); the trailing matrix right of an
-// outer block is then updated once, with K = 256, which keeps that update --
-// most of the flops -- on the matrix cores instead of bound by HBM traffic.
+// Two levels of blocking.  Outer blocks of kOuter = 256 (float32: 512) columns
+// are factored panel by panel (kMaxNb = 64 columns each); the trailing matrix
+// right of an outer block is then updated once, with K = kOuter, which keeps
+// that update -- most of the flops -- on the matrix cores instead of bound by
+// HBM traffic.
 //
 // Inner panel at column p0 (M = s - p0 rows):
 //   k_qr_panel   unblocked Householder on the M x 64 panel, spread over G
@@ -14,8 +15,8 @@
 //                workgroup forms the same reflector and applies it to its rows;
 //   inside the outer block: W = V^T [V | C] (split-K GEMM), T from V^T V
 //                (dlarft, forward, columnwise), C <- C - V (T^T W).
-// Outer block at column k0 (M0 = s - k0 rows, V_o = its 256 Householder vectors):
-//   W = V_o^T [V_o | C] (split-K GEMM; the first 256 columns are the Gram V_o^T V_o),
+// Outer block at column k0 (M0 = s - k0 rows, V_o = its kOuter Householder vectors):
+//   W = V_o^T [V_o | C] (split-K GEMM; the first kOuter columns are the Gram V_o^T V_o),
 //   T_o from the Gram: diagonal 64-blocks by dlarft, off-diagonal blocks by
 //   T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
 // All reductions run in a fixed order, so the factorisation is deterministic.
@@ -371,7 +372,13 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
     p[i] = 0ull;
 }
 
-constexpr int64_t kOuter = 256;
+// Outer block width: 256 columns for float64; 512 for float32, whose trailing
+// update then reads and writes the trailing matrix half as often (measured on
+// the 4^3-box sketch: 2.5% less QR time; neutral for float64, where the inner
+// products grow by as much as the trailing update gains).
+constexpr int64_t kOuterMax = 512;
+template <typename T>
+constexpr int64_t outer_width() { return sizeof(T) == 4 ? 512 : 256; }
 inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
 // Panel launch shapes (rows per thread Q, rows per block 16 Q), increasing.
@@ -465,12 +472,13 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
 // ragged edge); the extra columns only ever hold values nothing reads.
 template <typename T>
 rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld) {
+  constexpr int64_t kOuter = outer_width<T>();
   hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 8192;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
   const int64_t nsp_out_max = (s + split_out - 1) / split_out;
   void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
-  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuter, &p_tau));
+  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuterMax, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
   // rows of the products W, W' are padded to 32 elements (128-byte aligned
   // rows for every column count)
