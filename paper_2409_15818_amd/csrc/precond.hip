@@ -194,18 +194,23 @@ __global__ void k_unpack_tiles_f32(const float* __restrict__ pk, int64_t n, int6
 }
 
 // X = R^{-1} by blocked back substitution, two levels: outer blocks of
-// kInvOuter rows (4 tiles), inner block rows of 64.  For block row I inside
-// the outer block [o2, e2):
-//   R_{I,>I} X_{>I} = R_{I,(I,e2)} X_{(I,e2)}  (near: K < 256, one GEMM per row)
+// kInvOuter rows (kInvTiles tiles), inner block rows of 64.  For block row I
+// inside the outer block [o2, e2):
+//   R_{I,>I} X_{>I} = R_{I,(I,e2)} X_{(I,e2)}  (near: K < kInvOuter, one GEMM
+//                                                 per block row)
 //                   + R_{I,>=e2} X_{>=e2}        (far: computed once per outer
-//                                                 block for all its rows, M = 256)
-// so the dominant n^3/3 flops run as 256-row GEMMs.  Pf holds up to 4 split-K
-// slices of (e2 - o2) x (n - e2); Pn one 64 x n slice.
-constexpr int64_t kInvOuter = 4 * kTile;
+//                                                 block for all its rows)
+// so the dominant n^3/3 flops run as kInvOuter-row GEMMs, each panel of X read
+// by kInvTiles tile rows.  Measured (total of the three kernels, 12,800 /
+// 25,600 columns): 40 / 188 ms at 4 tiles, 39 / 180 ms at 16, 42 / 180 ms at 32
+// (the near products grow as fast as the far one shrinks).  Pf holds up to 4
+// split-K slices of (e2 - o2) x (n - e2); Pn one 64 x n slice.
+constexpr int64_t kInvTiles = 16;
+constexpr int64_t kInvOuter = kInvTiles * kTile;
 
 rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* Pf, double* Pn,
                           int64_t n, int64_t nt, int64_t kslice) {
-  const int64_t nt2 = (nt + 3) / 4;
+  const int64_t nt2 = (nt + kInvTiles - 1) / kInvTiles;
   for (int64_t I2 = nt2 - 1; I2 >= 0; --I2) {
     const int64_t o2 = I2 * kInvOuter;
     const int64_t e2 = o2 + kInvOuter < n ? o2 + kInvOuter : n;
@@ -240,7 +245,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
                (double)(e2 - o2) * (double)far * (double)far);
       RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
     }
-    for (int64_t I = (e2 - 1) / kTile; I >= I2 * 4; --I) {
+    for (int64_t I = (e2 - 1) / kTile; I >= I2 * kInvTiles; --I) {
       const int64_t o = I * kTile;
       const int64_t b = n - o < kTile ? n - o : kTile;
       const int64_t kn = e2 - o - b;  // solved rows of this outer block below row block I
