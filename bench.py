@@ -27,6 +27,8 @@ METRIC = "time to rel. residual 1e-10 (FP64 vs FP32-precond); SpMV/trsv HBM GB/s
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 COMPUTE_KERNELS = ("qr_gemm_update", "qr_gemm_VtC", "inv_gemm", "qr_inner_update", "qr_inner_VtC")
+# everything else in the kernel list (SpMV / SpMM, triangular and dense products
+# with the preconditioner, sketch) is priced against HBM bandwidth
 # vector-ALU kernels (no matrix cores), priced against the vector peak
 ALU_KERNELS = ("qr_panel", "inv_blockrow")
 ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
@@ -113,6 +115,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides u_k = sin(k pi x) sin(pi y)..., k = 1..nrhs, solved together")
     ap.add_argument("--lockstep", type=int, default=1, help="1: lockstep blocks of 32; 0: one at a time")
+    ap.add_argument("--operator", default="implicit", choices=["implicit", "explicit"],
+                    help="implicit: A (R^-1 v), R^-T (A^T u) (Remark 3.2); explicit: dense B = A R^-1 "
+                         "formed once, then dense products (Alg. 1 step 4; one right-hand side at a time)")
     ap.add_argument("--start", default="sketch", choices=["sketch", "zero"],
                     help="LSQR starting point: sketch = y0 = Q^T (S b) from the QR of [SA | Sb] "
                          "(Remark 3.1); zero = y0 = 0 (Sec. 4.1)")
@@ -136,7 +141,7 @@ def main():
 
     import paper_2409_15818_amd as R
     from oracle import pipeline  # only for the L2 error / residual check of the output
-    from rfmgen import build_config, exact_solution, feature_eval, sample_points
+    from rfmgen import build_config, feature_eval, sample_points
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -176,7 +181,12 @@ def main():
         del SA
         if ev is not None:
             ev[3].record()
-        X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts, x0=X0)
+        if args.operator == "explicit":
+            Bm = R.rfmls_form_B(h, A, P)
+            X, Rres, info, rc = R.rfmls_solve_explicit(h, A, AT, P, Bm, b, opts, x0=X0)
+            del Bm
+        else:
+            X, Rres, info, rc = R.rfmls_solve(h, A, AT, P, b, opts, x0=X0)
         if ev is not None:
             ev[4].record()
         return X, info, P, AT, Rres
@@ -239,7 +249,7 @@ def main():
     pts = sample_points(S.d)
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
     mets = [pipeline.residual_metrics(Ah, Xn[k], S.b[k]) for k in range(args.nrhs)]
-    l2s = [pipeline.l2_error(E, Xn[k], exact_solution(pts, S.modes[k])) for k in range(args.nrhs)]
+    l2s = [pipeline.l2_error(E, Xn[k], S.exact(pts, S.modes[k])) for k in range(args.nrhs)]
     met, l2, x = mets[0], l2s[0], Xn[0]
     gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
     vs_oracle = None
@@ -251,7 +261,7 @@ def main():
     bwd = None
     if args.backward:
         # dL/dx_k = E^T (E x_k - u_k) (the loss's own gradient, host side, untimed)
-        Gn = np.stack([E.T @ (E @ Xn[k] - exact_solution(pts, S.modes[k])) for k in range(args.nrhs)])
+        Gn = np.stack([E.T @ (E @ Xn[k] - S.exact(pts, S.modes[k])) for k in range(args.nrhs)])
         G = torch.tensor(Gn[0] if args.nrhs == 1 else Gn, device="cuda")
         Xd = X.reshape(args.nrhs, S.n) if args.nrhs > 1 else X
         bt = []
@@ -286,7 +296,7 @@ def main():
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
                    "precision": args.precision, "refine": args.refine, "itmax": args.itmax, "atol": opts.atol, "btol": opts.btol,
                    "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1),
-                   "start": args.start},
+                   "start": args.start, "operator": args.operator},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),
                        "istop": int(info[0]["istop"]),

@@ -15,6 +15,8 @@
  *   rfmls_solve    LSQR on A R^{-1} (applied implicitly,          (Alg. 1 steps 4-6,
  *                  Remark 3.2) from y = 0 or a given x, x = R^{-1} y, Remarks 3.2-3.3, Sec. 4.1)
  *                  iterative refinement on the true residual
+ *   rfmls_form_B / rfmls_solve_explicit  the same with the dense B = A R^{-1}
+ *                  formed explicitly (Alg. 1 step 4 taken literally)
  *   rfmls_solve_backward  gradients of a loss of x w.r.t. b and A's stored values
  *
  * Conventions for every entry point
@@ -206,6 +208,24 @@ rfmls_status rfmls_solve(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *A
                          double *X, int64_t ldx, double *Rout, int64_t ldr,
                          const rfmls_opts *opts, rfmls_info *info);
 
+/* Alg. 1 step 4 in its literal form: the dense preconditioned matrix
+ * B = A R^{-1} (m x n, row-major float64, ld_bmat >= n; caller-allocated,
+ * 8 m n bytes), formed as A times the stored X = R^{-1}, 32 columns at a time
+ * (each slab of X gathered from the stored tiles, one sparse-times-dense
+ * product with A, the slab written into B).  Asynchronous. */
+rfmls_status rfmls_form_B(rfmls_handle *h, const rfmls_csr *A, const rfmls_precond_t *P, double *Bmat,
+                          int64_t ld_bmat);
+/* rfmls_solve with LSQR's products taken with the explicit Bmat from
+ * rfmls_form_B (B v and B^T u as dense matrix-vector products) instead of
+ * the implicit A (R^{-1} v) and R^{-T} (A^T u) (Alg. 1 step 4 vs Remark 3.2);
+ * x = R^{-1} y, the refinement sweeps and the reported residuals use A (and
+ * AT for ||A^T r||).  One right-hand side at a time (opts->lockstep is not
+ * used); other arguments and results as rfmls_solve. */
+rfmls_status rfmls_solve_explicit(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *AT,
+                                  const rfmls_precond_t *P, const double *Bmat, int64_t ld_bmat,
+                                  const double *B, int64_t ldb, int64_t nrhs, double *X, int64_t ldx,
+                                  double *Rout, int64_t ldr, const rfmls_opts *opts,
+                                  rfmls_info *info);
 /* Backward of x = A^+ b for a loss L with G = dL/dX (n x nrhs, ldg >= n).
  * With r = b - A x, w = (A^T A)^{-1} g and lambda = A w:
  *   dB[:, k] = lambda_k                        (m x nrhs column-major, lddb >= m)

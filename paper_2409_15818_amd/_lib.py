@@ -25,7 +25,8 @@ EXPORTED = [
     "rfmls_default_opts", "rfmls_create", "rfmls_destroy", "rfmls_last_error", "rfmls_transpose",
     "rfmls_sketch", "rfmls_precond", "rfmls_precond_x0", "rfmls_precond_free", "rfmls_precond_n",
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
-    "rfmls_solve", "rfmls_solve_backward", "rfmls_trace_enable", "rfmls_trace_read",
+    "rfmls_solve", "rfmls_form_B", "rfmls_solve_explicit", "rfmls_solve_backward",
+    "rfmls_trace_enable", "rfmls_trace_read",
 ]
 
 
@@ -92,6 +93,9 @@ def load():
     lib.rfmls_precond_import_R.argtypes = [vp, i64, vp, C.c_int, P(vp)]
     lib.rfmls_solve.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, i64, vp, i64, vp, i64,
                                 P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_form_B.argtypes = [vp, P(rfmls_csr), vp, vp, i64]
+    lib.rfmls_solve_explicit.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, i64, vp,
+                                         i64, vp, i64, P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_solve_backward.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, vp,
                                          i64, i64, vp, i64, vp, P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_trace_enable.argtypes = [vp, C.c_int]

@@ -245,6 +245,39 @@ def rfmls_solve(h: Handle, A: CSR, AT: CSR, P: Precond, B: torch.Tensor, opts: r
     return X, R, info, rc
 
 
+def rfmls_form_B(h: Handle, A: CSR, P: Precond) -> torch.Tensor:
+    """The explicit B = A R^{-1} ([m, n] row-major float64)."""
+    Bm = torch.empty((A.m, A.n), dtype=torch.float64, device=A.row_ptr.device)
+    h.check(h._lib.rfmls_form_B(h._h, C.byref(A.c()), P._p, _ptr(Bm), A.n))
+    return Bm
+
+
+def rfmls_solve_explicit(h: Handle, A: CSR, AT: CSR, P: Precond, Bm: torch.Tensor, B: torch.Tensor,
+                         opts: rfmls_opts | None = None, want_residual: bool = True,
+                         x0: torch.Tensor | None = None):
+    """rfmls_solve with the products taken with the explicit Bm (rfmls_form_B)."""
+    single = B.dim() == 1
+    Bb = (B.reshape(1, -1) if single else B).contiguous()
+    nrhs = Bb.shape[0]
+    if x0 is None:
+        X = torch.empty((nrhs, A.n), dtype=torch.float64, device=B.device)
+    else:
+        X = x0.reshape(nrhs, A.n).to(dtype=torch.float64, device=B.device).clone()
+    R = torch.empty((nrhs, A.m), dtype=torch.float64, device=B.device) if want_residual else None
+    infos = (rfmls_info * nrhs)()
+    o = opts if opts is not None else default_opts()
+    if x0 is not None:
+        o = rfmls_opts.from_buffer_copy(o)
+        o.x_init = 1
+    rc = h.check(h._lib.rfmls_solve_explicit(h._h, C.byref(A.c()), C.byref(AT.c()), P._p, _ptr(Bm),
+                                             Bm.stride(0), _ptr(Bb), A.m, nrhs, _ptr(X), A.n, _ptr(R),
+                                             A.m, C.byref(o), infos))
+    info = [infos[k].as_dict() for k in range(nrhs)]
+    if single:
+        return X[0], (R[0] if R is not None else None), info, rc
+    return X, R, info, rc
+
+
 def rfmls_solve_backward(h: Handle, A: CSR, AT: CSR, P: Precond, X: torch.Tensor, Rres: torch.Tensor,
                          G: torch.Tensor, opts: rfmls_opts | None = None, want_db=True, want_dA=True):
     """X [nrhs, n], Rres [nrhs, m], G [nrhs, n].  Returns (dB [nrhs, m], dAval [nnz], [info], status)."""

@@ -331,6 +331,33 @@ rfmls_status rfmls_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* A
   return run_solve(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
 }
 
+rfmls_status rfmls_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond_t* P, double* Bmat,
+                          int64_t ld_bmat) {
+  if (!h) return RFMLS_E_ARG;
+  if (!csr_ok(A) || A->m < 1) return fail(h, RFMLS_E_ARG, "rfmls_form_B: invalid CSR matrix");
+  if (!P || P->n != A->n) return fail(h, RFMLS_E_ARG, "rfmls_form_B: preconditioner size does not match A");
+  if (!Bmat || ld_bmat < A->n) return fail(h, RFMLS_E_ARG, "rfmls_form_B: Bmat null or ld_bmat < n");
+  RFMLS_CHECK(set_device(h));
+  return run_form_B(h, A, P, Bmat, ld_bmat);
+}
+
+rfmls_status rfmls_solve_explicit(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                  const rfmls_precond_t* P, const double* Bmat, int64_t ld_bmat,
+                                  const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                                  double* Rout, int64_t ldr, const rfmls_opts* opts, rfmls_info* info) {
+  if (!h) return RFMLS_E_ARG;
+  rfmls_opts def;
+  rfmls_default_opts(&def);
+  const rfmls_opts* o = opts ? opts : &def;
+  RFMLS_CHECK(check_solve_args(h, A, AT, P, o));
+  if (!Bmat || ld_bmat < A->n) return fail(h, RFMLS_E_ARG, "rfmls_solve_explicit: Bmat null or ld_bmat < n");
+  if (nrhs < 0 || (nrhs > 0 && (!B || !X)) || ldb < A->m || ldx < A->n || (Rout && ldr < A->m))
+    return fail(h, RFMLS_E_ARG, "rfmls_solve_explicit: invalid B / X / leading dimensions");
+  if (nrhs == 0) return RFMLS_OK;
+  RFMLS_CHECK(set_device(h));
+  return run_solve_explicit(h, A, AT, P, Bmat, ld_bmat, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
+}
+
 rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                                   const rfmls_precond_t* P, const double* X, int64_t ldx,
                                   const double* Rres, int64_t ldr, const double* G, int64_t ldg,

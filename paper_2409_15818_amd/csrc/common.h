@@ -121,6 +121,7 @@ enum WsSlot {
   WS_LSQR_BSTATE,
   WS_TRANSPOSE,
   WS_X0,
+  WS_GEMV,
   WS_MISC,
   WS_NUM_SLOTS
 };
@@ -209,6 +210,12 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                        const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
                        double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
                        rfmls_info* info);
+rfmls_status run_solve_explicit(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                const rfmls_precond_t* P, const double* Bm, int64_t ldbm,
+                                const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                                double* Rout, int64_t ldr, const rfmls_opts* o, rfmls_info* info);
+rfmls_status run_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond_t* P, double* Bmat,
+                        int64_t ldb);
 rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                              const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
                              double* X, int64_t ldx, double* Rout, int64_t ldr,

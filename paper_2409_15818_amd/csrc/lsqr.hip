@@ -380,6 +380,92 @@ __global__ void k_pattern_grad(const int64_t* __restrict__ rp, const int32_t* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dense products with the explicit B = A R^{-1} (row-major m x n, Alg. 1 step 4).
+// ---------------------------------------------------------------------------
+// out[i] = sA (B v)[i] - cf prev[i], cf = hcoef (*dcoef); one wavefront per
+// row, four independent partial sums per lane, a fixed-order tree across the
+// wavefront; per-block sums of squares of out into sq.
+__global__ void __launch_bounds__(kThreads)
+    k_gemv(const double* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
+           const double* __restrict__ v, double sA, double hcoef, const double* __restrict__ dcoef,
+           const double* prev, double* out, double* __restrict__ sq, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double cf = hcoef;
+  if (dcoef) cf *= *dcoef;
+  double ss = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / 64) + w; i < m; i += (int64_t)gridDim.x * (kThreads / 64)) {
+    const double* row = B + i * ldb;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t j = lane;
+    for (; j + 192 < n; j += 256) {
+      a0 += row[j] * v[j];
+      a1 += row[j + 64] * v[j + 64];
+      a2 += row[j + 128] * v[j + 128];
+      a3 += row[j + 192] * v[j + 192];
+    }
+    for (; j < n; j += 64) a0 += row[j] * v[j];
+    double t = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) {
+      t = sA * t;
+      if (prev && cf != 0.0) t -= cf * prev[i];
+      out[i] = t;
+      ss += t * t;
+    }
+  }
+  if (sq) {
+    ss = block_sum(ss, scratch);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
+  }
+}
+
+// part[z][j] = sum over the rows i of slice z of B[i][j] u[i]: block (x, z)
+// covers the 2 kThreads columns from 2 kThreads x and rows [z rps, (z + 1) rps).
+__global__ void __launch_bounds__(kThreads)
+    k_gemvT_part(const double* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
+                 const double* __restrict__ u, int64_t rps, double* __restrict__ part,
+                 const int* __restrict__ done) {
+  if (done && *done) return;
+  const int64_t j0 = (int64_t)blockIdx.x * 2 * kThreads + threadIdx.x, j1 = j0 + kThreads;
+  const int64_t r0 = (int64_t)blockIdx.y * rps;
+  const int64_t r1 = r0 + rps < m ? r0 + rps : m;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const double ui = u[i];
+    const double* row = B + i * ldb;
+    if (j0 < n) a0 += row[j0] * ui;
+    if (j1 < n) a1 += row[j1] * ui;
+  }
+  double* p = part + (int64_t)blockIdx.y * n;
+  if (j0 < n) p[j0] = a0;
+  if (j1 < n) p[j1] = a1;
+}
+
+// out[j] = sum_z part[z][j] (in slice order) - cf prev[j]; per-block sums of squares.
+__global__ void __launch_bounds__(kThreads)
+    k_gemvT_reduce(const double* __restrict__ part, int nz, int64_t n, double hcoef,
+                   const double* __restrict__ dcoef, const double* prev, double* out,
+                   double* __restrict__ sq, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  double cf = hcoef;
+  if (dcoef) cf *= *dcoef;
+  double ss = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+    double t = 0.0;
+    for (int z = 0; z < nz; ++z) t += part[(int64_t)z * n + j];
+    if (prev && cf != 0.0) t -= cf * prev[j];
+    out[j] = t;
+    ss += t * t;
+  }
+  if (sq) {
+    ss = block_sum(ss, scratch);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -390,6 +476,9 @@ struct Ctx {
   const rfmls_csr* A;
   const rfmls_csr* AT;
   const rfmls_precond_t* P;
+  const double* Bm = nullptr;  // explicit B = A R^{-1} (row-major), or null: implicit operator
+  int64_t ldbm = 0;
+  double* gpart = nullptr;     // slice partials of B^T u
   hipStream_t st;
   // work vectors
   double *u, *v, *w, *y, *z, *q, *t, *r, *xs;
@@ -468,6 +557,43 @@ static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA,
   return RFMLS_OK;
 }
 
+// Products with the explicit B (Ctx::Bm): out = B v - cf prev over the m rows,
+// and out = B^T u - cf prev over the n columns (slice partials, then a
+// fixed-order sum); each writes per-block sums of squares to sq and returns
+// their count in *nblk.
+constexpr int kGemvTSlices = 64;
+static rfmls_status bmul(Ctx& c, const double* v, double hcoef, const double* dcoef,
+                         const double* prev, double* out, double* sq, const int* done, int* nblk) {
+  const int64_t m = c.A->m, n = c.A->n;
+  const int64_t b = (m + kThreads / 64 - 1) / (kThreads / 64);
+  const unsigned nb = (unsigned)(b < kSpmvMaxBlocks ? (b > 0 ? b : 1) : kSpmvMaxBlocks);
+  Trace tr(c.h, "gemv_B", 8.0 * (double)m * (double)n + 8.0 * (double)n + 8.0 * (double)m * (prev ? 2.0 : 1.0),
+           2.0 * (double)m * (double)n);
+  hipLaunchKernelGGL(k_gemv, dim3(nb), dim3(kThreads), 0, c.st, c.Bm, c.ldbm, m, n, v, 1.0, hcoef, dcoef,
+                     prev, out, sq, done);
+  *nblk = (int)nb;
+  RFMLS_HIP(c.h, hipGetLastError());
+  return RFMLS_OK;
+}
+static rfmls_status btmul(Ctx& c, const double* u, double hcoef, const double* dcoef,
+                          const double* prev, double* out, double* sq, const int* done, int* nblk) {
+  const int64_t m = c.A->m, n = c.A->n;
+  const int64_t rps = (m + kGemvTSlices - 1) / kGemvTSlices;
+  const int nz = (int)((m + rps - 1) / rps);
+  const unsigned nr = vec_blocks(n);
+  {
+    Trace tr(c.h, "gemvT_B", 8.0 * (double)m * (double)n + 8.0 * (double)m + 8.0 * (double)nz * (double)n,
+             2.0 * (double)m * (double)n);
+    hipLaunchKernelGGL(k_gemvT_part, dim3(ceil_div(n, 2 * kThreads), (unsigned)nz), dim3(kThreads), 0, c.st,
+                       c.Bm, c.ldbm, m, n, u, rps, c.gpart, done);
+    hipLaunchKernelGGL(k_gemvT_reduce, dim3(nr), dim3(kThreads), 0, c.st, (const double*)c.gpart, nz, n,
+                       hcoef, dcoef, prev, out, sq, done);
+  }
+  *nblk = (int)nr;
+  RFMLS_HIP(c.h, hipGetLastError());
+  return RFMLS_OK;
+}
+
 // The pinned staging buffer: [0, 1024) uploads, [1024, 4096) downloads.  Every
 // upload is followed by a stream synchronisation before the buffer is reused.
 static rfmls_status upload_state(Ctx& c, const rfmls_opts* o, int64_t itmax) {
@@ -507,10 +633,14 @@ static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, i
                      &c.dst->beta, (const int*)nullptr);
   hipLaunchKernelGGL(k_lsqr_start, dim3(1), dim3(1), 0, c.st, c.dst);
   hipLaunchKernelGGL(k_fill, dim3(vbn), dim3(kThreads), 0, c.st, c.y, n, 0.0);
-  // alpha_1 v_1 = B^T u_1 = X^T (A^T u_1)
-  RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
-  RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 0.0, nullptr, nullptr, c.sqB, done));
-  const int nred = tri_reduce_blocks(n);
+  // alpha_1 v_1 = B^T u_1 = X^T (A^T u_1) (or the explicit B^T u_1)
+  int nred = tri_reduce_blocks(n);
+  if (c.Bm) {
+    RFMLS_CHECK(btmul(c, c.u, 0.0, nullptr, nullptr, c.v, c.sqB, done, &nred));
+  } else {
+    RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
+    RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 0.0, nullptr, nullptr, c.sqB, done));
+  }
   hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
                      &c.dst->alpha, done);
   hipLaunchKernelGGL(k_lsqr_start2, dim3(1), dim3(1), 0, c.st, c.dst);
@@ -526,15 +656,23 @@ static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, i
   int hd = 0;
   RFMLS_CHECK(poll_done(c, &hd));
   for (int64_t it = 0; it < itmax && !hd; ++it) {
-    // beta u = A (X v) - alpha u
-    RFMLS_CHECK(tri_apply(h, c.P, 0, c.v, c.z, 0.0, nullptr, nullptr, nullptr, done));
+    // beta u = A (X v) - alpha u  (or B v - alpha u)
     int nb = 0;
-    RFMLS_CHECK(spmv(c, c.A, c.z, 1.0, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+    if (c.Bm) {
+      RFMLS_CHECK(bmul(c, c.v, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+    } else {
+      RFMLS_CHECK(tri_apply(h, c.P, 0, c.v, c.z, 0.0, nullptr, nullptr, nullptr, done));
+      RFMLS_CHECK(spmv(c, c.A, c.z, 1.0, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+    }
     hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA, nb,
                        &c.dst->beta, done);
-    // alpha v = X^T (A^T u) - beta v
-    RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
-    RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 1.0, &c.dst->beta, c.v, c.sqB, done));
+    // alpha v = X^T (A^T u) - beta v  (or B^T u - beta v)
+    if (c.Bm) {
+      RFMLS_CHECK(btmul(c, c.u, 1.0, &c.dst->beta, c.v, c.v, c.sqB, done, &nred));
+    } else {
+      RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
+      RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 1.0, &c.dst->beta, c.v, c.sqB, done));
+    }
     hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
                        &c.dst->alpha, done);
     hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqW, (int)vbn);
@@ -613,12 +751,21 @@ static rfmls_status host_norm(Ctx& c, const double* v, int64_t len, double* out)
   return RFMLS_OK;
 }
 
-rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
-                       const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
-                       double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
-                       rfmls_info* info) {
+// One right-hand side at a time; Bm (row-major m x n, or null) is the explicit
+// operator B = A R^{-1}.
+static rfmls_status solve_impl(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                               const rfmls_precond_t* P, const double* Bm, int64_t ldbm,
+                               const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                               double* Rout, int64_t ldr, const rfmls_opts* o, rfmls_info* info) {
   Ctx c;
   RFMLS_CHECK(make_ctx(h, A, AT, P, c));
+  if (Bm) {
+    void* p;
+    RFMLS_CHECK(workspace(h, WS_GEMV, sizeof(double) * (size_t)kGemvTSlices * (size_t)A->n, &p));
+    c.Bm = Bm;
+    c.ldbm = ldbm;
+    c.gpart = (double*)p;
+  }
   const int64_t m = A->m, n = A->n;
   const int64_t itmax = o->itmax > 0 ? o->itmax : n;
   const unsigned vbn = vec_blocks(n), vbm = vec_blocks(m);
@@ -676,6 +823,20 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
   }
   RFMLS_HIP(h, hipStreamSynchronize(c.st));
   return ret;
+}
+
+rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                       const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                       double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                       rfmls_info* info) {
+  return solve_impl(h, A, AT, P, nullptr, 0, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
+}
+
+rfmls_status run_solve_explicit(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                const rfmls_precond_t* P, const double* Bm, int64_t ldbm,
+                                const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                                double* Rout, int64_t ldr, const rfmls_opts* o, rfmls_info* info) {
+  return solve_impl(h, A, AT, P, Bm, ldbm, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
 }
 
 // Backward: LSQR on the consistent system B^T lam = c (c = X^T g), operator

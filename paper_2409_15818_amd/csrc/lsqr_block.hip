@@ -873,6 +873,33 @@ static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_c
   return RFMLS_OK;
 }
 
+// ---- the explicit preconditioned matrix B = A X (Alg. 1 step 4) ----
+// out[j][k] = X[j][c0 + k] for k < nb (zero below the diagonal and beyond nb):
+// a 32-column slab of X = R^{-1} in the lockstep block layout, read from the
+// packed upper-triangular tiles.
+template <typename TS>
+__global__ void k_x_slab(const TS* __restrict__ Xpk, int64_t n, int64_t nt, int64_t c0, int nb,
+                         double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / kBlk, c = c0 + e % kBlk;
+    double v = 0.0;
+    if (e % kBlk < nb && j <= c)
+      v = (double)Xpk[tile_index(j / kTile, c / kTile, nt) * (int64_t)(kTile * kTile) +
+                      (j % kTile) * kTile + c % kTile];
+    out[e] = v;
+  }
+}
+// B[i][c0 + k] = in[i][k] for k < nb (rows of B ldb apart)
+__global__ void k_scatter_slab(const double* __restrict__ in, int64_t m, int64_t c0, int nb,
+                               double* __restrict__ B, int64_t ldb) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * kBlk;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / kBlk, k = e % kBlk;
+    if (k < nb) B[i * ldb + c0 + k] = in[e];
+  }
+}
+
 }  // namespace
 
 rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
@@ -1074,6 +1101,31 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
   }
   RFMLS_HIP(h, hipStreamSynchronize(c.st));
   return ret;
+}
+
+// B = A X in slabs of 32 columns: X's slab in the block layout, one lockstep
+// SpMM with A (the kernel the multi-right-hand-side solve uses), the m x 32
+// result scattered into B's rows.
+rfmls_status run_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond_t* P, double* Bmat,
+                        int64_t ldb) {
+  const int64_t m = A->m, n = A->n;
+  BCtx c;
+  RFMLS_CHECK(make_bctx(h, A, A, P, c));
+  const unsigned gn = grid_for(n * kBlk), gm = grid_for(m * kBlk);
+  for (int64_t c0 = 0; c0 < n; c0 += kBlk) {
+    const int nb = (int)(n - c0 < kBlk ? n - c0 : kBlk);
+    if (P->store == RFMLS_F64)
+      hipLaunchKernelGGL(k_x_slab<double>, dim3(gn), dim3(kThreads), 0, c.st, (const double*)P->Xpk, n,
+                         P->nt, c0, nb, c.Xb);
+    else
+      hipLaunchKernelGGL(k_x_slab<float>, dim3(gn), dim3(kThreads), 0, c.st, (const float*)P->Xpk, n,
+                         P->nt, c0, nb, c.Xb);
+    RFMLS_CHECK(spmm(c, A, c.Xb, 1.0, 0.0, nullptr, nullptr, c.U, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(k_scatter_slab, dim3(gm), dim3(kThreads), 0, c.st, (const double*)c.U, m, c0, nb,
+                       Bmat, ldb);
+    RFMLS_HIP(h, hipGetLastError());
+  }
+  return RFMLS_OK;
 }
 
 }  // namespace rfmls

@@ -12,8 +12,9 @@ from dataclasses import dataclass, field
 
 import torch
 
-from .api import (CSR, Handle, Precond, default_opts, rfmls_precond, rfmls_precond_x0, rfmls_sketch,
-                  rfmls_solve, rfmls_solve_backward, rfmls_transpose, sketch_buffer)
+from .api import (CSR, Handle, Precond, default_opts, rfmls_form_B, rfmls_precond, rfmls_precond_x0,
+                  rfmls_sketch, rfmls_solve, rfmls_solve_backward, rfmls_solve_explicit,
+                  rfmls_transpose, sketch_buffer)
 
 
 @dataclass
@@ -29,9 +30,11 @@ class Result:
 
 def csqrp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, qr_dtype: str = "f64",
                r_store: str = "f64", opts=None, AT: CSR | None = None,
-               start: str = "zero") -> Result:
+               start: str = "zero", operator: str = "implicit") -> Result:
     """Alg. 1 on the GPU: s = gamma n sketch rows, seed of the count sketch.
-    start "zero": y^(0) = 0 (Sec. 4.1); "sketch": y^(0) = Q^T (S b) (Remark 3.1)."""
+    start "zero": y^(0) = 0 (Sec. 4.1); "sketch": y^(0) = Q^T (S b) (Remark 3.1).
+    operator "implicit": A (R^{-1} v) and R^{-T} (A^T u) (Remark 3.2); "explicit":
+    the dense B = A R^{-1} formed first (Alg. 1 step 4)."""
     if AT is None:
         AT = rfmls_transpose(h, A)
     if start == "zero":
@@ -46,7 +49,14 @@ def csqrp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, qr_dty
     else:
         raise ValueError(f"unknown start {start!r}")
     del SA
-    X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts, x0=x0)
+    if operator == "explicit":
+        Bm = rfmls_form_B(h, A, P)
+        X, R, info, rc = rfmls_solve_explicit(h, A, AT, P, Bm, b, opts, x0=x0)
+        del Bm
+    elif operator == "implicit":
+        X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts, x0=x0)
+    else:
+        raise ValueError(f"unknown operator {operator!r}")
     return Result(X, R, info, rc, P, AT)
 
 

@@ -1,6 +1,7 @@
 """Parity at the full sizes the benchmark runs: the 8x8-box 2D Poisson system
-(m 112,640, n 12,800, 24.3M nonzeros, s 51,200) and the 4x4x4-box 3D one
-(m 165,888, n 25,600, 82.9M nonzeros, s 51,200), in the launch configuration
+(m 112,640, n 12,800, 24.3M nonzeros, s 51,200), the 4x4x4-box 3D one
+(m 165,888, n 25,600, 82.9M nonzeros, s 51,200) and the 2x2x2-box 3D Helmholtz
+one (m 83,200, n 3,200, 37.1M nonzeros, s 12,800), in the launch configuration
 bench.py times.
 
 Against the oracle:
@@ -11,7 +12,8 @@ Against the oracle:
   * the final true residual ||b - A x|| and the PDE error at 10^4 sample
     points against the stored oracle results in tests/golden/ (written by
     tests/golden/make_golden.py, which calls only the oracle), from the zero
-    and from the sketched starting point.
+    and from the sketched starting point, and with the explicit B = A R^{-1}
+    (the least-squares optimum is the same for all).
 
 Residual tolerance: 1e-10 relative where cond(A) u^2-level effects stay below
 it (3D system, pivot ratio min|r_jj|/max|r_jj| = 1.7e-7).  The 2D system has a
@@ -26,7 +28,7 @@ import numpy as np
 import pytest
 
 from oracle import countsketch, pipeline
-from rfmgen import build_config, exact_solution, feature_eval, sample_points
+from rfmgen import build_config, feature_eval, sample_points
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +37,7 @@ R = pytest.importorskip("paper_2409_15818_amd")
 
 SEED = 2
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-RES_TOL = {"poisson2d_8x8": 1e-6, "poisson3d_4x4x4": 1e-10}
+RES_TOL = {"poisson2d_8x8": 1e-6, "poisson3d_4x4x4": 1e-10, "helmholtz3d_2x2x2": 1e-10}
 
 _cache = {}
 
@@ -74,18 +76,22 @@ def _golden(name):
 
 # both starting points (y0 = 0, Sec. 4.1; y0 = Q^T S b, Remark 3.1) reach the
 # same least-squares optimum, so both are gated on the same stored oracle result
-@pytest.mark.parametrize("name,prec,start", [("poisson2d_8x8", "f64", "zero"),
-                                             ("poisson2d_8x8", "f64", "sketch"),
-                                             ("poisson3d_4x4x4", "f64", "zero"),
-                                             ("poisson3d_4x4x4", "f32", "zero"),
-                                             ("poisson3d_4x4x4", "f32", "sketch")])
-def test_fullsize_solve_matches_oracle(handle, name, prec, start):
+@pytest.mark.parametrize("name,prec,start,op", [("poisson2d_8x8", "f64", "zero", "implicit"),
+                                                ("poisson2d_8x8", "f64", "sketch", "implicit"),
+                                                ("poisson2d_8x8", "f64", "zero", "explicit"),
+                                                ("poisson3d_4x4x4", "f64", "zero", "implicit"),
+                                                ("poisson3d_4x4x4", "f32", "zero", "implicit"),
+                                                ("poisson3d_4x4x4", "f32", "sketch", "implicit"),
+                                                ("helmholtz3d_2x2x2", "f64", "zero", "implicit"),
+                                                ("helmholtz3d_2x2x2", "f64", "sketch", "implicit"),
+                                                ("helmholtz3d_2x2x2", "f32", "sketch", "implicit")])
+def test_fullsize_solve_matches_oracle(handle, name, prec, start, op):
     S, s, A = _system(name)
     gold = _golden(name)
     assert (gold["m"], gold["n"], gold["nnz"], gold["s"]) == (S.m, S.n, S.nnz, s)
     opts = R.default_opts(refine=gold["refine"])
     res = R.csqrp_lsqr(handle, A, torch.tensor(S.b[0], device="cuda"), s, SEED,
-                       qr_dtype=prec, r_store=prec, opts=opts, start=start)
+                       qr_dtype=prec, r_store=prec, opts=opts, start=start, operator=op)
     info = res.info[0]
     assert res.status == 0 and info["istop"] in (1, 2)
     x = res.x.cpu().numpy()
@@ -97,6 +103,6 @@ def test_fullsize_solve_matches_oracle(handle, name, prec, start):
         (met["normr"], gold["normr"])
     pts = sample_points(S.d)
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
-    l2 = pipeline.l2_error(E, x, exact_solution(pts))
+    l2 = pipeline.l2_error(E, x, S.exact(pts))
     assert l2 <= 1.1 * gold["l2_error"], (l2, gold["l2_error"])
     del res

@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 R = pytest.importorskip("paper_2409_15818_amd")
 
 SEED = 2
-SMALL = ["poisson2d_2x2", "poisson2d_3x3", "poisson3d_2x2x2"]
+SMALL = ["poisson2d_2x2", "poisson2d_3x3", "poisson3d_2x2x2", "helmholtz3d_2x2x2_small"]
 
 
 def gpu_csr(rp, col, val, m, n):
@@ -185,7 +185,7 @@ def _oracle(S, s, **kw):
 def _l2(S, x):
     pts = sample_points(S.d)
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
-    return pipeline.l2_error(E, x, exact_solution(pts))
+    return pipeline.l2_error(E, x, S.exact(pts))
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -319,6 +319,51 @@ def test_lockstep_from_sketched_starts(handle):
         assert abs(info[k]["normr"] - orc["normr"]) <= tol, (k, info[k]["normr"], orc["normr"])
         # lockstep and one-at-a-time agree
         assert abs(info[k]["normr"] - infos[k]["normr"]) <= tol
+
+
+# ------------------------------------------- explicit B = A R^{-1} (Alg. 1 step 4)
+@pytest.mark.parametrize("name", SMALL + ["random"])
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_form_B_is_A_times_stored_inverse(handle, name, store):
+    if name == "random":
+        m, n = 700, 150  # ragged 32-column slabs and 64-tiles
+        Ad = dense_with_condition(m, n, 1e3, seed=31)
+        rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+        A, s = gpu_csr(rp, col, val, m, n), 4 * n
+    else:
+        S, s, A = system(name)
+        Ad = dense_from_csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, s, SEED)[0], "f64", store)
+    Xg = R.rfmls_precond_export_Rinv(handle, P).cpu().numpy()
+    Bg = R.rfmls_form_B(handle, A, P).cpu().numpy()
+    # each entry is a dot product of a row of A with a column of the stored X,
+    # summed in some order: forward error within (row length) u |A| |X|
+    nnz_row = int(np.max(np.count_nonzero(Ad, axis=1)))
+    bound = 2 * nnz_row * 1.1e-16 * (np.abs(Ad) @ np.abs(Xg))
+    assert np.all(np.abs(Bg - Ad @ Xg) <= bound + 1e-300)
+    if name == "random" and store == "f64":
+        # and it is the paper's B = A R^{-1} (triangular solve by the oracle)
+        pre = pipeline.precondition(rp, col, val, m, n, s, SEED)
+        Bo = sla.solve_triangular(pre["R"], Ad.T, trans="T").T
+        assert np.abs(Bg - Bo).max() <= 1e-11 * np.abs(Bo).max()
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("start", ["zero", "sketch"])
+def test_pipeline_with_explicit_operator(handle, name, start):
+    S, s, A = system(name)
+    b = torch.tensor(S.b[0], device="cuda")
+    res = R.csqrp_lsqr(handle, A, b, s, SEED, start=start, operator="explicit")
+    info = res.info[0]
+    orc = _oracle(S, s, start=start, operator="explicit")
+    assert info["istop"] in (1, 2)
+    assert abs(info["normr"] - orc["normr"]) <= 1e-10 * orc["normr"], (info["normr"], orc["normr"])
+    x = res.x.cpu().numpy()
+    assert _l2(S, x) <= 1.1 * _l2(S, orc["x"])
+    assert abs(info["itn_first"] - orc["itn_sweeps"][0]) <= 2
+    # the same least-squares optimum as the implicit operator's
+    imp = _oracle(S, s)
+    assert abs(info["normr"] - imp["normr"]) <= 1e-10 * imp["normr"]
 
 
 def test_solve_deterministic_and_multi_rhs(handle):
