@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for the sketch-preconditioned least-squares path.
 
 This package only *builds inputs*: random-feature-method (RFM) collocation
-systems for the Poisson problem, test points, exact solutions and a few
+systems for the Poisson and Helmholtz problems, test points, exact solutions and a few
 structured test matrices.  It contains none of the solver's arithmetic (no
 sketch, no QR, no LSQR); both the CPU oracle and the GPU path consume what it
 produces.

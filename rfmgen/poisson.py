@@ -1,4 +1,5 @@
-"""Random-feature-method collocation systems for -Laplace(u) = f on the unit cube.
+"""Random-feature-method collocation systems for -Laplace(u) = f (and the 3D
+Helmholtz problem of Example 4.5) on the unit cube.
 
 Discretisation (Sec. 2.1 of the paper, eqs. (2.1)-(2.3); hyper-parameters of
 Appendix B): the domain [0,1]^d is split into N^d boxes with centre c_q and
@@ -25,6 +26,16 @@ lower box of an interface always has the smaller index).
 Manufactured solution u = sin(k pi x_0) prod_{i>0} sin(pi x_i), so
 f = (k^2 + d - 1) pi^2 u.  k = 1 gives the single right-hand side; k = 1..32 the
 batched one.
+
+The same construction with pde="helmholtz" gives the three-dimensional
+Helmholtz problem of Example 4.5: Laplace(u) + kappa^2 u = f with Dirichlet
+data, kappa = 0.5 (the paper's wave number), interior rows
+Laplace(phi) + kappa^2 phi = -2 t (1 - t^2) |w|^2 / r^2 + kappa^2 t, and the
+paper's manufactured solution
+    u = -a prod_i cos(pi x_i + 2 pi/5)
+        -b cos(pi x + 2 pi/5) cos(2 pi y + 2 pi/5) cos(4 pi z + 2 pi/5),
+mode 1 = low frequency (a, b) = (1, 0), mode 2 = high (0, 1), mode 3 = mixed
+(0.5, 0.5); f = (kappa^2 - 3 pi^2) u_a + (kappa^2 - 21 pi^2) u_b.
 """
 
 from __future__ import annotations
@@ -53,6 +64,12 @@ class RFMSystem:
     W: np.ndarray  # float64[N^d, J, d]
     B0: np.ndarray  # float64[N^d, J]
     counts: dict = field(default_factory=dict)
+    pde: str = "poisson"
+    kwave: float = 0.0
+
+    def exact(self, pts: np.ndarray, k: int = 1) -> np.ndarray:
+        """The manufactured solution of right-hand side mode k at pts."""
+        return exact_solution(pts, k, self.pde)
 
     @property
     def nnz(self) -> int:
@@ -76,6 +93,11 @@ CONFIGS = {
     "poisson2d_3x3": dict(d=2, N=3, J=70, Q=18, gamma=4),  # n=630
     "poisson2d_4x4": dict(d=2, N=4, J=100, Q=24, gamma=4),  # n=1,600
     "poisson3d_2x2x2": dict(d=3, N=2, J=90, Q=8, gamma=2),  # n=720
+    # Example 4.5 (3D Helmholtz, kappa = 0.5) on the paper's 2x2x2 boxes with its
+    # smallest feature count (J = 400 per box, 20 points per axis):
+    #   m = 64,000 + 9,600 + 9,600 = 83,200, n = 3,200, s = 4n
+    "helmholtz3d_2x2x2": dict(d=3, N=2, J=400, Q=20, gamma=4, pde="helmholtz", kwave=0.5),
+    "helmholtz3d_2x2x2_small": dict(d=3, N=2, J=90, Q=8, gamma=2, pde="helmholtz", kwave=0.5),  # n=720
 }
 
 FEATURE_SEED = 1
@@ -97,14 +119,34 @@ def _box_index(ijk, N):
     return idx
 
 
-def exact_solution(pts: np.ndarray, k: int = 1) -> np.ndarray:
+HELMHOLTZ_MODES = {1: (1.0, 0.0), 2: (0.0, 1.0), 3: (0.5, 0.5)}  # low, high, mixed (a, b)
+
+
+def _helmholtz_parts(pts: np.ndarray):
+    ph = 2.0 * np.pi / 5.0
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    ua = -np.cos(np.pi * x + ph) * np.cos(np.pi * y + ph) * np.cos(np.pi * z + ph)
+    ub = -np.cos(np.pi * x + ph) * np.cos(2 * np.pi * y + ph) * np.cos(4 * np.pi * z + ph)
+    return ua, ub
+
+
+def exact_solution(pts: np.ndarray, k: int = 1, pde: str = "poisson") -> np.ndarray:
+    if pde == "helmholtz":
+        a, b = HELMHOLTZ_MODES[k]
+        ua, ub = _helmholtz_parts(pts)
+        return a * ua + b * ub
     u = np.sin(k * np.pi * pts[:, 0])
     for i in range(1, pts.shape[1]):
         u = u * np.sin(np.pi * pts[:, i])
     return u
 
 
-def _rhs_f(pts: np.ndarray, k: int) -> np.ndarray:
+def _rhs_f(pts: np.ndarray, k: int, pde: str = "poisson", kwave: float = 0.0) -> np.ndarray:
+    if pde == "helmholtz":
+        a, b = HELMHOLTZ_MODES[k]
+        ua, ub = _helmholtz_parts(pts)
+        # Laplace(u_a) = -3 pi^2 u_a, Laplace(u_b) = -(1 + 4 + 16) pi^2 u_b
+        return a * (kwave ** 2 - 3 * np.pi ** 2) * ua + b * (kwave ** 2 - 21 * np.pi ** 2) * ub
     d = pts.shape[1]
     return (k * k + d - 1) * np.pi ** 2 * exact_solution(pts, k)
 
@@ -115,7 +157,10 @@ def _features(sys_c: np.ndarray, r: float, W: np.ndarray, B0: np.ndarray, pts: n
     return np.tanh(z)
 
 
-def poisson_system(d: int, N: int, J: int, Q: int, modes=(1,), seed: int = FEATURE_SEED) -> RFMSystem:
+def poisson_system(d: int, N: int, J: int, Q: int, modes=(1,), seed: int = FEATURE_SEED,
+                   pde: str = "poisson", kwave: float = 0.0) -> RFMSystem:
+    if pde not in ("poisson", "helmholtz") or (pde == "helmholtz" and d != 3):
+        raise ValueError("pde is 'poisson' (d = 2, 3) or 'helmholtz' (d = 3)")
     nbox = N ** d
     r = 1.0 / (2 * N)
     boxes = list(itertools.product(range(N), repeat=d))
@@ -142,9 +187,10 @@ def poisson_system(d: int, N: int, J: int, Q: int, modes=(1,), seed: int = FEATU
         pts = _cell_centres(lo, hi, Q)
         t = _features(centres[q], r, W[q], B0[q], pts)
         wn2 = (W[q] ** 2).sum(axis=1) / (r * r)
-        vals = 2.0 * t * (1.0 - t * t) * wn2[None, :]
+        lap = 2.0 * t * (1.0 - t * t) * wn2[None, :]  # -Laplace(phi)
+        vals = lap if pde == "poisson" else kwave ** 2 * t - lap
         cols = np.broadcast_to(q * J + np.arange(J, dtype=np.int64), vals.shape)
-        add(cols, vals, np.stack([_rhs_f(pts, k) for k in modes], axis=0))
+        add(cols, vals, np.stack([_rhs_f(pts, k, pde, kwave) for k in modes], axis=0))
         counts["interior"] += pts.shape[0]
 
     # Dirichlet rows
@@ -162,7 +208,7 @@ def poisson_system(d: int, N: int, J: int, Q: int, modes=(1,), seed: int = FEATU
                 pts[:, axis] = float(side)
                 t = _features(centres[q], r, W[q], B0[q], pts)
                 cols = np.broadcast_to(q * J + np.arange(J, dtype=np.int64), t.shape)
-                add(cols, t, np.stack([exact_solution(pts, k) for k in modes], axis=0))
+                add(cols, t, np.stack([exact_solution(pts, k, pde) for k in modes], axis=0))
                 counts["dirichlet"] += pts.shape[0]
 
     # interface rows (C0 then C1 per point)
@@ -203,13 +249,15 @@ def poisson_system(d: int, N: int, J: int, Q: int, modes=(1,), seed: int = FEATU
     val = np.concatenate([v.reshape(-1) for v in blocks_vals]).astype(np.float64)
     b = np.ascontiguousarray(np.concatenate(rhs, axis=1))
     return RFMSystem(d=d, N=N, J=J, Q=Q, m=m, n=n, row_ptr=row_ptr, col=col, val=val, b=b,
-                     modes=modes, centres=centres, radius=r, W=W, B0=B0, counts=counts)
+                     modes=modes, centres=centres, radius=r, W=W, B0=B0, counts=counts, pde=pde,
+                     kwave=kwave)
 
 
 def build_config(name: str, modes=(1,)) -> tuple[RFMSystem, int]:
     """Return (system, s) for a named workload; s = gamma * n sketch rows."""
     c = CONFIGS[name]
-    sysm = poisson_system(c["d"], c["N"], c["J"], c["Q"], modes=modes)
+    sysm = poisson_system(c["d"], c["N"], c["J"], c["Q"], modes=modes, pde=c.get("pde", "poisson"),
+                          kwave=c.get("kwave", 0.0))
     return sysm, int(c["gamma"] * sysm.n)
 
 

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import countsketch, pipeline, qr  # noqa: E402
-from rfmgen import build_config, exact_solution, feature_eval, sample_points  # noqa: E402
+from rfmgen import build_config, feature_eval, sample_points  # noqa: E402
 
 SKETCH_SEED = 2
 
@@ -41,7 +41,7 @@ def main(name: str, refine: int = 2):
         workload=name, m=S.m, n=S.n, nnz=S.nnz, s=s, sketch_seed=SKETCH_SEED, refine=refine,
         itn_sweeps=[r.itn for r in results], istop_sweeps=[r.istop for r in results],
         normb=float(np.linalg.norm(S.b[0])), normr=met["normr"], relres=met["relres"],
-        normal_relres=met["normal_relres"], l2_error=pipeline.l2_error(E, x, exact_solution(pts)),
+        normal_relres=met["normal_relres"], l2_error=pipeline.l2_error(E, x, S.exact(pts)),
         rdiag_min=float(np.abs(np.diag(R)).min()), rdiag_max=float(np.abs(np.diag(R)).max()),
         seconds=dict(sketch=t1 - t0, qr=t2 - t1, lsqr=t3 - t2),
     )

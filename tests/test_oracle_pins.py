@@ -380,3 +380,48 @@ def test_manufactured_solution_error_decreases_with_features():
         errs.append(pipeline.l2_error(E, out["x"], exact_solution(pts)))
     assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:])), errs
     assert errs[-1] < 1e-2
+
+
+# ------------------------------------------- Helmholtz inputs (Example 4.5)
+def _fd_laplacian(fun, p, h=1e-3):
+    lap = np.zeros(p.shape[0])
+    for a in range(p.shape[1]):
+        e = np.zeros(p.shape[1])
+        e[a] = h
+        lap += (fun(p + e) - 2.0 * fun(p) + fun(p - e)) / (h * h)
+    return lap
+
+
+def test_helmholtz_rhs_and_rows_match_finite_differences():
+    S, _ = build_config("helmholtz3d_2x2x2_small", modes=(1, 2, 3))
+    pts = np.random.default_rng(5).uniform(0.1, 0.9, (40, 3))
+    for k in (1, 2, 3):
+        # f = Laplace(u) + kappa^2 u (second-order differences, h = 1e-3)
+        f_fd = _fd_laplacian(lambda q: S.exact(q, k), pts) + S.kwave ** 2 * S.exact(pts, k)
+        f_gen = build_config.__globals__["_rhs_f"](pts, k, "helmholtz", S.kwave)
+        assert np.abs(f_fd - f_gen).max() <= 1e-4 * np.abs(f_gen).max()
+    # an interior row holds Laplace(phi_j) + kappa^2 phi_j of box 0's features at its point
+    row = 5
+    c0 = S.centres[0]
+    Q = S.Q
+    ijk = np.unravel_index(row, (Q, Q, Q))
+    p = (c0 - S.radius + (np.array(ijk) + 0.5) * 2 * S.radius / Q)[None, :]
+    vals = S.val[S.row_ptr[row]:S.row_ptr[row + 1]]
+    for j in (0, 7, S.J - 1):
+        phi = lambda q: np.tanh(((q - c0) / S.radius) @ S.W[0][j] + S.B0[0][j])
+        want = _fd_laplacian(phi, p)[0] + S.kwave ** 2 * phi(p)[0]
+        assert abs(vals[j] - want) <= 1e-4 * max(1.0, abs(want))
+    # Dirichlet data is the exact solution
+    assert S.counts == {"interior": 4096, "dirichlet": 1536, "interface": 1536}
+
+
+def test_helmholtz_manufactured_error_decreases_with_features():
+    pts = sample_points(3, 2000)
+    errs = []
+    for J in (50, 100, 200):  # measured 0.50, 0.10, 0.014 (12 points per axis)
+        S = poisson_system(3, 2, J, 12, pde="helmholtz", kwave=0.5)
+        out = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, 4 * S.n, 2)
+        E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+        errs.append(pipeline.l2_error(E, out["x"], S.exact(pts)))
+    assert all(e2 < 0.5 * e1 for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 0.05
