@@ -1,4 +1,5 @@
-"""The CSQRP-LSQR solve (Alg. 1) and the quantities Sec. 4.1 reports.
+"""The CSQRP-LSQR solve (Alg. 1), its SVD variant CSSVDP-LSQR (Alg. 2) and
+the quantities Sec. 4.1 reports.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -14,6 +15,10 @@ Remark 3.3 observes that the implicit operator loses accuracy on ill-conditioned
 problems; the reading adopted here recovers it with iterative refinement: after
 a sweep, the true residual r = b - A x is recomputed and the same preconditioned
 LSQR solves min ||A d - r||, x <- x + d (`refine` extra sweeps, default 1).
+
+CSSVDP-LSQR (Alg. 2) replaces step 3 by the truncated SVD of SA and R^{-1} by
+P = V_r Sigma_r^{-1} (svd.svd_preconditioner): LSQR runs on B = A P, applied
+implicitly as B v = A (P v), B^T u = P^T (A^T u), and x = P y.
 
 Starting point (Alg. 1 takes y^(0) as an input).  Sec. 4.1 starts from zero;
 Remark 3.1 offers y^(0) = Q^T (S b), obtained by carrying S b through the
@@ -33,7 +38,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from . import countsketch, qr
+from . import countsketch, qr, svd
 from .lsqr import lsqr
 
 
@@ -89,6 +94,17 @@ def lsqr_on_preconditioned(A, R, b, atol=1e-10, btol=1e-10, conlim=1e8, itmax=No
     return x, res
 
 
+def lsqr_on_svd_preconditioned(A, P, b, atol=1e-10, btol=1e-10, conlim=1e8, itmax=None,
+                               keep_history=False):
+    """Alg. 2 steps 4-6 for one right-hand side with B = A P applied implicitly;
+    returns (x, LSQRResult)."""
+    AT = A.T.tocsr()
+    r = P.shape[1]
+    res = lsqr(lambda v: A @ (P @ v), lambda u: P.T @ (AT @ u), b, r, atol=atol, btol=btol,
+               conlim=conlim, itmax=A.shape[1] if itmax is None else itmax, keep_history=keep_history)
+    return P @ res.y, res
+
+
 def residual_metrics(A, x, b):
     r = b - A @ x
     nb = float(np.linalg.norm(b))
@@ -122,21 +138,47 @@ def sketched_start(SA, SB, check_rank=True):
     return R, Y0, X0
 
 
-def refined_lsqr(A, R, b, refine=1, x0=None, **kw):
+def refined_lsqr(A, R, b, refine=1, x0=None, P=None, **kw):
     """LSQR sweeps with iterative refinement on the true residual, from x = 0
-    or from x0; returns (x, [results])."""
+    or from x0; returns (x, [results]).  With P given (CSSVDP-LSQR) the
+    preconditioner is P instead of R^{-1}."""
     b = np.asarray(b, np.float64)
     x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
     r = b.copy() if x0 is None else b - A @ x
     results = []
     for sweep in range(1 + refine):
-        dx, res = lsqr_on_preconditioned(A, R, r, **kw)
+        if P is None:
+            dx, res = lsqr_on_preconditioned(A, R, r, **kw)
+        else:
+            kw.pop("operator", None)
+            dx, res = lsqr_on_svd_preconditioned(A, P, r, **kw)
         results.append(res)
         x = x + dx
         r = b - A @ x
         if res.itn == 0:
             break
     return x, results
+
+
+def solve_svd(row_ptr, col, val, b, m, n, s, seed, rcond=None, atol=1e-10, btol=1e-10,
+              conlim=1e8, itmax=None, refine=1, hash_in=None):
+    """Full CSSVDP-LSQR (Alg. 2) for one right-hand side from y^(0) = 0, float64;
+    returns a dict of results (sigma, V, rank r, P, x and the residual metrics)."""
+    if hash_in is None:
+        h, sign = countsketch.hash_sign(m, s, seed)
+    else:
+        h, sign = hash_in
+    SA, _ = countsketch.sketch_dense(row_ptr, col, val, h, sign, s, n)
+    sigma, V, r, P = svd.svd_preconditioner(SA, rcond)
+    A = csr(row_ptr, col, val, m, n)
+    x, results = refined_lsqr(A, None, b, refine=refine, P=P, atol=atol, btol=btol,
+                              conlim=conlim, itmax=itmax)
+    res = results[0]
+    out = dict(x=x, itn=sum(q.itn for q in results), itn_sweeps=[q.itn for q in results],
+               istop=res.istop, acond=res.acond, sigma=sigma, V=V, rank=r, P=P, SA=SA, h=h,
+               sign=sign)
+    out.update(residual_metrics(A, x, np.asarray(b, np.float64)))
+    return out
 
 
 def solve(row_ptr, col, val, b, m, n, s, seed, atol=1e-10, btol=1e-10, conlim=1e8, itmax=None,

@@ -15,7 +15,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle import backward, countsketch, pipeline, qr
+from oracle import backward, countsketch, pipeline, qr, svd
 from oracle.lsqr import lsqr
 from rfmgen import (build_config, csr_from_dense, dense_from_csr, dense_with_condition,
                     exact_solution, feature_eval, poisson_system, random_csr, sample_points)
@@ -237,6 +237,115 @@ def test_refined_solve_reaches_dense_optimum():
     out = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1)
     assert abs(out["normr"] - rstar) <= 1e-10 * rstar
     assert out["istop"] in (1, 2)
+
+
+# --------------------------------------------- SVD preconditioner (Alg. 2)
+def test_svd_2x2_closed_form():
+    # singular values of [[a, b], [c, d]]: (sqrt((a+d)^2+(b-c)^2) +- sqrt((a-d)^2+(b+c)^2)) / 2
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        a, b, c, d = rng.standard_normal(4)
+        p, q = np.hypot(a + d, b - c), np.hypot(a - d, b + c)
+        sigma, V, r, P = svd.svd_preconditioner(np.array([[a, b], [c, d]]))
+        assert np.allclose(sigma, [(p + q) / 2, abs(p - q) / 2], rtol=1e-13, atol=1e-15)
+        assert r == 2 and P.shape == (2, 2)
+
+
+def _constructed(s, sig, seed):
+    # U (s x n) and V (n x n) with orthonormal columns from Householder QR of
+    # random matrices; SA = U diag(sig) V^T has exactly the singular values sig
+    rng = np.random.default_rng(seed)
+    n = len(sig)
+    U, _ = np.linalg.qr(rng.standard_normal((s, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (U * np.asarray(sig)) @ V.T, U, V
+
+
+def test_svd_recovers_constructed_factors():
+    sig = np.geomspace(1.0, 1e-6, 8)
+    SA, U, V = _constructed(60, sig, 3)
+    sigma, Vo, r, P = svd.svd_preconditioner(SA)
+    assert r == 8
+    assert np.max(np.abs(sigma - sig)) <= 1e-14
+    # right singular vectors equal the construction's up to sign (distinct sigma)
+    assert np.allclose(np.abs(np.sum(Vo * V, axis=0)), 1.0, atol=1e-9)
+    # P = V Sigma^{-1}: SA P = U up to column signs, i.e. orthonormal columns
+    SP = SA @ P
+    assert np.max(np.abs(SP.T @ SP - np.eye(8))) <= 1e-9
+    assert np.allclose(np.abs(np.sum(SP * U, axis=0)), 1.0, atol=1e-9)
+
+
+def test_svd_rank_truncation():
+    sig = np.array([1.0, 0.3, 1e-9, 1e-17, 0.0])
+    SA, U, V = _constructed(40, sig, 5)
+    sigma, Vo, r, P = svd.svd_preconditioner(SA)  # rcond = n u = 5.6e-16
+    assert r == 3 and P.shape == (5, 3)
+    SP = SA @ P
+    assert np.max(np.abs(SP.T @ SP - np.eye(3))) <= 1e-6  # sigma_3 = 1e-9 amplifies u by 1e9
+    assert svd.svd_preconditioner(SA, rcond=1e-6)[2] == 2
+    # the threshold is relative to sigma_1: scaling SA keeps the rank
+    assert svd.svd_preconditioner(1e3 * SA)[2] == 3
+    assert svd.svd_preconditioner(1e-3 * SA)[2] == 3
+    assert svd.svd_preconditioner(np.zeros((6, 3)))[2] == 0
+
+
+def test_cssvdp_injective_sketch_gives_one_iteration():
+    A, b = _small_problem(m=80, n=10, kappa=1e6)
+    rp, col, val = csr_from_dense(A)
+    m, n = A.shape
+    h = np.random.default_rng(3).permutation(m).astype(np.int32)
+    sign = np.where(np.arange(m) % 3 == 0, -1, 1).astype(np.int8)
+    SA, _ = countsketch.sketch_dense(rp, col, val, h, sign, m, n)
+    _, _, r, P = svd.svd_preconditioner(SA)
+    x, res = pipeline.lsqr_on_svd_preconditioned(sp.csr_matrix(A), P, b)
+    assert r == n and res.itn == 1
+    Q, RA = np.linalg.qr(A)
+    xs = sla.solve_triangular(RA, Q.T @ b)
+    assert np.linalg.norm(A @ (x - xs)) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e8, 1e14])
+def test_svd_preconditioned_condition_independent_of_kappa(kappa):
+    m, n = 3000, 50
+    A = dense_with_condition(m, n, kappa, seed=11)
+    rp, col, val = csr_from_dense(A, keep_zeros=True)
+    h, sign = countsketch.hash_sign(m, 4 * n, 2)
+    SA, _ = countsketch.sketch_dense(rp, col, val, h, sign, 4 * n, n)
+    _, _, r, P = svd.svd_preconditioner(SA)
+    sv = np.linalg.svd(A @ P, compute_uv=False)
+    assert r == n and sv[0] / sv[-1] < 10.0
+
+
+def test_cssvdp_minimum_norm_with_a_duplicated_column():
+    # Sec. 3.2 / Thm 3.4: a rank-deficient A; duplicating column j of a full-rank
+    # A0 leaves the residual unchanged and the minimum-norm solution splits
+    # A0's coefficient x0_j equally between the two copies.
+    A0, b = _small_problem(m=300, n=12, kappa=1e3)
+    j = 4
+    A = np.hstack([A0, A0[:, [j]]])
+    m, n = A.shape
+    rp, col, val = csr_from_dense(A)
+    out = pipeline.solve_svd(rp, col, val, b, m, n, 4 * n, seed=9, rcond=1e-12)
+    assert out["rank"] == n - 1
+    Q, R0 = np.linalg.qr(A0)
+    x0 = sla.solve_triangular(R0, Q.T @ b)
+    x = out["x"]
+    assert abs(x[j] - x[n - 1]) <= 1e-9 * np.abs(x0).max()
+    expect = x0.copy()
+    expect[j] = x0[j] / 2
+    assert np.max(np.abs(x[:n - 1] - expect)) <= 1e-9 * np.abs(x0).max()
+    # the QR preconditioner cannot be formed for this A
+    with pytest.raises(qr.RankDeficient):
+        pipeline.precondition(rp, col, val, m, n, 4 * n, seed=9)
+
+
+def test_cssvdp_and_csqrp_reach_the_same_optimum():
+    S, s = build_config("poisson2d_2x2")
+    qo = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1)
+    so = pipeline.solve_svd(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1)
+    assert so["rank"] == S.n
+    assert abs(so["normr"] - qo["normr"]) <= 1e-10 * qo["normr"]
+    assert so["istop"] in (1, 2)
 
 
 # ------------------------------------------------- starting point (Remark 3.1)
