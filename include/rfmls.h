@@ -12,6 +12,8 @@
  *                  R^{-1} (upper triangular) as the preconditioner
  *                  (rfmls_precond_x0 also returns the sketched     (Remark 3.1)
  *                  solution x^(0) = R^{-1} Q^T S b as a starting point)
+ *   rfmls_precond_svd  CSSVDP-LSQR's preconditioner instead:     (Alg. 2 step 3)
+ *                  the truncated SVD of SA through R, P = V_r Sigma_r^{-1}
  *   rfmls_solve    LSQR on A R^{-1} (applied implicitly,          (Alg. 1 steps 4-6,
  *                  Remark 3.2) from y = 0 or a given x, x = R^{-1} y, Remarks 3.2-3.3, Sec. 4.1)
  *                  iterative refinement on the true residual
@@ -178,13 +180,45 @@ rfmls_status rfmls_precond_x0(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype
                               rfmls_dtype r_store, void *SA, int64_t ld_sa, const double *SB,
                               int64_t nrhs, double *X0, int64_t ldx0,
                               rfmls_precond_t **P_out /* [host] out */);
+/* SVD preconditioner of CSSVDP-LSQR (Alg. 2 step 3; Sec. 3.2, Thm 3.4).
+ * Householder QR of SA (s x n, s >= n, row-major float64, ld_sa >= n;
+ * overwritten) as rfmls_precond, then the SVD of R (SA = Q R, so SA and R share
+ * Sigma and V) by one-sided Jacobi on the GPU, and the preconditioner
+ * P = V_r Sigma_r^{-1}: the columns whose singular value is at most
+ * rcond * sigma_1 are dropped (stored as zero columns, so LSQR never moves
+ * along them), r = the number kept.  rcond <= 0 selects n u (u = 2^-53);
+ * rcond >= 1 is rejected.  P is stored n x n in p_store precision and used by
+ * rfmls_solve, rfmls_solve_explicit and rfmls_form_B in place of R^{-1}, and
+ * by rfmls_solve_backward when r = n.  No rank check: a rank-deficient A gives
+ * the minimum-norm solution of the truncated problem.  n <= 16384.
+ *   max_sweeps  limit on Jacobi sweeps (<= 0: 60); if the columns are still
+ *               not orthogonal to the tolerance, *P_out is returned anyway
+ *               with the warning RFMLS_W_NOCONV.
+ * Synchronises the stream once per sweep.  RFMLS_E_RANK if every singular
+ * value is below the threshold; on an error nothing is returned in *P_out. */
+rfmls_status rfmls_precond_svd(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype p_store, void *SA,
+                               int64_t ld_sa, double rcond, int max_sweeps,
+                               rfmls_precond_t **P_out /* [host] out */);
+/* [host] Numerical rank r, Jacobi sweeps taken and the last sweep's largest
+ * |cos| between two columns of R V; any pointer may be null.  RFMLS_E_ARG for a
+ * QR preconditioner. */
+rfmls_status rfmls_precond_svd_stats(const rfmls_precond_t *P, int64_t *rank, int *sweeps,
+                                     double *off);
 void rfmls_precond_free(rfmls_precond_t *P);
 int64_t rfmls_precond_n(const rfmls_precond_t *P);
 
 /* Copies of the factor for tests: R (with positive diagonal) and X = R^{-1},
- * each n x n row-major float64 (ld = n) with zeros below the diagonal. */
+ * each n x n row-major float64 (ld = n) with zeros below the diagonal
+ * (export_Rinv: RFMLS_E_ARG for an SVD preconditioner). */
 rfmls_status rfmls_precond_export_R(rfmls_handle *h, const rfmls_precond_t *P, double *R);
 rfmls_status rfmls_precond_export_Rinv(rfmls_handle *h, const rfmls_precond_t *P, double *X);
+/* The stored preconditioner as n x n row-major float64 (ld = n): X = R^{-1}
+ * for rfmls_precond, P = V_r Sigma_r^{-1} for rfmls_precond_svd (columns in the
+ * Jacobi order, zero for the dropped ones). */
+rfmls_status rfmls_precond_export_P(rfmls_handle *h, const rfmls_precond_t *P, double *X);
+/* The n singular values of an SVD preconditioner (float64, device), in the
+ * order of P's columns (not sorted). */
+rfmls_status rfmls_precond_export_sigma(rfmls_handle *h, const rfmls_precond_t *P, double *sigma);
 /* Build a preconditioner from a given upper-triangular R (n x n row-major
  * float64, ld = n, positive diagonal); only the upper triangle is read. */
 rfmls_status rfmls_precond_import_R(rfmls_handle *h, int64_t n, const double *R,

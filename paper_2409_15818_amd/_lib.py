@@ -25,6 +25,7 @@ EXPORTED = [
     "rfmls_default_opts", "rfmls_create", "rfmls_destroy", "rfmls_last_error", "rfmls_transpose",
     "rfmls_sketch", "rfmls_precond", "rfmls_precond_x0", "rfmls_precond_free", "rfmls_precond_n",
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
+    "rfmls_precond_svd", "rfmls_precond_svd_stats", "rfmls_precond_export_P", "rfmls_precond_export_sigma",
     "rfmls_solve", "rfmls_form_B", "rfmls_solve_explicit", "rfmls_solve_backward",
     "rfmls_trace_enable", "rfmls_trace_read",
 ]
@@ -91,6 +92,10 @@ def load():
     lib.rfmls_precond_export_R.argtypes = [vp, vp, vp]
     lib.rfmls_precond_export_Rinv.argtypes = [vp, vp, vp]
     lib.rfmls_precond_import_R.argtypes = [vp, i64, vp, C.c_int, P(vp)]
+    lib.rfmls_precond_svd.argtypes = [vp, i64, i64, C.c_int, vp, i64, C.c_double, C.c_int, P(vp)]
+    lib.rfmls_precond_svd_stats.argtypes = [vp, P(i64), P(C.c_int), P(C.c_double)]
+    lib.rfmls_precond_export_P.argtypes = [vp, vp, vp]
+    lib.rfmls_precond_export_sigma.argtypes = [vp, vp, vp]
     lib.rfmls_solve.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, i64, vp, i64, vp, i64,
                                 P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_form_B.argtypes = [vp, P(rfmls_csr), vp, vp, i64]

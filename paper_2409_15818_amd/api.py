@@ -100,12 +100,20 @@ class Handle:
 
 
 class Precond:
-    """Library-owned preconditioner (R and X = R^{-1}); freed with rfmls_precond_free."""
+    """Library-owned preconditioner (R and X = R^{-1}, or the SVD preconditioner
+    P = V_r Sigma_r^{-1}); freed with rfmls_precond_free.  For the SVD kind,
+    `rank`, `sweeps`, `off` and `status` (0, or RFMLS_W_NOCONV when the Jacobi
+    sweeps hit their limit) are filled in."""
 
-    def __init__(self, handle: Handle, ptr: C.c_void_p, n: int):
+    def __init__(self, handle: Handle, ptr: C.c_void_p, n: int, kind: str = "qr"):
         self.handle = handle
         self._p = ptr
         self.n = n
+        self.kind = kind
+        self.rank = n
+        self.sweeps = 0
+        self.off = 0.0
+        self.status = 0
 
     def free(self):
         if getattr(self, "_p", None):
@@ -197,6 +205,36 @@ def rfmls_precond_x0(h: Handle, SA: torch.Tensor, n: int, Sb: torch.Tensor, qr_d
     h.check(h._lib.rfmls_precond_x0(h._h, s, n, DTYPES[qr_dtype], DTYPES[r_store], _ptr(SA),
                                     SA.stride(0), _ptr(SB), nrhs, _ptr(X0), n, C.byref(p)))
     return Precond(h, p, n), (X0[0] if single else X0)
+
+
+def rfmls_precond_svd(h: Handle, SA: torch.Tensor, n: int | None = None, rcond: float = 0.0,
+                      p_store: str = "f64", max_sweeps: int = 0) -> Precond:
+    """CSSVDP preconditioner (Alg. 2 step 3) of the float64 sketch SA [s, ld]
+    (its first n columns; consumed).  rcond <= 0 selects n u."""
+    s = SA.shape[0]
+    n = SA.shape[1] if n is None else n
+    p = C.c_void_p()
+    st = h.check(h._lib.rfmls_precond_svd(h._h, s, n, DTYPES[p_store], _ptr(SA), SA.stride(0),
+                                          float(rcond), int(max_sweeps), C.byref(p)))
+    P = Precond(h, p, n, kind="svd")
+    rank, sweeps, off = C.c_int64(), C.c_int(), C.c_double()
+    h.check(h._lib.rfmls_precond_svd_stats(p, C.byref(rank), C.byref(sweeps), C.byref(off)))
+    P.rank, P.sweeps, P.off, P.status = rank.value, sweeps.value, off.value, st
+    return P
+
+
+def rfmls_precond_export_P(h: Handle, P: Precond) -> torch.Tensor:
+    """The stored preconditioner as a dense n x n float64 matrix."""
+    X = torch.empty((P.n, P.n), dtype=torch.float64, device=h.device)
+    h.check(h._lib.rfmls_precond_export_P(h._h, P._p, _ptr(X)))
+    return X
+
+
+def rfmls_precond_export_sigma(h: Handle, P: Precond) -> torch.Tensor:
+    """Singular values of an SVD preconditioner, in the order of P's columns."""
+    sig = torch.empty(P.n, dtype=torch.float64, device=h.device)
+    h.check(h._lib.rfmls_precond_export_sigma(h._h, P._p, _ptr(sig)))
+    return sig
 
 
 def rfmls_precond_import_R(h: Handle, R: torch.Tensor, r_store: str = "f64") -> Precond:

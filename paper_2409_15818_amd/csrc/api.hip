@@ -250,6 +250,59 @@ rfmls_status rfmls_precond_x0(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype
   return RFMLS_OK;
 }
 
+rfmls_status rfmls_precond_svd(rfmls_handle* h, int64_t s, int64_t n, rfmls_dtype p_store, void* SA,
+                               int64_t ld_sa, double rcond, int max_sweeps, rfmls_precond_t** P_out) {
+  if (!h) return RFMLS_E_ARG;
+  if (!P_out) return fail(h, RFMLS_E_ARG, "rfmls_precond_svd: P_out is null");
+  *P_out = nullptr;
+  if (n < 1 || s < n || !SA || ld_sa < n)
+    return fail(h, RFMLS_E_ARG, "rfmls_precond_svd: need s >= n >= 1, SA non-null and ld_sa >= n");
+  if (n > svd_max_n())
+    return fail(h, RFMLS_E_ARG, "rfmls_precond_svd: n = %lld exceeds %lld", (long long)n,
+                (long long)svd_max_n());
+  if (p_store != RFMLS_F64 && p_store != RFMLS_F32)
+    return fail(h, RFMLS_E_ARG, "rfmls_precond_svd: unknown dtype");
+  if (!(rcond < 1.0)) return fail(h, RFMLS_E_ARG, "rfmls_precond_svd: rcond must be below 1");
+  if (max_sweeps <= 0) max_sweeps = 60;
+  RFMLS_CHECK(set_device(h));
+  RFMLS_CHECK(qr_checked(h, s, n, n, RFMLS_F64, SA, ld_sa));
+  rfmls_precond_t* P = new (std::nothrow) rfmls_precond_t();
+  if (!P) return fail(h, RFMLS_E_NOMEM, "rfmls_precond_svd: out of host memory");
+  P->device = h->device;
+  rfmls_status st = run_build_svd_precond(h, n, (const double*)SA, ld_sa, p_store, rcond, max_sweeps, P);
+  if (st < 0) {
+    rfmls_precond_free(P);
+    return st;
+  }
+  *P_out = P;
+  return st;
+}
+
+rfmls_status rfmls_precond_svd_stats(const rfmls_precond_t* P, int64_t* rank, int* sweeps, double* off) {
+  if (!P || !P->full) return RFMLS_E_ARG;
+  if (rank) *rank = P->rank;
+  if (sweeps) *sweeps = P->sweeps;
+  if (off) *off = P->off;
+  return RFMLS_OK;
+}
+
+rfmls_status rfmls_precond_export_P(rfmls_handle* h, const rfmls_precond_t* P, double* X) {
+  if (!h) return RFMLS_E_ARG;
+  if (!P || !X) return fail(h, RFMLS_E_ARG, "rfmls_precond_export_P: null argument");
+  RFMLS_CHECK(set_device(h));
+  return unpack_precond(h, P, X);
+}
+
+rfmls_status rfmls_precond_export_sigma(rfmls_handle* h, const rfmls_precond_t* P, double* sigma) {
+  if (!h) return RFMLS_E_ARG;
+  if (!P || !sigma) return fail(h, RFMLS_E_ARG, "rfmls_precond_export_sigma: null argument");
+  if (!P->full) return fail(h, RFMLS_E_ARG, "rfmls_precond_export_sigma: not an SVD preconditioner");
+  RFMLS_CHECK(set_device(h));
+  RFMLS_HIP(h, hipMemcpyAsync(sigma, P->sigma, sizeof(double) * (size_t)P->n, hipMemcpyDeviceToDevice,
+                              h->stream));
+  return RFMLS_OK;
+}
+
 void rfmls_precond_free(rfmls_precond_t* P) {
   if (!P) return;
   hipSetDevice(P->device);
@@ -259,6 +312,7 @@ void rfmls_precond_free(rfmls_precond_t* P) {
   if (P->tab_row) hipFree(P->tab_row);
   if (P->tab_col) hipFree(P->tab_col);
   if (P->part) hipFree(P->part);
+  if (P->sigma) hipFree(P->sigma);
   delete P;
 }
 
@@ -276,6 +330,7 @@ rfmls_status rfmls_precond_export_R(rfmls_handle* h, const rfmls_precond_t* P, d
 rfmls_status rfmls_precond_export_Rinv(rfmls_handle* h, const rfmls_precond_t* P, double* X) {
   if (!h) return RFMLS_E_ARG;
   if (!P || !X) return fail(h, RFMLS_E_ARG, "rfmls_precond_export_Rinv: null argument");
+  if (P->full) return fail(h, RFMLS_E_ARG, "rfmls_precond_export_Rinv: an SVD preconditioner holds P, not R^{-1}");
   RFMLS_CHECK(set_device(h));
   return unpack_precond(h, P, X);
 }
@@ -371,6 +426,9 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
   if (nrhs < 0 || (nrhs > 0 && !G) || ldg < A->n || (dB && lddb < A->m) ||
       (dAval && (!X || !Rres || ldx < A->n || ldr < A->m)))
     return fail(h, RFMLS_E_ARG, "rfmls_solve_backward: invalid arguments");
+  if (P->full && P->rank < P->n)
+    return fail(h, RFMLS_E_ARG, "rfmls_solve_backward: the SVD preconditioner is truncated (rank %lld < n = %lld)",
+                (long long)P->rank, (long long)P->n);
   if (nrhs == 0) return RFMLS_OK;
   RFMLS_CHECK(set_device(h));
   if (o->lockstep && nrhs > 1)

@@ -55,8 +55,18 @@ struct rfmls_precond {
   int64_t n = 0;
   int64_t nt = 0;            // number of tile rows, ceil(n / kTile)
   rfmls_dtype store = RFMLS_F64;
-  void* Xpk = nullptr;       // packed tiles of X = R^{-1} (upper triangle)
+  // full = 0: X = R^{-1}, upper-triangular tile packing (CSQRP, Alg. 1);
+  // full = 1: X = P = V_r Sigma_r^{-1}, the full nt x nt tile grid (CSSVDP, Alg. 2)
+  int full = 0;
+  void* Xpk = nullptr;       // packed tiles of X
   double* Rdense = nullptr;  // R (row-major n x n, float64) kept for export
+  // SVD preconditioner only: singular values in the column order of P, the
+  // numerical rank, the Jacobi sweeps taken and the last sweep's largest
+  // |cos| between two columns
+  double* sigma = nullptr;
+  int64_t rank = 0;
+  int sweeps = 0;
+  double off = 0.0;
   int device = 0;
   // work decomposition of the triangular products: chunks of `chunk` tiles
   int chunk = 4;
@@ -75,6 +85,17 @@ constexpr int kTile = 64;
 __host__ __device__ inline int64_t tile_index(int64_t I, int64_t J, int64_t nt) {
   // tiles before row I: sum_{r<I} (nt - r) = I*nt - I*(I-1)/2
   return I * nt - (I * (I - 1)) / 2 + (J - I);
+}
+// The same for either packing (full: the nt x nt grid, row after row), and
+// the stored tiles of a tile row I: columns [row_first(I), nt); of a tile
+// column J: rows [0, col_end(J)).
+__host__ __device__ inline int64_t ptile(int64_t I, int64_t J, int64_t nt, int full) {
+  return full ? I * nt + J : tile_index(I, J, nt);
+}
+__host__ __device__ inline int64_t row_first(int64_t I, int full) { return full ? 0 : I; }
+__host__ __device__ inline int64_t col_end(int64_t J, int64_t nt, int full) { return full ? nt : J + 1; }
+__host__ __device__ inline int64_t stored_tiles(int64_t nt, int full) {
+  return full ? nt * nt : nt * (nt + 1) / 2;
 }
 
 // Error plumbing --------------------------------------------------------------
@@ -122,6 +143,7 @@ enum WsSlot {
   WS_TRANSPOSE,
   WS_X0,
   WS_GEMV,
+  WS_SVD,
   WS_MISC,
   WS_NUM_SLOTS
 };
@@ -194,12 +216,23 @@ rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, rfmls
 rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, const void* SA,
                                int64_t ld, rfmls_dtype store, rfmls_precond_t* P, int check_rank);
 rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit);
+// tables of the tiled products and the packed tiles of X (row-major n x n
+// dense, float64) in P->store precision, for either packing (P->full)
+rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X);
+// R (normalised, row-major n x n float64) from the top n rows of a float64 QR
+// result into a new P->Rdense
+rfmls_status run_extract_R(rfmls_handle* h, int64_t n, const double* SA, int64_t ld, rfmls_precond_t* P);
+// CSSVDP preconditioner (Alg. 2 step 3) from the R factor in SA's top n rows
+rfmls_status run_build_svd_precond(rfmls_handle* h, int64_t n, const double* SA, int64_t ld,
+                                   rfmls_dtype store, double rcond, int max_sweeps,
+                                   rfmls_precond_t* P);
+int64_t svd_max_n();
 rfmls_status put_sketched_rhs(rfmls_handle* h, int64_t s, int64_t n, int64_t nrhs, rfmls_dtype dt,
                               void* SA, int64_t ld, const double* SB);
 rfmls_status sketched_solution(rfmls_handle* h, const rfmls_precond_t* P, int64_t nrhs,
                                rfmls_dtype dt, const void* SA, int64_t ld, double* X0,
                                int64_t ldx0);
-// out = X in (trans 0) or X^T in (trans 1), X = R^{-1} the stored preconditioner,
+// out = X in (trans 0) or X^T in (trans 1), X the stored preconditioner (R^{-1} or P),
 // minus hcoef (*dcoef) prev when prev is given; per-block sums of squares of
 // out into sq when given; nothing when *done is set
 rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, const double* in,

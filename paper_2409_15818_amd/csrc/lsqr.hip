@@ -23,26 +23,27 @@ constexpr int kSpmvMaxBlocks = 2048;
 // ---------------------------------------------------------------------------
 // Triangular products with the packed tiles of X (64 x 64, upper triangle)
 // ---------------------------------------------------------------------------
-// z = X v: block e handles tile row I = tab[e].x, tiles J in [I + k C, I + (k+1) C).
+// z = X v: block e handles tile row I = tab[e].x, tiles J in [J_0 + k C, J_0 + (k+1) C)
+// with J_0 = row_first(I) (I for the triangular packing, 0 for the full grid).
 // Thread (c = lane, w = wave) accumulates rows w + 4q of the tile row against
 // column c, then each row is summed across the wavefront.
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
-    k_trmv_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+    k_trmv_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, int full, const int2* __restrict__ tab,
                 int C, int maxk, const double* __restrict__ v, double* __restrict__ part,
                 const int* __restrict__ done) {
   if (done && *done) return;
   const int2 e = tab[blockIdx.x];
   const int64_t I = e.x;
   const int k = e.y;
-  const int64_t J0 = I + (int64_t)k * C;
+  const int64_t J0 = row_first(I, full) + (int64_t)k * C;
   const int64_t J1 = J0 + C < nt ? J0 + C : nt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   for (int64_t J = J0; J < J1; ++J) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+    const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
     const int64_t gc = J * kTile + lane;
     const double vc = gc < n ? v[gc] : 0.0;
 #pragma unroll
@@ -55,10 +56,10 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// p = X^T q: block e handles tile column J = tab[e].x, tiles I in [k C, min((k+1) C, J+1)).
+// p = X^T q: block e handles tile column J = tab[e].x, tiles I in [k C, min((k+1) C, col_end(J))).
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
-    k_trmvT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+    k_trmvT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, int full, const int2* __restrict__ tab,
                  int C, int maxk, const double* __restrict__ qv, double* __restrict__ part,
                  const int* __restrict__ done) {
   if (done && *done) return;
@@ -67,11 +68,12 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t J = e.x;
   const int k = e.y;
   const int64_t I0 = (int64_t)k * C;
-  const int64_t I1 = I0 + C < J + 1 ? I0 + C : J + 1;
+  const int64_t Iend = col_end(J, nt, full);
+  const int64_t I1 = I0 + C < Iend ? I0 + C : Iend;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double acc = 0.0;
   for (int64_t I = I0; I < I1; ++I) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+    const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int r = w + 4 * q;
@@ -88,14 +90,15 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // out[i] = sum_k part[row(i)][k] - coef * prev[i];  partial sum of squares per block.
-// nk(I) = number of chunks of tile row/column I (trans: ceil((I+1)/C), else ceil((nt-I)/C)).
+// nk(I) = number of chunks of tile row/column I (trans: ceil(col_end(I)/C), else
+// ceil((nt - row_first(I))/C)).
 // A block handles tile rows I (64 outputs each, grid-stride); its four
 // wavefronts sum every fourth partial of each output (independent loads in
 // flight), and the four quarter sums are added in a fixed order.
 constexpr int kRedMaxBlocks = 2048;
 
 __global__ void __launch_bounds__(kThreads)
-    k_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int C, int maxk, int trans,
+    k_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int full, int C, int maxk, int trans,
                  double hcoef, const double* __restrict__ dcoef, const double* prev,
                  double* out, double* __restrict__ sq, const int* __restrict__ done) {
   if (done && *done) return;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(kThreads)
   double ss = 0.0;
   for (int64_t I = blockIdx.x; I < nt; I += gridDim.x) {
     const int64_t i = I * kTile + r;
-    const int64_t nk = trans ? (I + 1 + C - 1) / C : (nt - I + C - 1) / C;
+    const int64_t nk = trans ? (col_end(I, nt, full) + C - 1) / C : (nt - row_first(I, full) + C - 1) / C;
     double s = 0.0;
     if (i < n)
       for (int64_t k = q; k < nk; k += kThreads / kTile) s += part[(I * maxk + k) * kTile + r];
@@ -510,31 +513,32 @@ rfmls_status tri_apply(rfmls_handle* h, const rfmls_precond_t* P, int trans, con
   hipStream_t st = h->stream;
   double* part = (double*)P->part;
   const double esz = P->store == RFMLS_F64 ? 8.0 : 4.0;
-  const double tiles = (double)nt * (double)(nt + 1) / 2.0;
-  const double tri_elems = (double)n * (double)(n + 1) / 2.0;
+  const int full = P->full;
+  const double tri_elems = full ? (double)n * (double)n : (double)n * (double)(n + 1) / 2.0;
   {
-  // algorithmic: the n(n+1)/2 stored entries of X once, the input vector, the output
-  Trace tr(h, trans ? "trmv_Xt" : "trmv_X", esz * tri_elems + 16.0 * (double)n, 2.0 * tri_elems);
-  (void)tiles;
+  // algorithmic: the stored entries of X once (n(n+1)/2, or n^2 for the full
+  // SVD preconditioner), the input vector, the output
+  Trace tr(h, full ? (trans ? "gemv_Pt" : "gemv_P") : (trans ? "trmv_Xt" : "trmv_X"),
+           esz * tri_elems + 16.0 * (double)n, 2.0 * tri_elems);
   if (!trans) {
     if (P->store == RFMLS_F64)
       hipLaunchKernelGGL(k_trmv_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
-                         (const double*)P->Xpk, nt, n, P->tab_row, C, maxk, in, part, done);
+                         (const double*)P->Xpk, nt, n, full, P->tab_row, C, maxk, in, part, done);
     else
       hipLaunchKernelGGL(k_trmv_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
-                         (const float*)P->Xpk, nt, n, P->tab_row, C, maxk, in, part, done);
+                         (const float*)P->Xpk, nt, n, full, P->tab_row, C, maxk, in, part, done);
   } else {
     if (P->store == RFMLS_F64)
       hipLaunchKernelGGL(k_trmvT_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
-                         (const double*)P->Xpk, nt, n, P->tab_col, C, maxk, in, part, done);
+                         (const double*)P->Xpk, nt, n, full, P->tab_col, C, maxk, in, part, done);
     else
       hipLaunchKernelGGL(k_trmvT_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, st,
-                         (const float*)P->Xpk, nt, n, P->tab_col, C, maxk, in, part, done);
+                         (const float*)P->Xpk, nt, n, full, P->tab_col, C, maxk, in, part, done);
   }
   }
   Trace tr2(h, "tri_reduce", 8.0 * (double)nt * maxk * kTile + 16.0 * (double)n, 0.0);
   hipLaunchKernelGGL(k_tri_reduce, dim3((unsigned)tri_reduce_blocks(n)), dim3(kThreads), 0, st, part, nt, n,
-                     C, maxk, trans, hcoef, dcoef, prev, out, sq, done);
+                     full, C, maxk, trans, hcoef, dcoef, prev, out, sq, done);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }

@@ -55,7 +55,7 @@ __device__ __forceinline__ bool all_done(const BlockState* st) { return st->all_
 // HBM would fetch 32-byte pieces of 16 different rows per load.
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
-    k_trmm_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+    k_trmm_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, int full, const int2* __restrict__ tab,
                 int C, int maxk, const double* __restrict__ V, double* __restrict__ part,
                 const BlockState* __restrict__ st) {
   if (st && all_done(st)) return;
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kThreads)
   const int2 e = tab[blockIdx.x];
   const int64_t I = e.x;
   const int k = e.y;
-  const int64_t J0 = I + (int64_t)k * C;
+  const int64_t J0 = row_first(I, full) + (int64_t)k * C;
   const int64_t J1 = J0 + C < nt ? J0 + C : nt;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(kThreads)
   TS xr[kPer];
   double vr[kTile * kBlk / kThreads];  // 8 V elements per thread
   auto fetch = [&](int64_t J) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+    const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) xr[q] = t[tid + q * kThreads];
 #pragma unroll
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kThreads)
 // staged in LDS like k_trmm_part (the operand is the tile read transposed).
 template <typename TS>
 __global__ void __launch_bounds__(kThreads)
-    k_trmmT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, const int2* __restrict__ tab,
+    k_trmmT_part(const TS* __restrict__ Xpk, int64_t nt, int64_t n, int full, const int2* __restrict__ tab,
                  int C, int maxk, const double* __restrict__ Qv, double* __restrict__ part,
                  const BlockState* __restrict__ st) {
   if (st && all_done(st)) return;
@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t J = e.x;
   const int k = e.y;
   const int64_t I0 = (int64_t)k * C;
-  const int64_t I1 = I0 + C < J + 1 ? I0 + C : J + 1;
+  const int64_t Iend = col_end(J, nt, full);
+  const int64_t I1 = I0 + C < Iend ? I0 + C : Iend;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(kThreads)
   TS xr[kPer];
   double qr[kTile * kBlk / kThreads];
   auto fetch = [&](int64_t I) {
-    const TS* t = Xpk + tile_index(I, J, nt) * (int64_t)(kTile * kTile);
+    const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) xr[q] = t[tid + q * kThreads];
 #pragma unroll
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(kThreads)
 // out[i][c] = sum_k part[...][i][c] - coef_c prev[i][c]; per-column partial sums of squares.
 // coef_c = hcoef * coef[c * cstride] (coef may be null).  Thread (i, c) with c = tid % 32.
 __global__ void __launch_bounds__(kThreads)
-    k_blk_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int C, int maxk,
+    k_blk_tri_reduce(const double* __restrict__ part, int64_t nt, int64_t n, int full, int C, int maxk,
                      int trans, double hcoef, const double* __restrict__ coef, int cstride,
                      const double* prev, double* out, double* __restrict__ sq,
                      const BlockState* __restrict__ st) {
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(kThreads)
        i += (int64_t)gridDim.x * (kThreads / kBlk)) {
     const int64_t I = i / kTile;
     const int r = (int)(i % kTile);
-    const int64_t nk = trans ? (I + 1 + C - 1) / C : (nt - I + C - 1) / C;
+    const int64_t nk = trans ? (col_end(I, nt, full) + C - 1) / C : (nt - row_first(I, full) + C - 1) / C;
     double s = 0.0;
     for (int64_t kq = 0; kq < nk; ++kq) s += part[((I * maxk + kq) * kTile + r) * kBlk + c];
     if (prev && cf != 0.0) s -= cf * prev[i * kBlk + c];
@@ -717,28 +718,29 @@ rfmls_status tri_block(BCtx& c, int trans, const double* in, double* out, double
   const int C = P->chunk;
   const int maxk = (int)((nt + C - 1) / C);
   const double esz = P->store == RFMLS_F64 ? 8.0 : 4.0;
-  const double tri = (double)n * (double)(n + 1) / 2.0;
+  const int full = P->full;
+  const double tri = full ? (double)n * (double)n : (double)n * (double)(n + 1) / 2.0;
   {
-    Trace tr(c.h, trans ? "trmm_Xt" : "trmm_X", esz * tri + 2.0 * 8.0 * kBlk * (double)n,
-             2.0 * tri * kBlk);
+    Trace tr(c.h, full ? (trans ? "gemm_Pt" : "gemm_P") : (trans ? "trmm_Xt" : "trmm_X"),
+             esz * tri + 2.0 * 8.0 * kBlk * (double)n, 2.0 * tri * kBlk);
     if (!trans) {
       if (P->store == RFMLS_F64)
         hipLaunchKernelGGL(k_trmm_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
-                           (const double*)P->Xpk, nt, n, P->tab_row, C, maxk, in, c.part, stp);
+                           (const double*)P->Xpk, nt, n, full, P->tab_row, C, maxk, in, c.part, stp);
       else
         hipLaunchKernelGGL(k_trmm_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
-                           (const float*)P->Xpk, nt, n, P->tab_row, C, maxk, in, c.part, stp);
+                           (const float*)P->Xpk, nt, n, full, P->tab_row, C, maxk, in, c.part, stp);
     } else {
       if (P->store == RFMLS_F64)
         hipLaunchKernelGGL(k_trmmT_part<double>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
-                           (const double*)P->Xpk, nt, n, P->tab_col, C, maxk, in, c.part, stp);
+                           (const double*)P->Xpk, nt, n, full, P->tab_col, C, maxk, in, c.part, stp);
       else
         hipLaunchKernelGGL(k_trmmT_part<float>, dim3((unsigned)P->ntab), dim3(kThreads), 0, c.st,
-                           (const float*)P->Xpk, nt, n, P->tab_col, C, maxk, in, c.part, stp);
+                           (const float*)P->Xpk, nt, n, full, P->tab_col, C, maxk, in, c.part, stp);
     }
   }
   hipLaunchKernelGGL(k_blk_tri_reduce, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)c.part,
-                     nt, n, C, maxk, trans, hcoef, coef, kStride, prev, out, sq, stp);
+                     nt, n, full, C, maxk, trans, hcoef, coef, kStride, prev, out, sq, stp);
   RFMLS_HIP(c.h, hipGetLastError());
   return RFMLS_OK;
 }
@@ -874,18 +876,18 @@ static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_c
 }
 
 // ---- the explicit preconditioned matrix B = A X (Alg. 1 step 4) ----
-// out[j][k] = X[j][c0 + k] for k < nb (zero below the diagonal and beyond nb):
-// a 32-column slab of X = R^{-1} in the lockstep block layout, read from the
-// packed upper-triangular tiles.
+// out[j][k] = X[j][c0 + k] for k < nb (zero beyond nb, and below the diagonal
+// for the triangular X = R^{-1}): a 32-column slab of X in the lockstep block
+// layout, read from the packed tiles.
 template <typename TS>
-__global__ void k_x_slab(const TS* __restrict__ Xpk, int64_t n, int64_t nt, int64_t c0, int nb,
+__global__ void k_x_slab(const TS* __restrict__ Xpk, int64_t n, int64_t nt, int full, int64_t c0, int nb,
                          double* __restrict__ out) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * kBlk;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / kBlk, c = c0 + e % kBlk;
     double v = 0.0;
-    if (e % kBlk < nb && j <= c)
-      v = (double)Xpk[tile_index(j / kTile, c / kTile, nt) * (int64_t)(kTile * kTile) +
+    if (e % kBlk < nb && (full || j <= c))
+      v = (double)Xpk[ptile(j / kTile, c / kTile, nt, full) * (int64_t)(kTile * kTile) +
                       (j % kTile) * kTile + c % kTile];
     out[e] = v;
   }
@@ -1116,10 +1118,10 @@ rfmls_status run_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond
     const int nb = (int)(n - c0 < kBlk ? n - c0 : kBlk);
     if (P->store == RFMLS_F64)
       hipLaunchKernelGGL(k_x_slab<double>, dim3(gn), dim3(kThreads), 0, c.st, (const double*)P->Xpk, n,
-                         P->nt, c0, nb, c.Xb);
+                         P->nt, P->full, c0, nb, c.Xb);
     else
       hipLaunchKernelGGL(k_x_slab<float>, dim3(gn), dim3(kThreads), 0, c.st, (const float*)P->Xpk, n,
-                         P->nt, c0, nb, c.Xb);
+                         P->nt, P->full, c0, nb, c.Xb);
     RFMLS_CHECK(spmm(c, A, c.Xb, 1.0, 0.0, nullptr, nullptr, c.U, nullptr, nullptr, nullptr));
     hipLaunchKernelGGL(k_scatter_slab, dim3(gm), dim3(kThreads), 0, c.st, (const double*)c.U, m, c0, nb,
                        Bmat, ldb);

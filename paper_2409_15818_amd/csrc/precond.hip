@@ -144,14 +144,20 @@ __global__ void __launch_bounds__(kInvCols)
   }
 }
 
+// Tiles of X (row-major n x n) in the packed order of either layout: the
+// upper-triangular packing keeps tiles J >= I (and zeros below the diagonal
+// inside diagonal tiles), the full one every tile.
 template <typename TS>
-__global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt,
+__global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt, int full,
                              TS* __restrict__ pk) {
   // blockIdx.x = tile index in packed order; decode (I, J)
   const int64_t t = blockIdx.x;
-  int64_t I = 0;
-  // rows: tile_index(I, I) <= t < tile_index(I+1, I+1)
-  {
+  int64_t I = 0, J = 0;
+  if (full) {
+    I = t / nt;
+    J = t % nt;
+  } else {
+    // rows: tile_index(I, I) <= t < tile_index(I+1, I+1)
     int64_t lo = 0, hi = nt - 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) / 2;
@@ -159,37 +165,27 @@ __global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt
       else hi = mid - 1;
     }
     I = lo;
+    J = I + (t - tile_index(I, I, nt));
   }
-  const int64_t J = I + (t - tile_index(I, I, nt));
   TS* out = pk + t * (int64_t)(kTile * kTile);
   for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
     const int r = e / kTile, c = e % kTile;
     const int64_t gi = I * kTile + r, gj = J * kTile + c;
     double v = 0.0;
-    if (gi < n && gj < n && gj >= gi) v = X[gi * n + gj];
+    if (gi < n && gj < n && (full || gj >= gi)) v = X[gi * n + gj];
     out[e] = (TS)v;
   }
 }
 
-__global__ void k_unpack_tiles_f64(const double* __restrict__ pk, int64_t n, int64_t nt,
-                                   double* __restrict__ X) {
+template <typename TS>
+__global__ void k_unpack_tiles(const TS* __restrict__ pk, int64_t n, int64_t nt, int full,
+                               double* __restrict__ X) {
   const int64_t i = blockIdx.x;
   const int64_t I = i / kTile;
   const int r = (int)(i % kTile);
   for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
     const int64_t J = j / kTile;
-    X[i * n + j] = J < I ? 0.0 : (j < i ? 0.0 : pk[tile_index(I, J, nt) * (kTile * kTile) + r * kTile + (j % kTile)]);
-  }
-}
-
-__global__ void k_unpack_tiles_f32(const float* __restrict__ pk, int64_t n, int64_t nt,
-                                   double* __restrict__ X) {
-  const int64_t i = blockIdx.x;
-  const int64_t I = i / kTile;
-  const int r = (int)(i % kTile);
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const int64_t J = j / kTile;
-    X[i * n + j] = J < I ? 0.0 : (j < i ? 0.0 : (double)pk[tile_index(I, J, nt) * (kTile * kTile) + r * kTile + (j % kTile)]);
+    X[i * n + j] = (!full && j < i) ? 0.0 : (double)pk[ptile(I, J, nt, full) * (kTile * kTile) + r * kTile + (j % kTile)];
   }
 }
 
@@ -306,18 +302,25 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   double* X = (double*)p_x;
   RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
                            P->nt, kslice));
-  const int64_t ntiles = P->nt * (P->nt + 1) / 2;
+  return pack_precond(h, P, X);
+}
+
+rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X) {
+  const int64_t n = P->n;
+  const int full = P->full;
+  const int64_t ntiles = stored_tiles(P->nt, full);
   const size_t esz = P->store == RFMLS_F64 ? sizeof(double) : sizeof(float);
-  // work tables of the triangular products
+  // work tables of the tiled products: (tile row, chunk) and (tile column, chunk)
   {
     const int C = P->chunk;
     const int64_t nt = P->nt;
     const int64_t maxk = (nt + C - 1) / C;
     std::vector<int2> tr, tc;
     for (int64_t I = 0; I < nt; ++I)
-      for (int64_t k = 0; k < (nt - I + C - 1) / C; ++k) tr.push_back(make_int2((int)I, (int)k));
+      for (int64_t k = 0; k < (nt - row_first(I, full) + C - 1) / C; ++k) tr.push_back(make_int2((int)I, (int)k));
     for (int64_t J = 0; J < nt; ++J)
-      for (int64_t k = 0; k < (J + 1 + C - 1) / C; ++k) tc.push_back(make_int2((int)J, (int)k));
+      for (int64_t k = 0; k < (col_end(J, nt, full) + C - 1) / C; ++k) tc.push_back(make_int2((int)J, (int)k));
+    if (tr.size() != tc.size()) return fail(h, RFMLS_E_ARG, "preconditioner work tables disagree");
     P->ntab = (int64_t)tr.size();
     RFMLS_HIP(h, hipMalloc(&P->tab_row, sizeof(int2) * tr.size()));
     RFMLS_HIP(h, hipMalloc(&P->tab_col, sizeof(int2) * tc.size()));
@@ -328,21 +331,21 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   RFMLS_HIP(h, hipMalloc(&P->Xpk, esz * (size_t)ntiles * kTile * kTile));
   if (P->store == RFMLS_F64)
     hipLaunchKernelGGL(k_pack_tiles<double>, dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
-                       P->nt, (double*)P->Xpk);
+                       P->nt, full, (double*)P->Xpk);
   else
     hipLaunchKernelGGL(k_pack_tiles<float>, dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
-                       P->nt, (float*)P->Xpk);
+                       P->nt, full, (float*)P->Xpk);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
 
 rfmls_status unpack_precond(rfmls_handle* h, const rfmls_precond_t* P, double* Xdense) {
   if (P->store == RFMLS_F64)
-    hipLaunchKernelGGL(k_unpack_tiles_f64, dim3((unsigned)P->n), dim3(256), 0, h->stream,
-                       (const double*)P->Xpk, P->n, P->nt, Xdense);
+    hipLaunchKernelGGL(k_unpack_tiles<double>, dim3((unsigned)P->n), dim3(256), 0, h->stream,
+                       (const double*)P->Xpk, P->n, P->nt, P->full, Xdense);
   else
-    hipLaunchKernelGGL(k_unpack_tiles_f32, dim3((unsigned)P->n), dim3(256), 0, h->stream,
-                       (const float*)P->Xpk, P->n, P->nt, Xdense);
+    hipLaunchKernelGGL(k_unpack_tiles<float>, dim3((unsigned)P->n), dim3(256), 0, h->stream,
+                       (const float*)P->Xpk, P->n, P->nt, P->full, Xdense);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
@@ -378,6 +381,13 @@ rfmls_status sketched_solution(rfmls_handle* h, const rfmls_precond_t* P, int64_
   // x0_k = R^{-1} y0_k with the stored X
   for (int64_t k = 0; k < nrhs; ++k)
     RFMLS_CHECK(tri_apply(h, P, 0, Y0 + k * n, X0 + k * ldx0, 0.0, nullptr, nullptr, nullptr, nullptr));
+  return RFMLS_OK;
+}
+
+rfmls_status run_extract_R(rfmls_handle* h, int64_t n, const double* SA, int64_t ld, rfmls_precond_t* P) {
+  RFMLS_HIP(h, hipMalloc(&P->Rdense, sizeof(double) * (size_t)n * (size_t)n));
+  hipLaunchKernelGGL(k_extract_R<double>, dim3((unsigned)n), dim3(256), 0, h->stream, SA, ld, n, P->Rdense);
+  RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
 

@@ -1,6 +1,8 @@
-"""The CSQRP-LSQR pipeline (Alg. 1) over the C-ABI, and its differentiable form.
+"""The CSQRP-LSQR pipeline (Alg. 1) over the C-ABI, its SVD variant
+CSSVDP-LSQR (Alg. 2), and the differentiable form.
 
 csqrp_lsqr      sketch -> QR preconditioner -> LSQR for one or many right-hand sides
+cssvdp_lsqr     sketch -> truncated SVD preconditioner -> LSQR
 LstsqFunction   torch.autograd.Function: x = A^+ b with gradients w.r.t. b and the
                 stored values of A (restricted to A's pattern), the backward running
                 the preconditioned LSQR on the transposed operator.
@@ -12,8 +14,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from .api import (CSR, Handle, Precond, default_opts, rfmls_form_B, rfmls_precond, rfmls_precond_x0,
-                  rfmls_sketch, rfmls_solve, rfmls_solve_backward, rfmls_solve_explicit,
+from .api import (CSR, Handle, Precond, default_opts, rfmls_form_B, rfmls_precond, rfmls_precond_svd,
+                  rfmls_precond_x0, rfmls_sketch, rfmls_solve, rfmls_solve_backward, rfmls_solve_explicit,
                   rfmls_transpose, sketch_buffer)
 
 
@@ -58,6 +60,28 @@ def csqrp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, qr_dty
     else:
         raise ValueError(f"unknown operator {operator!r}")
     return Result(X, R, info, rc, P, AT)
+
+
+def cssvdp_lsqr(h: Handle, A: CSR, b: torch.Tensor, s: int, seed: int = 2, rcond: float = 0.0,
+                p_store: str = "f64", opts=None, AT: CSR | None = None,
+                operator: str = "implicit") -> Result:
+    """Alg. 2 on the GPU: the count sketch, the truncated SVD preconditioner
+    P = V_r Sigma_r^{-1} (rcond <= 0: n u) and LSQR on A P from y^(0) = 0,
+    x = P y.  operator "explicit" forms the dense B = A P first."""
+    if AT is None:
+        AT = rfmls_transpose(h, A)
+    SA, _, _, _ = rfmls_sketch(h, A, s, seed, dtype="f64")
+    P = rfmls_precond_svd(h, SA, A.n, rcond=rcond, p_store=p_store)
+    del SA
+    if operator == "explicit":
+        Bm = rfmls_form_B(h, A, P)
+        X, R, info, rc = rfmls_solve_explicit(h, A, AT, P, Bm, b, opts)
+        del Bm
+    elif operator == "implicit":
+        X, R, info, rc = rfmls_solve(h, A, AT, P, b, opts)
+    else:
+        raise ValueError(f"unknown operator {operator!r}")
+    return Result(X, R, info, max(rc, P.status), P, AT)
 
 
 class LstsqFunction(torch.autograd.Function):
