@@ -121,6 +121,10 @@ def main():
     ap.add_argument("--start", default="sketch", choices=["sketch", "zero"],
                     help="LSQR starting point: sketch = y0 = Q^T (S b) from the QR of [SA | Sb] "
                          "(Remark 3.1); zero = y0 = 0 (Sec. 4.1)")
+    ap.add_argument("--precond", default="qr", choices=["qr", "svd"],
+                    help="qr: CSQRP-LSQR (Alg. 1); svd: CSSVDP-LSQR (Alg. 2), the truncated SVD "
+                         "preconditioner P = V_r Sigma_r^-1 (float64 QR and SVD; --precision f64f32 "
+                         "stores P in float32; starts from y0 = 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--backward", action="store_true",
@@ -130,6 +134,10 @@ def main():
                     help="run one plain 1 GiB device-to-device copy first (reference kernel of "
                          "known traffic for hardware byte counters)")
     args = ap.parse_args()
+    if args.precond == "svd":
+        if args.precision == "f32":
+            ap.error("--precond svd factors in float64 (use --precision f64 or f64f32)")
+        args.start = "zero"  # the sketched start of Remark 3.1 comes from the QR's own factor
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -174,7 +182,9 @@ def main():
             SA, _, _, _ = R.rfmls_sketch(h, A, s, SKETCH_SEED, dtype=qd)
         if ev is not None:
             ev[2].record()
-        if args.start == "sketch":
+        if args.precond == "svd":
+            P, X0 = R.rfmls_precond_svd(h, SA, S.n, p_store=rd), None
+        elif args.start == "sketch":
             P, X0 = R.rfmls_precond_x0(h, SA, S.n, Sb if args.nrhs > 1 else Sb[0], qd, rd)
         else:
             P, X0 = R.rfmls_precond(h, SA, qd, rd), None
@@ -207,7 +217,8 @@ def main():
         dt = time.perf_counter() - t0
         times.append(dt)
         phases.append({"transpose": ev[0].elapsed_time(ev[1]), "sketch": ev[1].elapsed_time(ev[2]),
-                       "qr_and_inverse": ev[2].elapsed_time(ev[3]), "lsqr": ev[3].elapsed_time(ev[4])})
+                       ("qr_and_svd" if args.precond == "svd" else "qr_and_inverse"): ev[2].elapsed_time(ev[3]),
+                       "lsqr": ev[3].elapsed_time(ev[4])})
         log(f"[bench] step {k + 1}/{args.steps}: {dt * 1e3:.1f} ms  itn={[i['itn'] for i in info]}")
         if k + 1 < args.steps:
             del P, AT, Rres
@@ -255,6 +266,9 @@ def main():
     vs_oracle = None
     if os.path.exists(gold_path):
         gold = json.load(open(gold_path))
+        if args.precond == "svd":
+            gold = gold.get("svd")
+    if os.path.exists(gold_path) and gold:
         vs_oracle = {"oracle_normr": gold["normr"], "rel_diff_normr": abs(met["normr"] - gold["normr"]) / gold["normr"],
                      "oracle_l2_error": gold["l2_error"], "l2_ratio": l2 / gold["l2_error"]}
 
@@ -296,7 +310,8 @@ def main():
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
                    "precision": args.precision, "refine": args.refine, "itmax": args.itmax, "atol": opts.atol, "btol": opts.btol,
                    "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1),
-                   "start": args.start, "operator": args.operator},
+                   "start": args.start, "operator": args.operator, "precond": args.precond},
+        "svd": None if args.precond != "svd" else {"rank": P.rank, "sweeps": P.sweeps, "last_off": P.off},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),
                        "istop": int(info[0]["istop"]),

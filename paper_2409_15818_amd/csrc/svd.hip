@@ -11,10 +11,15 @@
 // stopping tolerance however wide the spread of sigma, so SA P = Q U keeps the
 // conditioning Thm 3.4 relies on.
 //
-// Ordering: the round-robin (circle) schedule over N = n rounded up to even
-// columns; in each of the N - 1 steps of a sweep the N / 2 pairs are disjoint,
-// one block per pair, and every pair meets once per sweep.  A pair (p, q) is
-// rotated when |m_p . m_q| > tol ||m_p|| ||m_q||; the sweeps stop when none is.
+// Ordering: columns in groups of b (4 for n <= 4096); the round-robin (circle)
+// schedule pairs the groups, Gp = the group count rounded up to even, so each
+// of the Gp - 1 steps of a sweep gives Gp / 2 disjoint group pairs, one block
+// each, and every pair of columns from two groups meets once per sweep.  A
+// block rotates all pairs of its 2b columns in registers before it writes
+// them back, so a step passes over M and J once for (2b)(2b-1)/2 rotations per
+// block instead of one; inside the block the pairs go in 2b - 1 rounds of b
+// disjoint pairs, one block reduction per round.  A pair (p, q) is rotated when
+// |m_p . m_q| > tol ||m_p|| ||m_q||; the sweeps stop when none is.
 //
 // Layout: M and J column-major (column k contiguous, ld = ldm), so a block
 // reads and writes two contiguous columns of each; float64 throughout.
@@ -54,93 +59,166 @@ __global__ void k_eye_cols(double* __restrict__ J, int64_t n, int64_t ldm) {
     J[e] = (e / ldm == e % ldm) ? 1.0 : 0.0;
 }
 
-// counters of one sweep: [0] = bits of the largest |cos| met, [1] = rotations
+// counters of one sweep: [0] = bits of the largest |cos| met, [1] = rotations,
+// [2] = blocks that rotated (and so wrote their columns of M and J)
 __global__ void k_zero_counters(unsigned long long* ctr) {
-  if (threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
+  if (threadIdx.x < 3) ctr[threadIdx.x] = 0ull;
 }
 
-// column p of step t in the circle schedule: slot 0 stays, the others turn
-__device__ __forceinline__ int64_t circle(int64_t slot, int64_t t, int64_t N) {
-  return slot == 0 ? 0 : (slot - 1 + t) % (N - 1) + 1;
+// group of step t at slot `slot` in the circle schedule over Gp groups: slot 0
+// stays, the others turn
+__device__ __forceinline__ int64_t circle(int64_t slot, int64_t t, int64_t Gp) {
+  return slot == 0 ? 0 : (slot - 1 + t) % (Gp - 1) + 1;
 }
 
-// One step of a sweep: block k rotates the pair (circle(k), circle(N-1-k)).
-// Each of the NT threads holds E rows of both columns in registers.
-template <int NT, int E>
+// local column of slot i in round r of the circle schedule over B2 columns
+__host__ __device__ constexpr int lcol(int i, int r, int B2) { return i == 0 ? 0 : (i - 1 + r) % (B2 - 1) + 1; }
+
+// One step of a sweep over column groups of b = B2 / 2: block k takes the
+// groups (circle(k), circle(Gp-1-k)) and rotates every pair of its B2 columns,
+// all held in registers (thread tid has rows tid + e NT, e < E).  The pairs are
+// taken in B2 - 1 rounds of B2 / 2 disjoint pairs (the circle schedule again),
+// so the products of a round's pairs share one block reduction; the rotations
+// are then replayed, round by round, on the same columns of J.  Over a sweep
+// every pair of columns from different groups meets once, pairs inside a
+// group at every step.  A column index past n (the ragged last group, the
+// padding group of an odd group count) is a zero column and never rotates.
+template <int NT, int E, int B2>
 __global__ void __launch_bounds__(NT)
-    k_jacobi_step(double* __restrict__ M, double* __restrict__ J, int64_t n, int64_t ldm, int64_t N,
+    k_jacobi_step(double* __restrict__ M, double* __restrict__ J, int64_t n, int64_t ldm, int64_t Gp,
                   int64_t t, double tol, unsigned long long* __restrict__ ctr) {
-  __shared__ double red[3][NT / 64];
-  const int64_t p = circle(blockIdx.x, t, N), q = circle(N - 1 - blockIdx.x, t, N);
-  if (p >= n || q >= n) return;  // the padding column of an odd n
+  constexpr int b = B2 / 2;
+  constexpr int H = B2 / 2;       // pairs per round
+  constexpr int NR = B2 - 1;      // rounds
+  constexpr int NW = NT / 64;     // wavefronts
+  __shared__ double red[3 * H][NW];
+  __shared__ double rot[NR][H][2];
+  const int64_t g1 = circle(blockIdx.x, t, Gp), g2 = circle(Gp - 1 - blockIdx.x, t, Gp);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double* mp = M + p * ldm;
-  double* mq = M + q * ldm;
-  double a[E], b[E];
-  double aa = 0.0, bb = 0.0, ab = 0.0;
+  int64_t col[B2];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int64_t i = tid + (int64_t)e * NT;
-    a[e] = i < n ? mp[i] : 0.0;
-    b[e] = i < n ? mq[i] : 0.0;
-    aa += a[e] * a[e];
-    bb += b[e] * b[e];
-    ab += a[e] * b[e];
+  for (int c = 0; c < B2; ++c) {
+    const int64_t k = c < b ? g1 * b + c : g2 * b + (c - b);
+    col[c] = k < n ? k : -1;
   }
-  aa = wave_sum(aa);
-  bb = wave_sum(bb);
-  ab = wave_sum(ab);
-  if (lane == 0) {
-    red[0][w] = aa;
-    red[1][w] = bb;
-    red[2][w] = ab;
-  }
-  __syncthreads();
-  aa = bb = ab = 0.0;
+  // element (row tid + e NT, column k) of M is Mt[k ldm + e NT]: a per-thread
+  // base plus a block-uniform offset.  The base is made opaque between the
+  // loads and the stores, so the stores recompute their addresses instead of
+  // keeping B2 x E 64-bit addresses live (spilled) across the rotations.
+  double* Mt = M + tid;
+  double x[B2][E];
 #pragma unroll
-  for (int k = 0; k < NT / 64; ++k) {
-    aa += red[0][k];
-    bb += red[1][k];
-    ab += red[2][k];
-  }
-  // |cos| of the angle between the columns (uniform over the block)
-  const double den = sqrt(aa) * sqrt(bb);
-  const double rel = den > 0.0 ? fabs(ab) / den : 0.0;
-  if (tid == 0 && rel > 0.0) atomicMax(&ctr[0], (unsigned long long)__double_as_longlong(rel));
-  if (!(rel > tol)) return;
-  if (tid == 0) atomicAdd(&ctr[1], 1ull);
-  // rotation [c s; -s c] on (m_p, m_q) that zeroes m_p . m_q:
-  // zeta = (||m_q||^2 - ||m_p||^2) / (2 m_p . m_q), t the root of smaller
-  // magnitude of t^2 + 2 zeta t - 1 = 0
-  const double zeta = (bb - aa) / (2.0 * ab);
-  const double az = fabs(zeta);
-  const double dz = az > 1.0 ? az * (1.0 + sqrt(1.0 + 1.0 / (az * az))) : az + sqrt(1.0 + az * az);
-  const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / dz;
-  const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
+  for (int c = 0; c < B2; ++c)
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int64_t i = tid + (int64_t)e * NT;
-    if (i < n) {
-      mp[i] = cs * a[e] - sn * b[e];
-      mq[i] = sn * a[e] + cs * b[e];
+    for (int e = 0; e < E; ++e)
+      x[c][e] = (col[c] >= 0 && tid + (int64_t)e * NT < n) ? Mt[col[c] * ldm + (int64_t)e * NT] : 0.0;
+  double offmax = 0.0;
+  int nrot = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double s3[3 * H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int p = lcol(k, r, B2), q = lcol(B2 - 1 - k, r, B2);
+      double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        aa += x[p][e] * x[p][e];
+        bb += x[q][e] * x[q][e];
+        ab += x[p][e] * x[q][e];
+      }
+      s3[3 * k] = wave_sum(aa);
+      s3[3 * k + 1] = wave_sum(bb);
+      s3[3 * k + 2] = wave_sum(ab);
+    }
+    __syncthreads();  // the previous round's reads of red are done
+    if (lane == 0) {
+#pragma unroll
+      for (int v = 0; v < 3 * H; ++v) red[v][w] = s3[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int p = lcol(k, r, B2), q = lcol(B2 - 1 - k, r, B2);
+      double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+      for (int u = 0; u < NW; ++u) {
+        aa += red[3 * k][u];
+        bb += red[3 * k + 1][u];
+        ab += red[3 * k + 2][u];
+      }
+      // |cos| of the angle between the columns (uniform over the block)
+      const double den = sqrt(aa) * sqrt(bb);
+      const double rel = den > 0.0 ? fabs(ab) / den : 0.0;
+      offmax = rel > offmax ? rel : offmax;
+      double cs = 1.0, sn = 0.0;
+      if (rel > tol) {
+        // rotation [c s; -s c] on (x_p, x_q) that zeroes x_p . x_q:
+        // zeta = (||x_q||^2 - ||x_p||^2) / (2 x_p . x_q), t the root of smaller
+        // magnitude of t^2 + 2 zeta t - 1 = 0
+        const double zeta = (bb - aa) / (2.0 * ab);
+        const double az = fabs(zeta);
+        const double dz = az > 1.0 ? az * (1.0 + sqrt(1.0 + 1.0 / (az * az))) : az + sqrt(1.0 + az * az);
+        const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / dz;
+        cs = 1.0 / sqrt(1.0 + tn * tn);
+        sn = cs * tn;
+        ++nrot;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double xp = x[p][e], xq = x[q][e];
+          x[p][e] = cs * xp - sn * xq;
+          x[q][e] = sn * xp + cs * xq;
+        }
+      }
+      if (tid == 0) {
+        rot[r][k][0] = cs;
+        rot[r][k][1] = sn;
+      }
     }
   }
-  double* jp = J + p * ldm;
-  double* jq = J + q * ldm;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int64_t i = tid + (int64_t)e * NT;
-    a[e] = i < n ? jp[i] : 0.0;
-    b[e] = i < n ? jq[i] : 0.0;
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int64_t i = tid + (int64_t)e * NT;
-    if (i < n) {
-      jp[i] = cs * a[e] - sn * b[e];
-      jq[i] = sn * a[e] + cs * b[e];
+  if (tid == 0) {
+    if (offmax > 0.0) atomicMax(&ctr[0], (unsigned long long)__double_as_longlong(offmax));
+    if (nrot) {
+      atomicAdd(&ctr[1], (unsigned long long)nrot);
+      atomicAdd(&ctr[2], 1ull);
     }
   }
+  if (nrot == 0) return;  // uniform: nothing moved in this block
+  asm volatile("" : "+v"(Mt));
+#pragma unroll
+  for (int c = 0; c < B2; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (col[c] >= 0 && tid + (int64_t)e * NT < n) Mt[col[c] * ldm + (int64_t)e * NT] = x[c][e];
+  // the same rotations, in the same order, on J's columns
+  double* Jt = J + tid;
+#pragma unroll
+  for (int c = 0; c < B2; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      x[c][e] = (col[c] >= 0 && tid + (int64_t)e * NT < n) ? Jt[col[c] * ldm + (int64_t)e * NT] : 0.0;
+  __syncthreads();  // rot[] complete
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int p = lcol(k, r, B2), q = lcol(B2 - 1 - k, r, B2);
+      const double cs = rot[r][k][0], sn = rot[r][k][1];
+      if (sn != 0.0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double xp = x[p][e], xq = x[q][e];
+          x[p][e] = cs * xp - sn * xq;
+          x[q][e] = sn * xp + cs * xq;
+        }
+      }
+    }
+  asm volatile("" : "+v"(Jt));
+#pragma unroll
+  for (int c = 0; c < B2; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (col[c] >= 0 && tid + (int64_t)e * NT < n) Jt[col[c] * ldm + (int64_t)e * NT] = x[c][e];
 }
 
 // sigma[k] = ||M_k|| (fixed-order block sum), one block per column
@@ -157,19 +235,21 @@ __global__ void __launch_bounds__(256)
 typedef void (*StepFn)(double*, double*, int64_t, int64_t, int64_t, int64_t, double,
                        unsigned long long*);
 
-// (threads, rows per thread) for columns of length n: every row in a register
+// (threads, columns per block) for columns of length n: every row of the
+// block's columns in a register (at most 32 doubles per thread at 1024
+// threads and 64 at 512, beside the round's partial sums; more spills)
 struct StepShape {
-  int nt;
+  int nt, b2;
   StepFn fn;
 };
 bool pick_step(int64_t n, StepShape* out) {
-  if (n <= 256) *out = {256, k_jacobi_step<256, 1>};
-  else if (n <= 512) *out = {256, k_jacobi_step<256, 2>};
-  else if (n <= 1024) *out = {256, k_jacobi_step<256, 4>};
-  else if (n <= 2048) *out = {256, k_jacobi_step<256, 8>};
-  else if (n <= 4096) *out = {256, k_jacobi_step<256, 16>};
-  else if (n <= 8192) *out = {1024, k_jacobi_step<1024, 8>};
-  else if (n <= 16384) *out = {1024, k_jacobi_step<1024, 16>};
+  if (n <= 256) *out = {256, 8, k_jacobi_step<256, 1, 8>};
+  else if (n <= 512) *out = {256, 8, k_jacobi_step<256, 2, 8>};
+  else if (n <= 1024) *out = {256, 8, k_jacobi_step<256, 4, 8>};
+  else if (n <= 2048) *out = {512, 8, k_jacobi_step<512, 4, 8>};
+  else if (n <= 4096) *out = {512, 8, k_jacobi_step<512, 8, 8>};
+  else if (n <= 8192) *out = {1024, 4, k_jacobi_step<1024, 8, 4>};
+  else if (n <= 16384) *out = {1024, 2, k_jacobi_step<1024, 16, 2>};
   else return false;
   return true;
 }
@@ -193,7 +273,10 @@ rfmls_status run_build_svd_precond(rfmls_handle* h, int64_t n, const double* SA,
   // R (normalised, row-major) kept for export, as for the QR preconditioner
   RFMLS_CHECK(run_extract_R(h, n, SA, ld, P));
   const int64_t ldm = (n + 31) / 32 * 32;  // 256-byte aligned columns
-  const int64_t N = n + (n & 1);
+  // column groups of b = sh.b2 / 2, rounded up to an even count
+  const int64_t gb = sh.b2 / 2;
+  const int64_t Gn = (n + gb - 1) / gb;
+  const int64_t Gp = Gn + (Gn & 1);
   void* pw;
   RFMLS_CHECK(workspace(h, WS_SVD, sizeof(double) * (2 * (size_t)n * ldm + (size_t)n) + 64, &pw));
   double* Mc = (double*)pw;
@@ -224,19 +307,24 @@ rfmls_status run_build_svd_precond(rfmls_handle* h, int64_t n, const double* SA,
       // and for each pair that rotates M's two written and J's two read and
       // written (set below from the sweep's rotation count)
       Trace tr(h, "svd_jacobi_sweep", 0.0, 0.0);
-      for (int64_t t = 0; t < N - 1; ++t)
-        hipLaunchKernelGGL(sh.fn, dim3((unsigned)(N / 2)), dim3(sh.nt), 0, st, Mc, Jc, n, ldm, N, t, tol,
+      for (int64_t t = 0; t < Gp - 1; ++t)
+        hipLaunchKernelGGL(sh.fn, dim3((unsigned)(Gp / 2)), dim3(sh.nt), 0, st, Mc, Jc, n, ldm, Gp, t, tol,
                            ctr);
     }
     RFMLS_HIP(h, hipGetLastError());
-    RFMLS_HIP(h, hipMemcpyAsync(pin, ctr, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    RFMLS_HIP(h, hipMemcpyAsync(pin, ctr, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     RFMLS_HIP(h, hipStreamSynchronize(st));
     double off;
     const unsigned long long bits = pin[0];
     memcpy(&off, &bits, sizeof(off));
     if (h->trace && !h->trace_recs.empty()) {
-      const double pairs = (double)(N / 2) * (double)(N - 1), rot = (double)pin[1];
-      h->trace_recs.back().bytes = 8.0 * (double)n * (2.0 * pairs + 6.0 * rot);
+      // algorithmic bytes of the sweep: every step reads all n columns of M;
+      // each block that rotated writes its 2b columns of M back and reads and
+      // writes those of J.  Flops: 6 per row for a pair's three products, 12
+      // for a rotation of M's and J's two columns.
+      const double steps = (double)(Gp - 1), pairs = steps * (double)(Gp / 2) * (sh.b2 * (sh.b2 - 1) / 2);
+      const double rot = (double)pin[1], rblocks = (double)pin[2];
+      h->trace_recs.back().bytes = 8.0 * (double)n * ((double)n * steps + 3.0 * sh.b2 * rblocks);
       h->trace_recs.back().flops = (double)n * (6.0 * pairs + 12.0 * rot);
     }
     P->sweeps = sweep + 1;

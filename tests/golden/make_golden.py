@@ -3,7 +3,9 @@
 Calls only the CPU oracle (oracle/) on inputs from the seeded generator
 (rfmgen/); the GPU path is never involved.  Usage:
     python tests/golden/make_golden.py poisson2d_8x8 [poisson3d_4x4x4 ...]
-writes tests/golden/<name>.json.
+writes tests/golden/<name>.json;
+    python tests/golden/make_golden.py --svd helmholtz3d_2x2x2
+adds the CSSVDP-LSQR (Alg. 2) results under the key "svd" of that file.
 """
 
 import json
@@ -16,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import countsketch, pipeline, qr  # noqa: E402
+from oracle import countsketch, pipeline, qr, svd  # noqa: E402
 from rfmgen import build_config, feature_eval, sample_points  # noqa: E402
 
 SKETCH_SEED = 2
@@ -51,6 +53,31 @@ def main(name: str, refine: int = 2):
     print(json.dumps(out))
 
 
+def main_svd(name: str, refine: int = 2):
+    t0 = time.time()
+    S, s = build_config(name)
+    out = pipeline.solve_svd(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, SKETCH_SEED, refine=refine)
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    sig = out["sigma"]
+    rec = dict(rcond=svd.default_rcond(S.n), rank=out["rank"], sigma_max=float(sig[0]),
+               sigma_min=float(sig[-1]), sigma_quantiles=[float(v) for v in np.quantile(sig, [0.1, 0.5, 0.9])],
+               itn_sweeps=out["itn_sweeps"], normr=out["normr"], relres=out["relres"],
+               normal_relres=out["normal_relres"], l2_error=pipeline.l2_error(E, out["x"], S.exact(pts)),
+               seconds=time.time() - t0)
+    path = os.path.join(HERE, f"{name}.json")
+    data = json.load(open(path))
+    data["svd"] = rec
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+    print(json.dumps(rec))
+
+
 if __name__ == "__main__":
-    for nm in sys.argv[1:]:
-        main(nm)
+    args = sys.argv[1:]
+    if args and args[0] == "--svd":
+        for nm in args[1:]:
+            main_svd(nm)
+    else:
+        for nm in args:
+            main(nm)

@@ -13,7 +13,9 @@ Against the oracle:
     points against the stored oracle results in tests/golden/ (written by
     tests/golden/make_golden.py, which calls only the oracle), from the zero
     and from the sketched starting point, and with the explicit B = A R^{-1}
-    (the least-squares optimum is the same for all).
+    (the least-squares optimum is the same for all);
+  * on the Helmholtz system, CSSVDP-LSQR (Alg. 2): the Jacobi SVD's singular
+    values and the solve against the stored oracle CSSVDP results.
 
 Residual tolerance: 1e-10 relative where cond(A) u^2-level effects stay below
 it (3D system, pivot ratio min|r_jj|/max|r_jj| = 1.7e-7).  The 2D system has a
@@ -105,4 +107,34 @@ def test_fullsize_solve_matches_oracle(handle, name, prec, start, op):
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
     l2 = pipeline.l2_error(E, x, S.exact(pts))
     assert l2 <= 1.1 * gold["l2_error"], (l2, gold["l2_error"])
+    del res
+
+
+# CSSVDP-LSQR (Alg. 2) on the Helmholtz system: the singular values of the
+# GPU's Jacobi SVD against the oracle's LAPACK SVD (sigma_1, sigma_n, rank and
+# quantiles, to a few units of rounding relative to sigma_1), and the solve
+# against the oracle's CSSVDP result, which is the same least-squares optimum
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_fullsize_cssvdp_matches_oracle(handle, store):
+    name = "helmholtz3d_2x2x2"
+    S, s, A = _system(name)
+    gold = _golden(name)["svd"]
+    opts = R.default_opts(refine=2)
+    res = R.cssvdp_lsqr(handle, A, torch.tensor(S.b[0], device="cuda"), s, SEED, p_store=store,
+                        opts=opts)
+    P = res.precond
+    assert res.status == 0 and P.rank == gold["rank"]
+    sig = np.sort(R.rfmls_precond_export_sigma(handle, P).cpu().numpy())[::-1]
+    tol = 1e-11 * gold["sigma_max"]
+    assert abs(sig[0] - gold["sigma_max"]) <= tol and abs(sig[-1] - gold["sigma_min"]) <= tol
+    assert np.max(np.abs(np.quantile(sig, [0.1, 0.5, 0.9]) - gold["sigma_quantiles"])) <= tol
+    info = res.info[0]
+    assert info["istop"] in (1, 2)
+    x = res.x.cpu().numpy()
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    met = pipeline.residual_metrics(Ah, x, S.b[0])
+    assert abs(met["normr"] - gold["normr"]) <= RES_TOL[name] * gold["normr"], (met["normr"], gold["normr"])
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    assert pipeline.l2_error(E, x, S.exact(pts)) <= 1.1 * gold["l2_error"]
     del res
