@@ -71,6 +71,32 @@ __device__ __forceinline__ int64_t circle(int64_t slot, int64_t t, int64_t Gp) {
   return slot == 0 ? 0 : (slot - 1 + t) % (Gp - 1) + 1;
 }
 
+// Wavefront sum of a double on the DPP path (no LDS traffic): rotations by 1, 2,
+// 4 and 8 lanes inside each 16-lane row leave every lane with its row's sum,
+// and the four row sums (lanes 0, 16, 32, 48) are added in a fixed order, so
+// the result is the same on every lane and run to run.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  constexpr int kRowRor = 0x120;  // DPP row_ror:n = 0x120 + n
+  v += dpp_move<kRowRor + 1>(v);
+  v += dpp_move<kRowRor + 2>(v);
+  v += dpp_move<kRowRor + 4>(v);
+  v += dpp_move<kRowRor + 8>(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
 // local column of slot i in round r of the circle schedule over B2 columns
 __host__ __device__ constexpr int lcol(int i, int r, int B2) { return i == 0 ? 0 : (i - 1 + r) % (B2 - 1) + 1; }
 
@@ -101,22 +127,25 @@ __global__ void __launch_bounds__(NT)
     const int64_t k = c < b ? g1 * b + c : g2 * b + (c - b);
     col[c] = k < n ? k : -1;
   }
-  // element (row tid + e NT, column k) of M is Mt[k ldm + e NT]: a per-thread
-  // base plus a block-uniform offset.  The base is made opaque between the
-  // loads and the stores, so the stores recompute their addresses instead of
-  // keeping B2 x E 64-bit addresses live (spilled) across the rotations.
-  double* Mt = M + tid;
+  // column k of M starts at the block-uniform M + k ldm; a thread's rows are
+  // 32-bit offsets tid + e NT from it (n < 2^31), so every access is a scalar
+  // base plus a small per-thread offset and no 64-bit per-element address
+  // has to stay live across the rotations
   double x[B2][E];
 #pragma unroll
-  for (int c = 0; c < B2; ++c)
+  for (int c = 0; c < B2; ++c) {
+    const double* mc = M + (col[c] >= 0 ? col[c] : 0) * ldm;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      x[c][e] = (col[c] >= 0 && tid + (int64_t)e * NT < n) ? Mt[col[c] * ldm + (int64_t)e * NT] : 0.0;
+    for (int e = 0; e < E; ++e) {
+      const unsigned i = (unsigned)tid + (unsigned)(e * NT);
+      x[c][e] = (col[c] >= 0 && i < n) ? mc[i] : 0.0;
+    }
+  }
   double offmax = 0.0;
   int nrot = 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    double s3[3 * H];
+    __syncthreads();  // the previous round's reads of red are done
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const int p = lcol(k, r, B2), q = lcol(B2 - 1 - k, r, B2);
@@ -127,14 +156,14 @@ __global__ void __launch_bounds__(NT)
         bb += x[q][e] * x[q][e];
         ab += x[p][e] * x[q][e];
       }
-      s3[3 * k] = wave_sum(aa);
-      s3[3 * k + 1] = wave_sum(bb);
-      s3[3 * k + 2] = wave_sum(ab);
-    }
-    __syncthreads();  // the previous round's reads of red are done
-    if (lane == 0) {
-#pragma unroll
-      for (int v = 0; v < 3 * H; ++v) red[v][w] = s3[v];
+      aa = wave_sum_dpp(aa);
+      bb = wave_sum_dpp(bb);
+      ab = wave_sum_dpp(ab);
+      if (lane == 0) {
+        red[3 * k][w] = aa;
+        red[3 * k + 1][w] = bb;
+        red[3 * k + 2][w] = ab;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -184,19 +213,25 @@ __global__ void __launch_bounds__(NT)
     }
   }
   if (nrot == 0) return;  // uniform: nothing moved in this block
-  asm volatile("" : "+v"(Mt));
 #pragma unroll
-  for (int c = 0; c < B2; ++c)
+  for (int c = 0; c < B2; ++c) {
+    double* mc = M + (col[c] >= 0 ? col[c] : 0) * ldm;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (col[c] >= 0 && tid + (int64_t)e * NT < n) Mt[col[c] * ldm + (int64_t)e * NT] = x[c][e];
+    for (int e = 0; e < E; ++e) {
+      const unsigned i = (unsigned)tid + (unsigned)(e * NT);
+      if (col[c] >= 0 && i < n) mc[i] = x[c][e];
+    }
+  }
   // the same rotations, in the same order, on J's columns
-  double* Jt = J + tid;
 #pragma unroll
-  for (int c = 0; c < B2; ++c)
+  for (int c = 0; c < B2; ++c) {
+    const double* jc = J + (col[c] >= 0 ? col[c] : 0) * ldm;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      x[c][e] = (col[c] >= 0 && tid + (int64_t)e * NT < n) ? Jt[col[c] * ldm + (int64_t)e * NT] : 0.0;
+    for (int e = 0; e < E; ++e) {
+      const unsigned i = (unsigned)tid + (unsigned)(e * NT);
+      x[c][e] = (col[c] >= 0 && i < n) ? jc[i] : 0.0;
+    }
+  }
   __syncthreads();  // rot[] complete
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -213,12 +248,15 @@ __global__ void __launch_bounds__(NT)
         }
       }
     }
-  asm volatile("" : "+v"(Jt));
 #pragma unroll
-  for (int c = 0; c < B2; ++c)
+  for (int c = 0; c < B2; ++c) {
+    double* jc = J + (col[c] >= 0 ? col[c] : 0) * ldm;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (col[c] >= 0 && tid + (int64_t)e * NT < n) Jt[col[c] * ldm + (int64_t)e * NT] = x[c][e];
+    for (int e = 0; e < E; ++e) {
+      const unsigned i = (unsigned)tid + (unsigned)(e * NT);
+      if (col[c] >= 0 && i < n) jc[i] = x[c][e];
+    }
+  }
 }
 
 // sigma[k] = ||M_k|| (fixed-order block sum), one block per column
