@@ -144,6 +144,7 @@ enum WsSlot {
   WS_X0,
   WS_GEMV,
   WS_SVD,
+  WS_SPMM_PART,
   WS_MISC,
   WS_NUM_SLOTS
 };

@@ -231,6 +231,12 @@ __global__ void __launch_bounds__(kThreads)
 // are accumulated in CSR order, so results are deterministic.
 // Malformed input (columns out of order or out of range) cannot make the
 // kernel read outside Xin or LDS: such entries end a window's prefix early.
+//
+// Split groups (nsplit > 1, for matrices with few long rows): work item
+// (group, z) takes only the entries whose column lies in the z-th of nsplit
+// ranges cut at equal-count points of the group's first row, and writes its
+// raw sums to part[z][row][32]; k_spmm_merge adds the nsplit parts in order and
+// applies the scaling, the subtraction and the sums of squares.
 constexpr int kGroup = 16;
 constexpr int kWin = 128;
 
@@ -239,7 +245,8 @@ __global__ void __launch_bounds__(kThreads)
     k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
            const double* __restrict__ val, int64_t rows, int64_t ncols, const double* __restrict__ Xin,
            double sA, double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
-           double* out, double* __restrict__ sq, const BlockState* __restrict__ st) {
+           double* out, double* __restrict__ sq, const BlockState* __restrict__ st, int nsplit,
+           double* __restrict__ part) {
   if (st && all_done(st)) return;
   __shared__ double Xs[kWin][kBlk];
   __shared__ double Vs[kGroup][kWin];
@@ -259,12 +266,41 @@ __global__ void __launch_bounds__(kThreads)
   const bool act = !st || !st->col[c].done;
   double ss = 0.0;
   const int64_t ngroups = (rows + kGroup - 1) / kGroup;
-  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+  for (int64_t wi = blockIdx.x; wi < ngroups * nsplit; wi += gridDim.x) {
+    const int64_t gi = wi / nsplit;
+    const int z = (int)(wi % nsplit);
     const int64_t r0 = gi * kGroup;
     if (tid < kGroup) {
       const int64_t r = r0 + tid;
-      cur[tid] = r < rows ? rp[r] : 0;
-      endp[tid] = r < rows ? rp[r + 1] : 0;
+      int64_t b = r < rows ? rp[r] : 0, e = r < rows ? rp[r + 1] : 0;
+      if (nsplit > 1) {
+        // column range [lo, hi) of split z, cut at equal-count points of row r0
+        const int64_t f0 = rp[r0], len0 = rp[r0 + 1] - rp[r0];
+        const int32_t lo = z == 0 ? INT32_MIN : (len0 > 0 ? col[f0 + (int64_t)z * len0 / nsplit] : INT32_MAX);
+        const int32_t hi = z == nsplit - 1 ? INT32_MAX
+                                           : (len0 > 0 ? col[f0 + (int64_t)(z + 1) * len0 / nsplit] : INT32_MAX);
+        // first entries of this row at or beyond lo and beyond hi (binary searches)
+        int64_t a = b, c2 = e;
+        while (a < c2) {
+          const int64_t mid = (a + c2) / 2;
+          if (col[mid] < lo) a = mid + 1;
+          else c2 = mid;
+        }
+        int64_t a2 = a, c3 = e;
+        if (hi != INT32_MAX) {
+          while (a2 < c3) {
+            const int64_t mid = (a2 + c3) / 2;
+            if (col[mid] < hi) a2 = mid + 1;
+            else c3 = mid;
+          }
+        } else {
+          a2 = e;
+        }
+        b = a;
+        e = a2;
+      }
+      cur[tid] = b;
+      endp[tid] = e;
     }
     double acc[RPS];
 #pragma unroll
@@ -345,7 +381,15 @@ __global__ void __launch_bounds__(kThreads)
       __syncthreads();
       if (tid < kGroup) cur[tid] += cnt[tid];
     }
-    // write the group's rows
+    // write the group's rows (a split group: its raw partial sums)
+    if (nsplit > 1) {
+#pragma unroll
+      for (int h2 = 0; h2 < RPS; ++h2) {
+        const int64_t row = r0 + slot + kSlots * h2;
+        if (row < rows) part[((int64_t)z * rows + row) * kBlk + c] = acc[h2];
+      }
+      continue;
+    }
 #pragma unroll
     for (int h2 = 0; h2 < RPS; ++h2) {
       const int64_t row = r0 + slot + kSlots * h2;
@@ -364,6 +408,39 @@ __global__ void __launch_bounds__(kThreads)
       double t = 0.0;
       for (int q = 0; q < kThreads / kBlk; ++q) t += red[q][tid];
       sq[blockIdx.x * kBlk + tid] = t;
+    }
+  }
+}
+
+// out[row][c] = sA sum_z part[z][row][c] (z in order) - cf prev[row][c] for the
+// rows of a split SpMM; per-column sums of squares per block as k_spmm's.
+__global__ void __launch_bounds__(kThreads)
+    k_spmm_merge(const double* __restrict__ part, int nsplit, int64_t rows, double sA, double hcoef,
+                 const double* __restrict__ coef, int cstride, const double* prev, double* out,
+                 double* __restrict__ sq, const BlockState* __restrict__ st) {
+  if (st && all_done(st)) return;
+  __shared__ double red[kThreads / kBlk][kBlk];
+  const int c = threadIdx.x % kBlk, rsub = threadIdx.x / kBlk;
+  double cf = hcoef;
+  if (coef) cf *= coef[c * cstride];
+  const bool act = !st || !st->col[c].done;
+  double ss = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * (kThreads / kBlk) + rsub; row < rows;
+       row += (int64_t)gridDim.x * (kThreads / kBlk)) {
+    double a = 0.0;
+    for (int z = 0; z < nsplit; ++z) a += part[((int64_t)z * rows + row) * kBlk + c];
+    double o = sA * a;
+    if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
+    if (act) out[row * kBlk + c] = o;
+    ss += o * o;
+  }
+  if (sq) {
+    red[rsub][c] = ss;
+    __syncthreads();
+    if (threadIdx.x < kBlk) {
+      double t = 0.0;
+      for (int q = 0; q < kThreads / kBlk; ++q) t += red[q][threadIdx.x];
+      sq[blockIdx.x * kBlk + threadIdx.x] = t;
     }
   }
 }
@@ -691,6 +768,20 @@ SpmmShape spmm_shape(const rfmls_csr* M) {
   if (M->m > 0 && M->nnz / M->m > 512) return {(const void*)k_spmm<8, 32>, 8, 1792};
   return {(const void*)k_spmm<16, 64>, 16, 1024};
 }
+// Split row groups of a matrix with fewer than 4 groups per compute unit and
+// long rows (at least 8 windows per split) so that the grid covers the chip:
+// nsplit = ceil(4 CUs / groups), at most 8.
+int spmm_split(const rfmls_csr* M, int num_cus) {
+  const SpmmShape sh = spmm_shape(M);
+  const int64_t ng = (M->m + sh.group - 1) / sh.group;
+  const int64_t target = 4 * (int64_t)num_cus;
+  if (ng <= 0 || ng >= target || M->nnz / M->m < 8 * 32) return 1;
+  const int64_t sp = (target + ng - 1) / ng;
+  const int64_t win = M->nnz / M->m / 32;  // windows of a row at the long-row shape
+  int64_t k = sp < 8 ? sp : 8;
+  while (k > 1 && win / k < 8) --k;
+  return (int)k;
+}
 
 struct BCtx {
   rfmls_handle* h;
@@ -700,6 +791,7 @@ struct BCtx {
   hipStream_t st;
   double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX, *Sm, *Sn;
   double *sqA, *sqB, *sqY, *sqW, *part;
+  double* spart;  // partial sums of split SpMM groups (nsplit x rows x 32)
   BlockState* dst;
 };
 
@@ -750,17 +842,27 @@ rfmls_status spmm(BCtx& c, const rfmls_csr* M, const double* x, double sA, doubl
                   const BlockState* stp, int* nblk) {
   const SpmmShape sh = spmm_shape(M);
   const int64_t ng = (M->m + sh.group - 1) / sh.group;
-  const unsigned nb = (unsigned)(ng < (int64_t)sh.max_blocks ? (ng > 0 ? ng : 1) : sh.max_blocks);
+  const int nsplit = spmm_split(M, c.h->num_cus);
+  const int64_t work = ng * nsplit;
+  const unsigned nb = (unsigned)(work < (int64_t)sh.max_blocks ? (work > 0 ? work : 1) : sh.max_blocks);
   Trace tr(c.h, M == c.A ? "spmm_A" : "spmm_At",
            12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) +
                8.0 * kBlk * ((double)M->n + (double)M->m * (prev ? 2.0 : 1.0)),
            2.0 * kBlk * (double)M->nnz);
   int kStride_v = kStride;
+  double* spart = c.spart;
   void* args[] = {(void*)&M->row_ptr, (void*)&M->col, (void*)&M->val, (void*)&M->m, (void*)&M->n,
                   (void*)&x, (void*)&sA, (void*)&hcoef, (void*)&coef, (void*)&kStride_v, (void*)&prev,
-                  (void*)&out, (void*)&sq, (void*)&stp};
+                  (void*)&out, (void*)&sq, (void*)&stp, (void*)&nsplit, (void*)&spart};
   RFMLS_HIP(c.h, hipLaunchKernel(sh.fn, dim3(nb), dim3(kThreads), args, 0, c.st));
-  if (nblk) *nblk = (int)nb;
+  if (nsplit > 1) {
+    const unsigned gm = rows_grid(M->m);
+    hipLaunchKernelGGL(k_spmm_merge, dim3(gm), dim3(kThreads), 0, c.st, (const double*)spart, nsplit, M->m,
+                       sA, hcoef, coef, kStride, prev, out, sq, stp);
+    if (nblk) *nblk = (int)gm;
+  } else if (nblk) {
+    *nblk = (int)nb;
+  }
   RFMLS_HIP(c.h, hipGetLastError());
   return RFMLS_OK;
 }
@@ -869,6 +971,14 @@ static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_c
   c.sqY = take(kSpmmMaxBlocks * kBlk);
   c.sqW = take(kSpmmMaxBlocks * kBlk);
   c.part = take(P->nt * maxk * kTile * kBlk);
+  {
+    const int64_t need = (int64_t)spmm_split(A, h->num_cus) * A->m > (int64_t)spmm_split(AT, h->num_cus) * AT->m
+                             ? (int64_t)spmm_split(A, h->num_cus) * A->m
+                             : (int64_t)spmm_split(AT, h->num_cus) * AT->m;
+    void* pp;
+    RFMLS_CHECK(workspace(h, WS_SPMM_PART, sizeof(double) * (size_t)need * kBlk, &pp));
+    c.spart = (double*)pp;
+  }
   void* ps;
   RFMLS_CHECK(workspace(h, WS_LSQR_BSTATE, sizeof(BlockState), &ps));
   c.dst = (BlockState*)ps;
