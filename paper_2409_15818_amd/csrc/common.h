@@ -145,6 +145,8 @@ enum WsSlot {
   WS_GEMV,
   WS_SVD,
   WS_SPMM_PART,
+  WS_SVD2,
+  WS_APPLYQ,
   WS_MISC,
   WS_NUM_SLOTS
 };
@@ -211,9 +213,14 @@ rfmls_status run_transpose(rfmls_handle* h, const rfmls_csr* A, int64_t* rp, int
                            double* val);
 rfmls_status scan_counts(rfmls_handle* h, const int32_t* count, int64_t n, int64_t* ptr);
 // Householder QR of SA (s x n); columns n .. n_room-1 (n_room <= ld) may be
-// used as scratch
+// used as scratch; tau_out (n values of SA's dtype, device) receives every
+// reflector's tau when given
 rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, rfmls_dtype dt, void* SA,
-                    int64_t ld);
+                    int64_t ld, void* tau_out = nullptr);
+// Y <- Q Y (Y: s x ny row-major, ldy) for the float64 QR run_qr left in P
+// (s x n, ld) with its taus
+rfmls_status apply_householder(rfmls_handle* h, const double* P, int64_t ld, int64_t s, int64_t n,
+                               const double* tau, double* Y, int64_t ldy, int64_t ny);
 rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, const void* SA,
                                int64_t ld, rfmls_dtype store, rfmls_precond_t* P, int check_rank);
 rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit);

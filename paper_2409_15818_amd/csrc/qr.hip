@@ -471,7 +471,7 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
 // their column count up to the tile width inside that room (full tiles, no
 // ragged edge); the extra columns only ever hold values nothing reads.
 template <typename T>
-rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld) {
+rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld, T* tau_out) {
   constexpr int64_t kOuter = outer_width<T>();
   hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 8192;
@@ -550,6 +550,9 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       }
       RFMLS_HIP(h, hipGetLastError());
     }
+    // every reflector's tau, for a caller that applies Q afterwards
+    if (tau_out)
+      RFMLS_HIP(h, hipMemcpyAsync(tau_out + k0, tau, sizeof(T) * (size_t)bw, hipMemcpyDeviceToDevice, st));
     // ---------------- trailing update with the whole outer block ----------------
     if (n - k0 - bw <= 0) continue;
     // columns right of the block, rounded up to the widest tile (128) within
@@ -638,10 +641,75 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
 }  // namespace
 
 rfmls_status run_qr(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, rfmls_dtype dt, void* SA,
-                    int64_t ld) {
+                    int64_t ld, void* tau_out) {
   if (n_room < n || n_room > ld) n_room = n;
-  if (dt == RFMLS_F64) return qr_impl<double>(h, s, n, n_room, (double*)SA, ld);
-  return qr_impl<float>(h, s, n, n_room, (float*)SA, ld);
+  if (dt == RFMLS_F64) return qr_impl<double>(h, s, n, n_room, (double*)SA, ld, (double*)tau_out);
+  return qr_impl<float>(h, s, n, n_room, (float*)SA, ld, (float*)tau_out);
+}
+
+// Y <- Q Y with Q = H_0 H_1 ... H_{n-1} of a float64 Householder QR left by
+// run_qr in P (s x n, vectors below the diagonal, tau from its tau_out): the
+// 64-column panels from last to first, each as Y <- (I - V T V^T) Y with
+// T from the panel's Gram V^T V and tau, i.e. W = V^T Y, W' = T W, Y -= V W'.
+rfmls_status apply_householder(rfmls_handle* h, const double* P, int64_t ld, int64_t s, int64_t n,
+                               const double* tau, double* Y, int64_t ldy, int64_t ny) {
+  hipStream_t st = h->stream;
+  const int64_t ldw = (ny + 31) / 32 * 32;
+  void* pw;
+  RFMLS_CHECK(workspace(h, WS_APPLYQ, sizeof(double) * (size_t)(2 * kMaxNb * kMaxNb + 2 * kMaxNb * ldw), &pw));
+  double* G = (double*)pw;
+  double* Tq = G + kMaxNb * kMaxNb;
+  double* W = Tq + kMaxNb * kMaxNb;
+  double* Wp = W + kMaxNb * ldw;
+  for (int64_t p0 = (n - 1) / kMaxNb * kMaxNb; p0 >= 0; p0 -= kMaxNb) {
+    const int jb = (int)(n - p0 < kMaxNb ? n - p0 : kMaxNb);
+    const int64_t M = s - p0;
+    double* V = const_cast<double*>(P) + p0 * ld + p0;
+    RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(vt_gemm<double>(V, ld, M, jb, jb, G, kMaxNb, 0), st)));
+    hipLaunchKernelGGL(k_qr_buildT<double>, dim3(1), dim3(256), 0, st, (const double*)G, (int64_t)0, 1,
+                       (int64_t)kMaxNb, jb, tau + p0, Tq, (int64_t)kMaxNb);
+    GemmArgs<double> gw;  // W = V^T Y[p0:, :]
+    gw.M = jb;
+    gw.N = ny;
+    gw.K = M;
+    gw.A = V;
+    gw.lda = ld;
+    gw.transA = 1;
+    gw.a_vmask = 1;
+    gw.B = Y + p0 * ldy;
+    gw.ldb = ldy;
+    gw.C = W;
+    gw.ldc = ldw;
+    RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(gw, st)));
+    GemmArgs<double> gt;  // W' = T W (T upper triangular)
+    gt.M = jb;
+    gt.N = ny;
+    gt.K = jb;
+    gt.A = Tq;
+    gt.lda = kMaxNb;
+    gt.a_upper = 1;
+    gt.B = W;
+    gt.ldb = ldw;
+    gt.C = Wp;
+    gt.ldc = ldw;
+    RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(gt, st)));
+    GemmArgs<double> gu;  // Y[p0:, :] -= V W'
+    gu.M = M;
+    gu.N = ny;
+    gu.K = jb;
+    gu.A = V;
+    gu.lda = ld;
+    gu.a_vmask = 1;
+    gu.B = Wp;
+    gu.ldb = ldw;
+    gu.C = Y + p0 * ldy;
+    gu.ldc = ldy;
+    gu.alpha = -1.0;
+    gu.beta = 1.0;
+    RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(gu, st)));
+  }
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
 }
 
 }  // namespace rfmls
