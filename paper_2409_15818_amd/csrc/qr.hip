@@ -476,7 +476,9 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 8192;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
-  const int64_t nsp_out_max = (s + split_out - 1) / split_out;
+  // slices of the outer V^T [V | C]: the masked top rows, the clean 8192-row
+  // slices and a ragged tail
+  const int64_t nsp_out_max = (s + split_out - 1) / split_out + 2;
   void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
   RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuterMax, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
@@ -562,13 +564,33 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     T* P0 = SA + k0 * ld + k0;
     const int64_t ncols = bw + ntr;
     const int64_t ldw = pad32(ncols), ldwp = pad32(ntr);
-    const int64_t nsp = (M0 + split_out - 1) / split_out;
+    // V^T [V | C] in row slices summed in order: rows [0, bw) hold the
+    // triangle of V (masked, general kernel); the rows below are clear of every
+    // mask, so a whole number of 16-row chunks of them goes to the clean-only
+    // kernel in 8192-row slices, and a tail of fewer than 16 rows (if any) to the
+    // general kernel without masks
+    const int64_t Kc = (M0 - bw) / 16 * 16, Kt = M0 - bw - Kc;
+    const int64_t nsc = (Kc + split_out - 1) / split_out;
+    const int64_t nsp = 1 + nsc + (Kt > 0 ? 1 : 0);
+    const int64_t zs = bw * ldw;
     {
       Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
                2.0 * (double)bw * ncols * M0);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, M0, bw, ncols, Wz, ldw, split_out), st)));
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, bw, bw, ncols, Wz, ldw, 0), st)));
+      if (Kc > 0) {
+        GemmArgs<T> gc = vt_gemm<T>(P0 + bw * ld, ld, Kc, bw, ncols, Wz + zs, ldw, split_out);
+        gc.a_vmask = 0;
+        gc.b_vcols = 0;
+        RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrVtC>(gc, st)));
+      }
+      if (Kt > 0) {
+        GemmArgs<T> gr = vt_gemm<T>(P0 + (bw + Kc) * ld, ld, Kt, bw, ncols, Wz + (1 + nsc) * zs, ldw, 0);
+        gr.a_vmask = 0;
+        gr.b_vcols = 0;
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gr, st)));
+      }
       hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ldw, 256) < 4096 ? ceil_div(bw * ldw, 256) : 4096),
-                         dim3(256), 0, st, (const T*)Wz, bw * ldw, (int)nsp, bw * ldw, W);
+                         dim3(256), 0, st, (const T*)Wz, bw * ldw, (int)nsp, zs, W);
     }
     {
       // T_o: its diagonal 64-blocks are the inner panels' T, written above,
@@ -631,7 +653,14 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     {
       Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr + (double)M0 * bw + (double)bw * ntr),
                2.0 * (double)M0 * ntr * bw);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, M0, bw, ntr, Wp, ldwp), st)));
+      // rows [0, bw) meet the triangle of V (masked, general kernel); the rows
+      // below are clear of it and take the clean-only kernel
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, bw, bw, ntr, Wp, ldwp), st)));
+      if (M0 > bw) {
+        GemmArgs<T> gu = v_update<T>(P0 + bw * ld, ld, M0 - bw, bw, ntr, Wp, ldwp);
+        gu.a_vmask = 0;
+        RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrTrailingUpdate>(gu, st)));
+      }
     }
     RFMLS_HIP(h, hipGetLastError());
   }
