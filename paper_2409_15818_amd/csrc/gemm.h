@@ -12,7 +12,10 @@
 //     (k, i) (transpose); for B they are (k, j) for the first b_vcols columns.
 //   - triangular operands: op(A) upper (k >= i only) or lower (k <= i only)
 //     triangular and/or B upper triangular (k <= j only); zero K-tiles are
-//     skipped and the zero triangle is never read (it may hold anything).
+//     skipped and the zero triangle is never read (it may hold anything),
+//     unless b_lower_zero says that B's entries below the diagonal inside the
+//     K range of each 64-column tile are stored zeros: then they are read as
+//     they are and a diagonal chunk needs no mask.
 // Split-K: blockIdx.z selects the K range [z*ksplit, (z+1)*ksplit) and output
 // C + z*c_zstride (each slice writes its own partial result, no atomics).
 //
@@ -42,6 +45,7 @@ struct GemmArgs {
   int a_upper = 0;      // op(A) upper triangular
   int a_lower = 0;      // op(A) lower triangular
   int b_upper = 0;      // B upper triangular
+  int b_lower_zero = 0; // with b_upper: B's lower triangle holds zeros where read
   int64_t ksplit = 0;   // 0 = no split
   int64_t c_zstride = 0;
 };
@@ -197,7 +201,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
     if (g.a_upper && k0 < ilast) return false;
     if (g.a_lower && klast > i0) return false;
     if (g.a_vmask && (g.transA ? !(k0 > ilast) : !(i0 > klast))) return false;
-    if (g.b_upper && klast > j0) return false;
+    if (g.b_upper && !g.b_lower_zero && klast > j0) return false;
     if (j0 < g.b_vcols && !(k0 > jlast)) return false;
     return true;
   };
@@ -326,12 +330,13 @@ inline hipError_t gemm(const GemmArgs<T>& g, hipStream_t st) {
 }
 
 // The same product on the clean-only instantiation when nothing needs the
-// element-wise path: no mask or triangle and every block's K range a whole
-// number of 16-row chunks; otherwise the general kernel.
+// element-wise path: no mask, no triangle (except an upper-triangular B whose
+// lower triangle is stored zeros) and every block's K range a whole number of
+// 16-row chunks; otherwise the general kernel.
 template <typename T, GemmRole Role = GemmRole::Generic>
 inline hipError_t gemm_clean(const GemmArgs<T>& g, hipStream_t st) {
-  const bool ok = !g.a_vmask && g.b_vcols == 0 && !g.a_upper && !g.a_lower && !g.b_upper && g.K % 16 == 0 &&
-                  (g.ksplit == 0 || g.ksplit % 16 == 0);
+  const bool ok = !g.a_vmask && g.b_vcols == 0 && !g.a_upper && !g.a_lower && (!g.b_upper || g.b_lower_zero) &&
+                  g.K % 16 == 0 && (g.ksplit == 0 || g.ksplit % 16 == 0);
   if (ok) return gemm_detail::launch<T, Role, true>(g, st);
   return gemm_detail::launch<T, Role, false>(g, st);
 }

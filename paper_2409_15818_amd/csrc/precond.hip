@@ -87,6 +87,9 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
 }
 
 // Block row I of X = R^{-1} (rows [o, o + b), o = 64 I), columns j in [o, n).
+// Every column j >= o of the block row is written, so the diagonal block's
+// lower triangle gets the exact zeros back substitution leaves there (0 / r_ii
+// below a unit right-hand side); the GEMMs above read those as stored.
 // Right-hand side: e_j restricted to the block row, minus R_{I,>I} X_{>I}, which
 // arrives in two parts (see invert_upper): Pn (b x (n - o - 64), one slice) from
 // the rows of X solved earlier inside the same outer block, and nzf split-K
@@ -235,11 +238,12 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       g.C = Pf;
       g.ldc = ldf;
       g.b_upper = 1;
+      g.b_lower_zero = 1;  // k_inv_blockrow wrote the diagonal blocks' lower triangles as zeros
       g.ksplit = ks;
       g.c_zstride = zsf;
       Trace tr(h, "inv_gemm", 8.0 * ((double)(e2 - o2) * far + 0.5 * (double)far * far + (double)nzf * (e2 - o2) * far),
                (double)(e2 - o2) * (double)far * (double)far);
-      RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
+      RFMLS_HIP(h, (gemm_clean<double, GemmRole::Inverse>(g, h->stream)));
     }
     for (int64_t I = (e2 - 1) / kTile; I >= I2 * kInvTiles; --I) {
       const int64_t o = I * kTile;
@@ -258,9 +262,10 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
         g.C = Pn;
         g.ldc = ldn;
         g.b_upper = 1;
+        g.b_lower_zero = 1;
         Trace tr(h, "inv_gemm_near", 8.0 * ((double)b * kn + (double)kn * g.N + (double)b * g.N),
                  2.0 * (double)b * kn * (double)g.N);
-        RFMLS_HIP(h, (gemm<double, GemmRole::Inverse>(g, h->stream)));
+        RFMLS_HIP(h, (gemm_clean<double, GemmRole::Inverse>(g, h->stream)));
       }
       {
         Trace tr(h, "inv_blockrow", 8.0 * ((double)(nzf + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
