@@ -95,61 +95,83 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
 // the rows of X solved earlier inside the same outer block, and nzf split-K
 // slices of Pf (rows roff .. roff + b of a (rows of the outer block) x (n - e2)
 // partial) from the rows beyond the outer block, for columns j >= e2.  Then
-// R_II x = rhs by back substitution.  One thread per column with its 64 values
-// in registers; the substitution is column-oriented (x_i = rhs_i / r_ii, then
-// every rhs_k, k < i, is updated at once), so each step offers up to 63
-// independent FMAs instead of one dependent dot product per row.
-constexpr int kInvCols = 128;
+// R_II x = rhs by back substitution, column-oriented (x_i = rhs_i / r_ii, then
+// every rhs_k, k < i, is updated at once).  Four neighbouring lanes share a
+// column, each holding 16 of its 64 rows in registers; x_i is passed from the
+// lane holding row i to the other three by a DPP quad broadcast.  Every element
+// sees the same operations in the same order as a one-lane-per-column
+// substitution, at a quarter of the registers (more wavefronts in flight).
+constexpr int kInvCols = 64;               // columns per block
+constexpr int kInvLanes = 4;               // lanes per column
+constexpr int kInvRows = kTile / kInvLanes;  // rows per lane
 
-__global__ void __launch_bounds__(kInvCols)
+// value of lane (lane & ~3) + Q of each quad, for every lane of the quad
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int kCtrl = Q | (Q << 2) | (Q << 4) | (Q << 6);  // DPP quad_perm(Q, Q, Q, Q)
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__global__ void __launch_bounds__(kInvCols * kInvLanes)
     k_inv_blockrow(const double* __restrict__ R, int64_t n, int64_t I, const double* __restrict__ Pn,
                    int64_t ldn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
                    int64_t roff, int64_t e2, double* __restrict__ X) {
-  __shared__ double Rs[kTile][kTile];
+  __shared__ double Rs[kTile][kTile + 1];
   const int64_t o = I * kTile;
   const int b = (int)(n - o < kTile ? n - o : kTile);
   const int t = threadIdx.x;
-  for (int e = t; e < kTile * kTile; e += kInvCols) {
+  for (int e = t; e < kTile * kTile; e += kInvCols * kInvLanes) {
     const int i = e / kTile, k = e % kTile;
     Rs[i][k] = (i < b && k < b) ? R[(o + i) * n + o + k] : (i == k ? 1.0 : 0.0);
   }
-  const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t;
+  const int q = t % kInvLanes;  // this lane holds rows q*16 .. q*16 + 15
+  const int r0 = q * kInvRows;
+  const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t / kInvLanes;
   const bool live = j < n;
-  double v[kTile];
+  double v[kInvRows];
 #pragma unroll
-  for (int i = 0; i < kTile; ++i) v[i] = (live && j == o + i) ? 1.0 : 0.0;
+  for (int l = 0; l < kInvRows; ++l) v[l] = (live && j == o + r0 + l) ? 1.0 : 0.0;
   if (live && j >= o + kTile && Pn) {
     const int64_t jc = j - o - kTile;
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) v[i] = i < b ? -Pn[(int64_t)i * ldn + jc] : 0.0;
+    for (int l = 0; l < kInvRows; ++l) v[l] = r0 + l < b ? -Pn[(int64_t)(r0 + l) * ldn + jc] : 0.0;
   }
   if (live && j >= e2) {
     const int64_t jf = j - e2;
     for (int z = 0; z < nzf; ++z) {
       const double* Pz = Pf + (int64_t)z * zsf + roff * ldf + jf;
 #pragma unroll
-      for (int i = 0; i < kTile; ++i)
-        if (i < b) v[i] -= Pz[(int64_t)i * ldf];
+      for (int l = 0; l < kInvRows; ++l)
+        if (r0 + l < b) v[l] -= Pz[(int64_t)(r0 + l) * ldf];
     }
   }
   __syncthreads();
   // rows >= b are the identity with v = 0 and stay 0
 #pragma unroll
-  for (int i = kTile - 1; i >= 0; --i) {
-    v[i] = v[i] / Rs[i][i];
+  for (int qi = kInvLanes - 1; qi >= 0; --qi) {
 #pragma unroll
-    for (int k = 0; k < i; ++k) v[k] -= Rs[k][i] * v[i];
+    for (int li = kInvRows - 1; li >= 0; --li) {
+      const int i = qi * kInvRows + li;
+      // x_i on the lane that holds row i, then on the whole quad
+      double xi = v[li] / Rs[i][i];
+      xi = qi == 0 ? quad_bcast<0>(xi) : qi == 1 ? quad_bcast<1>(xi) : qi == 2 ? quad_bcast<2>(xi) : quad_bcast<3>(xi);
+      if (q == qi) v[li] = xi;
+      // rhs_k -= r_ki x_i for the rows k < i this lane holds
+#pragma unroll
+      for (int l = 0; l < kInvRows; ++l)
+        if (r0 + l < i) v[l] -= Rs[r0 + l][i] * xi;
+    }
   }
   if (live) {
 #pragma unroll
-    for (int i = 0; i < kTile; ++i)
-      if (i < b) X[(o + i) * n + j] = v[i];
+    for (int l = 0; l < kInvRows; ++l)
+      if (r0 + l < b) X[(o + r0 + l) * n + j] = v[l];
   }
 }
 
-// Tiles of X (row-major n x n) in the packed order of either layout: the
-// upper-triangular packing keeps tiles J >= I (and zeros below the diagonal
-// inside diagonal tiles), the full one every tile.
 template <typename TS>
 __global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt, int full,
                              TS* __restrict__ pk) {
@@ -270,7 +292,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       {
         Trace tr(h, "inv_blockrow", 8.0 * ((double)(nzf + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
                  (double)kTile * kTile * (double)(n - o));
-        hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols), 0, h->stream, R,
+        hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols * kInvLanes), 0, h->stream, R,
                            n, I, kn > 0 ? (const double*)Pn : (const double*)nullptr, ldn, (const double*)Pf,
                            nzf, ldf, zsf, o - o2, e2, X);
       }
