@@ -311,9 +311,11 @@ inline hipError_t launch(const GemmArgs<T>& g, hipStream_t st) {
   if (gz == 0) gz = 1;
   // Tiles measured fastest at the QR's shapes on gfx950: 64 x 64 (higher
   // occupancy beats larger register tiles), except float32 products with a
-  // long K range (W = V^T [V | C] over 8192-row slices), which prefer 128 x 128.
+  // long K range (W = V^T [V | C] over 8192-row slices) and, on the clean-only
+  // instance, float32 products with K >= 256 (the trailing update: 112 -> 123
+  // TFLOP/s in isolation), which prefer 128 x 128.
   const int64_t kspan = g.ksplit > 0 ? g.ksplit : g.K;
-  if (sizeof(T) == 4 && g.M > 64 && g.N > 64 && kspan >= 1024) {
+  if (sizeof(T) == 4 && g.M > 64 && g.N > 64 && (kspan >= 1024 || (CleanOnly && kspan >= 256))) {
     dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), gz);
     hipLaunchKernelGGL((k_gemm<T, 128, 128, 16, 2, 2, Role, CleanOnly>), grid, dim3(256), 0, st, g);
   } else {
