@@ -14,11 +14,12 @@
 //                sum_{i>j} a_ij a_ic and the pivot row, after which every
 //                workgroup forms the same reflector and applies it to its rows;
 //   inside the outer block: W = V^T [V | C] (split-K GEMM), T from V^T V
-//                (dlarft, forward, columnwise), C <- C - V (T^T W).
+//                (the inverse of its strict upper part plus diag(1/tau), by
+//                back substitution), C <- C - V (T^T W).
 // Outer block at column k0 (M0 = s - k0 rows, V_o = its kOuter Householder vectors):
 //   W = V_o^T [V_o | C] (split-K GEMM; the first kOuter columns are the Gram V_o^T V_o),
-//   T_o from the Gram: diagonal 64-blocks by dlarft, off-diagonal blocks by
-//   T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
+//   T_o from the Gram: diagonal 64-blocks are the panels' T, off-diagonal
+//   blocks T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
 // All reductions run in a fixed order, so the factorisation is deterministic.
 #include "common.h"
 #include "gemm.h"
@@ -275,55 +276,44 @@ __global__ void __launch_bounds__(kPanelThreads)
 }
 
 // Build T (nb x nb upper triangular, row-major) of the compact-WY form
-// H_1 ... H_nb = I - V T V^T from tau and the Gram V^T V = sum of nsplit
-// partial slices Wz (each nb x ldw; its leading nb columns hold V^T V).
-// T is assembled by doubling: starting from T_jj = tau_j, neighbouring
-// diagonal blocks T_1, T_2 (b columns each) are joined by
-//   T_12 = -T_1 (V_1^T V_2) T_2,
-// the block form of the column recursion T[:j, j] = -tau_j T[:j, :j] V_:j^T v_j
-// (Schreiber and Van Loan), with all threads working on each level.
+// H_1 ... H_nb = I - V T V^T from tau and the Gram V^T V (the sum of nsplit
+// partial slices Wz, each nb x ldw, whose leading nb columns hold V^T V).
+// T is the inverse of U = (strictly upper part of V^T V) + diag(1/tau): that
+// is the matrix form of the column recursion T[:j, j] = -tau_j T[:j, :j]
+// V_:j^T v_j (Schreiber and Van Loan).  Column k of T solves U t = e_k by
+// back substitution on one wavefront (lane i holds row i), t_l = tau_l x_l
+// from the bottom up, so 1/tau is never formed and a reflector with tau_j = 0
+// (H_j = I) leaves row and column j zero, as the recursion does.  The 16
+// wavefronts take columns {w, 31 - w, 32 + w, 63 - w}, equal total lengths.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_qr_buildT(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb,
                 const T* __restrict__ tau, T* __restrict__ Tout, int64_t ldt) {
-  __shared__ double Gm[kMaxNb][kMaxNb + 1];
-  __shared__ double Tm[kMaxNb][kMaxNb + 1];
-  __shared__ double Ym[kMaxNb][kMaxNb + 1];
+  __shared__ double Us[kMaxNb][kMaxNb + 1];  // Us[i][l] = (V^T V)_il for i < l
+  __shared__ double ts[kMaxNb];
   const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e / nb, k = e % nb;
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int i = e / nb, l = e % nb;
     double sacc = 0.0;
-    for (int z = 0; z < nsplit; ++z) sacc += (double)Wz[(int64_t)z * zstride + (int64_t)i * ldw + k];
-    Gm[i][k] = sacc;
-    Tm[i][k] = (i == k) ? (double)tau[i] : 0.0;
+    if (i < l)
+      for (int z = 0; z < nsplit; ++z) sacc += (double)Wz[(int64_t)z * zstride + (int64_t)i * ldw + l];
+    Us[i][l] = sacc;
   }
+  if (tid < nb) ts[tid] = (double)tau[tid];
   __syncthreads();
-  for (int b = 1; b < nb; b *= 2) {
-    const int npair = (nb + 2 * b - 1) / (2 * b);
-    // Y = T_1 G_12 for every pair (rows of the first block, columns of the second)
-    for (int e = tid; e < npair * b * b; e += 256) {
-      const int pr = e / (b * b), r = e % (b * b);
-      const int f0 = pr * 2 * b, s0 = f0 + b;
-      const int i = f0 + r / b, j = s0 + r % b;
-      if (j >= nb) continue;
-      double acc = 0.0;
-      for (int k = i; k < s0; ++k) acc += Tm[i][k] * Gm[k][j];
-      Ym[i][j] = acc;
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int k = m == 0 ? w : m == 1 ? 31 - w : m == 2 ? 32 + w : 63 - w;
+    if (k >= nb) continue;  // uniform within the wavefront
+    double x = lane == k ? 1.0 : 0.0, t = 0.0;
+    for (int l = k; l >= 0; --l) {
+      const double tl = ts[l] * lane_value(x, l);  // x_l is final once rows > l are done
+      if (lane == l) t = tl;
+      if (lane < l) x -= Us[lane][l] * tl;
     }
-    __syncthreads();
-    // T_12 = -Y T_2
-    for (int e = tid; e < npair * b * b; e += 256) {
-      const int pr = e / (b * b), r = e % (b * b);
-      const int f0 = pr * 2 * b, s0 = f0 + b;
-      const int i = f0 + r / b, j = s0 + r % b;
-      if (j >= nb) continue;
-      double acc = 0.0;
-      for (int k = s0; k <= j; ++k) acc += Ym[i][k] * Tm[k][j];
-      Tm[i][j] = -acc;
-    }
-    __syncthreads();
+    if (lane < nb) Tout[(int64_t)lane * ldt + k] = (T)(lane <= k ? t : 0.0);
   }
-  for (int e = tid; e < nb * nb; e += 256) Tout[(int64_t)(e / nb) * ldt + e % nb] = (T)Tm[e / nb][e % nb];
 }
 
 // W[e] = sum_z Wz[z * zstride + e] over a contiguous range of len elements
@@ -335,34 +325,6 @@ __global__ void k_sum_slices(const T* __restrict__ Wz, int64_t zstride, int nspl
     double acc = 0.0;
     for (int z = 0; z < nsplit; ++z) acc += (double)Wz[(int64_t)z * zstride + e];
     W[e] = (T)acc;
-  }
-}
-
-// W'[:, cols] = T^T * sum_z Wz[:, nb + cols], one block per 64 columns.
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_qr_wp(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb, int64_t N,
-            const T* __restrict__ Tm, int64_t ldt, T* __restrict__ Wp, int64_t ldwp) {
-  __shared__ double Ws[kMaxNb][64 + 1];
-  __shared__ double Ts[kMaxNb][kMaxNb + 1];
-  const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  for (int e = tid; e < nb * nb; e += 256) Ts[e / nb][e % nb] = (double)Tm[(int64_t)(e / nb) * ldt + e % nb];
-  for (int e = tid; e < nb * 64; e += 256) {
-    const int i = e / 64, cc = e % 64;
-    double sacc = 0.0;
-    if (c0 + cc < N)
-      for (int z = 0; z < nsplit; ++z)
-        sacc += (double)Wz[(int64_t)z * zstride + (int64_t)i * ldw + nb + c0 + cc];
-    Ws[i][cc] = sacc;
-  }
-  __syncthreads();
-  for (int e = tid; e < nb * 64; e += 256) {
-    const int i = e / 64, cc = e % 64;
-    if (c0 + cc >= N) continue;
-    double a = 0.0;
-    for (int k = 0; k <= i; ++k) a += Ts[k][i] * Ws[k][cc];
-    Wp[(int64_t)i * ldwp + c0 + cc] = (T)a;
   }
 }
 
@@ -380,6 +342,51 @@ constexpr int64_t kOuterMax = 512;
 template <typename T>
 constexpr int64_t outer_width() { return sizeof(T) == 4 ? 512 : 256; }
 inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
+
+// W' = T^T W_C for one panel: W = V^T [V | C] (nb x ldw, its leading nb
+// columns the Gram, W_C the ncol columns after them) and the panel's T (nb x
+// nb upper triangular, rows ldt apart).  One workgroup per 32 columns; thread
+// (ty, tx) forms rows ty + 32 a and columns tx + 8 b of its strip, summing in
+// float64 over LDS copies of T and of the strip.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_qr_wp(const T* __restrict__ W, int64_t ldw, int nb, const T* __restrict__ Tm, int64_t ldt,
+            int64_t ncol, T* __restrict__ Wp, int64_t ldwp) {
+  constexpr int SW = 32;
+  __shared__ double Ts[kMaxNb][kMaxNb + 1];  // [k][i] = T_ki (zero below the diagonal)
+  __shared__ double Ws[kMaxNb][SW + 1];      // [k][c]
+  const int tid = threadIdx.x;
+  const int ty = tid >> 3, tx = tid & 7;
+  const int64_t c0 = (int64_t)blockIdx.x * SW;
+  for (int e = tid; e < kMaxNb * kMaxNb; e += 256) {
+    const int k = e / kMaxNb, i = e % kMaxNb;
+    Ts[k][i] = (k <= i && i < nb) ? (double)Tm[(int64_t)k * ldt + i] : 0.0;
+  }
+  for (int e = tid; e < kMaxNb * SW; e += 256) {
+    const int k = e / SW, c = e % SW;
+    Ws[k][c] = (k < nb && c0 + c < ncol) ? (double)W[(int64_t)k * ldw + nb + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  double o[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 4
+  for (int k = 0; k < kMaxNb; ++k) {
+    const double m0 = Ts[k][ty], m1 = Ts[k][ty + 32];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double r = Ws[k][tx + 8 * b];
+      o[0][b] += m0 * r;
+      o[1][b] += m1 * r;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 32 * a;
+      const int64_t c = c0 + tx + 8 * b;
+      if (i < nb && c < ncol) Wp[(int64_t)i * ldwp + c] = (T)o[a][b];
+    }
+}
 
 // Panel launch shapes (rows per thread Q, rows per block 16 Q), increasing.
 // The largest are the largest that compile without spills at 1024 threads.
@@ -538,12 +545,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       }
       {
         Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
-        // this panel's T is also the diagonal block of the outer block's T_o
+        // this panel's T is also a diagonal block of the outer block's T_o
         T* Tq = To + (p0 - k0) * kOuter + (p0 - k0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)W, (int64_t)0, 1,
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(1024), 0, st, (const T*)W, (int64_t)0, 1,
                            ldw, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
-        hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 64)), dim3(256), 0, st, (const T*)W,
-                           (int64_t)0, 1, ldw, jb, rem, (const T*)Tq, (int64_t)kOuter, Wp, ldwp);
+        hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 32)), dim3(256), 0, st, (const T*)W, ldw, jb,
+                           (const T*)Tq, (int64_t)kOuter, rem, Wp, ldwp);
       }
       {
         Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
@@ -601,7 +608,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       {
         const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
         const int jq = (int)(bw - q0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(256), 0, st, (const T*)(W + q0 * ldw + q0),
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(1024), 0, st, (const T*)(W + q0 * ldw + q0),
                            (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
                            (int64_t)kOuter);
       }
@@ -696,7 +703,7 @@ rfmls_status apply_householder(rfmls_handle* h, const double* P, int64_t ld, int
     const int64_t M = s - p0;
     double* V = const_cast<double*>(P) + p0 * ld + p0;
     RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(vt_gemm<double>(V, ld, M, jb, jb, G, kMaxNb, 0), st)));
-    hipLaunchKernelGGL(k_qr_buildT<double>, dim3(1), dim3(256), 0, st, (const double*)G, (int64_t)0, 1,
+    hipLaunchKernelGGL(k_qr_buildT<double>, dim3(1), dim3(1024), 0, st, (const double*)G, (int64_t)0, 1,
                        (int64_t)kMaxNb, jb, tau + p0, Tq, (int64_t)kMaxNb);
     GemmArgs<double> gw;  // W = V^T Y[p0:, :]
     gw.M = jb;
