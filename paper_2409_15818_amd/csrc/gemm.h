@@ -48,7 +48,7 @@ struct GemmArgs {
   int b_lower_zero = 0; // with b_upper: B's lower triangle holds zeros where read
   int64_t ksplit = 0;   // 0 = no split
   int64_t c_zstride = 0;
-  int col_grid = 0;     // issue the tiles column by column (see k_gemm)
+  int tile_order = 0;   // order the tiles are issued in (see k_gemm)
 };
 
 // What a GEMM launch is for.  The role only names the kernel symbol (so that
@@ -151,14 +151,24 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wy = wave / WN, wx = wave % WN;
-  // Tiles are issued row by row (grid x = tile column), or with col_grid
-  // column by column (grid x = tile row), which runs the tiles that share a
-  // B column strip together.  Triangular operands make the K range grow with
-  // the tile column (B upper: k <= j) or row (op(A) lower: k <= i); those tiles
-  // are issued first (reversed order) so the longest blocks do not form a tail
-  // at the end of the grid.
-  const unsigned gx = g.col_grid ? blockIdx.y : blockIdx.x, nx = g.col_grid ? gridDim.y : gridDim.x;
-  const unsigned gy = g.col_grid ? blockIdx.x : blockIdx.y, ny = g.col_grid ? gridDim.x : gridDim.y;
+  // Tile order: 0 row by row (grid x = tile column); 1 column by column
+  // (grid x = tile row), which runs the tiles that share a B column strip
+  // together; 2 in bands of 32 tile rows, each band column by column, so a
+  // band's A strips stay in L2 while its B strips are each read for 32 tiles
+  // in a row.  Triangular operands make the K range grow with the tile column
+  // (B upper: k <= j) or row (op(A) lower: k <= i); those tiles are issued
+  // first (reversed order) so the longest blocks do not form a tail at the
+  // end of the grid.
+  unsigned gx = g.tile_order == 1 ? blockIdx.y : blockIdx.x, nx = g.tile_order == 1 ? gridDim.y : gridDim.x;
+  unsigned gy = g.tile_order == 1 ? blockIdx.x : blockIdx.y, ny = g.tile_order == 1 ? gridDim.x : gridDim.y;
+  if (g.tile_order == 2) {
+    constexpr unsigned kBand = 32;
+    const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;
+    const unsigned r0 = L / (kBand * nx) * kBand, idx = L % (kBand * nx);
+    const unsigned gm = ny - r0 < kBand ? ny - r0 : kBand;
+    gx = idx / gm;
+    gy = r0 + idx % gm;
+  }
   const unsigned bx = g.b_upper ? nx - 1 - gx : gx;
   const unsigned by = g.a_lower ? ny - 1 - gy : gy;
   const int64_t i0 = (int64_t)by * BMt;
@@ -323,11 +333,11 @@ inline hipError_t launch(const GemmArgs<T>& g, hipStream_t st) {
   const int64_t kspan = g.ksplit > 0 ? g.ksplit : g.K;
   if (sizeof(T) == 4 && g.M > 64 && g.N > 64 && (kspan >= 1024 || (CleanOnly && kspan >= 256))) {
     const unsigned tn = (unsigned)((g.N + 127) / 128), tm = (unsigned)((g.M + 127) / 128);
-    dim3 grid(g.col_grid ? tm : tn, g.col_grid ? tn : tm, gz);
+    dim3 grid(g.tile_order == 1 ? tm : tn, g.tile_order == 1 ? tn : tm, gz);
     hipLaunchKernelGGL((k_gemm<T, 128, 128, 16, 2, 2, Role, CleanOnly>), grid, dim3(256), 0, st, g);
   } else {
     const unsigned tn = (unsigned)((g.N + 63) / 64), tm = (unsigned)((g.M + 63) / 64);
-    dim3 grid(g.col_grid ? tm : tn, g.col_grid ? tn : tm, gz);
+    dim3 grid(g.tile_order == 1 ? tm : tn, g.tile_order == 1 ? tn : tm, gz);
     hipLaunchKernelGGL((k_gemm<T, 64, 64, 16, 2, 2, Role, CleanOnly>), grid, dim3(256), 0, st, g);
   }
   return hipGetLastError();

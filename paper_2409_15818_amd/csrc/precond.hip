@@ -264,7 +264,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       g.ksplit = ks;
       // the kInvTiles row tiles that read one column strip of X run together,
       // so the strip comes from HBM once: 46 -> 60 TFLOP/s at 24,576 columns
-      g.col_grid = 1;
+      g.tile_order = 1;
       g.c_zstride = zsf;
       Trace tr(h, "inv_gemm", 8.0 * ((double)(e2 - o2) * far + 0.5 * (double)far * far + (double)nzf * (e2 - o2) * far),
                (double)(e2 - o2) * (double)far * (double)far);
