@@ -70,18 +70,24 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t I0 = (int64_t)k * C;
   const int64_t Iend = col_end(J, nt, full);
   const int64_t I1 = I0 + C < Iend ? I0 + C : Iend;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double acc = 0.0;
+  const int lane = threadIdx.x & 63;
+  // the wavefront index as a uniform value: the 16 entries of qv a wavefront
+  // needs per tile are then scalar loads, with no branch for the bound test
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double acc0 = 0.0, acc1 = 0.0;  // two chains over alternate rows
   for (int64_t I = I0; I < I1; ++I) {
     const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 16; q += 2) {
       const int r = w + 4 * q;
       const int64_t gr = I * kTile + r;
-      const double qr = gr < n ? qv[gr] : 0.0;
-      acc += (double)t[r * kTile + lane] * qr;
+      const double q0 = gr < n ? qv[gr] : 0.0;
+      const double q1 = gr + 4 < n ? qv[gr + 4] : 0.0;
+      acc0 += (double)t[r * kTile + lane] * q0;
+      acc1 += (double)t[(r + 4) * kTile + lane] * q1;
     }
   }
+  const double acc = acc0 + acc1;
   red[w][lane] = acc;
   __syncthreads();
   if (w == 0)
