@@ -95,8 +95,8 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
 // the rows of X solved earlier inside the same outer block, and nzf split-K
 // slices of Pf (rows roff .. roff + b of a (rows of the outer block) x (n - e2)
 // partial) from the rows beyond the outer block, for columns j >= e2.  Then
-// R_II x = rhs by back substitution, column-oriented (x_i = rhs_i / r_ii, then
-// every rhs_k, k < i, is updated at once).  Four neighbouring lanes share a
+// R_II x = rhs by back substitution, column-oriented (x_i = rhs_i * (1 / r_ii),
+// the 64 reciprocals formed once, then every rhs_k, k < i, is updated at once).  Four neighbouring lanes share a
 // column, each holding 16 of its 64 rows in registers; x_i is passed from the
 // lane holding row i to the other three by a DPP quad broadcast.  Every element
 // sees the same operations in the same order as a one-lane-per-column
@@ -120,13 +120,16 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
                    int64_t ldn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
                    int64_t roff, int64_t e2, double* __restrict__ X) {
   __shared__ double Rs[kTile][kTile + 1];
+  __shared__ double rinv[kTile];  // 1 / r_ii, formed once so no division sits on the chain
   const int64_t o = I * kTile;
   const int b = (int)(n - o < kTile ? n - o : kTile);
   const int t = threadIdx.x;
   for (int e = t; e < kTile * kTile; e += kInvCols * kInvLanes) {
     const int i = e / kTile, k = e % kTile;
-    Rs[i][k] = (i < b && k < b) ? R[(o + i) * n + o + k] : (i == k ? 1.0 : 0.0);
+    // zeros below the diagonal: the update loop below then needs no per-row test
+    Rs[i][k] = (i < b && k < b && k >= i) ? R[(o + i) * n + o + k] : (i == k ? 1.0 : 0.0);
   }
+  if (t < kTile) rinv[t] = t < b ? 1.0 / R[(o + t) * n + o + t] : 1.0;
   const int q = t % kInvLanes;  // this lane holds rows q*16 .. q*16 + 15
   const int r0 = q * kInvRows;
   const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t / kInvLanes;
@@ -156,13 +159,13 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
     for (int li = kInvRows - 1; li >= 0; --li) {
       const int i = qi * kInvRows + li;
       // x_i on the lane that holds row i, then on the whole quad
-      double xi = v[li] / Rs[i][i];
+      double xi = v[li] * rinv[i];
       xi = qi == 0 ? quad_bcast<0>(xi) : qi == 1 ? quad_bcast<1>(xi) : qi == 2 ? quad_bcast<2>(xi) : quad_bcast<3>(xi);
-      if (q == qi) v[li] = xi;
-      // rhs_k -= r_ki x_i for the rows k < i this lane holds
+      // rhs_k -= r_ki x_i on every row this lane holds: rows k > i meet the
+      // stored zeros (v_k - 0 = v_k), row i is overwritten by x_i just after
 #pragma unroll
-      for (int l = 0; l < kInvRows; ++l)
-        if (r0 + l < i) v[l] -= Rs[r0 + l][i] * xi;
+      for (int l = 0; l < kInvRows; ++l) v[l] -= Rs[r0 + l][i] * xi;
+      if (q == qi) v[li] = xi;
     }
   }
   if (live) {
