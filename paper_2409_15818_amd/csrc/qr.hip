@@ -289,17 +289,19 @@ template <typename T>
 __global__ void __launch_bounds__(1024)
     k_qr_buildT(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb,
                 const T* __restrict__ tau, T* __restrict__ Tout, int64_t ldt) {
-  __shared__ double Us[kMaxNb][kMaxNb + 1];  // Us[i][l] = (V^T V)_il for i < l
-  __shared__ double ts[kMaxNb];
+  // Us[i][l] = (V^T V)_il for i < l < nb, zero elsewhere, so the update below
+  // needs no per-row test (rows i >= l subtract exactly 0)
+  __shared__ double Us[kMaxNb][kMaxNb + 1];
+  __shared__ double ts[kMaxNb + 3];  // three zero entries below index 0 (steps past l = 0)
   const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 1024) {
-    const int i = e / nb, l = e % nb;
+  for (int e = tid; e < kMaxNb * kMaxNb; e += 1024) {
+    const int i = e / kMaxNb, l = e % kMaxNb;
     double sacc = 0.0;
-    if (i < l)
+    if (i < l && l < nb)
       for (int z = 0; z < nsplit; ++z) sacc += (double)Wz[(int64_t)z * zstride + (int64_t)i * ldw + l];
     Us[i][l] = sacc;
   }
-  if (tid < nb) ts[tid] = (double)tau[tid];
+  if (tid < kMaxNb + 3) ts[tid] = (tid >= 3 && tid - 3 < nb) ? (double)tau[tid - 3] : 0.0;
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
@@ -307,10 +309,23 @@ __global__ void __launch_bounds__(1024)
     const int k = m == 0 ? w : m == 1 ? 31 - w : m == 2 ? 32 + w : 63 - w;
     if (k >= nb) continue;  // uniform within the wavefront
     double x = lane == k ? 1.0 : 0.0, t = 0.0;
-    for (int l = k; l >= 0; --l) {
-      const double tl = ts[l] * lane_value(x, l);  // x_l is final once rows > l are done
-      if (lane == l) t = tl;
-      if (lane < l) x -= Us[lane][l] * tl;
+    // four steps per group, their LDS reads issued together; steps past l = 0
+    // read tau = 0 and column 0 of Us (zeros) and change nothing
+    for (int l0 = k; l0 >= 0; l0 -= 4) {
+      double u[4], tt[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int l = l0 - d;
+        u[d] = Us[lane][l > 0 ? l : 0];
+        tt[d] = ts[l + 3];
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int l = l0 - d;
+        const double tl = tt[d] * lane_value(x, l > 0 ? l : 0);  // x_l is final once rows > l are done
+        if (lane == l) t = tl;
+        x -= u[d] * tl;
+      }
     }
     if (lane < nb) Tout[(int64_t)lane * ldt + k] = (T)(lane <= k ? t : 0.0);
   }
