@@ -174,12 +174,22 @@ __global__ void __launch_bounds__(kPanelThreads)
       piv[c] = pv;
     }
     // ---- local partials over rows i > j: sum_i a_ij a_ic ----
+    // (up to 16 rows per thread, a_ij of the wavefront's rows is kept for the
+    // update below, column j not changing in between; more rows would spill)
+    constexpr bool kKeep = Q <= 16;
     double s = 0.0;
+    T aj[kKeep ? Q : 1];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int li = rg + kPanelGroups * q;
       // rows li >= kMaxNb > j always take part (compile-time for large q)
-      if (kPanelGroups * q >= kMaxNb || !top || li > j) s += lane_value(a[q], j) * (double)a[q];
+      if (kPanelGroups * q >= kMaxNb || !top || li > j) {
+        const T v = (T)lane_value(a[q], j);
+        if constexpr (kKeep) aj[q] = v;
+        s += (double)v * (double)a[q];
+      } else if constexpr (kKeep) {
+        aj[q] = T(0);
+      }
     }
     grp[rg][c] = s;
     __syncthreads();
@@ -249,16 +259,21 @@ __global__ void __launch_bounds__(kPanelThreads)
     const bool upd = (c > j && c < nb && tj != 0.0);
     const double f = upd ? tj * (red[L + c - j] + scal * red[c - j]) : 0.0;
     const double sf = scal * f;
+    // one multiply-add per row below the diagonal, with no per-lane branch:
+    // a - sf v_j on the columns updated, scal v_j on column j (it becomes v),
+    // a + 0 v_j (exactly a) on the columns left alone
+    const double kv = upd ? -sf : (c == j ? scal : 0.0);
+    const bool keep = (c != j);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int li = rg + kPanelGroups * q;
-      const double vj = lane_value(a[q], j);  // read before lane j rewrites it
       if (kPanelGroups * q >= kMaxNb || !top || li > j) {
-        if (upd) a[q] = (T)((double)a[q] - sf * vj);
-        else if (c == j) a[q] = (T)(scal * vj);
+        double vj;
+        if constexpr (kKeep) vj = (double)aj[q];
+        else vj = lane_value(a[q], j);  // read before lane j rewrites it
+        a[q] = (T)fma(kv, vj, keep ? (double)a[q] : 0.0);
       } else if (li == j) {
-        if (upd) a[q] = (T)((double)a[q] - f);
-        else if (c == j) a[q] = (T)beta;
+        a[q] = (T)(upd ? (double)a[q] - f : (c == j ? beta : (double)a[q]));
       }
     }
     // no barrier here: the next writes of red, refl and part follow the next
