@@ -62,11 +62,15 @@ __device__ __forceinline__ double ll_wait(const uint64_t* slot, unsigned tag, in
       *ok = 0;
       return 0.0;
     }
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(4);
   }
   return v;
 }
-// Two values polled together (one round trip per attempt for both).
+// Two values polled together (one round trip per attempt for both).  Every
+// workgroup polls the same few slots here (the totals and the pivot row), so
+// the attempts are spaced out: 24 x 64 clocks between them measured about 1%
+// faster on the whole panel than back-to-back polls (fewer reads queue at
+// those cache lines), and two polls kept in flight 8% slower.
 __device__ __forceinline__ void ll_wait2(const uint64_t* s0, const uint64_t* s1, unsigned tag,
                                          double* v0, double* v1, int* err, int* ok) {
   uint64_t* p0 = const_cast<uint64_t*>(s0);
@@ -82,7 +86,7 @@ __device__ __forceinline__ void ll_wait2(const uint64_t* s0, const uint64_t* s1,
       *v0 = *v1 = 0.0;
       return;
     }
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(24);
   }
 }
 
