@@ -1,7 +1,7 @@
 // Blocked Householder QR of the sketch SA (s x n, row-major, in place):
 // Alg. 1 step 3.  Only R is needed; Q is never formed.
 //
-// Two levels of blocking.  Outer blocks of kOuter = 256 (float32: 512) columns
+// Two levels of blocking.  Outer blocks of kOuter = 256 or 512 columns
 // are factored panel by panel (kMaxNb = 64 columns each); the trailing matrix
 // right of an outer block is then updated once, with K = kOuter, which keeps
 // that update -- most of the flops -- on the matrix cores instead of bound by
@@ -368,13 +368,15 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
     p[i] = 0ull;
 }
 
-// Outer block width: 256 columns for float64; 512 for float32, whose trailing
-// update then reads and writes the trailing matrix half as often (measured on
-// the 4^3-box sketch: 2.5% less QR time; neutral for float64, where the inner
-// products grow by as much as the trailing update gains).
+// Outer block width: 512 columns for float32, whose trailing update then
+// reads and writes the trailing matrix half as often (4^3-box sketch: 2.5% less
+// QR time than 256), and for float64 from 16,384 columns on (4^3-box, 25,600
+// columns: 1.3% less solve time); narrower float64 systems keep 256, where the
+// inner 64-column products, which grow with the width, cancel the gain (8x8-box,
+// 12,800 columns: equal).
 constexpr int64_t kOuterMax = 512;
 template <typename T>
-constexpr int64_t outer_width() { return sizeof(T) == 4 ? 512 : 256; }
+int64_t outer_width(int64_t n) { return sizeof(T) == 4 || n >= 16384 ? 512 : 256; }
 inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
 // W' = T^T W_C for one panel: W = V^T [V | C] (nb x ldw, its leading nb
@@ -513,7 +515,7 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
 // ragged edge); the extra columns only ever hold values nothing reads.
 template <typename T>
 rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld, T* tau_out) {
-  constexpr int64_t kOuter = outer_width<T>();
+  const int64_t kOuter = outer_width<T>(n);
   hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 4096;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
