@@ -153,14 +153,31 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(GemmArgs<T> g) {
   const int wy = wave / WN, wx = wave % WN;
   // Tile order: 0 row by row (grid x = tile column); 1 column by column
   // (grid x = tile row), which runs the tiles that share a B column strip
-  // together; 2 in bands of 32 tile rows, each band column by column, so a
-  // band's A strips stay in L2 while its B strips are each read for 32 tiles
-  // in a row.  Triangular operands make the K range grow with the tile column
+  // together; 3 the same with each column's tiles on one XCD; 2 in bands of
+  // 32 tile rows, each band column by column, so a band's A strips stay in L2
+  // while its B strips are each read for 32 tiles in a row.  Triangular operands make the K range grow with the tile column
   // (B upper: k <= j) or row (op(A) lower: k <= i); those tiles are issued
   // first (reversed order) so the longest blocks do not form a tail at the
   // end of the grid.
   unsigned gx = g.tile_order == 1 ? blockIdx.y : blockIdx.x, nx = g.tile_order == 1 ? gridDim.y : gridDim.x;
   unsigned gy = g.tile_order == 1 ? blockIdx.x : blockIdx.y, ny = g.tile_order == 1 ? gridDim.x : gridDim.y;
+  if (g.tile_order == 3) {
+    // column by column, XCD-aware: workgroups are dealt to the 8 XCDs in
+    // turn, so XCD x runs linear ids x, x + 8, ...; its k-th workgroup takes
+    // row k % ny of column x + 8 (k / ny), so a column's row tiles share one
+    // L2.  The columns past the last whole group of 8 follow in plain column
+    // order.
+    const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;
+    const unsigned nc8 = nx & ~7u, full = ny * nc8;
+    if (L < full) {
+      const unsigned k = L >> 3;
+      gx = (L & 7u) + 8u * (k / ny);
+      gy = k % ny;
+    } else {
+      gx = nc8 + (L - full) / ny;
+      gy = (L - full) % ny;
+    }
+  }
   if (g.tile_order == 2) {
     constexpr unsigned kBand = 32;
     const unsigned L = blockIdx.x + blockIdx.y * gridDim.x;

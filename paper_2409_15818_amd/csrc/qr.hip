@@ -625,7 +625,10 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
         GemmArgs<T> gc = vt_gemm<T>(P0 + bw * ld, ld, Kc, bw, ncols, Wz + zs, ldw, split_out);
         gc.a_vmask = 0;
         gc.b_vcols = 0;
-        gc.tile_order = 1;  // the kOuter / 64 row tiles of a B strip run together: 56 -> 59 TFLOP/s (float64)
+        // the kOuter / 64 row tiles of a B strip run together (56 -> 59 TFLOP/s,
+        // float64, 256-column blocks) on one XCD (then 481 -> 469 ms on the
+        // 4^3-box float64 solve's 512-column blocks, equal at 256)
+        gc.tile_order = 3;
         RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrVtC>(gc, st)));
       }
       if (Kt > 0) {
