@@ -154,6 +154,29 @@ def test_qr_defining_identity(handle, s, n, dtype):
     assert np.abs(Xg - Xo).max() / np.abs(Xo).max() < (1e-12 if dtype == "f64" else 1e-6)
 
 
+def test_qr_wide_float64_outer_blocks(handle):
+    """From 16,384 columns the float64 QR takes 512-column outer blocks: a
+    16,600 x 16,448 matrix (32 whole blocks and a 64-column last one, 4096-row
+    split-K slices with a ragged tail) checked by the identity every QR meets,
+    R^T R = (SA)^T (SA), on sampled columns (panel, block and slice borders)."""
+    s, n = 16600, 16448
+    SAo = np.random.default_rng(16448).standard_normal((s, n))
+    SA = torch.tensor(SAo, device="cuda")
+    P = R.rfmls_precond(handle, SA, "f64", "f64")
+    Rg = R.rfmls_precond_export_R(handle, P).cpu().numpy()
+    del SA, P
+    J = np.unique(np.concatenate([
+        [0, 1, 63, 64, 255, 256, 511, 512, 513, 1023, 1024, 4095, 4096, 8191, 8192,
+         16383, 16384, 16385, 16447],
+        np.random.default_rng(5).integers(0, n, 45)]))
+    assert all(np.all(Rg[j + 1:, j] == 0.0) for j in J)
+    assert np.all(np.diag(Rg)[J] > 0)
+    lhs = Rg.T @ Rg[:, J]
+    rhs = SAo.T @ SAo[:, J]
+    err = np.linalg.norm(lhs - rhs) / (np.linalg.norm(SAo) * np.linalg.norm(SAo[:, J]))
+    assert err < 20 * n * 1.1e-16, err
+
+
 @pytest.mark.parametrize("name", SMALL)
 def test_qr_on_sketch_backward_error(handle, name):
     S, s, A = system(name)
