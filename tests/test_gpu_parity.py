@@ -136,10 +136,10 @@ def _qr_case(handle, SAo, dtype):
 
 
 # panel grids from 1 block to a few hundred (64 rows per block up to 16,384 rows,
-# then 128): both ways the panel kernel sums its partials across blocks, a grid
-# of exactly 64 blocks, and ragged last blocks
+# then 128, 256, and 512 past 65,536 rows): both ways the panel kernel sums its
+# partials across blocks, a grid of exactly 64 blocks, and ragged last blocks
 @pytest.mark.parametrize("s,n", [(800, 200), (333, 129), (64, 64), (2000, 65), (130, 1),
-                                 (4096, 64), (6000, 96), (20000, 130)])
+                                 (4096, 64), (6000, 96), (20000, 130), (70000, 70)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_qr_defining_identity(handle, s, n, dtype):
     SAo = np.random.default_rng(s + n).standard_normal((s, n))
