@@ -362,6 +362,26 @@ __global__ void k_sum_slices(const T* __restrict__ Wz, int64_t zstride, int nspl
   }
 }
 
+// The same sum for one panel's V^T [V | C] (a short range over many slices):
+// a workgroup per 64 elements, its four wavefronts summing every fourth slice,
+// the four partial sums then added in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sum_slices_narrow(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t len,
+                        T* __restrict__ W) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (e < len) {
+#pragma unroll 4
+    for (int z = w; z < nsplit; z += 4) acc += (double)Wz[(int64_t)z * zstride + e];
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < len) W[e] = (T)((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
+}
+
 __global__ void k_zero_u64(uint64_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -577,7 +597,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
         Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
                  2.0 * (double)jb * ncols * M);
         RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, ldw, split_in), st)));
-        hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(jb * ldw, 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_sum_slices_narrow<T>, dim3(ceil_div(jb * ldw, 64)), dim3(256), 0, st,
                            (const T*)Wz, (int64_t)jb * ldw, (int)nsp, (int64_t)jb * ldw, W);
       }
       {
