@@ -36,7 +36,9 @@ constexpr int kMaxNb = 64;
 // caches.  A reader accepts the value once both words carry the tag it
 // expects, so no flag, counter or store-completion wait sits on the critical
 // path: a hand-over costs one store propagation plus one load round trip.
-// Tags are the column index + 1; the slots are zeroed before every launch.
+// Tags are the column's index in the matrix + 1, unique within one QR; the
+// slots are zeroed once per QR (a stale value from an earlier panel carries
+// another tag).
 __device__ __forceinline__ void ll_put(uint64_t* slot, double v, unsigned tag) {
   const uint64_t x = (uint64_t)__double_as_longlong(v);
   const uint64_t t = (uint64_t)tag << 32;
@@ -132,7 +134,7 @@ __host__ __device__ constexpr int64_t ll_words(int64_t G) { return 2 * (2 * kMax
 template <typename T, int Q>
 __global__ void __launch_bounds__(kPanelThreads)
     k_qr_panel(T* __restrict__ P, int64_t ld, int64_t M, int nb, int rpw, T* __restrict__ tau,
-               uint64_t* __restrict__ ll, int* __restrict__ err) {
+               uint64_t* __restrict__ ll, int* __restrict__ err, unsigned tag0) {
   static_assert(kPanelGroups * Q >= kMaxNb, "block 0 must hold the panel's top rows");
   __shared__ double red[2 * kMaxNb];               // totals, then the pivot row
   __shared__ double grp[kPanelGroups][kMaxNb];     // per-wavefront partials
@@ -166,7 +168,7 @@ __global__ void __launch_bounds__(kPanelThreads)
 
   const bool top = (g == 0);
   for (int j = 0; j < nb; ++j) {
-    const unsigned tag = (unsigned)j + 1u;
+    const unsigned tag = tag0 + (unsigned)j + 1u;
     const int par = j & 1;
     const int L = nb - j;
     // Only block 0 holds rows i <= j (li > j is uniform per wavefront).
@@ -562,6 +564,12 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   T* Wp = (T*)p_wp;
   T* To = (T*)p_to;
   T* Y = (T*)p_y;
+  {
+    // the panels' exchange slots, zeroed once: their tags are column indices
+    const int64_t nll = ll_words(kPanelMaxBlocks);
+    hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nll, 256) < 512 ? ceil_div(nll, 256) : 512), dim3(256), 0, st,
+                       (uint64_t*)p_part, nll);
+  }
   for (int64_t k0 = 0; k0 < n; k0 += kOuter) {
     const int64_t bw = n - k0 < kOuter ? n - k0 : kOuter;
     // ---------------- inner panels of the outer block ----------------
@@ -575,12 +583,10 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       T* P = SA + p0 * ld + p0;
       T* tau_p = tau + (p0 - k0);
       uint64_t* ll = (uint64_t*)p_part;
-      const int64_t nll = ll_words(G);
-      hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nll, 256) < 512 ? ceil_div(nll, 256) : 512), dim3(256),
-                         0, st, ll, nll);
       int rpw_i = (int)rpw;
-      void* args[] = {(void*)&P,     (void*)&ld, (void*)&M,  (void*)&jb,
-                      (void*)&rpw_i, (void*)&tau_p, (void*)&ll, (void*)&h->dev_flags};
+      unsigned tag0 = (unsigned)p0;
+      void* args[] = {(void*)&P,     (void*)&ld,    (void*)&M,  (void*)&jb,           (void*)&rpw_i,
+                      (void*)&tau_p, (void*)&ll,    (void*)&h->dev_flags, (void*)&tag0};
       const void* fn = sh.fn;
       {
         // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
