@@ -304,8 +304,8 @@ __global__ void __launch_bounds__(kPanelThreads)
 // V_:j^T v_j (Schreiber and Van Loan).  Column k of T solves U t = e_k by
 // back substitution on one wavefront (lane i holds row i), t_l = tau_l x_l
 // from the bottom up, so 1/tau is never formed and a reflector with tau_j = 0
-// (H_j = I) leaves row and column j zero, as the recursion does.  The 16
-// wavefronts take columns {w, 31 - w, 32 + w, 63 - w}, equal total lengths.
+// (H_j = I) leaves row and column j zero, as the recursion does.  One
+// wavefront per column: ceil(nb / 16) workgroups of 16, each staging the Gram.
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_qr_buildT(const T* __restrict__ Wz, int64_t zstride, int nsplit, int64_t ldw, int nb,
@@ -325,10 +325,9 @@ __global__ void __launch_bounds__(1024)
   if (tid < kMaxNb + 3) ts[tid] = (tid >= 3 && tid - 3 < nb) ? (double)tau[tid - 3] : 0.0;
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int k = m == 0 ? w : m == 1 ? 31 - w : m == 2 ? 32 + w : 63 - w;
-    if (k >= nb) continue;  // uniform within the wavefront
+  {
+    const int k = (int)blockIdx.x * 16 + w;
+    if (k >= nb) return;  // uniform within the wavefront (no barrier follows)
     double x = lane == k ? 1.0 : 0.0, t = 0.0;
     // four steps per group, their LDS reads issued together; steps past l = 0
     // read tau = 0 and column 0 of Us (zeros) and change nothing
@@ -610,7 +609,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
         Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
         // this panel's T is also a diagonal block of the outer block's T_o
         T* Tq = To + (p0 - k0) * kOuter + (p0 - k0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(1024), 0, st, (const T*)W, (int64_t)0, 1,
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jb + 15) / 16), dim3(1024), 0, st, (const T*)W, (int64_t)0, 1,
                            ldw, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
         hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 32)), dim3(256), 0, st, (const T*)W, ldw, jb,
                            (const T*)Tq, (int64_t)kOuter, rem, Wp, ldwp);
@@ -674,7 +673,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       {
         const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
         const int jq = (int)(bw - q0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3(1), dim3(1024), 0, st, (const T*)(W + q0 * ldw + q0),
+        hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jq + 15) / 16), dim3(1024), 0, st, (const T*)(W + q0 * ldw + q0),
                            (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
                            (int64_t)kOuter);
       }
@@ -770,7 +769,7 @@ rfmls_status apply_householder(rfmls_handle* h, const double* P, int64_t ld, int
     const int64_t M = s - p0;
     double* V = const_cast<double*>(P) + p0 * ld + p0;
     RFMLS_HIP(h, (gemm<double, GemmRole::Generic>(vt_gemm<double>(V, ld, M, jb, jb, G, kMaxNb, 0), st)));
-    hipLaunchKernelGGL(k_qr_buildT<double>, dim3(1), dim3(1024), 0, st, (const double*)G, (int64_t)0, 1,
+    hipLaunchKernelGGL(k_qr_buildT<double>, dim3((jb + 15) / 16), dim3(1024), 0, st, (const double*)G, (int64_t)0, 1,
                        (int64_t)kMaxNb, jb, tau + p0, Tq, (int64_t)kMaxNb);
     GemmArgs<double> gw;  // W = V^T Y[p0:, :]
     gw.M = jb;
