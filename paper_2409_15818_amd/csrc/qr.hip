@@ -645,7 +645,13 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     {
       Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
                2.0 * (double)bw * ncols * M0);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(vt_gemm<T>(P0, ld, bw, bw, ncols, Wz, ldw, 0), st)));
+      {
+        // op(A) = V^T of the top rows is upper triangular (the mask zeroes the
+        // rest): each row tile starts its K range at its own first row
+        GemmArgs<T> gt = vt_gemm<T>(P0, ld, bw, bw, ncols, Wz, ldw, 0);
+        gt.a_upper = 1;
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gt, st)));
+      }
       if (Kc > 0) {
         GemmArgs<T> gc = vt_gemm<T>(P0 + bw * ld, ld, Kc, bw, ncols, Wz + zs, ldw, split_out);
         gc.a_vmask = 0;
@@ -728,7 +734,13 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
                2.0 * (double)M0 * ntr * bw);
       // rows [0, bw) meet the triangle of V (masked, general kernel); the rows
       // below are clear of it and take the clean-only kernel
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(v_update<T>(P0, ld, bw, bw, ntr, Wp, ldwp), st)));
+      {
+        // V's top rows are lower triangular (the mask zeroes the rest): each
+        // row tile ends its K range at its own last row
+        GemmArgs<T> gt = v_update<T>(P0, ld, bw, bw, ntr, Wp, ldwp);
+        gt.a_lower = 1;
+        RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(gt, st)));
+      }
       if (M0 > bw) {
         GemmArgs<T> gu = v_update<T>(P0 + bw * ld, ld, M0 - bw, bw, ntr, Wp, ldwp);
         gu.a_vmask = 0;
