@@ -64,9 +64,57 @@ def measured_traffic(kernel, workload, precision):
     return k["traffic_bytes_per_launch"]
 
 
+def cpu_model():
+    """The host CPU's model name and the number of cores this process may use."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name
+
+
+def cpu_full_run(S, s, refine, threads):
+    """The whole oracle solve of the workload, timed phase by phase (Sec. 4.1's
+    PCPU / CPU split): sketch, Householder QR, LSQR with the same refinement
+    sweeps.  Minutes of CPU time; only with --cpu-baseline full."""
+    from oracle import countsketch, pipeline, qr
+
+    t0 = time.perf_counter()
+    h, sign = countsketch.hash_sign(S.m, s, SKETCH_SEED)
+    SA, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+    t1 = time.perf_counter()
+    R = qr.r_factor(SA, check_rank=False)
+    del SA
+    t2 = time.perf_counter()
+    A = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    x, results = pipeline.refined_lsqr(A, R, S.b[0], refine=refine)
+    t3 = time.perf_counter()
+    met = pipeline.residual_metrics(A, x, S.b[0])
+    return {"value": t3 - t0, "unit": "s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"the whole oracle solve of the {S.m}x{S.n} system, measured (not extrapolated)",
+            "phases_s": {"sketch": t1 - t0, "qr": t2 - t1, "lsqr": t3 - t2},
+            "itn_sweeps": [r.itn for r in results], "relres": met["relres"]}
+
+
+def stored_full_run(workload):
+    """A measured whole-oracle run of this workload on the GPU machine's host
+    (profiles/oracle_full_<workload>.md, written from --cpu-baseline full), or None."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"oracle_full_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    return json.loads(m.group(1)) if m else None
+
+
 def cpu_baseline(S, s, itn_total, threads):
-    """The oracle, as it stands, on a bounded sample of the workload, scaled to a
-    full time-to-tolerance estimate: the full sketch, the QR of the first n/4
+    """The oracle, as it stands, on a bounded sample of the workload, extrapolated
+    to a full time-to-tolerance estimate: the full sketch, the QR of the first n/4
     columns of SA (scaled by the Householder flop ratio), and two LSQR
     iterations of the full-size implicit operator (scaled by the iteration count)."""
     import numpy as np
@@ -94,11 +142,37 @@ def cpu_baseline(S, s, itn_total, threads):
          conlim=0, itmax=2)
     t_it = (time.perf_counter() - t0) / 2.0
     est = t_sketch + t_qr_sample / ratio + t_it * itn_total
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "estimate": "extrapolated from the bounded sample below, not a whole run",
             "sample": (f"oracle on the {S.m}x{S.n} system: full count sketch ({t_sketch:.1f} s), "
                        f"Householder QR of SA[:, :{ns}] ({t_qr_sample:.1f} s, scaled by the flop "
                        f"ratio {ratio:.4f}), 2 LSQR iterations ({t_it:.2f} s each, scaled to "
                        f"{itn_total} iterations)")}
+
+
+def pipeline_ideal(S, s, qd, rd, itn, nrhs):
+    """The method's phase times at the nominal peaks (sketch and LSQR at HBM
+    bandwidth, the QR at the matrix-core peak of its precision), in ms:
+      sketch  12 B/nnz + row pointers + hash/sign + the dense SA written once
+      qr      2 n^2 (s - n/3) Householder flops (R only)
+      lsqr    per iteration two passes over R's n(n+1)/2 stored entries and two
+              over A's CSR (12 B/nnz + row pointers); with several right-hand
+              sides in lockstep, per block iteration the same passes plus the
+              m x p blocks read and written (2 m p 8 B per product)
+    itn is the total iteration count (the largest over the right-hand sides)."""
+    esz_sa = 8.0 if qd == "f64" else 4.0
+    esz_r = 8.0 if rd == "f64" else 4.0
+    n, m, nnz = S.n, S.m, S.nnz
+    sketch_b = 12.0 * nnz + 8.0 * (m + 1) + 5.0 * m + 8.0 * (s + 1) + esz_sa * s * n
+    qr_f = 2.0 * n * n * (s - n / 3.0)
+    csr_b = 12.0 * nnz + 8.0 * (m + 1)
+    it_b = 2.0 * esz_r * n * (n + 1) / 2.0 + 2.0 * csr_b
+    if nrhs > 1:
+        it_b += 2.0 * 2.0 * m * min(nrhs, 32) * 8.0 * ((nrhs + 31) // 32)
+    parts = {"sketch": sketch_b / (HBM_PEAK_GBS * 1e9) * 1e3,
+             "qr": qr_f / (MFMA_PEAK_TFLOPS[qd] * 1e12) * 1e3,
+             "lsqr": itn * it_b / (HBM_PEAK_GBS * 1e9) * 1e3}
+    return parts
 
 
 def main():
@@ -126,6 +200,9 @@ def main():
                          "preconditioner P = V_r Sigma_r^-1 (float64 QR and SVD; --precision f64f32 "
                          "stores P in float32; starts from y0 = 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline", default="sample", choices=["sample", "full"],
+                    help="sample: the oracle on a bounded sample (about 10-30 s), extrapolated; "
+                         "full: the whole oracle solve, measured (minutes)")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--backward", action="store_true",
                     help="also time the backward pass (gradients w.r.t. b and A's values) of "
@@ -232,6 +309,8 @@ def main():
         torch.cuda.synchronize()
         kernels = R.rfmls_trace_read(h)
         R.rfmls_trace_enable(h, False)
+        _[2].free()
+        del _
         for k in kernels:
             k["avg_ms"] = k["ms"] / max(k["launches"], 1)
             k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
@@ -300,7 +379,23 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        cpu = cpu_baseline(S, s, int(sum(i["itn"] for i in info)), threads)
+        if args.cpu_baseline == "full":
+            cpu = cpu_full_run(S, s, args.refine, threads)
+        else:
+            cpu = cpu_baseline(S, s, int(sum(i["itn"] for i in info)), threads)
+            full = stored_full_run(args.workload)
+            if full is not None:
+                # the extrapolation checked against a measured whole run on the same host
+                cpu["measured_full_run"] = {k: full[k] for k in ("value", "cores", "cpu", "phases_s")
+                                            if k in full}
+
+    pipe = None
+    if args.operator == "implicit" and args.precond == "qr":
+        parts = pipeline_ideal(S, s, qd, rd, int(max(i["itn"] for i in info)), args.nrhs)
+        ideal = sum(parts.values())
+        pipe = {"ideal_ms": round(ideal, 3), "measured_ms": round(1e3 * med, 3),
+                "frac": round(ideal / (1e3 * med), 4),
+                "ideal_parts_ms": {k: round(v, 3) for k, v in parts.items()}}
 
     out = {
         "metric": METRIC, "value": round(med, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -324,10 +419,16 @@ def main():
         "vs_oracle": vs_oracle,
         "backward": bwd,
         "roofline": roof,
+        "pipeline_roofline": pipe,
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kernels[:12]],
         "cpu_baseline": cpu,
     }
+    # release the library's objects while the runtime is fully up (not from
+    # finalisers at interpreter exit)
+    torch.cuda.synchronize()
+    P.free()
+    h.close()
     print(json.dumps(out), flush=True)
 
 

@@ -6,6 +6,7 @@ librfmls.so."""
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from dataclasses import dataclass
 
 import torch
@@ -93,6 +94,10 @@ class Handle:
             self._h = None
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be torn down: leave the
+        # release to process exit then (call close() to release earlier)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -121,6 +126,8 @@ class Precond:
             self._p = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

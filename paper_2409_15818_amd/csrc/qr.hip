@@ -633,6 +633,9 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     T* P0 = SA + k0 * ld + k0;
     const int64_t ncols = bw + ntr;
     const int64_t ldw = pad32(ncols), ldwp = pad32(ntr);
+    // the method's own trailing columns (the traced work counts these, not the
+    // rounded-up tile columns the products also write)
+    const int64_t ntr_m = n - k0 - bw, ncols_m = bw + ntr_m;
     // V^T [V | C] in row slices summed in order: rows [0, bw) hold the
     // triangle of V (masked, general kernel); the rows below are clear of every
     // mask, so a whole number of 16-row chunks of them goes to the clean-only
@@ -643,8 +646,8 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     const int64_t nsp = 1 + nsc + (Kt > 0 ? 1 : 0);
     const int64_t zs = bw * ldw;
     {
-      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols + 2.0 * (double)nsp * bw * ncols),
-               2.0 * (double)bw * ncols * M0);
+      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols_m + 2.0 * (double)nsp * bw * ncols_m),
+               2.0 * (double)bw * ncols_m * M0);
       {
         // op(A) = V^T of the top rows is upper triangular (the mask zeroes the
         // rest): each row tile starts its K range at its own first row
@@ -714,7 +717,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     }
     {
       // W' = T_o^T W[:, bw:]  (T_o^T lower triangular)
-      Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * ntr, (double)bw * bw * ntr);
+      Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * ntr_m, (double)bw * bw * ntr_m);
       GemmArgs<T> gt;
       gt.M = bw;
       gt.N = ntr;
@@ -730,8 +733,8 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
     }
     {
-      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr + (double)M0 * bw + (double)bw * ntr),
-               2.0 * (double)M0 * ntr * bw);
+      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr_m + (double)M0 * bw + (double)bw * ntr_m),
+               2.0 * (double)M0 * ntr_m * bw);
       // rows [0, bw) meet the triangle of V (masked, general kernel); the rows
       // below are clear of it and take the clean-only kernel
       {

@@ -10,6 +10,7 @@ LstsqFunction   torch.autograd.Function: x = A^+ b with gradients w.r.t. b and t
 
 from __future__ import annotations
 
+import warnings
 from dataclasses import dataclass, field
 
 import torch
@@ -95,6 +96,11 @@ class LstsqFunction(torch.autograd.Function):
         res = csqrp_lsqr(solver.handle, A, b.detach(), solver.s, solver.seed, solver.qr_dtype,
                          solver.r_store, solver.opts)
         solver.last = res
+        if res.status != 0:
+            # RFMLS_W_NOCONV: a right-hand side stopped at the iteration limit; x
+            # (and the gradients taken through it) are not at the tolerance
+            warnings.warn(f"LstsqFunction: the solve returned status {res.status} "
+                          f"(iteration limit reached); x is not converged", RuntimeWarning)
         ctx.solver = solver
         ctx.A = A
         ctx.res = res
@@ -108,6 +114,9 @@ class LstsqFunction(torch.autograd.Function):
         dB, dA, info, _ = rfmls_solve_backward(solver.handle, A, res.AT, res.precond, res.x,
                                                res.residual, G, solver.opts)
         solver.last_backward_info = info
+        if any(i["istop"] == 7 for i in info):
+            warnings.warn("LstsqFunction.backward: the adjoint solve reached its iteration limit; "
+                          "the gradients are not converged", RuntimeWarning)
         return dA, dB, None
 
 
