@@ -242,6 +242,29 @@ rfmls_status rfmls_solve(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *A
                          double *X, int64_t ldx, double *Rout, int64_t ldr,
                          const rfmls_opts *opts, rfmls_info *info);
 
+/* For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rfmls_solve with nothing allocated.  Arguments, results and status codes are
+ * those of rfmls_solve, with the right-hand sides solved one at a time
+ * (opts->lockstep is ignored; the iterates are those of rfmls_solve with
+ * lockstep = 0).  The solve's device scratch (work vectors, partial sums and
+ * LSQR state, 8 (4m + 8n + 8256) bytes plus 512) is a fixed array of
+ * rfmls_noalloc_scratch_bytes() bytes (32 MiB) that each device the library
+ * runs on holds until the process ends; a problem that needs more is rejected
+ * with RFMLS_E_ARG before anything is enqueued.  The preconditioner's buffers
+ * (allocated by rfmls_precond*) and the handle's pinned staging buffer
+ * (allocated by rfmls_create) are used as rfmls_solve uses them.  Every call on
+ * one device shares that device's array, which keeps the last call's
+ * contents (the solve initialises all it reads): calls that overlap in time on
+ * one device, from any handle or thread, race and give wrong results, so
+ * serialise them.  Synchronises the stream before returning. */
+rfmls_status rfmls_solve_noalloc(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *AT,
+                                 const rfmls_precond_t *P, const double *B, int64_t ldb,
+                                 int64_t nrhs, double *X, int64_t ldx, double *Rout, int64_t ldr,
+                                 const rfmls_opts *opts, rfmls_info *info);
+/* Size in bytes of rfmls_solve_noalloc's fixed device scratch. */
+int64_t rfmls_noalloc_scratch_bytes(void);
+
 /* Alg. 1 step 4 in its literal form: the dense preconditioned matrix
  * B = A R^{-1} (m x n, row-major float64, ld_bmat >= n; caller-allocated,
  * 8 m n bytes), formed as A times the stored X = R^{-1}, 32 columns at a time

@@ -27,7 +27,7 @@ EXPORTED = [
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
     "rfmls_precond_svd", "rfmls_precond_svd_stats", "rfmls_precond_export_P", "rfmls_precond_export_sigma",
     "rfmls_solve", "rfmls_form_B", "rfmls_solve_explicit", "rfmls_solve_backward",
-    "rfmls_trace_enable", "rfmls_trace_read",
+    "rfmls_trace_enable", "rfmls_trace_read", "rfmls_solve_noalloc", "rfmls_noalloc_scratch_bytes",
 ]
 
 
@@ -98,6 +98,10 @@ def load():
     lib.rfmls_precond_export_sigma.argtypes = [vp, vp, vp]
     lib.rfmls_solve.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, i64, vp, i64, vp, i64,
                                 P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_solve_noalloc.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, i64, vp, i64, vp, i64,
+                                        P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_noalloc_scratch_bytes.argtypes = []
+    lib.rfmls_noalloc_scratch_bytes.restype = i64
     lib.rfmls_form_B.argtypes = [vp, P(rfmls_csr), vp, vp, i64]
     lib.rfmls_solve_explicit.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, i64, vp,
                                          i64, vp, i64, P(rfmls_opts), P(rfmls_info)]
@@ -107,7 +111,7 @@ def load():
     lib.rfmls_trace_read.argtypes = [vp, P(rfmls_trace_entry), C.c_int, P(C.c_int)]
     for name in EXPORTED:
         if name not in ("rfmls_default_opts", "rfmls_precond_free", "rfmls_last_error",
-                        "rfmls_precond_n"):
+                        "rfmls_precond_n", "rfmls_noalloc_scratch_bytes"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -290,6 +290,27 @@ def rfmls_solve(h: Handle, A: CSR, AT: CSR, P: Precond, B: torch.Tensor, opts: r
     return X, R, info, rc
 
 
+def rfmls_solve_noalloc(h: Handle, A: CSR, AT: CSR, P: Precond, B: torch.Tensor, X: torch.Tensor,
+                        Rres: torch.Tensor | None = None, opts: rfmls_opts | None = None):
+    """rfmls_solve with nothing allocated: B [nrhs, m] (or [m]), X [nrhs, n] (or [n])
+    and Rres (same shape as B, or None) are caller-allocated contiguous float64
+    tensors; X is read as the starting point when opts.x_init is set.  Returns
+    ([info dicts], status)."""
+    for t in (B, X) + (() if Rres is None else (Rres,)):
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("B, X and Rres must be contiguous float64 tensors")
+    nrhs = 1 if B.dim() == 1 else B.shape[0]
+    infos = (rfmls_info * nrhs)()
+    o = opts if opts is not None else default_opts()
+    rc = h.check(h._lib.rfmls_solve_noalloc(h._h, C.byref(A.c()), C.byref(AT.c()), P._p, _ptr(B), A.m, nrhs,
+                                            _ptr(X), A.n, _ptr(Rres), A.m, C.byref(o), infos))
+    return [infos[k].as_dict() for k in range(nrhs)], rc
+
+
+def rfmls_noalloc_scratch_bytes() -> int:
+    return int(_lib.load().rfmls_noalloc_scratch_bytes())
+
+
 def rfmls_form_B(h: Handle, A: CSR, P: Precond) -> torch.Tensor:
     """The explicit B = A R^{-1} ([m, n] row-major float64)."""
     Bm = torch.empty((A.m, A.n), dtype=torch.float64, device=A.row_ptr.device)

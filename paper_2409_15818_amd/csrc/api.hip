@@ -110,6 +110,10 @@ rfmls_status rfmls_create(rfmls_handle** out, int device, void* stream) {
   h->pinned_bytes = 4096;
   hipMemset(h->barrier, 0, kBarrierWords * sizeof(unsigned));
   hipMemset(h->dev_flags, 0, 64 * sizeof(int));
+  if (noalloc_scratch_init(h) != RFMLS_OK) {
+    rfmls_destroy(h);
+    return RFMLS_E_HIP;
+  }
   *out = h;
   return RFMLS_OK;
 }
@@ -385,6 +389,28 @@ rfmls_status rfmls_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* A
     return run_solve_block(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
   return run_solve(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
 }
+
+rfmls_status rfmls_solve_noalloc(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                                 const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                                 double* X, int64_t ldx, double* Rout, int64_t ldr,
+                                 const rfmls_opts* opts, rfmls_info* info) {
+  if (!h) return RFMLS_E_ARG;
+  rfmls_opts def;
+  rfmls_default_opts(&def);
+  const rfmls_opts* o = opts ? opts : &def;
+  RFMLS_CHECK(check_solve_args(h, A, AT, P, o));
+  if (nrhs < 0 || (nrhs > 0 && (!B || !X)) || ldb < A->m || ldx < A->n || (Rout && ldr < A->m))
+    return fail(h, RFMLS_E_ARG, "rfmls_solve_noalloc: invalid B / X / leading dimensions");
+  if (noalloc_needed_bytes(A->m, A->n) > noalloc_scratch_bytes())
+    return fail(h, RFMLS_E_ARG, "rfmls_solve_noalloc: m = %lld, n = %lld need %lld bytes of scratch, above "
+                "the %lld-byte limit", (long long)A->m, (long long)A->n,
+                (long long)noalloc_needed_bytes(A->m, A->n), (long long)noalloc_scratch_bytes());
+  if (nrhs == 0) return RFMLS_OK;
+  RFMLS_CHECK(set_device(h));
+  return run_solve_noalloc(h, A, AT, P, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
+}
+
+int64_t rfmls_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
 
 rfmls_status rfmls_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond_t* P, double* Bmat,
                           int64_t ld_bmat) {

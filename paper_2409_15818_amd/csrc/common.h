@@ -251,6 +251,16 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                        const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
                        double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
                        rfmls_info* info);
+// allocation-free single-right-hand-side solve (device scratch in a file-scope
+// array of lsqr.hip); noalloc_scratch_init records the current device's
+// address of that array and is called once per handle by rfmls_create
+rfmls_status noalloc_scratch_init(rfmls_handle* h);
+int64_t noalloc_scratch_bytes();
+int64_t noalloc_needed_bytes(int64_t m, int64_t n);
+rfmls_status run_solve_noalloc(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                               const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                               double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                               rfmls_info* info);
 rfmls_status run_solve_explicit(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                                 const rfmls_precond_t* P, const double* Bm, int64_t ldbm,
                                 const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,

@@ -11,6 +11,8 @@
 // reduced in a fixed order (per-block partials, then a fixed tree), so runs
 // are bitwise reproducible.  The host only polls a device "done" flag every
 // few iterations; kernels launched after the stop return immediately.
+#include <mutex>
+
 #include "common.h"
 #include "lsqr_dev.h"
 
@@ -242,6 +244,14 @@ __global__ void k_fill(double* p, int64_t len, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// out[0] = sqrt(sum sq[0..nsq)) in the fixed order of reduce_partials (one block)
+__global__ void __launch_bounds__(kThreads) k_sqrt_sum(const double* __restrict__ sq, int nsq,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kThreads / 64];
+  const double t = reduce_partials(sq, nsq, red);
+  if (threadIdx.x == 0) out[0] = sqrt(t);
 }
 
 __global__ void __launch_bounds__(kThreads) k_sumsq(const double* __restrict__ x, int64_t len,
@@ -492,6 +502,7 @@ struct Ctx {
   // work vectors
   double *u, *v, *w, *y, *z, *q, *t, *r, *xs;
   double *sqA, *sqB, *sqY, *sqW;
+  double* hn;  // one device double for norms read by the host
   LsqrDev* dst;
   int nspmvA, nspmvAT, nvec_n, nvec_m;
 };
@@ -695,17 +706,24 @@ static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, i
   return RFMLS_OK;
 }
 
+// Doubles of device memory one single-right-hand-side solve works in: the
+// vectors and partial sums (make_ctx's layout) and the LSQR state after them.
+static int64_t ctx_doubles(int64_t m, int64_t n) { return 4 * m + 8 * n + 4 * kSpmvMaxBlocks + 64; }
+constexpr int64_t kStateDoubles = (2 * sizeof(LsqrDev) + 255) / 256 * 32;
+
+// base: device memory of at least ctx_doubles + kStateDoubles doubles, or null
+// for the handle's workspace
 static rfmls_status make_ctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
-                             const rfmls_precond_t* P, Ctx& c) {
+                             const rfmls_precond_t* P, Ctx& c, double* base = nullptr) {
   c.h = h;
   c.A = A;
   c.AT = AT;
   c.P = P;
   c.st = h->stream;
   const int64_t m = A->m, n = A->n;
-  const size_t nvec = (size_t)(4 * m + 8 * n + 4 * kSpmvMaxBlocks + 64);
-  void* p;
-  RFMLS_CHECK(workspace(h, WS_LSQR_VEC, sizeof(double) * nvec, &p));
+  const size_t nvec = (size_t)ctx_doubles(m, n);
+  void* p = base;
+  if (!base) RFMLS_CHECK(workspace(h, WS_LSQR_VEC, sizeof(double) * nvec, &p));
   double* d = (double*)p;
   c.u = d;
   d += m;
@@ -734,8 +752,10 @@ static rfmls_status make_ctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   c.sqY = d;
   d += kSpmvMaxBlocks;
   c.sqW = d;
-  void* ps;
-  RFMLS_CHECK(workspace(h, WS_LSQR_SCAL, sizeof(LsqrDev) * 2, &ps));
+  d += kSpmvMaxBlocks;
+  c.hn = d;
+  void* ps = base ? (void*)(base + nvec) : nullptr;
+  if (!base) RFMLS_CHECK(workspace(h, WS_LSQR_SCAL, sizeof(LsqrDev) * 2, &ps));
   c.dst = (LsqrDev*)ps;
   return RFMLS_OK;
 }
@@ -748,16 +768,16 @@ static rfmls_status read_state(Ctx& c, LsqrDev* out) {
   return RFMLS_OK;
 }
 
-// ||v||^2 of a device vector into host
+// ||v|| of a device vector into host (reduced on the device, 8 bytes copied
+// through the pinned staging buffer)
 static rfmls_status host_norm(Ctx& c, const double* v, int64_t len, double* out) {
   const unsigned nb = vec_blocks(len);
   hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(kThreads), 0, c.st, v, len, c.sqY);
-  std::vector<double> tmp(nb);
-  RFMLS_HIP(c.h, hipMemcpyAsync(tmp.data(), c.sqY, sizeof(double) * nb, hipMemcpyDeviceToHost, c.st));
+  hipLaunchKernelGGL(k_sqrt_sum, dim3(1), dim3(kThreads), 0, c.st, (const double*)c.sqY, (int)nb, c.hn);
+  double* pin = (double*)((char*)c.h->pinned + 3072);
+  RFMLS_HIP(c.h, hipMemcpyAsync(pin, c.hn, sizeof(double), hipMemcpyDeviceToHost, c.st));
   RFMLS_HIP(c.h, hipStreamSynchronize(c.st));
-  double s = 0.0;
-  for (double t : tmp) s += t;
-  *out = sqrt(s);
+  *out = *pin;
   return RFMLS_OK;
 }
 
@@ -766,9 +786,10 @@ static rfmls_status host_norm(Ctx& c, const double* v, int64_t len, double* out)
 static rfmls_status solve_impl(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                                const rfmls_precond_t* P, const double* Bm, int64_t ldbm,
                                const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
-                               double* Rout, int64_t ldr, const rfmls_opts* o, rfmls_info* info) {
+                               double* Rout, int64_t ldr, const rfmls_opts* o, rfmls_info* info,
+                               double* base = nullptr) {
   Ctx c;
-  RFMLS_CHECK(make_ctx(h, A, AT, P, c));
+  RFMLS_CHECK(make_ctx(h, A, AT, P, c, base));
   if (Bm) {
     void* p;
     RFMLS_CHECK(workspace(h, WS_GEMV, sizeof(double) * (size_t)kGemvTSlices * (size_t)A->n, &p));
@@ -840,6 +861,64 @@ rfmls_status run_solve(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                        double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
                        rfmls_info* info) {
   return solve_impl(h, A, AT, P, nullptr, 0, B, ldb, nrhs, X, ldx, Rout, ldr, o, info);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of the single-right-hand-side solve: its device
+// scratch (the vectors, partial sums and LSQR state of make_ctx) lives in one
+// file-scope array.  Each device holds its own copy of the array (allocated
+// when the library's code object is loaded on that device, kept until the
+// process ends); host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device, never through the
+// array's name, which on the host is only a stand-in for the symbol.
+// ---------------------------------------------------------------------------
+namespace noalloc {
+constexpr int64_t kScratchDoubles = (int64_t)1 << 22;  // 32 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex mu;
+static double* dev_ptr[kMaxDevices] = {};
+}  // namespace noalloc
+
+// Called by rfmls_create with h->device current: record this device's
+// address of the scratch array (once per device).
+rfmls_status noalloc_scratch_init(rfmls_handle* h) {
+  std::lock_guard<std::mutex> lk(noalloc::mu);
+  if (h->device < 0 || h->device >= noalloc::kMaxDevices)
+    return fail(h, RFMLS_E_ARG, "device %d out of range for the allocation-free scratch", h->device);
+  if (noalloc::dev_ptr[h->device]) return RFMLS_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc::scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(h, RFMLS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", h->device,
+                hipGetErrorString(e));
+  }
+  noalloc::dev_ptr[h->device] = (double*)p;
+  return RFMLS_OK;
+}
+
+int64_t noalloc_scratch_bytes() { return noalloc::kScratchDoubles * (int64_t)sizeof(double); }
+
+int64_t noalloc_needed_bytes(int64_t m, int64_t n) {
+  return (ctx_doubles(m, n) + kStateDoubles) * (int64_t)sizeof(double);
+}
+
+rfmls_status run_solve_noalloc(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
+                               const rfmls_precond_t* P, const double* B, int64_t ldb, int64_t nrhs,
+                               double* X, int64_t ldx, double* Rout, int64_t ldr, const rfmls_opts* o,
+                               rfmls_info* info) {
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(noalloc::mu);
+    base = (h->device >= 0 && h->device < noalloc::kMaxDevices) ? noalloc::dev_ptr[h->device] : nullptr;
+  }
+  if (!base) return fail(h, RFMLS_E_HIP, "rfmls_solve_noalloc: no scratch address for device %d", h->device);
+  if (noalloc_needed_bytes(A->m, A->n) > noalloc_scratch_bytes())
+    return fail(h, RFMLS_E_ARG, "rfmls_solve_noalloc: m = %lld, n = %lld need %lld bytes of scratch, above the "
+                "%lld-byte limit", (long long)A->m, (long long)A->n, (long long)noalloc_needed_bytes(A->m, A->n),
+                (long long)noalloc_scratch_bytes());
+  return solve_impl(h, A, AT, P, nullptr, 0, B, ldb, nrhs, X, ldx, Rout, ldr, o, info, base);
 }
 
 rfmls_status run_solve_explicit(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
