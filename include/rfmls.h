@@ -91,6 +91,12 @@ typedef struct {
                        from rfmls_precond_x0) and the first sweep solves for
                        the correction from b - A X; 0 (default): start from
                        x = 0 (y^(0) = 0, Sec. 4.1)                        */
+  int32_t graph;    /* nonzero (default): the check_every iterations between
+                       two polls of the stop flag are captured once per call
+                       as a HIP graph and replayed (not while kernel tracing
+                       is enabled); 0: launched one kernel at a time.  The
+                       iterates are the same either way                   */
+  int32_t reserved; /* set to 0                                           */
 } rfmls_opts;
 
 /* [host] per right-hand side results */

@@ -39,7 +39,8 @@ class rfmls_csr(C.Structure):
 class rfmls_opts(C.Structure):
     _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("conlim", C.c_double),
                 ("itmax", C.c_int64), ("refine", C.c_int32), ("check_every", C.c_int32),
-                ("lockstep", C.c_int32), ("x_init", C.c_int32)]
+                ("lockstep", C.c_int32), ("x_init", C.c_int32), ("graph", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class rfmls_info(C.Structure):

@@ -81,6 +81,8 @@ void rfmls_default_opts(rfmls_opts* o) {
   o->check_every = 8;
   o->lockstep = 1;
   o->x_init = 0;
+  o->graph = 1;
+  o->reserved = 0;
 }
 
 rfmls_status rfmls_create(rfmls_handle** out, int device, void* stream) {
@@ -127,6 +129,7 @@ rfmls_status rfmls_destroy(rfmls_handle* h) {
     hipEventDestroy(r.end);
   }
   for (auto e : h->event_pool) hipEventDestroy(e);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
   for (auto& w : h->ws)
     if (w.ptr) hipFree(w.ptr);
   if (h->barrier) hipFree(h->barrier);

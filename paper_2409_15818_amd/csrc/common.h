@@ -49,6 +49,7 @@ struct rfmls_handle {
   int* dev_flags = nullptr;         // device error / abort flags
   void* pinned = nullptr;           // small pinned host staging buffer
   size_t pinned_bytes = 0;
+  hipStream_t cap_stream = nullptr; // stream that graphs are captured on (created on first use)
 };
 
 struct rfmls_precond {
@@ -200,6 +201,56 @@ struct Trace {
     h->trace_recs.push_back(rec);
   }
 };
+}  // namespace rfmls
+
+// Captured iterations: the launches of the LSQR loop between two polls of the
+// device stop flag, recorded once as a HIP graph and replayed with one
+// hipGraphLaunch per poll interval.  Every kernel of the loop checks the
+// device "done" word first, so iterations past the stop are no-ops, exactly as
+// in the eager loop.
+namespace rfmls {
+struct IterGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  IterGraph() = default;
+  IterGraph(const IterGraph&) = delete;
+  IterGraph& operator=(const IterGraph&) = delete;
+  ~IterGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
+
+// Records what `body` enqueues on h->stream into g.  During the capture
+// h->stream is the handle's capture stream (a non-blocking stream of default
+// priority, created on first use); body must enqueue kernels only.
+template <class F>
+rfmls_status capture_graph(rfmls_handle* h, IterGraph* g, F&& body) {
+  if (!h->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(h, RFMLS_E_HIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+  }
+  hipStream_t saved = h->stream;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail(h, RFMLS_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  h->stream = h->cap_stream;
+  rfmls_status st = body();
+  hipGraph_t gr = nullptr;
+  e = hipStreamEndCapture(h->cap_stream, &gr);
+  h->stream = saved;
+  if (st < 0) {
+    if (gr) hipGraphDestroy(gr);
+    return st;
+  }
+  if (e != hipSuccess || !gr) return fail(h, RFMLS_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  g->graph = gr;
+  e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    g->exec = nullptr;
+    return fail(h, RFMLS_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return RFMLS_OK;
+}
 }  // namespace rfmls
 
 // Launch entry points implemented in the individual .hip files -----------------

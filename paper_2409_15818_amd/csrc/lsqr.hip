@@ -504,6 +504,7 @@ struct Ctx {
   double *sqA, *sqB, *sqY, *sqW;
   double* hn;  // one device double for norms read by the host
   LsqrDev* dst;
+  IterGraph* graph = nullptr;  // captured poll interval of the loop, or null: eager launches
   int nspmvA, nspmvAT, nvec_n, nvec_m;
 };
 
@@ -637,6 +638,40 @@ static rfmls_status poll_done(Ctx& c, int* host_done) {
   return RFMLS_OK;
 }
 
+// One LSQR iteration (Golub-Kahan step, plane rotation, updates of y and w,
+// stopping tests), enqueued on c.st; nred = number of partial sums of ||v||^2.
+static rfmls_status lsqr_iteration(Ctx& c, int nred) {
+  rfmls_handle* h = c.h;
+  const int64_t m = c.A->m, n = c.A->n;
+  const int* done = &c.dst->done;
+  const unsigned vbn = vec_blocks(n), vbm = vec_blocks(m);
+  // beta u = A (X v) - alpha u  (or B v - alpha u)
+  int nb = 0;
+  if (c.Bm) {
+    RFMLS_CHECK(bmul(c, c.v, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+  } else {
+    RFMLS_CHECK(tri_apply(h, c.P, 0, c.v, c.z, 0.0, nullptr, nullptr, nullptr, done));
+    RFMLS_CHECK(spmv(c, c.A, c.z, 1.0, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
+  }
+  hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA, nb,
+                     &c.dst->beta, done);
+  // alpha v = X^T (A^T u) - beta v  (or B^T u - beta v)
+  if (c.Bm) {
+    RFMLS_CHECK(btmul(c, c.u, 1.0, &c.dst->beta, c.v, c.v, c.sqB, done, &nred));
+  } else {
+    RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
+    RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 1.0, &c.dst->beta, c.v, c.sqB, done));
+  }
+  hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
+                     &c.dst->alpha, done);
+  hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqW, (int)vbn);
+  hipLaunchKernelGGL(k_lsqr_update, dim3(vbn), dim3(kThreads), 0, c.st, c.dst, c.v, c.w, c.y, n,
+                     c.sqY, c.sqW);
+  hipLaunchKernelGGL(k_lsqr_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqY, (int)vbn, 0);
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
 // One LSQR sweep for min ||A X y - rhs||; on return c.y holds y and the state
 // is in c.dst.  rhs is an m-vector (device).
 static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, int64_t itmax) {
@@ -676,31 +711,25 @@ static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, i
   const int every = o->check_every > 0 ? o->check_every : 8;
   int hd = 0;
   RFMLS_CHECK(poll_done(c, &hd));
+  if (c.graph && !h->trace) {
+    // the poll interval's launches recorded once per call, then replayed
+    if (!c.graph->exec)
+      RFMLS_CHECK(capture_graph(h, c.graph, [&]() -> rfmls_status {
+        const hipStream_t s0 = c.st;
+        c.st = h->stream;
+        rfmls_status r = RFMLS_OK;
+        for (int k = 0; k < every && r >= 0; ++k) r = lsqr_iteration(c, nred);
+        c.st = s0;
+        return r;
+      }));
+    for (int64_t it = 0; it < itmax && !hd; it += every) {
+      RFMLS_HIP(h, hipGraphLaunch(c.graph->exec, c.st));
+      RFMLS_CHECK(poll_done(c, &hd));
+    }
+    return RFMLS_OK;
+  }
   for (int64_t it = 0; it < itmax && !hd; ++it) {
-    // beta u = A (X v) - alpha u  (or B v - alpha u)
-    int nb = 0;
-    if (c.Bm) {
-      RFMLS_CHECK(bmul(c, c.v, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
-    } else {
-      RFMLS_CHECK(tri_apply(h, c.P, 0, c.v, c.z, 0.0, nullptr, nullptr, nullptr, done));
-      RFMLS_CHECK(spmv(c, c.A, c.z, 1.0, 1.0, &c.dst->alpha, c.u, c.u, c.sqA, done, &nb));
-    }
-    hipLaunchKernelGGL(k_normalize, dim3(vbm), dim3(kThreads), 0, c.st, c.u, m, c.sqA, nb,
-                       &c.dst->beta, done);
-    // alpha v = X^T (A^T u) - beta v  (or B^T u - beta v)
-    if (c.Bm) {
-      RFMLS_CHECK(btmul(c, c.u, 1.0, &c.dst->beta, c.v, c.v, c.sqB, done, &nred));
-    } else {
-      RFMLS_CHECK(spmv(c, c.AT, c.u, 1.0, 0.0, nullptr, nullptr, c.q, nullptr, done, nullptr));
-      RFMLS_CHECK(tri_apply(h, c.P, 1, c.q, c.v, 1.0, &c.dst->beta, c.v, c.sqB, done));
-    }
-    hipLaunchKernelGGL(k_normalize, dim3(vbn), dim3(kThreads), 0, c.st, c.v, n, c.sqB, nred,
-                       &c.dst->alpha, done);
-    hipLaunchKernelGGL(k_lsqr_rotate, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqW, (int)vbn);
-    hipLaunchKernelGGL(k_lsqr_update, dim3(vbn), dim3(kThreads), 0, c.st, c.dst, c.v, c.w, c.y, n,
-                       c.sqY, c.sqW);
-    hipLaunchKernelGGL(k_lsqr_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqY, (int)vbn, 0);
-    RFMLS_HIP(h, hipGetLastError());
+    RFMLS_CHECK(lsqr_iteration(c, nred));
     if ((it + 1) % every == 0) RFMLS_CHECK(poll_done(c, &hd));
   }
   return RFMLS_OK;
@@ -790,6 +819,9 @@ static rfmls_status solve_impl(rfmls_handle* h, const rfmls_csr* A, const rfmls_
                                double* base = nullptr) {
   Ctx c;
   RFMLS_CHECK(make_ctx(h, A, AT, P, c, base));
+  // the allocation-free variant launches eagerly (instantiating a graph allocates)
+  IterGraph graph;
+  if (o->graph && !base) c.graph = &graph;
   if (Bm) {
     void* p;
     RFMLS_CHECK(workspace(h, WS_GEMV, sizeof(double) * (size_t)kGemvTSlices * (size_t)A->n, &p));
@@ -951,6 +983,7 @@ rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* 
   double* lam = c.r;  // m
   const int* done = &c.dst->done;
   rfmls_status ret = RFMLS_OK;
+  IterGraph graph;  // one capture serves every right-hand side (same buffers)
   for (int64_t k = 0; k < nrhs; ++k) {
     RFMLS_CHECK(upload_state(c, o, itmax));
     // beta_1 u_1 = c = X^T g
@@ -978,7 +1011,7 @@ rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* 
     const int every = o->check_every > 0 ? o->check_every : 8;
     int hd = 0;
     RFMLS_CHECK(poll_done(c, &hd));
-    for (int64_t it = 0; it < itmax && !hd; ++it) {
+    auto iteration = [&]() -> rfmls_status {
       // beta u = X^T (A^T v) - alpha u
       RFMLS_CHECK(spmv(c, AT, vm, 1.0, 0.0, nullptr, nullptr, tmpn, nullptr, done, nullptr));
       RFMLS_CHECK(tri_apply(h, P, 1, tmpn, un, 1.0, &c.dst->alpha, un, c.sqB, done));
@@ -996,7 +1029,27 @@ rfmls_status run_backward(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* 
                          c.sqY, c.sqW);
       hipLaunchKernelGGL(k_lsqr_check, dim3(1), dim3(kThreads), 0, c.st, c.dst, c.sqY, (int)vbn, 1);
       RFMLS_HIP(h, hipGetLastError());
-      if ((it + 1) % every == 0) RFMLS_CHECK(poll_done(c, &hd));
+      return RFMLS_OK;
+    };
+    if (o->graph && !h->trace) {
+      if (!graph.exec)
+        RFMLS_CHECK(capture_graph(h, &graph, [&]() -> rfmls_status {
+          const hipStream_t s0 = c.st;
+          c.st = h->stream;
+          rfmls_status r = RFMLS_OK;
+          for (int q = 0; q < every && r >= 0; ++q) r = iteration();
+          c.st = s0;
+          return r;
+        }));
+      for (int64_t it = 0; it < itmax && !hd; it += every) {
+        RFMLS_HIP(h, hipGraphLaunch(graph.exec, c.st));
+        RFMLS_CHECK(poll_done(c, &hd));
+      }
+    } else {
+      for (int64_t it = 0; it < itmax && !hd; ++it) {
+        RFMLS_CHECK(iteration());
+        if ((it + 1) % every == 0) RFMLS_CHECK(poll_done(c, &hd));
+      }
     }
     LsqrDev s;
     RFMLS_CHECK(read_state(c, &s));

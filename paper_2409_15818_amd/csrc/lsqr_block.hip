@@ -793,7 +793,14 @@ struct BCtx {
   double *sqA, *sqB, *sqY, *sqW, *part;
   double* spart;  // partial sums of split SpMM groups (nsplit x rows x 32)
   BlockState* dst;
+  IterGraph* graph = nullptr;  // captured poll interval of the loop, or null: eager launches
 };
+
+// Runs the lockstep loop: `iteration` (which enqueues one iteration on c.st) up
+// to itmax times, the host polling the "all columns done" word after every
+// `every` iterations; with c.graph the poll interval is captured once and replayed.
+template <class F>
+static rfmls_status run_loop(BCtx& c, int64_t itmax, int every, F&& iteration);
 
 double* state_field(BlockState* s, int which) {
   // pointer to col[0].<field>; stride between columns in doubles
@@ -900,10 +907,8 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
                      c.sqW);
   RFMLS_HIP(c.h, hipGetLastError());
   const int every = o->check_every > 0 ? o->check_every : 8;
-  int hd = 0;
-  RFMLS_CHECK(poll_all(c, &hd));
   const BlockState* cst = c.dst;
-  for (int64_t it = 0; it < itmax && !hd; ++it) {
+  return run_loop(c, itmax, every, [&]() -> rfmls_status {
     RFMLS_CHECK(tri_block(c, 0, c.V, c.Z, 0.0, nullptr, nullptr, nullptr, cst));
     int nb = 0;
     RFMLS_CHECK(spmm(c, c.A, c.Z, 1.0, 1.0, state_field(c.dst, 1), c.U, c.U, c.sqA, cst, &nb));
@@ -921,6 +926,33 @@ rfmls_status block_sweep(BCtx& c, const double* rhs, const rfmls_opts* o, int64_
     hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqY,
                        (int)rows_grid(n), 0);
     RFMLS_HIP(c.h, hipGetLastError());
+    return RFMLS_OK;
+  });
+}
+
+template <class F>
+static rfmls_status run_loop(BCtx& c, int64_t itmax, int every, F&& iteration) {
+  rfmls_handle* h = c.h;
+  int hd = 0;
+  RFMLS_CHECK(poll_all(c, &hd));
+  if (c.graph && !h->trace) {
+    if (!c.graph->exec)
+      RFMLS_CHECK(capture_graph(h, c.graph, [&]() -> rfmls_status {
+        const hipStream_t s0 = c.st;
+        c.st = h->stream;
+        rfmls_status r = RFMLS_OK;
+        for (int k = 0; k < every && r >= 0; ++k) r = iteration();
+        c.st = s0;
+        return r;
+      }));
+    for (int64_t it = 0; it < itmax && !hd; it += every) {
+      RFMLS_HIP(h, hipGraphLaunch(c.graph->exec, c.st));
+      RFMLS_CHECK(poll_all(c, &hd));
+    }
+    return RFMLS_OK;
+  }
+  for (int64_t it = 0; it < itmax && !hd; ++it) {
+    RFMLS_CHECK(iteration());
     if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
   }
   return RFMLS_OK;
@@ -1022,6 +1054,8 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   const int64_t itmax = o->itmax > 0 ? o->itmax : n;
   BCtx c;
   RFMLS_CHECK(make_bctx(h, A, AT, P, c));
+  IterGraph graph;  // one capture serves every sweep and column block (same buffers)
+  if (o->graph) c.graph = &graph;
   const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
   rfmls_status ret = RFMLS_OK;
   std::vector<BlockState> hs(1);
@@ -1117,6 +1151,8 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
   const int64_t itmax = o->itmax > 0 ? o->itmax : m;
   BCtx c;
   RFMLS_CHECK(make_bctx(h, A, AT, P, c));
+  IterGraph graph;
+  if (o->graph) c.graph = &graph;
   // roles: un (n), vm (m), vt, wt, zz shadows (n), tmp (n), lam (m), gathered blocks
   double* un = c.V;
   double* vm = c.U;
@@ -1155,9 +1191,7 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
     hipLaunchKernelGGL(k_blk_copy, dim3(gn), dim3(kThreads), 0, c.st, (const double*)vt, wt, n);
     hipLaunchKernelGGL(k_blk_sumsq, dim3(rows_grid(n)), dim3(kThreads), 0, c.st, (const double*)wt, n, c.sqW);
     RFMLS_HIP(h, hipGetLastError());
-    int hd = 0;
-    RFMLS_CHECK(poll_all(c, &hd));
-    for (int64_t it = 0; it < itmax && !hd; ++it) {
+    RFMLS_CHECK(run_loop(c, itmax, every, [&]() -> rfmls_status {
       // beta u = X^T (A^T v) - alpha u
       RFMLS_CHECK(spmm(c, AT, vm, 1.0, 0.0, nullptr, nullptr, tmp, nullptr, cst, nullptr));
       RFMLS_CHECK(tri_block(c, 1, tmp, un, 1.0, state_field(c.dst, 1), un, c.sqB, cst));
@@ -1178,8 +1212,8 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
       hipLaunchKernelGGL(k_blk_check, dim3(1), dim3(kRedThreads), 0, c.st, c.dst, (const double*)c.sqY,
                          (int)rows_grid(n), 1);
       RFMLS_HIP(h, hipGetLastError());
-      if ((it + 1) % every == 0) RFMLS_CHECK(poll_all(c, &hd));
-    }
+      return RFMLS_OK;
+    }));
     RFMLS_CHECK(read_block_state(c, hs.data()));
     for (int64_t q = 0; q < nb; ++q) {
       const LsqrDev& st = hs[0].col[q];

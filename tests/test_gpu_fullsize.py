@@ -138,3 +138,59 @@ def test_fullsize_cssvdp_matches_oracle(handle, store):
     E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
     assert pipeline.l2_error(E, x, S.exact(pts)) <= 1.1 * gold["l2_error"]
     del res
+
+
+# The batched and differentiable form of the 8x8-box system: 32 right-hand
+# sides u_k = sin(k pi x) sin(pi y), k = 1..32, in one lockstep solve from
+# y0 = 0, and the backward pass of L = 1/2 ||E x_1 - u_1||^2 at the 10^4 sample
+# points (cotangent on column 1 only; the other 31 columns stop at once).
+# Columns k = 1, 2, 17, 32 are gated against the oracle's one-at-a-time solves
+# stored by make_golden.py --multi; the gradients against the oracle's
+# preconditioned adjoint solve for column 1.  lambda = A (A^T A)^{-1} g is
+# determined only to about cond(A) u relative (the product R^{-T} g alone
+# loses that much), so sampled entries of lambda and dA are gated at 1e-2 of
+# the sample's norm, and A^T lambda = g to the oracle's own level.
+def test_fullsize_32_rhs_lockstep_and_backward(handle):
+    name = "poisson2d_8x8"
+    gold = _golden(name)["multi"]
+    S, s = build_config(name, modes=tuple(range(1, 33)))
+    print(f"[fullsize] {name} 32 right-hand sides", flush=True)
+    A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
+    B = torch.tensor(S.b, device="cuda")
+    opts = R.default_opts(refine=gold["refine"])
+    res = R.csqrp_lsqr(handle, A, B, s, SEED, opts=opts)
+    assert res.status == 0
+    X = res.x.cpu().numpy()
+    Ah = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
+    pts = sample_points(S.d)
+    E = pipeline.csr(*feature_eval(S, pts), len(pts), S.n)
+    for mode, g in gold["per_mode"].items():
+        k = int(mode) - 1
+        met = pipeline.residual_metrics(Ah, X[k], S.b[k])
+        assert abs(met["normr"] - g["normr"]) <= RES_TOL[name] * g["normr"], (mode, met["normr"], g["normr"])
+        l2 = pipeline.l2_error(E, X[k], S.exact(pts, int(mode)))
+        assert l2 <= 1.1 * g["l2_error"], (mode, l2, g["l2_error"])
+        assert res.info[k]["istop"] in (1, 2)
+    gg = gold["gradient"]
+    k = gg["mode"] - 1
+    G = np.zeros((32, S.n))
+    G[k] = E.T @ (E @ X[k] - S.exact(pts, gg["mode"]))
+    dB, dA, binfo, brc = R.rfmls_solve_backward(handle, A, res.AT, res.precond, res.x, res.residual,
+                                                torch.tensor(G, device="cuda"), opts)
+    assert brc == 0 and all(i["itn"] == 0 for q, i in enumerate(binfo) if q != k)
+    lam = dB[k].cpu().numpy()
+    rows = np.array(gg["lambda_rows"])
+    ls, lo = lam[rows], np.array(gg["lambda_sample"])
+    dl = np.linalg.norm(ls - lo) / np.linalg.norm(lo)
+    da_s = dA.cpu().numpy()[np.array(gg["dA_entries"])]
+    do = np.array(gg["dA_sample"])
+    dd = np.linalg.norm(da_s - do) / np.linalg.norm(do)
+    nl = np.linalg.norm(lam)
+    atl = np.linalg.norm(Ah.T @ lam - G[k]) / np.linalg.norm(G[k])
+    print(f"[fullsize] lambda sample rel diff {dl:.3e}, dA sample rel diff {dd:.3e}, "
+          f"|lambda| {nl:.6e} vs {gg['norm_lambda']:.6e}, A^T lambda residual {atl:.3e} "
+          f"(oracle {gg['at_lambda_relres']:.3e}), itn {binfo[k]['itn']} vs {gg['itn']}", flush=True)
+    assert dl <= 1e-2 and dd <= 1e-2
+    assert abs(nl - gg["norm_lambda"]) <= 1e-2 * gg["norm_lambda"]
+    assert atl <= max(3.0 * gg["at_lambda_relres"], 1e-3)
+    del res
