@@ -280,7 +280,23 @@ def main():
 
     for w in range(args.warmup):
         log(f"[bench] warmup {w + 1}/{args.warmup}")
-        out = step()
+        try:
+            out = step()
+        except R.RfmlsError as e:
+            if e.status != -6:
+                raise
+            # the float32 factor cannot precondition this system (RFMLS_E_PRECISION):
+            # nothing to time; report the library's refusal
+            print(json.dumps({
+                "metric": METRIC, "value": None, "unit": "s", "n_gpus": 1, "steps": 0, "warmup": args.warmup,
+                "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+                "dtype": qd, "data": "synthetic",
+                "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
+                           "precision": args.precision, "refine": args.refine, "nrhs": args.nrhs,
+                           "start": args.start, "operator": args.operator, "precond": args.precond},
+                "refused": str(e)}), flush=True)
+            h.close()
+            return
         del out
     torch.cuda.synchronize()
     times, phases = [], []
@@ -420,6 +436,8 @@ def main():
         "backward": bwd,
         "roofline": roof,
         "pipeline_roofline": pipe,
+        "tuned_shapes": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
+                         for t in R.rfmls_tune_read(h)],
         "kernels": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in k.items()}
                     for k in kernels[:12]],
         "cpu_baseline": cpu,

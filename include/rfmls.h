@@ -57,7 +57,9 @@ typedef enum {
   RFMLS_E_RANK = -2,      /* R numerically singular: |r_ii| <= 16 u max|r_jj| */
   RFMLS_E_BREAKDOWN = -3, /* non-finite value met inside the iteration */
   RFMLS_E_HIP = -4,       /* HIP runtime error (message in rfmls_last_error) */
-  RFMLS_E_NOMEM = -5      /* device allocation of library workspace failed */
+  RFMLS_E_NOMEM = -5,     /* device allocation of library workspace failed */
+  RFMLS_E_PRECISION = -6  /* float32 factor too coarse for this system: some
+                             |r_jj| / ||SA[:, j]|| <= 16 u32 (rfmls_precond) */
 } rfmls_status;
 
 typedef enum { RFMLS_F64 = 0, RFMLS_F32 = 1 } rfmls_dtype;
@@ -160,9 +162,16 @@ rfmls_status rfmls_sketch(rfmls_handle *h, const rfmls_csr *A, int64_t s, uint64
  * rows of R scaled so diag(R) > 0.  The library forms and keeps X = R^{-1}
  * (upper triangular) stored in r_store precision.  Returns RFMLS_E_RANK if
  * some |r_ii| <= 16 u max_j |r_jj| (u = unit roundoff of qr_dtype; for
- * RFMLS_F32 only a zero or non-finite pivot is rejected).  *P_out is
- * library-owned; free with rfmls_precond_free.  Asynchronous except for the
- * rank check, which synchronises the stream. */
+ * RFMLS_F32 only a zero or non-finite pivot is rejected).  With qr_dtype or
+ * r_store RFMLS_F32 it returns RFMLS_E_PRECISION when
+ * min_j |r_jj| / ||SA[:, j]|| <= 16 u32 (u32 = 2^-24; the margin of the
+ * float64 rank test): some column of SA lies within float32 rounding of the
+ * span of the columns before it, so a factor computed or stored in float32
+ * carries no information in that direction and LSQR on A R^{-1} would stall
+ * or slow down severalfold; such a system must be factored and stored in
+ * float64 (the 8 x 8-box 2D Poisson RFM system is one).  *P_out is library-owned; free with rfmls_precond_free.  Asynchronous
+ * except for these checks, which synchronise the stream.  On an error nothing
+ * is returned in *P_out. */
 rfmls_status rfmls_precond(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtype qr_dtype,
                            rfmls_dtype r_store, void *SA, int64_t ld_sa,
                            rfmls_precond_t **P_out /* [host] out */);
@@ -210,6 +219,10 @@ rfmls_status rfmls_precond_svd(rfmls_handle *h, int64_t s, int64_t n, rfmls_dtyp
  * QR preconditioner. */
 rfmls_status rfmls_precond_svd_stats(const rfmls_precond_t *P, int64_t *rank, int *sweeps,
                                      double *off);
+/* [host] Statistics of the factor R of a QR preconditioner: min|r_ii| / max|r_jj|
+ * and min_j |r_jj| / ||R[:, j]|| (the column-relative pivot the float32 check
+ * of rfmls_precond uses); either pointer may be null. */
+rfmls_status rfmls_precond_stats(const rfmls_precond_t *P, double *pivot_ratio, double *rho_min);
 void rfmls_precond_free(rfmls_precond_t *P);
 int64_t rfmls_precond_n(const rfmls_precond_t *P);
 
@@ -303,6 +316,29 @@ rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfm
                                   const double *Rres, int64_t ldr, const double *G, int64_t ldg,
                                   int64_t nrhs, double *dB, int64_t lddb, double *dAval,
                                   const rfmls_opts *opts, rfmls_info *info);
+
+/* ---- Autotuning of launch shapes ----
+ * With tuning on (the default), the first lockstep solve, backward pass or
+ * rfmls_form_B that uses a matrix of a given shape (rows, columns, stored
+ * entries) on a handle times every candidate launch shape of its 32-column
+ * sparse products (the width of the input window staged in LDS) on that
+ * matrix, and keeps the fastest for later calls on the handle.  The candidates
+ * change neither the order of any sum nor the rows each block handles, so
+ * results do not depend on the choice.  Tuning synchronises the stream once
+ * per matrix shape; off, the hand-picked shape is used. */
+typedef struct {
+  char kernel[16];        /* kernel family ("spmm")                         */
+  int64_t rows, cols, nnz; /* the matrix it was tuned on                     */
+  char choice[48];        /* the launch shape kept                           */
+  double ms_best;         /* median time of the kept shape (ms)              */
+  double ms_default;      /* median time of the hand-picked shape (ms)       */
+  int32_t candidates;     /* shapes timed                                    */
+} rfmls_tune_entry;
+
+rfmls_status rfmls_tune_enable(rfmls_handle *h, int enable);
+/* Writes up to cap records [host] of the shapes tuned on this handle; *count
+ * [host] receives the number written. */
+rfmls_status rfmls_tune_read(const rfmls_handle *h, rfmls_tune_entry *out, int cap, int *count);
 
 /* ---- Kernel tracing (measurement support; not part of the numerical path) ----
  * While enabled, every launch of the library's kernels is bracketed by HIP

@@ -48,9 +48,11 @@ def csr(row_ptr, col, val, m, n):
 
 
 def precondition(row_ptr, col, val, m, n, s, seed, qr_dtype="f64", r_store="f64", b=None,
-                 hash_in=None):
+                 hash_in=None, check_precision=True):
     """Steps 1-3: returns dict(h, sign, SA, Sb, R) with R as a float64 array holding the
-    stored preconditioner (rounded to float32 first when r_store == 'f32')."""
+    stored preconditioner (rounded to float32 first when r_store == 'f32').  A factor
+    computed or stored in float32 with rho_min <= 16 u32 raises qr.PrecisionInsufficient
+    (check_precision)."""
     if hash_in is None:
         h, sign = countsketch.hash_sign(m, s, seed)
     else:
@@ -60,6 +62,8 @@ def precondition(row_ptr, col, val, m, n, s, seed, qr_dtype="f64", r_store="f64"
         R = qr.r_factor(SA.astype(np.float32), check_rank=False).astype(np.float64)
     else:
         R = qr.r_factor(SA)
+    if check_precision and "f32" in (qr_dtype, r_store) and qr.rho_min(R) <= qr.PRECISION_TOL:
+        raise qr.PrecisionInsufficient("float32 factor: min |r_jj| / ||SA[:, j]|| <= 16 u32")
     if r_store == "f32":
         R = R.astype(np.float32).astype(np.float64)
     return dict(h=h, sign=sign, SA=SA, Sb=Sb, R=R)

@@ -29,6 +29,10 @@ class RankDeficient(ValueError):
     pass
 
 
+class PrecisionInsufficient(ValueError):
+    """A float32 factor that cannot precondition the system (see rho_min)."""
+
+
 def _normalise(R: np.ndarray) -> np.ndarray:
     d = np.sign(np.diag(R)).astype(R.dtype)
     d[d == 0] = 1
@@ -42,6 +46,26 @@ def rank_ok(R: np.ndarray) -> bool:
     dg = np.abs(np.diag(R)).astype(np.float64)
     u = np.finfo(R.dtype).eps / 2
     return bool(dg.min() > 16.0 * u * dg.max())
+
+
+def rho_min(R: np.ndarray) -> float:
+    """min_j |r_jj| / ||R[:, j]||: the distance of column j of SA from the span of
+    the columns before it, relative to the column's length (||R[:, j]|| equals
+    ||SA[:, j]|| because Q has orthonormal columns).  Householder QR in unit
+    roundoff u perturbs each column of SA by a few u times its length, so a
+    factor computed or stored in float32 whose rho_min is within 16 u32
+    (u32 = 2^-24; the margin of the float64 rank test) carries only rounding
+    noise in that direction (the reading used for the float32 preconditioner;
+    the paper has no float32 factor)."""
+    R = np.asarray(R, dtype=np.float64)
+    if R.shape[0] == 0:
+        return np.inf
+    return float(np.min(np.abs(np.diag(R)) / np.linalg.norm(R, axis=0)))
+
+
+U32 = 2.0 ** -24
+# a factor computed or stored in float32 is refused at or below this rho_min
+PRECISION_TOL = 16.0 * U32
 
 
 def r_factor(SA: np.ndarray, check_rank: bool = True) -> np.ndarray:

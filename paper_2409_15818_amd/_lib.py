@@ -15,11 +15,13 @@ RFMLS_E_RANK = -2
 RFMLS_E_BREAKDOWN = -3
 RFMLS_E_HIP = -4
 RFMLS_E_NOMEM = -5
+RFMLS_E_PRECISION = -6
 RFMLS_F64 = 0
 RFMLS_F32 = 1
 
 STATUS_NAMES = {0: "RFMLS_OK", 1: "RFMLS_W_NOCONV", -1: "RFMLS_E_ARG", -2: "RFMLS_E_RANK",
-                -3: "RFMLS_E_BREAKDOWN", -4: "RFMLS_E_HIP", -5: "RFMLS_E_NOMEM"}
+                -3: "RFMLS_E_BREAKDOWN", -4: "RFMLS_E_HIP", -5: "RFMLS_E_NOMEM",
+                -6: "RFMLS_E_PRECISION"}
 
 EXPORTED = [
     "rfmls_default_opts", "rfmls_create", "rfmls_destroy", "rfmls_last_error", "rfmls_transpose",
@@ -27,7 +29,8 @@ EXPORTED = [
     "rfmls_precond_export_R", "rfmls_precond_export_Rinv", "rfmls_precond_import_R",
     "rfmls_precond_svd", "rfmls_precond_svd_stats", "rfmls_precond_export_P", "rfmls_precond_export_sigma",
     "rfmls_solve", "rfmls_form_B", "rfmls_solve_explicit", "rfmls_solve_backward",
-    "rfmls_trace_enable", "rfmls_trace_read", "rfmls_solve_noalloc", "rfmls_noalloc_scratch_bytes",
+    "rfmls_trace_enable", "rfmls_trace_read", "rfmls_solve_noalloc", "rfmls_noalloc_scratch_bytes", "rfmls_precond_stats",
+    "rfmls_tune_enable", "rfmls_tune_read",
 ]
 
 
@@ -51,6 +54,12 @@ class rfmls_info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rfmls_tune_entry(C.Structure):
+    _fields_ = [("kernel", C.c_char * 16), ("rows", C.c_int64), ("cols", C.c_int64), ("nnz", C.c_int64),
+                ("choice", C.c_char * 48), ("ms_best", C.c_double), ("ms_default", C.c_double),
+                ("candidates", C.c_int32)]
 
 
 class rfmls_trace_entry(C.Structure):
@@ -101,6 +110,7 @@ def load():
                                 P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_solve_noalloc.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, i64, vp, i64, vp, i64,
                                         P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_precond_stats.argtypes = [vp, P(C.c_double), P(C.c_double)]
     lib.rfmls_noalloc_scratch_bytes.argtypes = []
     lib.rfmls_noalloc_scratch_bytes.restype = i64
     lib.rfmls_form_B.argtypes = [vp, P(rfmls_csr), vp, vp, i64]
@@ -108,6 +118,8 @@ def load():
                                          i64, vp, i64, P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_solve_backward.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, vp,
                                          i64, i64, vp, i64, vp, P(rfmls_opts), P(rfmls_info)]
+    lib.rfmls_tune_enable.argtypes = [vp, C.c_int]
+    lib.rfmls_tune_read.argtypes = [vp, P(rfmls_tune_entry), C.c_int, P(C.c_int)]
     lib.rfmls_trace_enable.argtypes = [vp, C.c_int]
     lib.rfmls_trace_read.argtypes = [vp, P(rfmls_trace_entry), C.c_int, P(C.c_int)]
     for name in EXPORTED:

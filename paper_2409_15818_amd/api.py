@@ -134,6 +134,21 @@ class Precond:
             pass
 
 
+def rfmls_tune_enable(h: Handle, enable: bool = True):
+    h.check(h._lib.rfmls_tune_enable(h._h, int(bool(enable))))
+
+
+def rfmls_tune_read(h: Handle) -> list:
+    """The launch shapes the autotuner kept on this handle, one dict per tuned matrix."""
+    cap = 64
+    buf = (_lib.rfmls_tune_entry * cap)()
+    cnt = C.c_int(0)
+    h.check(h._lib.rfmls_tune_read(h._h, buf, cap, C.byref(cnt)))
+    return [dict(kernel=buf[k].kernel.decode(), rows=buf[k].rows, cols=buf[k].cols, nnz=buf[k].nnz,
+                 choice=buf[k].choice.decode(), ms_best=buf[k].ms_best, ms_default=buf[k].ms_default,
+                 candidates=buf[k].candidates) for k in range(cnt.value)]
+
+
 def rfmls_trace_enable(h: Handle, enable: bool = True):
     h.check(h._lib.rfmls_trace_enable(h._h, int(bool(enable))))
 
@@ -305,6 +320,15 @@ def rfmls_solve_noalloc(h: Handle, A: CSR, AT: CSR, P: Precond, B: torch.Tensor,
     rc = h.check(h._lib.rfmls_solve_noalloc(h._h, C.byref(A.c()), C.byref(AT.c()), P._p, _ptr(B), A.m, nrhs,
                                             _ptr(X), A.n, _ptr(Rres), A.m, C.byref(o), infos))
     return [infos[k].as_dict() for k in range(nrhs)], rc
+
+
+def rfmls_precond_stats(P: Precond) -> dict:
+    """min|r_ii| / max|r_jj| and min_j |r_jj| / ||R[:, j]|| of a QR preconditioner."""
+    pr, rho = C.c_double(0.0), C.c_double(0.0)
+    rc = _lib.load().rfmls_precond_stats(P._p, C.byref(pr), C.byref(rho))
+    if rc != 0:
+        raise RfmlsError(rc, "rfmls_precond_stats failed")
+    return {"pivot_ratio": pr.value, "rho_min": rho.value}
 
 
 def rfmls_noalloc_scratch_bytes() -> int:

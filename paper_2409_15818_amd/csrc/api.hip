@@ -415,6 +415,13 @@ rfmls_status rfmls_solve_noalloc(rfmls_handle* h, const rfmls_csr* A, const rfml
 
 int64_t rfmls_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
 
+rfmls_status rfmls_precond_stats(const rfmls_precond_t* P, double* pivot_ratio, double* rho_min) {
+  if (!P) return RFMLS_E_ARG;
+  if (pivot_ratio) *pivot_ratio = P->pivot_ratio;
+  if (rho_min) *rho_min = P->rho_min;
+  return RFMLS_OK;
+}
+
 rfmls_status rfmls_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond_t* P, double* Bmat,
                           int64_t ld_bmat) {
   if (!h) return RFMLS_E_ARG;
@@ -463,6 +470,32 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
   if (o->lockstep && nrhs > 1)
     return run_backward_block(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
   return run_backward(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
+}
+
+rfmls_status rfmls_tune_enable(rfmls_handle* h, int enable) {
+  if (!h) return RFMLS_E_ARG;
+  h->tune = enable != 0;
+  return RFMLS_OK;
+}
+
+rfmls_status rfmls_tune_read(const rfmls_handle* h, rfmls_tune_entry* out, int cap, int* count) {
+  if (!h || (!out && cap > 0) || !count) return RFMLS_E_ARG;
+  int k = 0;
+  for (const TuneRec& t : h->tuned) {
+    if (k >= cap) break;
+    rfmls_tune_entry& e = out[k++];
+    memset(&e, 0, sizeof(e));
+    strncpy(e.kernel, t.kernel, sizeof(e.kernel) - 1);
+    e.rows = t.rows;
+    e.cols = t.cols;
+    e.nnz = t.nnz;
+    strncpy(e.choice, t.desc, sizeof(e.choice) - 1);
+    e.ms_best = t.ms_best;
+    e.ms_default = t.ms_default;
+    e.candidates = t.candidates;
+  }
+  *count = k;
+  return RFMLS_OK;
 }
 
 rfmls_status rfmls_trace_enable(rfmls_handle* h, int enable) {

@@ -28,6 +28,16 @@ struct Workspace {
 }  // namespace rfmls
 
 namespace rfmls {
+// One autotuned launch shape: the kernel family, the shape of the operand it
+// was tuned on, the candidate chosen and its time beside the hand-picked one's.
+struct TuneRec {
+  char kernel[16];
+  int64_t rows, cols, nnz;
+  int choice;
+  char desc[48];
+  double ms_best, ms_default;
+  int candidates;
+};
 struct TraceRec {
   const char* name;
   hipEvent_t beg, end;
@@ -50,6 +60,8 @@ struct rfmls_handle {
   void* pinned = nullptr;           // small pinned host staging buffer
   size_t pinned_bytes = 0;
   hipStream_t cap_stream = nullptr; // stream that graphs are captured on (created on first use)
+  int tune = 1;                     // autotune launch shapes on first use (rfmls_tune_enable)
+  std::vector<rfmls::TuneRec> tuned;
 };
 
 struct rfmls_precond {
@@ -69,6 +81,8 @@ struct rfmls_precond {
   int sweeps = 0;
   double off = 0.0;
   int device = 0;
+  // statistics of R: min|r_ii| / max|r_jj| and min_j |r_jj| / ||R[:, j]||
+  double pivot_ratio = 0.0, rho_min = 0.0;
   // work decomposition of the triangular products: chunks of `chunk` tiles
   int chunk = 4;
   int64_t ntab = 0;          // number of (row-or-column, chunk) work items
@@ -274,7 +288,11 @@ rfmls_status apply_householder(rfmls_handle* h, const double* P, int64_t ld, int
                                const double* tau, double* Y, int64_t ldy, int64_t ny);
 rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, const void* SA,
                                int64_t ld, rfmls_dtype store, rfmls_precond_t* P, int check_rank);
-rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit);
+// checks R (zero / non-finite pivots; with check_rank the 16 u pivot ratio; with
+// check_precision the float32 column-relative pivot), records its statistics,
+// then forms and packs X = R^{-1}
+rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit,
+                            int check_precision);
 // tables of the tiled products and the packed tiles of X (row-major n x n
 // dense, float64) in P->store precision, for either packing (P->full)
 rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X);

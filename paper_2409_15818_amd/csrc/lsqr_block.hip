@@ -13,6 +13,9 @@
 // Vectors are interleaved row-major blocks (element (i, c) at i * 32 + c).
 // A column that has stopped keeps its y and x; the host polls one
 // "all columns done" flag every few iterations.
+#include <algorithm>
+#include <cstring>
+
 #include "common.h"
 #include "lsqr_dev.h"
 
@@ -754,19 +757,38 @@ unsigned spmm_grid(int64_t rows) {  // row groups of 16, grid-stride beyond kSpm
   return (unsigned)(b < kSpmmBlocks ? (b > 0 ? b : 1) : kSpmmBlocks);
 }
 
-// SpMM shape by average row length (measured on gfx950, 32 columns): short
-// rows (the RFM matrix, 200-400 entries) share 64-wide windows among 16 rows;
-// long rows (its transpose, ~2000 entries) run 8 rows per group in 32-wide
-// windows, whose small LDS footprint gives 7 resident blocks per compute unit
-// (the kernel is latency-bound).  Grids stop at about the resident block count.
+// SpMM launch shapes.  The row-group height follows the average row length
+// (measured on gfx950, 32 columns): short rows (the RFM matrix, 200-400
+// entries) in groups of 16, long rows (its transpose, ~2000 entries) in groups
+// of 8, whose smaller LDS footprint keeps more blocks resident (the kernel is
+// latency-bound); grids stop at about the resident block count.  The window
+// width (columns of the input block staged in LDS at a time) is chosen per
+// matrix by the autotuner below: it changes neither the order of any sum nor
+// the rows each block handles (so not the norm partials either), so every
+// candidate gives bitwise the same result.
 struct SpmmShape {
   const void* fn;
-  int group;
-  unsigned max_blocks;
+  int group, win;
+  unsigned max_blocks;  // grid cap (grid-stride over the groups beyond it)
 };
+static int spmm_group(const rfmls_csr* M) { return (M->m > 0 && M->nnz / M->m > 512) ? 8 : 16; }
+// the hand-picked shape (used when tuning is off, and the tuner's reference)
 SpmmShape spmm_shape(const rfmls_csr* M) {
-  if (M->m > 0 && M->nnz / M->m > 512) return {(const void*)k_spmm<8, 32>, 8, 1792};
-  return {(const void*)k_spmm<16, 64>, 16, 1024};
+  if (spmm_group(M) == 8) return {(const void*)k_spmm<8, 32>, 8, 32, 1792};
+  return {(const void*)k_spmm<16, 64>, 16, 64, 1024};
+}
+static std::vector<SpmmShape> spmm_candidates(const rfmls_csr* M, int /*num_cus*/) {
+  std::vector<SpmmShape> c;
+  c.push_back(spmm_shape(M));
+  if (spmm_group(M) == 8) {
+    c.push_back({(const void*)k_spmm<8, 64>, 8, 64, 1792});
+    c.push_back({(const void*)k_spmm<8, 128>, 8, 128, 1792});
+    c.push_back({(const void*)k_spmm<8, 16>, 8, 16, 1792});
+  } else {
+    c.push_back({(const void*)k_spmm<16, 32>, 16, 32, 1024});
+    c.push_back({(const void*)k_spmm<16, 128>, 16, 128, 1024});
+  }
+  return c;
 }
 // Split row groups of a matrix with fewer than 4 groups per compute unit and
 // long rows (at least 8 windows per split) so that the grid covers the chip:
@@ -782,7 +804,6 @@ int spmm_split(const rfmls_csr* M, int num_cus) {
   while (k > 1 && win / k < 8) --k;
   return (int)k;
 }
-
 struct BCtx {
   rfmls_handle* h;
   const rfmls_csr* A;
@@ -844,10 +865,99 @@ rfmls_status tri_block(BCtx& c, int trans, const double* in, double* out, double
   return RFMLS_OK;
 }
 
+// The tuned launch shape of products with M on this handle, if a matrix of M's
+// shape (rows, columns, stored entries) has been tuned: a rebuilt transpose
+// (same matrix at a new address) is not tuned again.
+static bool spmm_lookup(rfmls_handle* h, const rfmls_csr* M, SpmmShape* out) {
+  if (!h->tune) return false;
+  for (const TuneRec& t : h->tuned)
+    if (t.rows == M->m && t.cols == M->n && t.nnz == M->nnz && !strcmp(t.kernel, "spmm")) {
+      const std::vector<SpmmShape> cands = spmm_candidates(M, h->num_cus);
+      if (t.choice >= 0 && t.choice < (int)cands.size()) {
+        *out = cands[t.choice];
+        return true;
+      }
+    }
+  return false;
+}
+
+static rfmls_status spmm_launch(BCtx& c, const rfmls_csr* M, const SpmmShape& sh, const double* x, double sA,
+                                double hcoef, const double* coef, const double* prev, double* out, double* sq,
+                                const BlockState* stp, int* nblk);
+
+// Autotuner of the SpMM launch shape (window width) for M: the first time a
+// matrix of M's shape is used on this handle (with tuning on), every candidate of
+// spmm_candidates runs on M with a zero input block of 32 columns into
+// scratch (xin: M->n x 32, out: M->m x 32, sq: the partials), once to warm up
+// and then three times between HIP events; the candidate with the smallest
+// median is kept for M on this handle.  Synchronises the stream; never called
+// while a graph is being captured.
+static rfmls_status spmm_tune(BCtx& c, const rfmls_csr* M, double* xin, double* out, double* sq) {
+  rfmls_handle* h = c.h;
+  SpmmShape dummy;
+  if (!h->tune || M->m < 1 || spmm_lookup(h, M, &dummy)) return RFMLS_OK;
+  const std::vector<SpmmShape> cands = spmm_candidates(M, h->num_cus);
+  hipLaunchKernelGGL(k_blk_fill, dim3(grid_for(M->n * kBlk)), dim3(kThreads), 0, c.st, xin, M->n * kBlk, 0.0);
+  hipEvent_t ev[4];
+  for (auto& e : ev) RFMLS_HIP(h, hipEventCreate(&e));
+  std::vector<double> med(cands.size(), 0.0);
+  rfmls_status st = RFMLS_OK;
+  const bool trace = h->trace;
+  h->trace = false;  // the trial launches are not part of any traced step
+  for (size_t k = 0; k < cands.size() && st >= 0; ++k) {
+    float t[3];
+    st = spmm_launch(c, M, cands[k], xin, 1.0, 0.0, nullptr, nullptr, out, sq, nullptr, nullptr);
+    for (int r = 0; r < 3 && st >= 0; ++r) {
+      hipEventRecord(ev[0], c.st);
+      st = spmm_launch(c, M, cands[k], xin, 1.0, 0.0, nullptr, nullptr, out, sq, nullptr, nullptr);
+      hipEventRecord(ev[1], c.st);
+      if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t[r], ev[0], ev[1]) != hipSuccess)
+        st = fail(h, RFMLS_E_HIP, "SpMM autotuner: event timing failed");
+    }
+    if (st >= 0) {
+      std::sort(t, t + 3);
+      med[k] = t[1];
+    }
+  }
+  h->trace = trace;
+  for (auto& e : ev) hipEventDestroy(e);
+  if (st < 0) return st;
+  size_t best = 0;
+  for (size_t k = 1; k < cands.size(); ++k)
+    if (med[k] < med[best]) best = k;
+  TuneRec rec{};
+  snprintf(rec.kernel, sizeof(rec.kernel), "spmm");
+  rec.rows = M->m;
+  rec.cols = M->n;
+  rec.nnz = M->nnz;
+  rec.choice = (int)best;
+  snprintf(rec.desc, sizeof(rec.desc), "group %d window %d grid %u", cands[best].group, cands[best].win,
+           cands[best].max_blocks);
+  rec.ms_best = med[best];
+  rec.ms_default = med[0];
+  rec.candidates = (int)cands.size();
+  h->tuned.push_back(rec);
+  return RFMLS_OK;
+}
+
+// Tunes the products with A and A^T (before any capture of the loop).
+static rfmls_status spmm_tune_both(BCtx& c) {
+  RFMLS_CHECK(spmm_tune(c, c.A, c.Z, c.T, c.sqA));
+  if (c.AT != c.A) RFMLS_CHECK(spmm_tune(c, c.AT, c.T, c.Sn, c.sqA));
+  return RFMLS_OK;
+}
+
 rfmls_status spmm(BCtx& c, const rfmls_csr* M, const double* x, double sA, double hcoef,
                   const double* coef, const double* prev, double* out, double* sq,
                   const BlockState* stp, int* nblk) {
-  const SpmmShape sh = spmm_shape(M);
+  SpmmShape sh;
+  if (!spmm_lookup(c.h, M, &sh)) sh = spmm_shape(M);
+  return spmm_launch(c, M, sh, x, sA, hcoef, coef, prev, out, sq, stp, nblk);
+}
+
+static rfmls_status spmm_launch(BCtx& c, const rfmls_csr* M, const SpmmShape& sh, const double* x, double sA,
+                                double hcoef, const double* coef, const double* prev, double* out, double* sq,
+                                const BlockState* stp, int* nblk) {
   const int64_t ng = (M->m + sh.group - 1) / sh.group;
   const int nsplit = spmm_split(M, c.h->num_cus);
   const int64_t work = ng * nsplit;
@@ -1054,6 +1164,7 @@ rfmls_status run_solve_block(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   const int64_t itmax = o->itmax > 0 ? o->itmax : n;
   BCtx c;
   RFMLS_CHECK(make_bctx(h, A, AT, P, c));
+  RFMLS_CHECK(spmm_tune_both(c));
   IterGraph graph;  // one capture serves every sweep and column block (same buffers)
   if (o->graph) c.graph = &graph;
   const unsigned gm = grid_for(m * kBlk), gn = grid_for(n * kBlk);
@@ -1151,6 +1262,7 @@ rfmls_status run_backward_block(rfmls_handle* h, const rfmls_csr* A, const rfmls
   const int64_t itmax = o->itmax > 0 ? o->itmax : m;
   BCtx c;
   RFMLS_CHECK(make_bctx(h, A, AT, P, c));
+  RFMLS_CHECK(spmm_tune_both(c));
   IterGraph graph;
   if (o->graph) c.graph = &graph;
   // roles: un (n), vm (m), vt, wt, zz shadows (n), tmp (n), lam (m), gathered blocks
@@ -1257,6 +1369,7 @@ rfmls_status run_form_B(rfmls_handle* h, const rfmls_csr* A, const rfmls_precond
   const int64_t m = A->m, n = A->n;
   BCtx c;
   RFMLS_CHECK(make_bctx(h, A, A, P, c));
+  RFMLS_CHECK(spmm_tune_both(c));
   const unsigned gn = grid_for(n * kBlk), gm = grid_for(m * kBlk);
   for (int64_t c0 = 0; c0 < n; c0 += kBlk) {
     const int nb = (int)(n - c0 < kBlk ? n - c0 : kBlk);

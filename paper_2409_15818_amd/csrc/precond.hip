@@ -86,6 +86,55 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
   }
 }
 
+// Column-relative pivots rho_j = |r_jj| / ||R[:, j]|| (||R[:, j]|| = ||SA[:, j]||):
+// the distance of column j of SA from the span of the columns before it,
+// relative to its length.  A block takes 64 columns; its four wavefronts sum
+// every fourth row (a row's 64 loads are coalesced), the four partial sums are
+// added in a fixed order; per-block minima into part[blockIdx.x].
+__global__ void __launch_bounds__(256) k_col_rho(const double* __restrict__ R, int64_t n,
+                                                 double* __restrict__ part) {
+  __shared__ double ssum[4][64];
+  __shared__ double smin[64];
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  double ss = 0.0;
+  if (j < n)
+    for (int64_t i = q; i <= j; i += 4) {
+      const double v = R[i * n + j];
+      ss += v * v;
+    }
+  ssum[q][c] = ss;
+  __syncthreads();
+  if (q == 0) {
+    double rho = INFINITY;
+    if (j < n) {
+      const double t = (ssum[0][c] + ssum[1][c]) + (ssum[2][c] + ssum[3][c]);
+      rho = t > 0.0 ? fabs(R[j * n + j]) / sqrt(t) : 0.0;
+    }
+    smin[c] = rho;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mn = INFINITY;
+    for (int k = 0; k < 64; ++k) mn = fmin(mn, smin[k]);
+    part[blockIdx.x] = mn;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_min_partials(const double* __restrict__ part, int np,
+                                                      double* __restrict__ out) {
+  __shared__ double smin[256];
+  double mn = INFINITY;
+  for (int i = threadIdx.x; i < np; i += 256) mn = fmin(mn, part[i]);
+  smin[threadIdx.x] = mn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = smin[0];
+}
+
 // Block row I of X = R^{-1} (rows [o, o + b), o = 64 I), columns j in [o, n).
 // Every column j >= o of the block row is written, so the diagonal block's
 // lower triangle gets the exact zeros back substitution leaves there (0 / r_ii
@@ -312,20 +361,39 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
 
 // Shared tail of rfmls_precond / rfmls_precond_import_R: R (normalised,
 // float64 row-major n x n) is in P->Rdense.
-rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit) {
+rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit,
+                            int check_precision) {
   const int64_t n = P->n;
+  const unsigned ncb = ceil_div(n, 64);
   void* p_stats;
-  RFMLS_CHECK(workspace(h, WS_MISC, 64, &p_stats));
-  hipLaunchKernelGGL(k_diag_stats, dim3(1), dim3(256), 0, h->stream, P->Rdense, n,
-                     (double*)p_stats);
-  double stats[3] = {0, 0, 0};
+  RFMLS_CHECK(workspace(h, WS_MISC, sizeof(double) * (8 + (size_t)ncb), &p_stats));
+  double* dstats = (double*)p_stats;
+  hipLaunchKernelGGL(k_diag_stats, dim3(1), dim3(256), 0, h->stream, P->Rdense, n, dstats);
+  hipLaunchKernelGGL(k_col_rho, dim3(ncb), dim3(256), 0, h->stream, (const double*)P->Rdense, n, dstats + 8);
+  hipLaunchKernelGGL(k_min_partials, dim3(1), dim3(256), 0, h->stream, (const double*)(dstats + 8), (int)ncb,
+                     dstats + 3);
+  double stats[4] = {0, 0, 0, 0};
   RFMLS_HIP(h, hipMemcpyAsync(stats, p_stats, sizeof(stats), hipMemcpyDeviceToHost, h->stream));
   RFMLS_HIP(h, hipStreamSynchronize(h->stream));
   if (stats[2] > 0 || stats[0] == 0.0)
     return fail(h, RFMLS_E_RANK, "R has a zero or non-finite diagonal entry");
+  P->pivot_ratio = stats[0] / stats[1];
+  P->rho_min = stats[3];
   if (check_rank && stats[0] <= 16.0 * unit * stats[1])
     return fail(h, RFMLS_E_RANK, "R numerically singular: min|r_ii| = %.3e <= 16 u max|r_ii| = %.3e",
                 stats[0], 16.0 * unit * stats[1]);
+  // A factor computed or stored in float32 whose column-relative pivot is
+  // within 16 u32 (the margin of the float64 rank test above) carries only
+  // rounding noise in that direction: the float32 QR's backward error, or the
+  // rounding of R or R^{-1} to float32, is a few u32 relative per column.  It
+  // then does not precondition that direction, and LSQR on A R^{-1} stalls or
+  // slows down severalfold.
+  const double tol32 = 16.0 * 5.960464477539063e-08;
+  if (check_precision && stats[3] <= tol32)
+    return fail(h, RFMLS_E_PRECISION,
+                "a float32 factor cannot precondition this system: min_j |r_jj| / ||SA[:, j]|| = %.3e is within "
+                "16 u32 = %.3e (columns numerically dependent in float32); factor and store in float64",
+                stats[3], tol32);
   void* p_x;
   void* p_w;
   RFMLS_CHECK(workspace(h, WS_TRSM, sizeof(double) * (size_t)n * (size_t)n, &p_x));
@@ -439,7 +507,7 @@ rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, co
                        P->Rdense);
   RFMLS_HIP(h, hipGetLastError());
   const double unit = qr_dt == RFMLS_F64 ? 1.1102230246251565e-16 : 5.960464477539063e-08;
-  return finish_precond(h, P, check_rank, unit);
+  return finish_precond(h, P, check_rank, unit, qr_dt == RFMLS_F32 || store == RFMLS_F32);
 }
 
 }  // namespace rfmls

@@ -46,14 +46,15 @@ def test_default_opts_without_device(lib):
     o = _lib.rfmls_opts()
     lib.rfmls_default_opts(C.byref(o))
     assert o.atol == 1e-10 and o.btol == 1e-10 and o.itmax == 0 and o.refine >= 0
-    assert o.check_every >= 1 and o.lockstep == 1
+    assert o.check_every >= 1 and o.lockstep == 1 and o.graph == 1 and o.reserved == 0
 
 
 def test_struct_layout_matches_header(tmp_path):
     from paper_2409_15818_amd import _lib
 
     structs = {"rfmls_csr": _lib.rfmls_csr, "rfmls_opts": _lib.rfmls_opts,
-               "rfmls_info": _lib.rfmls_info, "rfmls_trace_entry": _lib.rfmls_trace_entry}
+               "rfmls_info": _lib.rfmls_info, "rfmls_trace_entry": _lib.rfmls_trace_entry,
+               "rfmls_tune_entry": _lib.rfmls_tune_entry}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')

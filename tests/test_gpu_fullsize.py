@@ -194,3 +194,33 @@ def test_fullsize_32_rhs_lockstep_and_backward(handle):
     assert abs(nl - gg["norm_lambda"]) <= 1e-2 * gg["norm_lambda"]
     assert atl <= max(3.0 * gg["at_lambda_relres"], 1e-3)
     del res
+
+
+# The mixed-precision form of the 8x8-box system (float32 QR of SA, R stored in
+# float32) cannot reach the tolerance: 1,460 of its 12,800 columns lie within
+# 1e-8 of the span of the columns before them (float64 factor: min_j
+# |r_jj| / ||SA[:, j]|| = 9.4e-12), which a float32 QR resolves only to its
+# rounding level (rho_min 2.1e-8 for LAPACK's, 1.6e-7 for this library's, both
+# within 16 u32); the oracle's float32 form stalls at relative residual 8.8e-4
+# after 2,500 iterations.  The library refuses it with RFMLS_E_PRECISION; the
+# 3D system's float32 factor (rho_min 5.4e-6) passes.
+@pytest.mark.parametrize("qd,rd", [("f32", "f32"), ("f64", "f32")])
+def test_fullsize_float32_factor_refused_on_8x8(handle, qd, rd):
+    S, s, A = _system("poisson2d_8x8")
+    print(f"[fullsize] 8x8 float32 factor refusal {qd}/{rd}", flush=True)
+    SA, _, _, _ = R.rfmls_sketch(handle, A, s, SEED, dtype=qd)
+    with pytest.raises(R.RfmlsError) as e:
+        R.rfmls_precond(handle, SA, qd, rd)
+    assert e.value.status == -6
+    del SA
+
+
+def test_fullsize_float32_factor_accepted_on_4x4x4(handle):
+    S, s, A = _system("poisson3d_4x4x4")
+    SA, _, _, _ = R.rfmls_sketch(handle, A, s, SEED, dtype="f32")
+    P = R.rfmls_precond(handle, SA, "f32", "f32")
+    st = R.rfmls_precond_stats(P)
+    print(f"[fullsize] 4x4x4 float32 factor {st}", flush=True)
+    assert st["rho_min"] > 16 * 2.0 ** -24
+    P.free()
+    del SA

@@ -216,3 +216,68 @@ def test_dense_and_iterative_gradients_match_long_double_on_rfm_2x2():
     dA_ld = backward.pattern_grad(S.row_ptr, S.col, r_ld, w_ld, lam_ld, x_ld)
     dA = backward.pattern_grad(S.row_ptr, S.col, r, w2, lam2, x)
     assert float(np.linalg.norm(dA - dA_ld) / np.linalg.norm(dA_ld)) < 1e-8
+
+
+# ---------------------------------------------------------------- float32 factor check
+def _near_dependent(delta, seed=3):
+    A = dense_with_condition(600, 40, 1e2, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    A[:, 7] = A[:, 3] + delta * np.linalg.norm(A[:, 3]) * rng.standard_normal(600) / np.sqrt(600)
+    return A, rng.standard_normal(600)
+
+
+def test_rho_min_is_the_distance_of_a_column_from_the_span_before_it():
+    # rho_j = |r_jj| / ||SA[:, j]|| is the sine of the angle between column j
+    # and the span of the columns before it: check it against a least-squares
+    # projection computed independently
+    A, _ = _near_dependent(1e-6)
+    R = qr.r_factor(A)
+    for j in (3, 7, 20):
+        coef = np.linalg.lstsq(A[:, :j], A[:, j], rcond=None)[0]
+        dist = np.linalg.norm(A[:, j] - A[:, :j] @ coef) / np.linalg.norm(A[:, j])
+        assert abs(abs(R[j, j]) / np.linalg.norm(R[:, j]) - dist) <= 1e-9 * dist
+    assert abs(qr.rho_min(R) - 1e-6) <= 0.2e-6
+
+
+def test_float32_factor_refused_where_it_cannot_precondition():
+    # a column within 1e-11 of an earlier one: the float32 QR leaves only
+    # rounding noise in that direction (its rho_min falls to the noise floor),
+    # the check refuses it, and without the check LSQR on A R32^{-1} ends far
+    # from the optimum that the float64 factor reaches
+    A, b = _near_dependent(1e-11)
+    m, n = A.shape
+    rp, col, val = csr_from_dense(A, keep_zeros=True)
+    with pytest.raises(qr.PrecisionInsufficient):
+        pipeline.precondition(rp, col, val, m, n, 4 * n, 5, qr_dtype="f32")
+    with pytest.raises(qr.PrecisionInsufficient):
+        pipeline.precondition(rp, col, val, m, n, 4 * n, 5, qr_dtype="f64", r_store="f32")
+    R64 = pipeline.precondition(rp, col, val, m, n, 4 * n, 5)["R"]
+    R32 = pipeline.precondition(rp, col, val, m, n, 4 * n, 5, qr_dtype="f32", check_precision=False)["R"]
+    # float64 resolves the true distance; float32's value is noise, far from it
+    assert abs(qr.rho_min(R64) - 1e-11) <= 0.2e-11
+    r32 = qr.rho_min(R32)
+    assert r32 <= qr.PRECISION_TOL and not 0.1 < r32 / 1e-11 < 10.0
+    rstar = np.linalg.norm(b - A @ np.linalg.lstsq(A, b, rcond=None)[0])
+    errs = {}
+    for name, R in (("f64", R64), ("f32", R32)):
+        x, _ = pipeline.lsqr_on_preconditioned(sp.csr_matrix(A), R, b, itmax=200)
+        errs[name] = abs(np.linalg.norm(b - A @ x) - rstar) / rstar
+    assert errs["f64"] <= 1e-7 and errs["f32"] >= 1e-6
+
+
+def test_float32_factor_on_rfm_3x3_accepted_and_4x4_refused():
+    # 3x3-box RFM system: the float32 factor's rho_min (4.3e-6) clears 16 u32
+    # and the float32 form reaches the float64 optimum.  4x4-box system: its
+    # rho_min (1.0e-7 in float32, 9.7e-8 in float64) is within 16 u32, so it is
+    # refused; the float32 form there still converges, but needs about three
+    # times the iterations of the float64 one (measured on the GPU: 187 vs 56)
+    S, s = build_config("poisson2d_3x3")
+    o64 = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1)
+    o32 = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, 2, refine=1, qr_dtype="f32",
+                         r_store="f32")
+    assert qr.rho_min(o32["R"]) > qr.PRECISION_TOL
+    assert o32["istop"] in (1, 2)
+    assert abs(o32["normr"] - o64["normr"]) <= 1e-10 * o64["normr"]
+    S, s = build_config("poisson2d_4x4")
+    with pytest.raises(qr.PrecisionInsufficient):
+        pipeline.precondition(S.row_ptr, S.col, S.val, S.m, S.n, s, 2, qr_dtype="f32", r_store="f32")
