@@ -317,6 +317,18 @@ rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfm
                                   int64_t nrhs, double *dB, int64_t lddb, double *dAval,
                                   const rfmls_opts *opts, rfmls_info *info);
 
+/* ---- Panel factorisation of the float64 QR ----
+ * mode 0 (default): 64-column panels of at least 1024 rows are factored by
+ * CholeskyQR2 on column-scaled Gram matrices followed by the reconstruction of
+ * their Householder vectors (a fixed number of passes over the panel instead
+ * of one grid-wide exchange per column); a panel whose first Cholesky pivot
+ * ratio falls below 1e-7 is factored by the unblocked Householder kernel.
+ * mode 1: the unblocked Householder kernel for every panel.  Modes 2 and 3 force
+ * the first, respectively second, Cholesky pass of every eligible panel to
+ * fail, so that the fallback paths can be tested.  Both ways R satisfies
+ * R^T R = (SA)^T SA to rounding; the float32 QR always uses the unblocked kernel. */
+rfmls_status rfmls_qr_panel_mode(rfmls_handle *h, int mode);
+
 /* ---- Autotuning of launch shapes ----
  * With tuning on (the default), the first lockstep solve, backward pass or
  * rfmls_form_B that uses a matrix of a given shape (rows, columns, stored

@@ -134,6 +134,12 @@ class Precond:
             pass
 
 
+def rfmls_qr_panel_mode(h: Handle, mode: int):
+    """0: CholeskyQR2 panels where eligible (default); 1: unblocked Householder panels;
+    2 / 3: CholeskyQR2 with its first / second pass forced to fail (fallback tests)."""
+    h.check(h._lib.rfmls_qr_panel_mode(h._h, int(mode)))
+
+
 def rfmls_tune_enable(h: Handle, enable: bool = True):
     h.check(h._lib.rfmls_tune_enable(h._h, int(bool(enable))))
 

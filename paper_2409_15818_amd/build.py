@@ -18,7 +18,7 @@ INCLUDE = PKG.parent / "include"
 LIB = PKG / "librfmls.so"
 OBJDIR = PKG / "_build"
 
-SOURCES = ["api.hip", "sketch.hip", "csr.hip", "qr.hip", "precond.hip", "svd.hip", "lsqr.hip",
+SOURCES = ["api.hip", "sketch.hip", "csr.hip", "qr.hip", "cholqr.hip", "precond.hip", "svd.hip", "lsqr.hip",
            "lsqr_block.hip"]
 
 HIPCC_FLAGS = [

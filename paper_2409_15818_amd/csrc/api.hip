@@ -472,6 +472,12 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
   return run_backward(h, A, AT, P, X, ldx, Rres, ldr, G, ldg, nrhs, dB, lddb, dAval, o, info);
 }
 
+rfmls_status rfmls_qr_panel_mode(rfmls_handle* h, int mode) {
+  if (!h || mode < 0 || mode > 3) return RFMLS_E_ARG;
+  h->qr_panel = mode;
+  return RFMLS_OK;
+}
+
 rfmls_status rfmls_tune_enable(rfmls_handle* h, int enable) {
   if (!h) return RFMLS_E_ARG;
   h->tune = enable != 0;

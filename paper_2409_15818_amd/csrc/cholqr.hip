@@ -1,0 +1,694 @@
+// Panel factorisation of the blocked Householder QR (Alg. 1 step 3) by
+// CholeskyQR2 with Householder reconstruction, float64.
+//
+// The unblocked panel (k_qr_panel) needs one grid-wide exchange per column.
+// Here a 64-column panel P (M x 64, row-major, in place) takes three passes
+// over its rows and two single-block factorisations:
+//   1. k_cq_gram + k_cq_reduce: G = P^T P (partial Grams of 256-row slabs on
+//      the matrix cores, then a fixed-order sum);
+//   2. k_cq_factor (pass 1): column scaling D = diag(sqrt(G_jj)), Cholesky
+//      D^{-1} G D^{-1} = U1^T U1, R1 = U1 D and W1 = R1^{-1};
+//   3. k_cq_apply_gram + k_cq_reduce: P <- Q1 = P W1 fused with the Gram of Q1;
+//   4. k_cq_factor (pass 2): Cholesky of Q1's Gram = U2^T U2 (Q = Q1 U2^{-1},
+//      R = U2 R1), then the Householder reconstruction (Ballard, Demmel,
+//      Grigori, Jacquelin, Knight and Nguyen, "Reconstructing Householder
+//      vectors from tall-skinny QR", 2015) of Q's top 64 x 64 block: with
+//      S = diag(s_j), Q S - [I; 0] = Y (-T Y_1^T) is an LU factorisation
+//      without pivoting whose unit lower factor Y holds the Householder vectors
+//      of a QR of P and whose pivots give tau_j = -U_jj = 1 + |c_j|, s_j =
+//      -sign(c_j) chosen column by column from the current pivot c_j (so
+//      |U_jj| >= 1 and the elimination is stable); the QR's triangular factor
+//      is S R.  The panel's top block gets S R and Y_1;
+//   5. k_cq_apply: the rows below become Y_2 = Q1 (U2^{-1} S U^{-1}).
+// The panel is left exactly as the unblocked kernel leaves it: S R on and
+// above the diagonal, the vectors below it (unit diagonal implied), tau.
+//
+// CholeskyQR2 is accurate while the scaled panel's condition number stays
+// well below u^{-1/2} (its first pass squares it).  The sketches of the RFM
+// systems here have scaled panel conditions up to 3.2e6 (8x8-box system, all
+// 200 panels; unscaled up to 2e13).  A panel whose first Cholesky meets a
+// non-positive pivot or a pivot ratio below the caller's threshold is flagged
+// (status 1) and factored by the unblocked kernel instead, on the untouched
+// panel; a second Cholesky failure (status 2) leaves Q1 in the panel, which the
+// unblocked kernel then factors, its R multiplied by R1 afterwards
+// (k_cq_fix).  Every sum runs in a fixed order.
+#include "common.h"
+
+namespace rfmls {
+namespace {
+
+constexpr int kNb = 64;      // panel width
+constexpr int kSlab = 256;   // rows per partial Gram
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// status: 0 CholeskyQR2 used; 1 first Cholesky failed (panel untouched);
+// 2 second Cholesky failed (panel holds Q1, R1 in Rc)
+
+// Operand layout of v_mfma_f64_16x16x4f64 (D += A B, A 16 x 4, B 4 x 16): lane
+// l = 16 lk + lr holds A[lr][lk] and B[lk][lr]; accumulator register r holds
+// D[lk + 4 r][lr].
+
+// Partial Gram of rows [z kSlab, (z + 1) kSlab) of P on the matrix cores.  Wave
+// w takes the 64 rows starting at z kSlab + 64 w and accumulates the ten upper
+// 16 x 16 tiles of their Gram; each lane loads its operands straight from P
+// (lane (lr, lk) reads row 4 s + lk, columns 16 q + lr: every 16 lanes read
+// 128 contiguous bytes), no LDS staging.  The four waves' tiles are then added
+// in wave order through LDS and the full symmetric 64 x 64 partial written.
+__global__ void __launch_bounds__(256) k_cq_gram(const double* __restrict__ P, int64_t ld, int64_t M,
+                                                 double* __restrict__ Gpart, const int* __restrict__ status) {
+  if (status && *status) return;
+  __shared__ double S[kNb][kNb + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * kSlab + 64 * w;
+#pragma unroll
+  for (int grp = 0; grp < 4; ++grp) {
+    double x[4][4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t row = r0 + 16 * grp + 4 * s4 + lk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[s4][q] = row < M ? P[row * ld + 16 * q + lr] : 0.0;
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      int tile = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b, ++tile)
+          acc[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s4][a], x[s4][b], acc[tile], 0, 0, 0);
+    }
+  }
+  // tile (a, b): D[lk + 4 r][lr] = G[16 a + lk + 4 r][16 b + lr]
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      int tile = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b, ++tile)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double& g = S[16 * a + lk + 4 * r][16 * b + lr];
+            g = ww == 0 ? acc[tile][r] : g + acc[tile][r];
+          }
+    }
+    __syncthreads();
+  }
+  double* gp = Gpart + (int64_t)blockIdx.x * kNb * kNb;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    // upper tiles hold G[i][j] for tile(i) <= tile(j); the rest by symmetry
+    gp[e] = (i >> 4) <= (j >> 4) ? S[i][j] : S[j][i];
+  }
+}
+
+// G = sum of the nslab partials in slab order.  Block b takes entries
+// 16 b .. 16 b + 15; its 16 slices of threads sum every 16th partial, then the
+// 16 slice sums are added in order.  With reset, the panel's status is set to 0
+// (first pass: a new panel).
+__global__ void __launch_bounds__(256) k_cq_reduce(const double* __restrict__ Gpart, int nslab,
+                                                   double* __restrict__ G, int* __restrict__ status, int reset) {
+  if (!reset && *status) return;
+  __shared__ double red[16][17];
+  const int t = threadIdx.x;
+  const int el = t & 15, zq = t >> 4;
+  const int e = blockIdx.x * 16 + el;
+  double s = 0.0;
+  for (int z = zq; z < nslab; z += 16) s += Gpart[(int64_t)z * kNb * kNb + e];
+  red[zq][el] = s;
+  __syncthreads();
+  if (t < 16) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tot += red[q][t];
+    G[blockIdx.x * 16 + t] = tot;
+  }
+  if (reset && blockIdx.x == 0 && t == 0) *status = 0;
+}
+
+// ---------------------------------------------------------------------------
+// 64 x 64 factorisations in LDS by one block of 256 threads, blocked by 16:
+// the 16 x 16 diagonal blocks on one wavefront in registers (values passed by
+// v_readlane), every product of blocks on the matrix cores (lds_mm).
+// ---------------------------------------------------------------------------
+constexpr int kB = 16;
+constexpr int kLd = kNb + 1;  // LDS row stride of a 64 x 64 matrix
+typedef double Mat[kNb][kLd];
+typedef double Blk[kB][kB + 1];
+
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// D = alpha op(A) B + beta D for LDS operands (row strides lda, ldb, ldd), D
+// m x n, K the inner dimension, all multiples of 16 (K of 4); op(A) = A (m x K)
+// or, with ta, A^T (A stored K x m).  Wave w computes 16 x 16 tiles w, w + 4,
+// ... (at most 16 tiles) into registers; after a barrier they are written, so
+// D may overlap A or B.  Every thread of the block calls it.
+__device__ void lds_mm(double* D, int ldd, const double* A, int lda, bool ta, const double* B, int ldb, int m, int n,
+                       int K, double alpha, double beta) {
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tn = n / 16, nt = (m / 16) * tn;
+  const int astep = ta ? 4 * lda : 4;
+  v4d acc[4];
+  const double* ap[4];
+  const double* bp[4];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    acc[sl] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int tile = w + 4 * sl;
+    const int ti = tile / tn, tj = tile % tn;
+    ap[sl] = ta ? A + lk * lda + 16 * ti + lr : A + (16 * ti + lr) * lda + lk;
+    bp[sl] = B + lk * ldb + 16 * tj + lr;
+  }
+  // the four tiles' chains interleaved: their operand loads issue together
+#pragma unroll 2
+  for (int k4 = 0; k4 < K / 4; ++k4) {
+    double a[4], b[4];
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl)
+      if (w + 4 * sl < nt) {
+        a[sl] = ap[sl][k4 * astep];
+        b[sl] = bp[sl][k4 * 4 * ldb];
+      }
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl)
+      if (w + 4 * sl < nt) acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl], b[sl], acc[sl], 0, 0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int tile = w + 4 * sl;
+    if (tile < nt) {
+      const int ti = tile / tn, tj = tile % tn;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* d = D + (16 * ti + lk + 4 * r) * ldd + 16 * tj + lr;
+        *d = beta == 0.0 ? alpha * acc[sl][r] : fma(alpha, acc[sl][r], beta * *d);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Orders a wavefront's LDS writes before its later LDS reads (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky A = U^T U of the symmetric positive definite A (upper triangle
+// read), U written over A with its lower triangle set to zero; Z[kb] receives
+// the inverse of diagonal block kb.  Returns false (every thread) on a
+// non-positive or non-finite pivot; pmin / pmax: the extreme pivots u_kk.
+__device__ bool blk_cholesky(Mat& A, Blk* Z, double* pmin, double* pmax) {
+  __shared__ int bad;
+  __shared__ double ext[2];
+  __shared__ double urow[kB][kB + 1];
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  double mn = 1e300, mx = 0.0;
+  __syncthreads();
+  for (int kb = 0; kb < kNb / kB; ++kb) {
+    const int k0 = kb * kB;
+    if (t < 64) {
+      // diagonal block on wavefront 0, lane l < 16 holding its column l.  Step
+      // s: pivot by readlane, r_s = 1/sqrt(pivot), row s of U; the next row's
+      // entry (the next pivot's only dependence) by readlane, the rest of the
+      // row through LDS (uniform reads).
+      const int l = t;
+      const bool act = l < kB;
+      double d[kB], rr[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) d[i] = act ? A[k0 + i][k0 + l] : 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < kB; ++s2) {
+        const double piv = lane_bcast(d[s2], s2);
+        if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
+        const double r = rsqrt(piv > 0.0 ? piv : 1.0);
+        const double ukk = piv * r;
+        rr[s2] = r;
+        mn = fmin(mn, ukk);
+        mx = fmax(mx, ukk);
+        const double us = (l == s2) ? ukk : (l > s2 ? d[s2] * r : 0.0);
+        d[s2] = us;
+        if (s2 + 1 < kB) {
+          if (act) urow[s2][l] = us;
+          const double un = lane_bcast(us, s2 + 1);
+          d[s2 + 1] = fma(-un, us, d[s2 + 1]);
+          wave_sync();
+#pragma unroll
+          for (int i = s2 + 2; i < kB; ++i) d[i] = fma(-urow[s2][i], us, d[i]);
+        }
+      }
+      // column l of U11^{-1} by a column sweep: z_m = acc_m / u_mm, then
+      // acc_i -= u_im z_m for i < m
+      double acc[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) acc[i] = (i == l) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m2 = kB - 1; m2 >= 0; --m2) {
+        const double zm = (m2 <= l) ? acc[m2] * rr[m2] : 0.0;
+        acc[m2] = zm;
+#pragma unroll
+        for (int i = 0; i < m2; ++i) acc[i] = fma(-urow[i][m2], zm, acc[i]);
+      }
+      if (act)
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          A[k0 + i][k0 + l] = d[i];  // d[i] = 0 below the diagonal
+          Z[kb][i][l] = acc[i];
+        }
+    }
+    __syncthreads();
+    if (bad) break;  // uniform: read after the barrier
+    const int nc = kNb - k0 - kB;
+    if (nc > 0) {
+      // block row U12 = U11^{-T} A12, then A22 -= U12^T U12
+      lds_mm(&A[k0][k0 + kB], kLd, &Z[kb][0][0], kB + 1, true, &A[k0][k0 + kB], kLd, kB, nc, kB, 1.0, 0.0);
+      lds_mm(&A[k0 + kB][k0 + kB], kLd, &A[k0][k0 + kB], kLd, true, &A[k0][k0 + kB], kLd, nc, nc, kB, -1.0, 1.0);
+    }
+  }
+  if (t < 64) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mn = fmin(mn, __shfl_xor(mn, off, 64));
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+    }
+    if (t == 0) {
+      ext[0] = mn;
+      ext[1] = mx;
+    }
+  }
+  // lower triangle outside the diagonal blocks
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    if ((i >> 4) > (j >> 4)) A[i][j] = 0.0;
+  }
+  __syncthreads();
+  *pmin = ext[0];
+  *pmax = ext[1];
+  return !bad;
+}
+
+// Z[w] = inverse of diagonal block w of the upper triangular U, wavefront w
+// taking block w, lane l < 16 column l, by a column sweep with U's entries read
+// uniformly from LDS.
+__device__ void blk_diag_inverses(const Mat& U, Blk* Z) {
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63;
+  const int k0 = w * kB;
+  double rd[kB], acc[kB];
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    rd[i] = 1.0 / U[k0 + i][k0 + i];
+    acc[i] = (i == l) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int m2 = kB - 1; m2 >= 0; --m2) {
+    const double zm = (m2 <= l) ? acc[m2] * rd[m2] : 0.0;
+    acc[m2] = zm;
+#pragma unroll
+    for (int i = 0; i < m2; ++i) acc[i] = fma(-U[k0 + i][k0 + m2], zm, acc[i]);
+  }
+  if (l < kB)
+#pragma unroll
+    for (int i = 0; i < kB; ++i) Z[w][i][l] = acc[i];
+  __syncthreads();
+}
+
+// W = U^{-1} for the upper triangular U (zero below the diagonal; Z the
+// inverses of its diagonal blocks) by block back substitution from the bottom
+// block row up: W[k, >k] = -Z_k (U[k, >k] W[>k, >k]).  T is scratch.
+__device__ void blk_upper_inverse(const Mat& U, const Blk* Z, Mat& W, Mat& T) {
+  const int t = threadIdx.x;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    W[i][j] = (i >> 4) == (j >> 4) ? Z[i >> 4][i & 15][j & 15] : 0.0;
+  }
+  __syncthreads();
+  for (int kb = kNb / kB - 2; kb >= 0; --kb) {
+    const int k0 = kb * kB, nc = kNb - k0 - kB;
+    lds_mm(&T[0][0], kLd, &U[k0][k0 + kB], kLd, false, &W[k0 + kB][k0 + kB], kLd, kB, nc, nc, 1.0, 0.0);
+    lds_mm(&W[k0][k0 + kB], kLd, &Z[kb][0][0], kB + 1, false, &T[0][0], kLd, kB, nc, kB, -1.0, 0.0);
+  }
+}
+
+// LU without pivoting of Q1 S - I (Q1 the top 64 x 64 block of Q, in A) with
+// s_j = -sign(c_j) taken from the current pivot c_j: the identity and the
+// column signs only touch the pivots (u_jj = -|c_j| - 1) and the multipliers
+// (l_ij = s_j a_ij / u_jj), so the elimination runs on Q1 itself, blocked by 16
+// columns: the 64 x 16 panel on wavefront 0 (lane i holding row i), the block
+// row by forward substitution, the trailing block on the matrix cores.  On
+// return A holds the multipliers below the diagonal and U = (eliminated Q1
+// entries times s_c) above it, u_jj on it; sg holds s.
+__device__ void blk_recon_lu(Mat& A, double* sg) {
+  __shared__ double prow[kB];
+  const int t = threadIdx.x;
+  for (int kb = 0; kb < kNb / kB; ++kb) {
+    const int k0 = kb * kB;
+    if (t < 64) {
+      // lane i holds row i of the 64 x 16 panel; step j: the pivot by
+      // readlane, the pivot row's next entry by readlane, the rest of it through
+      // LDS (written by the pivot row's lane, read uniformly)
+      const int i = t;
+      double p[kB];
+#pragma unroll
+      for (int m = 0; m < kB; ++m) p[m] = A[i][k0 + m];
+#pragma unroll
+      for (int j = 0; j < kB; ++j) {
+        const int pr = k0 + j;
+        const double cj = lane_bcast(p[j], pr);
+        const double sj = cj >= 0.0 ? -1.0 : 1.0;
+        const double ujj = -fabs(cj) - 1.0;
+        const double fj = sj * (1.0 / ujj);
+        if (i == pr) {
+          sg[pr] = sj;
+          p[j] = ujj;
+#pragma unroll
+          for (int m = j + 2; m < kB; ++m) prow[m] = p[m];
+        }
+        const double lij = p[j] * fj;
+        if (i > pr) p[j] = lij;
+        if (j + 1 < kB) {
+          const double un = lane_bcast(p[j + 1], pr);
+          if (i > pr) p[j + 1] = fma(-lij, un, p[j + 1]);
+          wave_sync();
+#pragma unroll
+          for (int m = j + 2; m < kB; ++m)
+            if (i > pr) p[m] = fma(-lij, prow[m], p[m]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kB; ++m) A[i][k0 + m] = p[m];
+    }
+    __syncthreads();
+    const int nc = kNb - k0 - kB;
+    if (nc > 0) {
+      if (t < nc) {  // block row: unit lower forward substitution, a column per thread
+        const int c = k0 + kB + t;
+        double x[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          double acc = A[k0 + i][c];
+#pragma unroll
+          for (int m = 0; m < i; ++m) acc = fma(-A[k0 + i][k0 + m], x[m], acc);
+          x[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < kB; ++i) A[k0 + i][c] = x[i];
+      }
+      __syncthreads();
+      lds_mm(&A[k0 + kB][k0 + kB], kLd, &A[k0 + kB][k0], kLd, false, &A[k0][k0 + kB], kLd, nc, nc, kB, -1.0, 1.0);
+    }
+  }
+  // the column signs on U's off-diagonal entries (the diagonal holds u_jj)
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, c = e % kNb;
+    if (i < c) A[i][c] *= sg[c];
+  }
+  __syncthreads();
+}
+
+// One Cholesky step of CholeskyQR2 on the reduced Gram G.
+// pass 1 (column-scaled Gram D^{-1} G D^{-1} = U^T U): R1 = U D into Rc and
+//   Wk = R1^{-1} = D^{-1} U^{-1} (the operand of the fused apply + Gram).
+// pass 2 (Gram of Q1 = U2^T U2): R = U2 R1 into the panel's top block as S R,
+//   and the Householder reconstruction of Q = Q1 U2^{-1}: its top block
+//   Q1top U2^{-1} is factored by blk_recon_lu, the multipliers go below the
+//   diagonal of the panel's top block, tau_j = -u_jj, and
+//   Wk = U2^{-1} S U^{-1}, with which the rows below become the Householder
+//   vectors L2 = Q1bot U2^{-1} S U^{-1}.
+// A pivot ratio u_min / u_max below min_pivot_ratio (or a non-positive pivot)
+// sets *status = pass and leaves everything else untouched.
+__global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G, double* __restrict__ Wk,
+                                                   double* __restrict__ Rc, double* __restrict__ P, int64_t ld,
+                                                   double* __restrict__ tau, int* __restrict__ status, int pass,
+                                                   double min_pivot_ratio) {
+  if (pass == 2 && *status) return;
+  __shared__ Mat M0, M1, M2, M3;
+  __shared__ Blk Z[kNb / kB];
+  __shared__ double dsc[kNb];
+  __shared__ double sg[kNb];
+  __shared__ int bad0;
+  const int t = threadIdx.x;
+  if (t < kNb) {
+    const double gjj = G[t * kNb + t];
+    dsc[t] = pass == 1 ? sqrt(gjj > 0.0 ? gjj : 0.0) : 1.0;
+  }
+  if (t == 0) bad0 = 0;
+  __syncthreads();
+  if (t < kNb && !(dsc[t] > 0.0)) bad0 = 1;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    const double di = dsc[i], dj = dsc[j];
+    M0[i][j] = (di > 0.0 && dj > 0.0) ? G[e] * (1.0 / di) * (1.0 / dj) : 0.0;
+  }
+  __syncthreads();
+  double pmin = 0.0, pmax = 0.0;
+  const bool ok = !bad0 && blk_cholesky(M0, Z, &pmin, &pmax);
+  if (!ok || !(pmin >= min_pivot_ratio * pmax)) {
+    if (t == 0) *status = pass;
+    return;
+  }
+  blk_upper_inverse(M0, Z, M1, M2);  // M1 = U^{-1}
+  if (pass == 1) {
+    for (int e = t; e < kNb * kNb; e += 256) {
+      const int i = e / kNb, j = e % kNb;
+      Wk[e] = M1[i][j] * (1.0 / dsc[i]);
+      Rc[e] = M0[i][j] * dsc[j];
+    }
+    return;
+  }
+  // pass 2: M3 = R = U2 R1; M0 = Q1top U2^{-1}
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    M2[i][j] = Rc[e];
+  }
+  __syncthreads();
+  lds_mm(&M3[0][0], kLd, &M0[0][0], kLd, false, &M2[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    M2[i][j] = P[(int64_t)i * ld + j];
+  }
+  __syncthreads();
+  lds_mm(&M0[0][0], kLd, &M2[0][0], kLd, false, &M1[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
+  blk_recon_lu(M0, sg);
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, c = e % kNb;
+    P[(int64_t)i * ld + c] = i <= c ? sg[i] * M3[i][c] : M0[i][c];
+  }
+  if (t < kNb) tau[t] = -M0[t][t];
+  __syncthreads();
+  for (int e = t; e < kNb * kNb; e += 256) {  // U alone (zero below the diagonal)
+    const int i = e / kNb, c = e % kNb;
+    if (i > c) M0[i][c] = 0.0;
+  }
+  __syncthreads();
+  blk_diag_inverses(M0, Z);
+  blk_upper_inverse(M0, Z, M2, M3);  // M2 = U^{-1}
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, c = e % kNb;
+    M2[i][c] *= sg[i];
+  }
+  __syncthreads();
+  lds_mm(&M3[0][0], kLd, &M1[0][0], kLd, false, &M2[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
+  for (int e = t; e < kNb * kNb; e += 256) Wk[e] = M3[e / kNb][e % kNb];
+}
+
+// Rows [r_begin, M) of P <- P W (W 64 x 64) on the matrix cores, in place:
+// wave w of a block takes 16 rows, reads all 64 of their columns (A operands,
+// in registers) before it writes them.  Runs when *status == 0.
+__global__ void __launch_bounds__(256) k_cq_apply(double* __restrict__ P, int64_t ld, int64_t r_begin, int64_t M,
+                                                  const double* __restrict__ W, const int* __restrict__ status) {
+  if (*status) return;
+  __shared__ double Ws[kNb][kNb + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int e = t; e < kNb * kNb; e += 256) Ws[e / kNb][e % kNb] = W[e];
+  const int64_t rbase = r_begin + (int64_t)blockIdx.x * 64 + 16 * w;
+  const int64_t ra = rbase + lr;
+  double a[16];
+#pragma unroll
+  for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? P[ra * ld + 4 * s4 + lk] : 0.0;
+  __syncthreads();
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < 16; ++s4) {
+    const int kk = 4 * s4 + lk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = rbase + lk + 4 * r;
+    if (row < M)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = acc[q][r];
+  }
+}
+
+// First pass's apply fused with the second pass's Gram: rows
+// [z kSlab, (z + 1) kSlab) of P <- P W (matrix cores, in place) and the
+// partial Gram of the new rows.  Wave w takes four groups of 16 rows from
+// z kSlab + 64 w; a group's product tiles (D[lk + 4 r][16 q + lr] in register
+// r of tile q) are already the Gram's operands for K-step r.  The waves' Gram
+// tiles are added in wave order through LDS.  Runs when *status == 0.
+__global__ void __launch_bounds__(256) k_cq_apply_gram(double* __restrict__ P, int64_t ld, int64_t M,
+                                                       const double* __restrict__ W, double* __restrict__ Gpart,
+                                                       const int* __restrict__ status) {
+  if (*status) return;
+  __shared__ double Ws[kNb][kNb + 1];
+  __shared__ double S[kNb][kNb + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int e = t; e < kNb * kNb; e += 256) Ws[e / kNb][e % kNb] = W[e];
+  __syncthreads();
+  v4d gacc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) gacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int grp = 0; grp < 4; ++grp) {
+    const int64_t rbase = (int64_t)blockIdx.x * kSlab + 64 * w + 16 * grp;
+    const int64_t ra = rbase + lr;
+    double a[16];
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? P[ra * ld + 4 * s4 + lk] : 0.0;
+    v4d acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const int kk = 4 * s4 + lk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rbase + lk + 4 * r;
+      if (row < M)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = acc[q][r];
+    }
+    // rows past M hold exact zeros (zero operands) and add nothing
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int tile = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < 4; ++a2)
+#pragma unroll
+        for (int b = a2; b < 4; ++b, ++tile)
+          gacc[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[a2][r], acc[b][r], gacc[tile], 0, 0, 0);
+    }
+  }
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      int tile = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < 4; ++a2)
+#pragma unroll
+        for (int b = a2; b < 4; ++b, ++tile)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double& g = S[16 * a2 + lk + 4 * r][16 * b + lr];
+            g = ww == 0 ? gacc[tile][r] : g + gacc[tile][r];
+          }
+    }
+    __syncthreads();
+  }
+  double* gp = Gpart + (int64_t)blockIdx.x * kNb * kNb;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    gp[e] = (i >> 4) <= (j >> 4) ? S[i][j] : S[j][i];
+  }
+}
+
+// After the unblocked kernel factored Q1 (status 2): its R' times R1 (upper
+// triangular products, terms in order), written back into the panel's top rows.
+__global__ void __launch_bounds__(256) k_cq_fix(double* __restrict__ P, int64_t ld, const double* __restrict__ Rc,
+                                                const int* __restrict__ status) {
+  if (*status != 2) return;
+  __shared__ double A[kNb][kNb + 1];
+  __shared__ double B[kNb][kNb + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int r = e / kNb, c = e % kNb;
+    A[r][c] = c >= r ? P[(int64_t)r * ld + c] : 0.0;
+    B[r][c] = Rc[e];
+  }
+  __syncthreads();
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int r = e / kNb, c = e % kNb;
+    if (c < r) continue;
+    double sacc = 0.0;
+    for (int k = r; k <= c; ++k) sacc = fma(A[r][k], B[k][c], sacc);
+    P[(int64_t)r * ld + c] = sacc;
+  }
+}
+
+}  // namespace
+
+int64_t cholqr_workspace_doubles(int64_t M) {
+  const int64_t nslab = (M + kSlab - 1) / kSlab;
+  return nslab * kNb * kNb + 3 * kNb * kNb + 64;
+}
+
+// Enqueues CholeskyQR2 and the reconstruction on the 64-column panel P
+// (M >= 64 rows); ws holds cholqr_workspace_doubles(M) doubles.  A pass whose
+// Cholesky pivot ratio falls below min_ratio1 (first pass) or min_ratio2
+// (second) sets the status.  The caller then launches the unblocked kernel
+// gated on *status != 0, and cholqr_fix.
+rfmls_status run_cholqr_panel(rfmls_handle* h, double* P, int64_t ld, int64_t M, double* tau, double* ws,
+                              int* status, double min_ratio1, double min_ratio2) {
+  hipStream_t st = h->stream;
+  const int64_t nslab = (M + kSlab - 1) / kSlab;
+  double* Gpart = ws;
+  double* G = Gpart + nslab * kNb * kNb;
+  double* Wk = G + kNb * kNb;
+  double* Rc = Wk + kNb * kNb;
+  hipLaunchKernelGGL(k_cq_gram, dim3((unsigned)nslab), dim3(256), 0, st, (const double*)P, ld, M, Gpart,
+                     (const int*)nullptr);
+  hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
+                     1);
+  hipLaunchKernelGGL(k_cq_factor, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 1,
+                     min_ratio1);
+  hipLaunchKernelGGL(k_cq_apply_gram, dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M, (const double*)Wk, Gpart,
+                     (const int*)status);
+  hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
+                     0);
+  hipLaunchKernelGGL(k_cq_factor, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 2,
+                     min_ratio2);
+  if (M > kNb)
+    hipLaunchKernelGGL(k_cq_apply, dim3((unsigned)((M - kNb + 63) / 64)), dim3(256), 0, st, P, ld, (int64_t)kNb, M,
+                       (const double*)Wk, (const int*)status);
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+// Status 2 only: the panel's R (from the unblocked kernel, on Q1) times R1.
+rfmls_status cholqr_fix(rfmls_handle* h, double* P, int64_t ld, int64_t M, const double* ws, const int* status) {
+  const int64_t nslab = (M + kSlab - 1) / kSlab;
+  const double* Rc = ws + nslab * kNb * kNb + 2 * kNb * kNb;
+  hipLaunchKernelGGL(k_cq_fix, dim3(1), dim3(256), 0, h->stream, P, ld, Rc, status);
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+}  // namespace rfmls

@@ -61,6 +61,9 @@ struct rfmls_handle {
   size_t pinned_bytes = 0;
   hipStream_t cap_stream = nullptr; // stream that graphs are captured on (created on first use)
   int tune = 1;                     // autotune launch shapes on first use (rfmls_tune_enable)
+  int qr_panel = 0;                 // rfmls_qr_panel_mode: 0 CholeskyQR2 panels where eligible,
+                                    // 1 unblocked Householder panels only, 2/3 CholeskyQR2 with its
+                                    // first / second pass forced to fail (tests of the fallback)
   std::vector<rfmls::TuneRec> tuned;
 };
 
@@ -163,6 +166,7 @@ enum WsSlot {
   WS_SVD2,
   WS_APPLYQ,
   WS_MISC,
+  WS_CHOLQR,
   WS_NUM_SLOTS
 };
 
@@ -269,6 +273,11 @@ rfmls_status capture_graph(rfmls_handle* h, IterGraph* g, F&& body) {
 
 // Launch entry points implemented in the individual .hip files -----------------
 namespace rfmls {
+// CholeskyQR2 panel with Householder reconstruction (cholqr.hip), float64
+int64_t cholqr_workspace_doubles(int64_t M);
+rfmls_status run_cholqr_panel(rfmls_handle* h, double* P, int64_t ld, int64_t M, double* tau, double* ws,
+                              int* status, double min_ratio1, double min_ratio2);
+rfmls_status cholqr_fix(rfmls_handle* h, double* P, int64_t ld, int64_t M, const double* ws, const int* status);
 rfmls_status launch_hash_sign(rfmls_handle* h, int64_t m, int64_t s, uint64_t seed, int32_t* hash,
                               int8_t* sign);
 rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const int32_t* hash,

@@ -21,6 +21,8 @@
 //   T_o from the Gram: diagonal 64-blocks are the panels' T, off-diagonal
 //   blocks T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
 // All reductions run in a fixed order, so the factorisation is deterministic.
+#include <type_traits>
+
 #include "common.h"
 #include "gemm.h"
 
@@ -28,6 +30,11 @@ namespace rfmls {
 namespace {
 
 constexpr int kMaxNb = 64;
+// CholeskyQR2 panels: at least this many rows (shorter panels are cheap for
+// the unblocked kernel), and the first Cholesky's pivot ratio below which a
+// panel falls back to it (scaled panel condition near u^{-1/2})
+constexpr int64_t kCholqrMinRows = 1024;
+constexpr double kCholqrMinPivot = 1e-7;
 
 // Cross-block exchange of the panel kernel.  Every value crosses blocks in a
 // "low-latency" slot: the float64 travels as two 64-bit words (its low or high
@@ -134,8 +141,11 @@ __host__ __device__ constexpr int64_t ll_words(int64_t G) { return 2 * (2 * kMax
 template <typename T, int Q>
 __global__ void __launch_bounds__(kPanelThreads)
     k_qr_panel(T* __restrict__ P, int64_t ld, int64_t M, int nb, int rpw, T* __restrict__ tau,
-               uint64_t* __restrict__ ll, int* __restrict__ err, unsigned tag0) {
+               uint64_t* __restrict__ ll, int* __restrict__ err, unsigned tag0, const int* __restrict__ run_if) {
   static_assert(kPanelGroups * Q >= kMaxNb, "block 0 must hold the panel's top rows");
+  // gated launch (after a CholeskyQR2 attempt): every block reads the same
+  // flag and leaves before any exchange when the panel is already factored
+  if (run_if && *run_if == 0) return;
   __shared__ double red[2 * kMaxNb];               // totals, then the pivot row
   __shared__ double grp[kPanelGroups][kMaxNb];     // per-wavefront partials
   __shared__ double part[kPanelGroups][kMaxNb];    // partial sums of the totals
@@ -557,6 +567,17 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)npad, &p_wp));
   RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * kOuter * kOuter, &p_to));
   RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
+  // CholeskyQR2 panels (float64; rfmls_qr_panel_mode): workspace for the
+  // largest panel and one status word after it
+  double* cq_ws = nullptr;
+  int* cq_status = nullptr;
+  if (std::is_same<T, double>::value && h->qr_panel != 1 && s >= kCholqrMinRows) {
+    const int64_t nd = cholqr_workspace_doubles(s);
+    void* p_cq;
+    RFMLS_CHECK(workspace(h, WS_CHOLQR, sizeof(double) * (size_t)(nd + 8), &p_cq));
+    cq_ws = (double*)p_cq;
+    cq_status = (int*)(cq_ws + nd);
+  }
   T* tau = (T*)p_tau;
   T* Wz = (T*)p_wz;
   T* W = (T*)p_w;
@@ -584,15 +605,30 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
       uint64_t* ll = (uint64_t*)p_part;
       int rpw_i = (int)rpw;
       unsigned tag0 = (unsigned)p0;
+      const int* run_if = nullptr;
+      // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel
+      // read and written once (the method's work, whichever way it is factored)
+      const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
+      if (cq_ws) {
+        // float64 64-column panels: CholeskyQR2 + reconstruction; the
+        // unblocked kernel below then runs only for a panel it flagged
+        if (jb == kMaxNb && M >= kCholqrMinRows) {
+          Trace tr(h, "qr_panel_cq", 2.0 * sizeof(T) * (double)M * jb, pf);
+          const double thr1 = h->qr_panel == 2 ? 2.0 : kCholqrMinPivot;
+          const double thr2 = h->qr_panel == 3 ? 2.0 : kCholqrMinPivot;
+          RFMLS_CHECK(run_cholqr_panel(h, (double*)P, ld, M, (double*)tau_p, cq_ws, cq_status, thr1, thr2));
+          run_if = cq_status;
+        }
+      }
       void* args[] = {(void*)&P,     (void*)&ld,    (void*)&M,  (void*)&jb,           (void*)&rpw_i,
-                      (void*)&tau_p, (void*)&ll,    (void*)&h->dev_flags, (void*)&tag0};
+                      (void*)&tau_p, (void*)&ll,    (void*)&h->dev_flags, (void*)&tag0, (void*)&run_if};
       const void* fn = sh.fn;
       {
-        // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel read and written once
-        const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
-        Trace tr(h, "qr_panel", 2.0 * sizeof(T) * (double)M * jb, pf);
+        Trace tr(h, run_if ? "qr_panel_fallback" : "qr_panel", run_if ? 0.0 : 2.0 * sizeof(T) * (double)M * jb,
+                 run_if ? 0.0 : pf);
         RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
       }
+      if (run_if) RFMLS_CHECK(cholqr_fix(h, (double*)P, ld, M, cq_ws, cq_status));
       const int64_t rem = k0 + bw - (p0 + jb);
       if (rem <= 0) continue;
       const int64_t ncols = jb + rem;

@@ -1,0 +1,105 @@
+"""The CholeskyQR2 panels of the float64 QR (with Householder reconstruction)
+against the unblocked Householder panels and the oracle.
+
+Mode 0 (default) factors 64-column panels of at least 1024 rows by CholeskyQR2
+on column-scaled Grams and reconstructs their Householder vectors; mode 1 uses
+the unblocked kernel throughout.  Both must satisfy R^T R = (SA)^T SA to a few
+n u, agree with each other and with the oracle's R to the sensitivity of R
+(about cond(SA) u), and give the same solve.  Modes 2 and 3 force the first or
+second Cholesky pass of every eligible panel to fail: the first fallback leaves
+the panel untouched for the unblocked kernel (bitwise mode 1's R), the second
+factors Q1 and multiplies by R1."""
+
+import numpy as np
+import pytest
+
+from oracle import countsketch, pipeline, qr as oqr
+from rfmgen import build_config, dense_with_condition
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2409_15818_amd")
+
+SEED = 2
+
+
+def _R(handle, SAo, mode):
+    R.rfmls_qr_panel_mode(handle, mode)
+    try:
+        SA = torch.tensor(SAo, device="cuda")
+        P = R.rfmls_precond(handle, SA, "f64", "f64")
+        Rg = R.rfmls_precond_export_R(handle, P).cpu().numpy()
+        P.free()
+    finally:
+        R.rfmls_qr_panel_mode(handle, 0)
+    return Rg
+
+
+def _ident(Rg, SAo):
+    return np.linalg.norm(Rg.T @ Rg - SAo.T @ SAo) / np.linalg.norm(SAo) ** 2
+
+
+def _cases():
+    rng = np.random.default_rng(3)
+    yield "gaussian 4096x64", rng.standard_normal((4096, 64)), 1e-12
+    yield "gaussian 6000x200", rng.standard_normal((6000, 200)), 1e-12
+    # ill-conditioned with columns of very different lengths (scaled panels)
+    A = dense_with_condition(5000, 192, 1e6, seed=4) * np.geomspace(1.0, 1e5, 192)[None, :]
+    yield "kappa 1e6, column scales 1e5", A, 1e-9
+    for name in ("poisson2d_3x3", "poisson2d_4x4"):
+        S, s = build_config(name)
+        h, sign = countsketch.hash_sign(S.m, s, SEED)
+        SAo, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+        yield name, SAo, 1e-6
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])
+def test_cholqr_panels_match_householder_panels(handle, case):
+    label, SAo, rtol = case
+    n = SAo.shape[1]
+    print(f"[cholqr] {label} {SAo.shape}", flush=True)
+    R0 = _R(handle, SAo, 0)
+    R1 = _R(handle, SAo, 1)
+    u = 1.1e-16
+    assert np.all(np.diag(R0) > 0) and not np.tril(R0, -1).any()
+    e0, e1 = _ident(R0, SAo), _ident(R1, SAo)
+    print(f"[cholqr] {label}: identity cholqr {e0:.2e} householder {e1:.2e}", flush=True)
+    assert e0 < 20 * n * u and e1 < 20 * n * u
+    # elementwise, relative to each row's scale: R is determined to about cond * u
+    Ro = oqr.r_factor(SAo, check_rank=False)
+    scale = np.abs(Ro).max(axis=1, keepdims=True)
+    d01 = (np.abs(R0 - R1) / scale).max()
+    d0o = (np.abs(R0 - Ro) / scale).max()
+    print(f"[cholqr] {label}: |R_cq - R_hh| {d01:.2e}, |R_cq - R_oracle| {d0o:.2e}", flush=True)
+    assert d01 < rtol and d0o < rtol
+
+
+def test_cholqr_fallback_paths(handle):
+    SAo = dense_with_condition(3000, 128, 1e4, seed=7) * np.geomspace(1.0, 1e3, 128)[None, :]
+    R1 = _R(handle, SAo, 1)
+    R2 = _R(handle, SAo, 2)  # first pass fails: the unblocked kernel on the untouched panels
+    R3 = _R(handle, SAo, 3)  # second pass fails: the unblocked kernel on Q1, then R' R1
+    assert np.array_equal(R2, R1)
+    assert _ident(R3, SAo) < 20 * 128 * 1.1e-16
+    scale = np.abs(R1).max(axis=1, keepdims=True)
+    assert (np.abs(R3 - R1) / scale).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["poisson2d_3x3", "poisson2d_4x4"])
+def test_solve_with_cholqr_panels_matches_oracle(handle, name):
+    S, s = build_config(name)
+    A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
+    b = torch.tensor(S.b[0], device="cuda")
+    out = {}
+    for mode in (0, 1):
+        R.rfmls_qr_panel_mode(handle, mode)
+        try:
+            res = R.csqrp_lsqr(handle, A, b, s, SEED, opts=R.default_opts(refine=1))
+        finally:
+            R.rfmls_qr_panel_mode(handle, 0)
+        out[mode] = res.info[0]
+    orc = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, SEED, refine=1)
+    for mode in (0, 1):
+        assert abs(out[mode]["normr"] - orc["normr"]) <= 1e-10 * orc["normr"]
+    assert abs(out[0]["itn_first"] - orc["itn_sweeps"][0]) <= 2
