@@ -204,6 +204,8 @@ def main():
                     help="sample: the oracle on a bounded sample (about 10-30 s), extrapolated; "
                          "full: the whole oracle solve, measured (minutes)")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--qr-lookahead", type=int, default=0, choices=[0, 1],
+                    help="1: next outer block's QR panels beside the trailing update (float64)")
     ap.add_argument("--backward", action="store_true",
                     help="also time the backward pass (gradients w.r.t. b and A's values) of "
                          "L = 1/2 sum_k ||E x_k - u_k||^2 at 10^4 sample points")
@@ -242,6 +244,7 @@ def main():
     A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
     b = torch.tensor(S.b[0] if args.nrhs == 1 else S.b, device="cuda")
     h = R.Handle()
+    R.rfmls_qr_lookahead(h, bool(args.qr_lookahead))
     opts = R.default_opts(refine=args.refine, lockstep=args.lockstep, itmax=args.itmax)
     qd, rd = {"f64": ("f64", "f64"), "f32": ("f32", "f32"), "f64f32": ("f64", "f32")}[args.precision]
 
@@ -421,7 +424,8 @@ def main():
         "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": S.nnz, "s": s,
                    "precision": args.precision, "refine": args.refine, "itmax": args.itmax, "atol": opts.atol, "btol": opts.btol,
                    "nrhs": args.nrhs, "lockstep": bool(args.lockstep and args.nrhs > 1),
-                   "start": args.start, "operator": args.operator, "precond": args.precond},
+                   "start": args.start, "operator": args.operator, "precond": args.precond,
+                   "qr_lookahead": bool(args.qr_lookahead)},
         "svd": None if args.precond != "svd" else {"rank": P.rank, "sweeps": P.sweeps, "last_off": P.off},
         "phases_ms": {k: round(v, 3) for k, v in ph.items()},
         "iterations": {"total": int(info[0]["itn"]), "first_sweep": int(info[0]["itn_first"]),

@@ -329,6 +329,20 @@ rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfm
  * R^T R = (SA)^T SA to rounding; the float32 QR always uses the unblocked kernel. */
 rfmls_status rfmls_qr_panel_mode(rfmls_handle *h, int mode);
 
+/* ---- Look-ahead in the blocked QR (Alg. 1 step 3) ----
+ * enable != 0: once an outer block's panels are factored, the trailing update
+ * first covers only the next outer block's columns; that block's panels then
+ * run on a second stream of the handle (default priority, created on first
+ * use) while the handle's stream updates the remaining columns.  The factors
+ * are bitwise those of the plain schedule.  Only float64 QRs in panel mode 0
+ * use it, and only for outer blocks whose panels are all CholeskyQR2-eligible;
+ * everything else keeps the plain schedule.  A panel that CholeskyQR2 declines
+ * is then factored by the unblocked kernel beside the trailing update, whose
+ * grid-wide exchange needs all of its workgroups resident: a bounded wait turns
+ * a failure to co-schedule into an error status (RFMLS_E_HIP), never a hang.
+ * Default off.  Errors: RFMLS_E_ARG for a null handle. */
+rfmls_status rfmls_qr_lookahead(rfmls_handle *h, int enable);
+
 /* ---- Autotuning of launch shapes ----
  * With tuning on (the default), the first lockstep solve, backward pass or
  * rfmls_form_B that uses a matrix of a given shape (rows, columns, stored

@@ -30,7 +30,7 @@ EXPORTED = [
     "rfmls_precond_svd", "rfmls_precond_svd_stats", "rfmls_precond_export_P", "rfmls_precond_export_sigma",
     "rfmls_solve", "rfmls_form_B", "rfmls_solve_explicit", "rfmls_solve_backward",
     "rfmls_trace_enable", "rfmls_trace_read", "rfmls_solve_noalloc", "rfmls_noalloc_scratch_bytes", "rfmls_precond_stats",
-    "rfmls_tune_enable", "rfmls_tune_read", "rfmls_qr_panel_mode",
+    "rfmls_tune_enable", "rfmls_tune_read", "rfmls_qr_panel_mode", "rfmls_qr_lookahead",
 ]
 
 
@@ -119,6 +119,7 @@ def load():
     lib.rfmls_solve_backward.argtypes = [vp, P(rfmls_csr), P(rfmls_csr), vp, vp, i64, vp, i64, vp,
                                          i64, i64, vp, i64, vp, P(rfmls_opts), P(rfmls_info)]
     lib.rfmls_qr_panel_mode.argtypes = [vp, C.c_int]
+    lib.rfmls_qr_lookahead.argtypes = [vp, C.c_int]
     lib.rfmls_tune_enable.argtypes = [vp, C.c_int]
     lib.rfmls_tune_read.argtypes = [vp, P(rfmls_tune_entry), C.c_int, P(C.c_int)]
     lib.rfmls_trace_enable.argtypes = [vp, C.c_int]

@@ -140,6 +140,11 @@ def rfmls_qr_panel_mode(h: Handle, mode: int):
     h.check(h._lib.rfmls_qr_panel_mode(h._h, int(mode)))
 
 
+def rfmls_qr_lookahead(h: Handle, enable: bool):
+    """Run the next outer block's QR panels beside the trailing update (float64 CholeskyQR2 panels)."""
+    h.check(h._lib.rfmls_qr_lookahead(h._h, int(bool(enable))))
+
+
 def rfmls_tune_enable(h: Handle, enable: bool = True):
     h.check(h._lib.rfmls_tune_enable(h._h, int(bool(enable))))
 

@@ -130,6 +130,9 @@ rfmls_status rfmls_destroy(rfmls_handle* h) {
   }
   for (auto e : h->event_pool) hipEventDestroy(e);
   if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  if (h->la_stream) hipStreamDestroy(h->la_stream);
+  for (hipEvent_t e : h->la_event)
+    if (e) hipEventDestroy(e);
   for (auto& w : h->ws)
     if (w.ptr) hipFree(w.ptr);
   if (h->barrier) hipFree(h->barrier);
@@ -475,6 +478,12 @@ rfmls_status rfmls_solve_backward(rfmls_handle* h, const rfmls_csr* A, const rfm
 rfmls_status rfmls_qr_panel_mode(rfmls_handle* h, int mode) {
   if (!h || mode < 0 || mode > 3) return RFMLS_E_ARG;
   h->qr_panel = mode;
+  return RFMLS_OK;
+}
+
+rfmls_status rfmls_qr_lookahead(rfmls_handle* h, int enable) {
+  if (!h) return RFMLS_E_ARG;
+  h->qr_lookahead = enable != 0;
   return RFMLS_OK;
 }
 

@@ -64,6 +64,9 @@ struct rfmls_handle {
   int qr_panel = 0;                 // rfmls_qr_panel_mode: 0 CholeskyQR2 panels where eligible,
                                     // 1 unblocked Householder panels only, 2/3 CholeskyQR2 with its
                                     // first / second pass forced to fail (tests of the fallback)
+  int qr_lookahead = 0;             // rfmls_qr_lookahead: next outer block's panels beside the trailing update
+  hipStream_t la_stream = nullptr;  // their stream (created on first use) and its two events
+  hipEvent_t la_event[2] = {nullptr, nullptr};
   std::vector<rfmls::TuneRec> tuned;
 };
 
@@ -152,6 +155,7 @@ enum WsSlot {
   WS_QR_T,
   WS_QR_WR,
   WS_QR_Y,
+  WS_QR_INNER,
   WS_TRSM,
   WS_LSQR_VEC,
   WS_LSQR_SCAL,

@@ -541,32 +541,299 @@ GemmArgs<T> v_update(T* P, int64_t ld, int64_t M, int64_t vcols, int64_t ncols, 
   return g;
 }
 
+// Buffers of one outer block's panels: tau and the diagonal 64-blocks of T_o
+// (written by the panels), and the inner products' slices, Gram and T^T W.
+template <typename T>
+struct PanelBufs {
+  T* tau;
+  T* To;
+  T* Wz;
+  T* W;
+  T* Wp;
+};
+
+// The inner panels of the outer block [k0, k0 + bw) of SA, each factored and
+// applied to the rest of the block, on h->stream; tau_out (if given) receives
+// the block's tau.
+template <typename T>
+rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw, int64_t kOuter, T* SA, int64_t ld,
+                             const PanelBufs<T>& pb, uint64_t* ll, double* cq_ws, int* cq_status, T* tau_out) {
+  hipStream_t st = h->stream;
+  const int64_t split_in = 512;
+  for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
+    const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
+    const int64_t M = s - p0;
+    PanelShape sh;
+    int64_t G = 0;
+    RFMLS_CHECK(pick_panel_shape<T>(h, M, &sh, &G));
+    const int64_t rpw = sh.rpw();
+    T* P = SA + p0 * ld + p0;
+    T* tau_p = pb.tau + (p0 - k0);
+    int rpw_i = (int)rpw;
+    unsigned tag0 = (unsigned)p0;
+    const int* run_if = nullptr;
+    // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel
+    // read and written once (the method's work, whichever way it is factored)
+    const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
+    if (cq_ws && jb == kMaxNb && M >= kCholqrMinRows) {
+      // float64 64-column panels: CholeskyQR2 + reconstruction; the unblocked
+      // kernel below then runs only for a panel it flagged
+      Trace tr(h, "qr_panel_cq", 2.0 * sizeof(T) * (double)M * jb, pf);
+      const double thr1 = h->qr_panel == 2 ? 2.0 : kCholqrMinPivot;
+      const double thr2 = h->qr_panel == 3 ? 2.0 : kCholqrMinPivot;
+      RFMLS_CHECK(run_cholqr_panel(h, (double*)P, ld, M, (double*)tau_p, cq_ws, cq_status, thr1, thr2));
+      run_if = cq_status;
+    }
+    void* args[] = {(void*)&P,     (void*)&ld, (void*)&M,            (void*)&jb,   (void*)&rpw_i,
+                    (void*)&tau_p, (void*)&ll, (void*)&h->dev_flags, (void*)&tag0, (void*)&run_if};
+    const void* fn = sh.fn;
+    {
+      Trace tr(h, run_if ? "qr_panel_fallback" : "qr_panel", run_if ? 0.0 : 2.0 * sizeof(T) * (double)M * jb,
+               run_if ? 0.0 : pf);
+      RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
+    }
+    if (run_if) RFMLS_CHECK(cholqr_fix(h, (double*)P, ld, M, cq_ws, cq_status));
+    const int64_t rem = k0 + bw - (p0 + jb);
+    if (rem <= 0) continue;
+    const int64_t ncols = jb + rem;
+    const int64_t ldw = pad32(ncols), ldwp = pad32(rem);
+    const int64_t nsp = (M + split_in - 1) / split_in;
+    {
+      Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
+               2.0 * (double)jb * ncols * M);
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, pb.Wz, ldw, split_in), st)));
+      hipLaunchKernelGGL(k_sum_slices_narrow<T>, dim3(ceil_div(jb * ldw, 64)), dim3(256), 0, st, (const T*)pb.Wz,
+                         (int64_t)jb * ldw, (int)nsp, (int64_t)jb * ldw, pb.W);
+    }
+    {
+      Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
+      // this panel's T is also a diagonal block of the outer block's T_o
+      T* Tq = pb.To + (p0 - k0) * kOuter + (p0 - k0);
+      hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jb + 15) / 16), dim3(1024), 0, st, (const T*)pb.W, (int64_t)0, 1, ldw,
+                         jb, (const T*)tau_p, Tq, (int64_t)kOuter);
+      hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 32)), dim3(256), 0, st, (const T*)pb.W, ldw, jb,
+                         (const T*)Tq, (int64_t)kOuter, rem, pb.Wp, ldwp);
+    }
+    {
+      Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
+               2.0 * (double)M * rem * jb);
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerUpdate>(v_update<T>(P, ld, M, jb, rem, pb.Wp, ldwp), st)));
+    }
+    RFMLS_HIP(h, hipGetLastError());
+  }
+  // every reflector's tau, for a caller that applies Q afterwards
+  if (tau_out)
+    RFMLS_HIP(h, hipMemcpyAsync(tau_out + k0, pb.tau, sizeof(T) * (size_t)bw, hipMemcpyDeviceToDevice, st));
+  return RFMLS_OK;
+}
+
+// Buffers of the trailing update: the outer products' slices, W = V^T [.],
+// W' = T_o^T W, and the scratch of T_o's block columns.
+template <typename T>
+struct TrailBufs {
+  T* Wz;
+  T* W;
+  T* Wp;
+  T* Y;
+};
+
+// Trailing update C <- C - V T_o^T (V^T C) with the outer block [k0, k0 + bw)
+// (V below its diagonal in SA) for the nc columns starting off columns right
+// of the block (nc_m of them the method's own, the rest tile padding within
+// the room).  With gram, off must be 0: the product then also covers V itself,
+// and T_o is built from that Gram (its diagonal 64-blocks from the panels,
+// except the last panel's); without, T_o must already hold the block's T.
+template <typename T>
+rfmls_status qr_block_trailing(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw, int64_t kOuter, T* SA, int64_t ld,
+                               int64_t off, int64_t nc, int64_t nc_m, bool gram, const T* tau, T* To,
+                               const TrailBufs<T>& tb) {
+  hipStream_t st = h->stream;
+  const int64_t split_out = 4096;
+  const int64_t M0 = s - k0;
+  T* P0 = SA + k0 * ld + k0;
+  const int64_t vc = gram ? bw : 0;  // V's own columns in the product
+  const int64_t ncols = vc + nc, ncols_m = vc + nc_m;
+  const int64_t ldw = pad32(ncols), ldwp = pad32(nc);
+  T* Bc = P0 + bw + off;  // first product column when V is not included
+  // V^T [V | C] (or V^T C) in row slices summed in order: rows [0, bw) hold the
+  // triangle of V (masked, general kernel); the rows below are clear of every
+  // mask, so a whole number of 16-row chunks of them goes to the clean-only
+  // kernel in split_out-row slices, and a tail of fewer than 16 rows (if any) to the
+  // general kernel without masks
+  const int64_t Kc = (M0 - bw) / 16 * 16, Kt = M0 - bw - Kc;
+  const int64_t nsc = (Kc + split_out - 1) / split_out;
+  const int64_t nsp = 1 + nsc + (Kt > 0 ? 1 : 0);
+  const int64_t zs = bw * ldw;
+  auto product = [&](int64_t r0, int64_t rows, T* out, int64_t ksplit) {
+    GemmArgs<T> g = vt_gemm<T>(P0 + r0 * ld, ld, rows, bw, ncols, out, ldw, ksplit);
+    if (!gram) {
+      g.B = Bc + r0 * ld;
+      g.b_vcols = 0;
+    }
+    return g;
+  };
+  {
+    Trace tr(h, gram ? "qr_gemm_VtC" : "qr_gemm_VtC_rest",
+             sizeof(T) * ((double)M0 * ncols_m + 2.0 * (double)nsp * bw * ncols_m), 2.0 * (double)bw * ncols_m * M0);
+    {
+      // op(A) = V^T of the top rows is upper triangular (the mask zeroes the
+      // rest): each row tile starts its K range at its own first row
+      GemmArgs<T> gt = product(0, bw, tb.Wz, 0);
+      gt.a_upper = 1;
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gt, st)));
+    }
+    if (Kc > 0) {
+      GemmArgs<T> gc = product(bw, Kc, tb.Wz + zs, split_out);
+      gc.a_vmask = 0;
+      gc.b_vcols = 0;
+      // the kOuter / 64 row tiles of a B strip run together (56 -> 59 TFLOP/s,
+      // float64, 256-column blocks) on one XCD (then 481 -> 469 ms on the
+      // 4^3-box float64 solve's 512-column blocks, equal at 256)
+      gc.tile_order = 3;
+      RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrVtC>(gc, st)));
+    }
+    if (Kt > 0) {
+      GemmArgs<T> gr = product(bw + Kc, Kt, tb.Wz + (1 + nsc) * zs, 0);
+      gr.a_vmask = 0;
+      gr.b_vcols = 0;
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gr, st)));
+    }
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ldw, 256) < 4096 ? ceil_div(bw * ldw, 256) : 4096),
+                       dim3(256), 0, st, (const T*)tb.Wz, bw * ldw, (int)nsp, zs, tb.W);
+  }
+  if (gram) {
+    // T_o: its diagonal 64-blocks are the inner panels' T, written by the
+    // panels, except the last panel's (no inner update follows it), built here
+    // from the Gram's diagonal block; then the block columns
+    Trace tr(h, "qr_outer_T", sizeof(T) * 4.0 * (double)bw * bw, 2.0 * (double)bw * bw * bw);
+    {
+      const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
+      const int jq = (int)(bw - q0);
+      hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jq + 15) / 16), dim3(1024), 0, st, (const T*)(tb.W + q0 * ldw + q0),
+                         (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0, (int64_t)kOuter);
+    }
+    for (int64_t q0 = kMaxNb; q0 < bw; q0 += kMaxNb) {
+      const int64_t jq = bw - q0 < kMaxNb ? bw - q0 : kMaxNb;
+      GemmArgs<T> ga;  // Y = T_o[:q0, :q0] * Gram[:q0, q0:q0+jq]
+      ga.M = q0;
+      ga.N = jq;
+      ga.K = q0;
+      ga.A = To;
+      ga.lda = kOuter;
+      ga.a_upper = 1;
+      ga.B = tb.W + q0;
+      ga.ldb = ldw;
+      ga.C = tb.Y;
+      ga.ldc = jq;
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(ga, st)));
+      GemmArgs<T> gb;  // T_o[:q0, q0:q0+jq] = -Y * T_qq
+      gb.M = q0;
+      gb.N = jq;
+      gb.K = jq;
+      gb.A = tb.Y;
+      gb.lda = jq;
+      gb.B = To + q0 * kOuter + q0;
+      gb.ldb = kOuter;
+      gb.b_upper = 1;
+      gb.C = To + q0;
+      gb.ldc = kOuter;
+      gb.alpha = T(-1);
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gb, st)));
+    }
+  }
+  {
+    // W' = T_o^T W[:, C's columns]  (T_o^T lower triangular)
+    Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * nc_m, (double)bw * bw * nc_m);
+    GemmArgs<T> gt;
+    gt.M = bw;
+    gt.N = nc;
+    gt.K = bw;
+    gt.A = To;
+    gt.lda = kOuter;
+    gt.transA = 1;
+    gt.a_lower = 1;
+    gt.B = tb.W + vc;
+    gt.ldb = ldw;
+    gt.C = tb.Wp;
+    gt.ldc = ldwp;
+    RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
+  }
+  {
+    Trace tr(h, gram ? "qr_gemm_update" : "qr_gemm_update_rest",
+             sizeof(T) * (2.0 * (double)M0 * nc_m + (double)M0 * bw + (double)bw * nc_m), 2.0 * (double)M0 * nc_m * bw);
+    // rows [0, bw) meet the triangle of V (masked, general kernel); the rows
+    // below are clear of it and take the clean-only kernel
+    {
+      // V's top rows are lower triangular (the mask zeroes the rest): each
+      // row tile ends its K range at its own last row
+      GemmArgs<T> gt = v_update<T>(P0, ld, bw, bw, nc, tb.Wp, ldwp);
+      gt.C = P0 + bw + off;
+      gt.a_lower = 1;
+      RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(gt, st)));
+    }
+    if (M0 > bw) {
+      GemmArgs<T> gu = v_update<T>(P0 + bw * ld, ld, M0 - bw, bw, nc, tb.Wp, ldwp);
+      gu.C = P0 + bw * ld + bw + off;
+      gu.a_vmask = 0;
+      gu.tile_order = 2;  // bands of 32 tile rows: 53.8 -> 56.5 TFLOP/s (float64, 51200 x 12800)
+      RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrTrailingUpdate>(gu, st)));
+    }
+  }
+  RFMLS_HIP(h, hipGetLastError());
+  return RFMLS_OK;
+}
+
+// Second stream and its two events for the look-ahead (created on first use).
+rfmls_status lookahead_stream(rfmls_handle* h) {
+  if (h->la_stream) return RFMLS_OK;
+  if (hipStreamCreateWithFlags(&h->la_stream, hipStreamNonBlocking) != hipSuccess) {
+    h->la_stream = nullptr;
+    return fail(h, RFMLS_E_HIP, "QR look-ahead: could not create its stream");
+  }
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&h->la_event[i], hipEventDisableTiming) != hipSuccess)
+      return fail(h, RFMLS_E_HIP, "QR look-ahead: could not create its events");
+  return RFMLS_OK;
+}
+
 // n_room >= n columns of SA may be written: the big trailing products round
 // their column count up to the tile width inside that room (full tiles, no
 // ragged edge); the extra columns only ever hold values nothing reads.
+//
+// Look-ahead (rfmls_qr_lookahead, float64 CholeskyQR2 panels only): after the
+// panels of outer block k, the trailing update first covers only block k + 1's
+// columns; block k + 1's panels then run on a second stream while the main
+// stream updates the remaining columns, and the main stream waits for them
+// before block k + 1's own trailing update.  The split is by columns, every
+// column's sums run in the same order, and the two streams touch disjoint
+// columns and buffers (T_o and tau alternate between two copies, the panels
+// have their own product buffers), so the factors are bitwise the same.
 template <typename T>
 rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld, T* tau_out) {
   const int64_t kOuter = outer_width<T>(n);
-  hipStream_t st = h->stream;
   const int64_t split_in = 512, split_out = 4096;
   const int64_t nsp_in_max = (s + split_in - 1) / split_in;
   // slices of the outer V^T [V | C]: the masked top rows, the clean 4096-row
   // slices (2% faster than 8192 rows on the 8x8-box sketch, net of the longer
   // slice sum) and a ragged tail
   const int64_t nsp_out_max = (s + split_out - 1) / split_out + 2;
-  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y;
-  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * kOuterMax, &p_tau));
+  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y, *p_in;
+  RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * 2 * kOuterMax, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
   // rows of the products W, W' are padded to 32 elements (128-byte aligned
   // rows for every column count)
   const int64_t npad = pad32(n_room);
-  const size_t wz_in = (size_t)nsp_in_max * kMaxNb * kOuter;
   const size_t wz_out = (size_t)nsp_out_max * kOuter * (size_t)npad;
-  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * (wz_in > wz_out ? wz_in : wz_out), &p_wz));
+  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(T) * wz_out, &p_wz));
   RFMLS_CHECK(workspace(h, WS_QR_WR, sizeof(T) * kOuter * (size_t)npad, &p_w));
   RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)npad, &p_wp));
-  RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * kOuter * kOuter, &p_to));
+  RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * 2 * kOuter * kOuter, &p_to));
   RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
+  // the panels' own product buffers: slices, Gram and T^T W of at most
+  // 64 x kOuter each
+  const int64_t kop = pad32(kOuter);
+  const size_t in_wz = (size_t)nsp_in_max * kMaxNb * kop, in_w = (size_t)kMaxNb * kop;
+  RFMLS_CHECK(workspace(h, WS_QR_INNER, sizeof(T) * (in_wz + 2 * in_w), &p_in));
   // CholeskyQR2 panels (float64; rfmls_qr_panel_mode): workspace for the
   // largest panel and one status word after it
   double* cq_ws = nullptr;
@@ -578,216 +845,60 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     cq_ws = (double*)p_cq;
     cq_status = (int*)(cq_ws + nd);
   }
-  T* tau = (T*)p_tau;
-  T* Wz = (T*)p_wz;
-  T* W = (T*)p_w;
-  T* Wp = (T*)p_wp;
-  T* To = (T*)p_to;
-  T* Y = (T*)p_y;
+  // only panels that never wait on each other's workgroups may run beside the
+  // trailing products: float64 CholeskyQR2 in its normal mode
+  const bool lookahead = h->qr_lookahead && cq_ws && h->qr_panel == 0;
+  if (lookahead) RFMLS_CHECK(lookahead_stream(h));
+  hipStream_t st = h->stream;
+  T* tau2[2] = {(T*)p_tau, (T*)p_tau + kOuterMax};
+  T* To2[2] = {(T*)p_to, (T*)p_to + kOuter * kOuter};
+  const TrailBufs<T> tb = {(T*)p_wz, (T*)p_w, (T*)p_wp, (T*)p_y};
+  T* in = (T*)p_in;
+  uint64_t* ll = (uint64_t*)p_part;
   {
     // the panels' exchange slots, zeroed once: their tags are column indices
     const int64_t nll = ll_words(kPanelMaxBlocks);
-    hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nll, 256) < 512 ? ceil_div(nll, 256) : 512), dim3(256), 0, st,
-                       (uint64_t*)p_part, nll);
+    hipLaunchKernelGGL(k_zero_u64, dim3(ceil_div(nll, 256) < 512 ? ceil_div(nll, 256) : 512), dim3(256), 0, st, ll,
+                       nll);
   }
-  for (int64_t k0 = 0; k0 < n; k0 += kOuter) {
+  auto bufs = [&](int64_t blk) {
+    PanelBufs<T> pb = {tau2[blk & 1], To2[blk & 1], in, in + in_wz, in + in_wz + in_w};
+    return pb;
+  };
+  // block k + 1's panels all CholeskyQR2-eligible (64 columns, enough rows)
+  auto cq_block = [&](int64_t k1, int64_t bw1) { return bw1 % kMaxNb == 0 && s - (k1 + bw1 - kMaxNb) >= kCholqrMinRows; };
+  RFMLS_CHECK(qr_block_panels<T>(h, s, 0, n < kOuter ? n : kOuter, kOuter, SA, ld, bufs(0), ll, cq_ws, cq_status,
+                                 tau_out));
+  int64_t blk = 0;
+  for (int64_t k0 = 0; k0 < n; k0 += kOuter, ++blk) {
     const int64_t bw = n - k0 < kOuter ? n - k0 : kOuter;
-    // ---------------- inner panels of the outer block ----------------
-    for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
-      const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
-      const int64_t M = s - p0;
-      PanelShape sh;
-      int64_t G = 0;
-      RFMLS_CHECK(pick_panel_shape<T>(h, M, &sh, &G));
-      const int64_t rpw = sh.rpw();
-      T* P = SA + p0 * ld + p0;
-      T* tau_p = tau + (p0 - k0);
-      uint64_t* ll = (uint64_t*)p_part;
-      int rpw_i = (int)rpw;
-      unsigned tag0 = (unsigned)p0;
-      const int* run_if = nullptr;
-      // Householder on an M x jb panel: sum_j 4 (M - j)(jb - j) flops; panel
-      // read and written once (the method's work, whichever way it is factored)
-      const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
-      if (cq_ws) {
-        // float64 64-column panels: CholeskyQR2 + reconstruction; the
-        // unblocked kernel below then runs only for a panel it flagged
-        if (jb == kMaxNb && M >= kCholqrMinRows) {
-          Trace tr(h, "qr_panel_cq", 2.0 * sizeof(T) * (double)M * jb, pf);
-          const double thr1 = h->qr_panel == 2 ? 2.0 : kCholqrMinPivot;
-          const double thr2 = h->qr_panel == 3 ? 2.0 : kCholqrMinPivot;
-          RFMLS_CHECK(run_cholqr_panel(h, (double*)P, ld, M, (double*)tau_p, cq_ws, cq_status, thr1, thr2));
-          run_if = cq_status;
-        }
-      }
-      void* args[] = {(void*)&P,     (void*)&ld,    (void*)&M,  (void*)&jb,           (void*)&rpw_i,
-                      (void*)&tau_p, (void*)&ll,    (void*)&h->dev_flags, (void*)&tag0, (void*)&run_if};
-      const void* fn = sh.fn;
-      {
-        Trace tr(h, run_if ? "qr_panel_fallback" : "qr_panel", run_if ? 0.0 : 2.0 * sizeof(T) * (double)M * jb,
-                 run_if ? 0.0 : pf);
-        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
-      }
-      if (run_if) RFMLS_CHECK(cholqr_fix(h, (double*)P, ld, M, cq_ws, cq_status));
-      const int64_t rem = k0 + bw - (p0 + jb);
-      if (rem <= 0) continue;
-      const int64_t ncols = jb + rem;
-      const int64_t ldw = pad32(ncols), ldwp = pad32(rem);
-      const int64_t nsp = (M + split_in - 1) / split_in;
-      {
-        Trace tr(h, "qr_inner_VtC", sizeof(T) * ((double)M * ncols + (double)nsp * jb * ncols),
-                 2.0 * (double)jb * ncols * M);
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerVtC>(vt_gemm<T>(P, ld, M, jb, ncols, Wz, ldw, split_in), st)));
-        hipLaunchKernelGGL(k_sum_slices_narrow<T>, dim3(ceil_div(jb * ldw, 64)), dim3(256), 0, st,
-                           (const T*)Wz, (int64_t)jb * ldw, (int)nsp, (int64_t)jb * ldw, W);
-      }
-      {
-        Trace tr(h, "qr_inner_T", sizeof(T) * 2.0 * jb * ncols, 2.0 * (double)jb * jb * rem);
-        // this panel's T is also a diagonal block of the outer block's T_o
-        T* Tq = To + (p0 - k0) * kOuter + (p0 - k0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jb + 15) / 16), dim3(1024), 0, st, (const T*)W, (int64_t)0, 1,
-                           ldw, jb, (const T*)tau_p, Tq, (int64_t)kOuter);
-        hipLaunchKernelGGL(k_qr_wp<T>, dim3(ceil_div(rem, 32)), dim3(256), 0, st, (const T*)W, ldw, jb,
-                           (const T*)Tq, (int64_t)kOuter, rem, Wp, ldwp);
-      }
-      {
-        Trace tr(h, "qr_inner_update", sizeof(T) * (2.0 * (double)M * rem + (double)M * jb),
-                 2.0 * (double)M * rem * jb);
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrInnerUpdate>(v_update<T>(P, ld, M, jb, rem, Wp, ldwp), st)));
-      }
-      RFMLS_HIP(h, hipGetLastError());
-    }
-    // every reflector's tau, for a caller that applies Q afterwards
-    if (tau_out)
-      RFMLS_HIP(h, hipMemcpyAsync(tau_out + k0, tau, sizeof(T) * (size_t)bw, hipMemcpyDeviceToDevice, st));
-    // ---------------- trailing update with the whole outer block ----------------
-    if (n - k0 - bw <= 0) continue;
+    if (n - k0 - bw <= 0) break;
+    const int64_t k1 = k0 + bw, bw1 = n - k1 < kOuter ? n - k1 : kOuter;
     // columns right of the block, rounded up to the widest tile (128) within
-    // the room
+    // the room; the method's own are the traced work
     const int64_t ntr = (n_room < (n + 127) / 128 * 128 ? n_room : (n + 127) / 128 * 128) - k0 - bw;
-    const int64_t M0 = s - k0;
-    T* P0 = SA + k0 * ld + k0;
-    const int64_t ncols = bw + ntr;
-    const int64_t ldw = pad32(ncols), ldwp = pad32(ntr);
-    // the method's own trailing columns (the traced work counts these, not the
-    // rounded-up tile columns the products also write)
-    const int64_t ntr_m = n - k0 - bw, ncols_m = bw + ntr_m;
-    // V^T [V | C] in row slices summed in order: rows [0, bw) hold the
-    // triangle of V (masked, general kernel); the rows below are clear of every
-    // mask, so a whole number of 16-row chunks of them goes to the clean-only
-    // kernel in split_out-row slices, and a tail of fewer than 16 rows (if any) to the
-    // general kernel without masks
-    const int64_t Kc = (M0 - bw) / 16 * 16, Kt = M0 - bw - Kc;
-    const int64_t nsc = (Kc + split_out - 1) / split_out;
-    const int64_t nsp = 1 + nsc + (Kt > 0 ? 1 : 0);
-    const int64_t zs = bw * ldw;
-    {
-      Trace tr(h, "qr_gemm_VtC", sizeof(T) * ((double)M0 * ncols_m + 2.0 * (double)nsp * bw * ncols_m),
-               2.0 * (double)bw * ncols_m * M0);
-      {
-        // op(A) = V^T of the top rows is upper triangular (the mask zeroes the
-        // rest): each row tile starts its K range at its own first row
-        GemmArgs<T> gt = vt_gemm<T>(P0, ld, bw, bw, ncols, Wz, ldw, 0);
-        gt.a_upper = 1;
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gt, st)));
-      }
-      if (Kc > 0) {
-        GemmArgs<T> gc = vt_gemm<T>(P0 + bw * ld, ld, Kc, bw, ncols, Wz + zs, ldw, split_out);
-        gc.a_vmask = 0;
-        gc.b_vcols = 0;
-        // the kOuter / 64 row tiles of a B strip run together (56 -> 59 TFLOP/s,
-        // float64, 256-column blocks) on one XCD (then 481 -> 469 ms on the
-        // 4^3-box float64 solve's 512-column blocks, equal at 256)
-        gc.tile_order = 3;
-        RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrVtC>(gc, st)));
-      }
-      if (Kt > 0) {
-        GemmArgs<T> gr = vt_gemm<T>(P0 + (bw + Kc) * ld, ld, Kt, bw, ncols, Wz + (1 + nsc) * zs, ldw, 0);
-        gr.a_vmask = 0;
-        gr.b_vcols = 0;
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrVtC>(gr, st)));
-      }
-      hipLaunchKernelGGL(k_sum_slices<T>, dim3(ceil_div(bw * ldw, 256) < 4096 ? ceil_div(bw * ldw, 256) : 4096),
-                         dim3(256), 0, st, (const T*)Wz, bw * ldw, (int)nsp, zs, W);
+    const int64_t ntr_m = n - k0 - bw;
+    const PanelBufs<T> pb = bufs(blk), pb1 = bufs(blk + 1);
+    if (lookahead && ntr_m > kOuter && cq_block(k1, bw1)) {
+      // block k + 1's columns first, its panels on the second stream, the rest here
+      RFMLS_CHECK(qr_block_trailing<T>(h, s, k0, bw, kOuter, SA, ld, 0, kOuter, kOuter, true, pb.tau, pb.To, tb));
+      RFMLS_HIP(h, hipEventRecord(h->la_event[0], st));
+      RFMLS_HIP(h, hipStreamWaitEvent(h->la_stream, h->la_event[0], 0));
+      h->stream = h->la_stream;
+      const rfmls_status ps =
+          qr_block_panels<T>(h, s, k1, bw1, kOuter, SA, ld, pb1, ll, cq_ws, cq_status, tau_out);
+      const hipError_t er = hipEventRecord(h->la_event[1], h->la_stream);
+      h->stream = st;
+      RFMLS_CHECK(ps);
+      RFMLS_HIP(h, er);
+      const rfmls_status ts = qr_block_trailing<T>(h, s, k0, bw, kOuter, SA, ld, kOuter, ntr - kOuter,
+                                                   ntr_m - kOuter, false, pb.tau, pb.To, tb);
+      RFMLS_HIP(h, hipStreamWaitEvent(st, h->la_event[1], 0));
+      RFMLS_CHECK(ts);
+    } else {
+      RFMLS_CHECK(qr_block_trailing<T>(h, s, k0, bw, kOuter, SA, ld, 0, ntr, ntr_m, true, pb.tau, pb.To, tb));
+      RFMLS_CHECK(qr_block_panels<T>(h, s, k1, bw1, kOuter, SA, ld, pb1, ll, cq_ws, cq_status, tau_out));
     }
-    {
-      // T_o: its diagonal 64-blocks are the inner panels' T, written above,
-      // except the last panel's (no inner update follows it), built here from
-      // the Gram's diagonal block; then the block columns
-      Trace tr(h, "qr_outer_T", sizeof(T) * 4.0 * (double)bw * bw, 2.0 * (double)bw * bw * bw);
-      {
-        const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
-        const int jq = (int)(bw - q0);
-        hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jq + 15) / 16), dim3(1024), 0, st, (const T*)(W + q0 * ldw + q0),
-                           (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0,
-                           (int64_t)kOuter);
-      }
-      for (int64_t q0 = kMaxNb; q0 < bw; q0 += kMaxNb) {
-        const int64_t jq = bw - q0 < kMaxNb ? bw - q0 : kMaxNb;
-        GemmArgs<T> ga;  // Y = T_o[:q0, :q0] * Gram[:q0, q0:q0+jq]
-        ga.M = q0;
-        ga.N = jq;
-        ga.K = q0;
-        ga.A = To;
-        ga.lda = kOuter;
-        ga.a_upper = 1;
-        ga.B = W + q0;
-        ga.ldb = ldw;
-        ga.C = Y;
-        ga.ldc = jq;
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(ga, st)));
-        GemmArgs<T> gb;  // T_o[:q0, q0:q0+jq] = -Y * T_qq
-        gb.M = q0;
-        gb.N = jq;
-        gb.K = jq;
-        gb.A = Y;
-        gb.lda = jq;
-        gb.B = To + q0 * kOuter + q0;
-        gb.ldb = kOuter;
-        gb.b_upper = 1;
-        gb.C = To + q0;
-        gb.ldc = kOuter;
-        gb.alpha = T(-1);
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gb, st)));
-      }
-    }
-    {
-      // W' = T_o^T W[:, bw:]  (T_o^T lower triangular)
-      Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * ntr_m, (double)bw * bw * ntr_m);
-      GemmArgs<T> gt;
-      gt.M = bw;
-      gt.N = ntr;
-      gt.K = bw;
-      gt.A = To;
-      gt.lda = kOuter;
-      gt.transA = 1;
-      gt.a_lower = 1;
-      gt.B = W + bw;
-      gt.ldb = ldw;
-      gt.C = Wp;
-      gt.ldc = ldwp;
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
-    }
-    {
-      Trace tr(h, "qr_gemm_update", sizeof(T) * (2.0 * (double)M0 * ntr_m + (double)M0 * bw + (double)bw * ntr_m),
-               2.0 * (double)M0 * ntr_m * bw);
-      // rows [0, bw) meet the triangle of V (masked, general kernel); the rows
-      // below are clear of it and take the clean-only kernel
-      {
-        // V's top rows are lower triangular (the mask zeroes the rest): each
-        // row tile ends its K range at its own last row
-        GemmArgs<T> gt = v_update<T>(P0, ld, bw, bw, ntr, Wp, ldwp);
-        gt.a_lower = 1;
-        RFMLS_HIP(h, (gemm<T, GemmRole::QrTrailingUpdate>(gt, st)));
-      }
-      if (M0 > bw) {
-        GemmArgs<T> gu = v_update<T>(P0 + bw * ld, ld, M0 - bw, bw, ntr, Wp, ldwp);
-        gu.a_vmask = 0;
-        gu.tile_order = 2;  // bands of 32 tile rows: 53.8 -> 56.5 TFLOP/s (float64, 51200 x 12800)
-        RFMLS_HIP(h, (gemm_clean<T, GemmRole::QrTrailingUpdate>(gu, st)));
-      }
-    }
-    RFMLS_HIP(h, hipGetLastError());
   }
   return RFMLS_OK;
 }

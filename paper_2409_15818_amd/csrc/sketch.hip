@@ -134,37 +134,170 @@ __global__ void __launch_bounds__(256) k_sort_buckets(const int64_t* __restrict_
   }
 }
 
-// One block per sketch row j.  Columns are produced in chunks of kChunk held in
-// LDS as float64; the bucket's rows are added in ascending order (a barrier
-// between rows), then the chunk is stored contiguously (row-major SA).
+// One block per sketch row j.  The bucket's rows (columns ascending within a
+// row) each cover one contiguous column span; the spans, merged in order of
+// their first column, map the row's touched columns onto a compact LDS window
+// (at most kWin doubles).  Zeros go out first for every 16-byte segment clear
+// of the window, the bucket's rows are then added into the window in ascending
+// row order (a barrier between rows), and the window's segments are stored:
+// the dense row is written once, with 16-byte non-temporal stores, and A's
+// entries are read once.  A bucket of more than kMaxBucketRows rows or a window
+// wider than kWin takes the chunked path: chunks of kWin columns, every row of
+// the bucket visited per chunk.  Either way every element is summed in float64
+// from +0 over the bucket's rows in ascending row order.
 constexpr int kSketchThreads = 256;
-constexpr int kChunk = 4096;
+constexpr int kWin = 2048;
+constexpr int kMaxBucketRows = 64;
 
 template <typename TOut>
+struct SketchVec;
+template <>
+struct SketchVec<double> {
+  static constexpr int V = 2;
+  typedef double vec __attribute__((ext_vector_type(2)));
+};
+template <>
+struct SketchVec<float> {
+  static constexpr int V = 4;
+  typedef float vec __attribute__((ext_vector_type(4)));
+};
+
+// Vec: the row start is 16-byte aligned (SA and ld suit 16-byte stores)
+template <typename TOut, bool Vec>
 __global__ void __launch_bounds__(kSketchThreads)
     k_sketch_rows(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                   const double* __restrict__ val, const int8_t* __restrict__ sign,
                   const int64_t* __restrict__ bptr, const int32_t* __restrict__ perm, int64_t n,
                   TOut* __restrict__ SA, int64_t ld) {
-  __shared__ double acc[kChunk];
+  constexpr int V = Vec ? SketchVec<TOut>::V : 1;
+  typedef typename SketchVec<TOut>::vec vec_t;
+  __shared__ double acc[kWin];
+  __shared__ int32_t sp0[kMaxBucketRows], sp1[kMaxBucketRows];
+  __shared__ int32_t ist[kMaxBucketRows], ien[kMaxBucketRows], ioff[kMaxBucketRows];
+  __shared__ int nint_s;
+  const int t = threadIdx.x;
   const int64_t j = blockIdx.x;
   const int64_t blo = bptr[j], bhi = bptr[j + 1];
+  const int64_t nb = bhi - blo;
   TOut* out = SA + j * ld;
-  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
-    const int64_t cw = (n - c0) < kChunk ? (n - c0) : kChunk;
-    for (int t = threadIdx.x; t < kChunk; t += kSketchThreads) acc[t] = 0.0;
+  int nint = -1;  // -1: chunked path
+  if (nb <= kMaxBucketRows) {
+    if (t < nb) {
+      const int32_t i = perm[blo + t];
+      const int64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+      sp0[t] = hi > lo ? col[lo] : 1;  // an empty row: an empty span
+      sp1[t] = hi > lo ? col[hi - 1] : 0;
+    }
+    __syncthreads();
+    if (t == 0) {
+      // sort the spans by first column (insertion sort; a handful of rows), merge
+      for (int a = 1; a < nb; ++a) {
+        const int32_t x0 = sp0[a], x1 = sp1[a];
+        int b2 = a - 1;
+        while (b2 >= 0 && sp0[b2] > x0) {
+          sp0[b2 + 1] = sp0[b2];
+          sp1[b2 + 1] = sp1[b2];
+          --b2;
+        }
+        sp0[b2 + 1] = x0;
+        sp1[b2 + 1] = x1;
+      }
+      int k = 0, total = 0;
+      for (int a = 0; a < nb; ++a) {
+        if (sp1[a] < sp0[a]) continue;  // empty
+        if (k > 0 && sp0[a] <= ien[k - 1] + 1) {
+          if (sp1[a] > ien[k - 1]) {
+            total += sp1[a] - ien[k - 1];
+            ien[k - 1] = sp1[a];
+          }
+        } else {
+          ist[k] = sp0[a];
+          ien[k] = sp1[a];
+          ioff[k] = total;
+          total += sp1[a] - sp0[a] + 1;
+          ++k;
+        }
+      }
+      nint_s = total <= kWin ? k : -1;
+    }
+    __syncthreads();
+    nint = nint_s;
+  }
+  if (nint >= 0) {
+    // window position of column c, or -1
+    auto wpos = [&](int64_t c) -> int {
+      for (int k = 0; k < nint; ++k)
+        if (c >= ist[k] && c <= ien[k]) return ioff[k] + (int)(c - ist[k]);
+      return -1;
+    };
+    auto touches = [&](int64_t c0) {
+      for (int k = 0; k < nint; ++k)
+        if (c0 <= ien[k] && c0 + V - 1 >= ist[k]) return true;
+      return false;
+    };
+    const int64_t nseg = n / V;
+    // zeros for the segments clear of the window (no wait on anything below)
+    for (int64_t g = t; g < nseg; g += kSketchThreads) {
+      const int64_t c0 = g * V;
+      if (touches(c0)) continue;
+      if constexpr (Vec) {
+        __builtin_nontemporal_store(vec_t{}, (vec_t*)(out + c0));
+      } else {
+        __builtin_nontemporal_store((TOut)0, out + c0);
+      }
+    }
+    const int wlen = nint > 0 ? ioff[nint - 1] + ien[nint - 1] - ist[nint - 1] + 1 : 0;
+    for (int w = t; w < wlen; w += kSketchThreads) acc[w] = 0.0;
     __syncthreads();
     for (int64_t q = blo; q < bhi; ++q) {
       const int32_t i = perm[q];
       const double sg = (double)sign[i];
       const int64_t lo = row_ptr[i], hi = row_ptr[i + 1];
-      for (int64_t e = lo + threadIdx.x; e < hi; e += kSketchThreads) {
+      for (int64_t e = lo + t; e < hi; e += kSketchThreads) acc[wpos(col[e])] += sg * val[e];
+      __syncthreads();
+    }
+    // the window's segments (a segment across two intervals is written twice, alike)
+    for (int k = 0; k < nint; ++k) {
+      const int64_t g0 = ist[k] / V, g1 = ien[k] / V < nseg ? ien[k] / V : nseg - 1;
+      for (int64_t g = g0 + t; g <= g1; g += kSketchThreads) {
+        const int64_t c0 = g * V;
+        if constexpr (Vec) {
+          vec_t v;
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            const int p = wpos(c0 + q);
+            v[q] = p >= 0 ? (TOut)acc[p] : (TOut)0;
+          }
+          __builtin_nontemporal_store(v, (vec_t*)(out + c0));
+        } else {
+          const int p = wpos(c0);
+          __builtin_nontemporal_store(p >= 0 ? (TOut)acc[p] : (TOut)0, out + c0);
+        }
+      }
+    }
+    // columns past the last whole segment
+    for (int64_t c = nseg * V + t; c < n; c += kSketchThreads) {
+      const int p = wpos(c);
+      out[c] = p >= 0 ? (TOut)acc[p] : (TOut)0;
+    }
+    return;
+  }
+  // chunked path
+  for (int64_t c0 = 0; c0 < n; c0 += kWin) {
+    const int64_t cw = (n - c0) < kWin ? (n - c0) : kWin;
+    for (int w = t; w < kWin; w += kSketchThreads) acc[w] = 0.0;
+    __syncthreads();
+    for (int64_t q = blo; q < bhi; ++q) {
+      const int32_t i = perm[q];
+      const double sg = (double)sign[i];
+      const int64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+      for (int64_t e = lo + t; e < hi; e += kSketchThreads) {
         const int64_t c = (int64_t)col[e] - c0;
         if (c >= 0 && c < cw) acc[c] += sg * val[e];
       }
       __syncthreads();
     }
-    for (int t = threadIdx.x; t < cw; t += kSketchThreads) out[c0 + t] = (TOut)acc[t];
+    for (int w = t; w < cw; w += kSketchThreads) out[c0 + w] = (TOut)acc[w];
     __syncthreads();
   }
 }
@@ -244,12 +377,23 @@ rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const in
            12.0 * (double)A->nnz + 8.0 * (double)(A->m + 1) + 5.0 * (double)A->m +
                8.0 * (double)(s + 1) + esz * (double)s * (double)A->n,
            (double)A->nnz);
-  if (dt == RFMLS_F64)
-    hipLaunchKernelGGL(k_sketch_rows<double>, dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
-                       A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (double*)SA, ld);
-  else
-    hipLaunchKernelGGL(k_sketch_rows<float>, dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
-                       A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (float*)SA, ld);
+  // 16-byte stores when every row starts 16-byte aligned
+  const bool vec = (reinterpret_cast<uintptr_t>(SA) % 16 == 0) && ((int64_t)esz * ld) % 16 == 0;
+  if (dt == RFMLS_F64) {
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_rows<double, true>), dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
+                         A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (double*)SA, ld);
+    else
+      hipLaunchKernelGGL((k_sketch_rows<double, false>), dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
+                         A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (double*)SA, ld);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_rows<float, true>), dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
+                         A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (float*)SA, ld);
+    else
+      hipLaunchKernelGGL((k_sketch_rows<float, false>), dim3((unsigned)s), dim3(kSketchThreads), 0, h->stream,
+                         A->row_ptr, A->col, A->val, sign, bptr, perm, A->n, (float*)SA, ld);
+  }
   }
   RFMLS_HIP(h, hipGetLastError());
   if (b != nullptr && Sb != nullptr && nrhs > 0) {

@@ -103,3 +103,59 @@ def test_solve_with_cholqr_panels_matches_oracle(handle, name):
     for mode in (0, 1):
         assert abs(out[mode]["normr"] - orc["normr"]) <= 1e-10 * orc["normr"]
     assert abs(out[0]["itn_first"] - orc["itn_sweeps"][0]) <= 2
+
+
+def _qr_factors(handle, SAo, lookahead, mode=0):
+    """R and the Householder vectors (the whole factored SA) from rfmls_precond_x0-free QR."""
+    R.rfmls_qr_panel_mode(handle, mode)
+    R.rfmls_qr_lookahead(handle, lookahead)
+    try:
+        SA = torch.tensor(SAo, device="cuda")
+        P = R.rfmls_precond(handle, SA, "f64", "f64")
+        torch.cuda.synchronize()
+        out = SA.cpu().numpy().copy()
+        P.free()
+    finally:
+        R.rfmls_qr_lookahead(handle, False)
+        R.rfmls_qr_panel_mode(handle, 0)
+    return out
+
+
+def _lookahead_cases():
+    rng = np.random.default_rng(11)
+    # four and five outer blocks of 256 columns, the last one ragged
+    yield "gaussian 6000x1024", rng.standard_normal((6000, 1024))
+    yield "gaussian 4000x1100", rng.standard_normal((4000, 1100)) * np.geomspace(1.0, 1e4, 1100)[None, :]
+    S, s = build_config("poisson2d_4x4")
+    h, sign = countsketch.hash_sign(S.m, s, SEED)
+    SAo, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+    yield "poisson2d_4x4", SAo
+
+
+@pytest.mark.parametrize("case", list(_lookahead_cases()), ids=lambda c: c[0])
+def test_lookahead_gives_bitwise_the_same_factorisation(handle, case):
+    """The look-ahead schedule splits the trailing update by columns and runs the
+    next block's panels on a second stream: every column's sums keep their order,
+    so the whole factored matrix (R and the Householder vectors) is bitwise equal."""
+    label, SAo = case
+    print(f"[lookahead] {label} {SAo.shape}", flush=True)
+    F0 = _qr_factors(handle, SAo, False)
+    F1 = _qr_factors(handle, SAo, True)
+    assert np.array_equal(F0, F1)
+    # a second run with look-ahead repeats itself exactly (no race between the streams)
+    F2 = _qr_factors(handle, SAo, True)
+    assert np.array_equal(F1, F2)
+
+
+def test_lookahead_solve_matches_oracle(handle):
+    S, s = build_config("poisson2d_4x4")
+    A = R.CSR.from_numpy(S.row_ptr, S.col, S.val, S.m, S.n)
+    b = torch.tensor(S.b[0], device="cuda")
+    R.rfmls_qr_lookahead(handle, True)
+    try:
+        res = R.csqrp_lsqr(handle, A, b, s, SEED, opts=R.default_opts(refine=1))
+    finally:
+        R.rfmls_qr_lookahead(handle, False)
+    orc = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, SEED, refine=1)
+    assert abs(res.info[0]["normr"] - orc["normr"]) <= 1e-10 * orc["normr"]
+    assert abs(res.info[0]["itn_first"] - orc["itn_sweeps"][0]) <= 2

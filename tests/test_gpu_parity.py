@@ -66,6 +66,45 @@ def test_sketch_ragged_wide_and_empty_rows(handle):
         assert np.array_equal(SA.cpu().numpy(), SAo), s
 
 
+def _span_csr(m, n, widths, seed):
+    """CSR whose row i holds one contiguous run of widths[i] columns at a random start."""
+    rng = np.random.default_rng(seed)
+    rp = np.zeros(m + 1, np.int64)
+    cols, vals = [], []
+    for i in range(m):
+        w = int(widths[i])
+        c0 = int(rng.integers(0, n - w + 1)) if w > 0 else 0
+        cols.append(np.arange(c0, c0 + w, dtype=np.int32))
+        vals.append(rng.standard_normal(w))
+        rp[i + 1] = rp[i] + w
+    return rp, np.concatenate(cols), np.concatenate(vals)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sketch_windowed_rows(handle, dtype):
+    """Rows of contiguous column runs (the RFM structure): buckets of a few rows
+    take the compact-window path; buckets of more than 64 rows, or whose merged
+    runs exceed 2048 columns, the chunked one.  Ragged widths (n odd), empty rows,
+    even and odd leading dimensions; bit-exact against the oracle either way."""
+    m, n = 3000, 5003
+    rng = np.random.default_rng(21)
+    widths = rng.integers(1, 300, size=m)
+    widths[::97] = 0                     # empty rows
+    widths[5::211] = rng.integers(1500, 2600, size=len(widths[5::211]))  # wide runs
+    rp, col, val = _span_csr(m, n, widths, seed=22)
+    A = gpu_csr(rp, col, val, m, n)
+    for s in (1000, 2999, 40):
+        for pad in (0, 1, 4):
+            buf = torch.full((s, n + pad), 3.0, dtype=torch.float64 if dtype == "f64" else torch.float32,
+                             device="cuda")
+            SA, hg, sg, _ = R.rfmls_sketch(handle, A, s, 7, dtype=dtype, SA=buf[:, :n], want_maps=True)
+            SAo, _ = countsketch.sketch_dense(rp, col, val, hg.cpu().numpy(), sg.cpu().numpy(), s, n)
+            if dtype == "f32":
+                SAo = SAo.astype(np.float32)
+            assert np.array_equal(buf[:, :n].cpu().numpy(), SAo), (s, pad)
+            assert torch.all(buf[:, n:] == 3.0)
+
+
 def test_sketch_padded_leading_dimension(handle):
     S, s, A = system("poisson2d_2x2")
     buf = torch.full((s, S.n + 13), 7.0, dtype=torch.float64, device="cuda")
