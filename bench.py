@@ -87,11 +87,15 @@ def cpu_full_run(S, s, refine, threads):
     h, sign = countsketch.hash_sign(S.m, s, SKETCH_SEED)
     SA, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
     t1 = time.perf_counter()
+    log(f"[cpu-full] sketch {t1 - t0:.1f} s")
     R = qr.r_factor(SA, check_rank=False)
     del SA
     t2 = time.perf_counter()
+    log(f"[cpu-full] QR {t2 - t1:.1f} s")
     A = pipeline.csr(S.row_ptr, S.col, S.val, S.m, S.n)
-    x, results = pipeline.refined_lsqr(A, R, S.b[0], refine=refine)
+    x, results = pipeline.refined_lsqr(
+        A, R, S.b[0], refine=refine,
+        on_sweep=lambda k, r: log(f"[cpu-full] LSQR sweep {k}: {r.itn} iterations, {time.perf_counter() - t2:.1f} s"))
     t3 = time.perf_counter()
     met = pipeline.residual_metrics(A, x, S.b[0])
     return {"value": t3 - t0, "unit": "s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
@@ -205,7 +209,7 @@ def main():
                          "full: the whole oracle solve, measured (minutes)")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--qr-lookahead", type=int, default=0, choices=[0, 1],
-                    help="1: next outer block's QR panels beside the trailing update (float64)")
+                    help="1: next outer block's QR panels beside the trailing update")
     ap.add_argument("--backward", action="store_true",
                     help="also time the backward pass (gradients w.r.t. b and A's values) of "
                          "L = 1/2 sum_k ||E x_k - u_k||^2 at 10^4 sample points")

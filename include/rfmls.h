@@ -317,16 +317,18 @@ rfmls_status rfmls_solve_backward(rfmls_handle *h, const rfmls_csr *A, const rfm
                                   int64_t nrhs, double *dB, int64_t lddb, double *dAval,
                                   const rfmls_opts *opts, rfmls_info *info);
 
-/* ---- Panel factorisation of the float64 QR ----
+/* ---- Panel factorisation of the QR (Alg. 1 step 3) ----
  * mode 0 (default): 64-column panels of at least 1024 rows are factored by
  * CholeskyQR2 on column-scaled Gram matrices followed by the reconstruction of
  * their Householder vectors (a fixed number of passes over the panel instead
- * of one grid-wide exchange per column); a panel whose first Cholesky pivot
- * ratio falls below 1e-7 is factored by the unblocked Householder kernel.
- * mode 1: the unblocked Householder kernel for every panel.  Modes 2 and 3 force
- * the first, respectively second, Cholesky pass of every eligible panel to
- * fail, so that the fallback paths can be tested.  Both ways R satisfies
- * R^T R = (SA)^T SA to rounding; the float32 QR always uses the unblocked kernel. */
+ * of one grid-wide exchange per column), in float64 arithmetic for float64 and
+ * float32 panels alike (a float32 panel is rounded where it is stored); a panel
+ * whose first Cholesky pivot ratio falls below 1e-7 is factored by the
+ * unblocked Householder kernel.  mode 1: the unblocked Householder kernel for
+ * every panel.  Modes 2 and 3 force the first, respectively second, Cholesky
+ * pass of every eligible panel to fail, so that the fallback paths can be
+ * tested.  Every way R satisfies R^T R = (SA)^T SA to the rounding of its
+ * dtype.  Errors: RFMLS_E_ARG for a null handle or a mode outside 0..3. */
 rfmls_status rfmls_qr_panel_mode(rfmls_handle *h, int mode);
 
 /* ---- Look-ahead in the blocked QR (Alg. 1 step 3) ----
@@ -334,8 +336,8 @@ rfmls_status rfmls_qr_panel_mode(rfmls_handle *h, int mode);
  * first covers only the next outer block's columns; that block's panels then
  * run on a second stream of the handle (default priority, created on first
  * use) while the handle's stream updates the remaining columns.  The factors
- * are bitwise those of the plain schedule.  Only float64 QRs in panel mode 0
- * use it, and only for outer blocks whose panels are all CholeskyQR2-eligible;
+ * are bitwise those of the plain schedule.  Only QRs in panel mode 0 use it,
+ * and only for outer blocks whose panels are all CholeskyQR2-eligible;
  * everything else keeps the plain schedule.  A panel that CholeskyQR2 declines
  * is then factored by the unblocked kernel beside the trailing update, whose
  * grid-wide exchange needs all of its workgroups resident: a bounded wait turns

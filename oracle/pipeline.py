@@ -142,10 +142,11 @@ def sketched_start(SA, SB, check_rank=True):
     return R, Y0, X0
 
 
-def refined_lsqr(A, R, b, refine=1, x0=None, P=None, **kw):
+def refined_lsqr(A, R, b, refine=1, x0=None, P=None, on_sweep=None, **kw):
     """LSQR sweeps with iterative refinement on the true residual, from x = 0
     or from x0; returns (x, [results]).  With P given (CSSVDP-LSQR) the
-    preconditioner is P instead of R^{-1}."""
+    preconditioner is P instead of R^{-1}.  on_sweep(k, result), if given, is
+    called after each sweep (progress reporting; no effect on the result)."""
     b = np.asarray(b, np.float64)
     x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
     r = b.copy() if x0 is None else b - A @ x
@@ -157,6 +158,8 @@ def refined_lsqr(A, R, b, refine=1, x0=None, P=None, **kw):
             kw.pop("operator", None)
             dx, res = lsqr_on_svd_preconditioned(A, P, r, **kw)
         results.append(res)
+        if on_sweep is not None:
+            on_sweep(sweep, res)
         x = x + dx
         r = b - A @ x
         if res.itn == 0:

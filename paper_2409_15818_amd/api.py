@@ -141,7 +141,7 @@ def rfmls_qr_panel_mode(h: Handle, mode: int):
 
 
 def rfmls_qr_lookahead(h: Handle, enable: bool):
-    """Run the next outer block's QR panels beside the trailing update (float64 CholeskyQR2 panels)."""
+    """Run the next outer block's QR panels beside the trailing update (CholeskyQR2 panels)."""
     h.check(h._lib.rfmls_qr_lookahead(h._h, int(bool(enable))))
 
 

@@ -1,5 +1,8 @@
 // Panel factorisation of the blocked Householder QR (Alg. 1 step 3) by
-// CholeskyQR2 with Householder reconstruction, float64.
+// CholeskyQR2 with Householder reconstruction: panels stored in float64 or
+// float32, every sum, factorisation and product in float64 (a float32 panel's
+// rows are rounded to float32 where they are stored, and the second pass's
+// Gram is of the stored rows).
 //
 // The unblocked panel (k_qr_panel) needs one grid-wide exchange per column.
 // Here a 64-column panel P (M x 64, row-major, in place) takes three passes
@@ -55,7 +58,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // (lane (lr, lk) reads row 4 s + lk, columns 16 q + lr: every 16 lanes read
 // 128 contiguous bytes), no LDS staging.  The four waves' tiles are then added
 // in wave order through LDS and the full symmetric 64 x 64 partial written.
-__global__ void __launch_bounds__(256) k_cq_gram(const double* __restrict__ P, int64_t ld, int64_t M,
+template <typename TS>
+__global__ void __launch_bounds__(256) k_cq_gram(const TS* __restrict__ P, int64_t ld, int64_t M,
                                                  double* __restrict__ Gpart, const int* __restrict__ status) {
   if (status && *status) return;
   __shared__ double S[kNb][kNb + 1];
@@ -73,7 +77,7 @@ __global__ void __launch_bounds__(256) k_cq_gram(const double* __restrict__ P, i
     for (int s4 = 0; s4 < 4; ++s4) {
       const int64_t row = r0 + 16 * grp + 4 * s4 + lk;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[s4][q] = row < M ? P[row * ld + 16 * q + lr] : 0.0;
+      for (int q = 0; q < 4; ++q) x[s4][q] = row < M ? (double)P[row * ld + 16 * q + lr] : 0.0;
     }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
@@ -434,9 +438,10 @@ __device__ void blk_recon_lu(Mat& A, double* sg) {
 //   vectors L2 = Q1bot U2^{-1} S U^{-1}.
 // A pivot ratio u_min / u_max below min_pivot_ratio (or a non-positive pivot)
 // sets *status = pass and leaves everything else untouched.
+template <typename TS>
 __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G, double* __restrict__ Wk,
-                                                   double* __restrict__ Rc, double* __restrict__ P, int64_t ld,
-                                                   double* __restrict__ tau, int* __restrict__ status, int pass,
+                                                   double* __restrict__ Rc, TS* __restrict__ P, int64_t ld,
+                                                   TS* __restrict__ tau, int* __restrict__ status, int pass,
                                                    double min_pivot_ratio) {
   if (pass == 2 && *status) return;
   __shared__ Mat M0, M1, M2, M3;
@@ -482,16 +487,16 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
   lds_mm(&M3[0][0], kLd, &M0[0][0], kLd, false, &M2[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
   for (int e = t; e < kNb * kNb; e += 256) {
     const int i = e / kNb, j = e % kNb;
-    M2[i][j] = P[(int64_t)i * ld + j];
+    M2[i][j] = (double)P[(int64_t)i * ld + j];
   }
   __syncthreads();
   lds_mm(&M0[0][0], kLd, &M2[0][0], kLd, false, &M1[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
   blk_recon_lu(M0, sg);
   for (int e = t; e < kNb * kNb; e += 256) {
     const int i = e / kNb, c = e % kNb;
-    P[(int64_t)i * ld + c] = i <= c ? sg[i] * M3[i][c] : M0[i][c];
+    P[(int64_t)i * ld + c] = (TS)(i <= c ? sg[i] * M3[i][c] : M0[i][c]);
   }
-  if (t < kNb) tau[t] = -M0[t][t];
+  if (t < kNb) tau[t] = (TS)(-M0[t][t]);
   __syncthreads();
   for (int e = t; e < kNb * kNb; e += 256) {  // U alone (zero below the diagonal)
     const int i = e / kNb, c = e % kNb;
@@ -512,7 +517,8 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
 // Rows [r_begin, M) of P <- P W (W 64 x 64) on the matrix cores, in place:
 // wave w of a block takes 16 rows, reads all 64 of their columns (A operands,
 // in registers) before it writes them.  Runs when *status == 0.
-__global__ void __launch_bounds__(256) k_cq_apply(double* __restrict__ P, int64_t ld, int64_t r_begin, int64_t M,
+template <typename TS>
+__global__ void __launch_bounds__(256) k_cq_apply(TS* __restrict__ P, int64_t ld, int64_t r_begin, int64_t M,
                                                   const double* __restrict__ W, const int* __restrict__ status) {
   if (*status) return;
   __shared__ double Ws[kNb][kNb + 1];
@@ -524,7 +530,7 @@ __global__ void __launch_bounds__(256) k_cq_apply(double* __restrict__ P, int64_
   const int64_t ra = rbase + lr;
   double a[16];
 #pragma unroll
-  for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? P[ra * ld + 4 * s4 + lk] : 0.0;
+  for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? (double)P[ra * ld + 4 * s4 + lk] : 0.0;
   __syncthreads();
   v4d acc[4];
 #pragma unroll
@@ -540,7 +546,7 @@ __global__ void __launch_bounds__(256) k_cq_apply(double* __restrict__ P, int64_
     const int64_t row = rbase + lk + 4 * r;
     if (row < M)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = acc[q][r];
+      for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = (TS)acc[q][r];
   }
 }
 
@@ -550,7 +556,8 @@ __global__ void __launch_bounds__(256) k_cq_apply(double* __restrict__ P, int64_
 // z kSlab + 64 w; a group's product tiles (D[lk + 4 r][16 q + lr] in register
 // r of tile q) are already the Gram's operands for K-step r.  The waves' Gram
 // tiles are added in wave order through LDS.  Runs when *status == 0.
-__global__ void __launch_bounds__(256) k_cq_apply_gram(double* __restrict__ P, int64_t ld, int64_t M,
+template <typename TS>
+__global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64_t ld, int64_t M,
                                                        const double* __restrict__ W, double* __restrict__ Gpart,
                                                        const int* __restrict__ status) {
   if (*status) return;
@@ -569,7 +576,7 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(double* __restrict__ P, i
     const int64_t ra = rbase + lr;
     double a[16];
 #pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? P[ra * ld + 4 * s4 + lk] : 0.0;
+    for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? (double)P[ra * ld + 4 * s4 + lk] : 0.0;
     v4d acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -580,12 +587,19 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(double* __restrict__ P, i
       for (int q = 0; q < 4; ++q)
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
     }
+    if constexpr (sizeof(TS) < sizeof(double)) {
+      // the Gram below is of the rows as stored
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[q][r] = (double)(TS)acc[q][r];
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rbase + lk + 4 * r;
       if (row < M)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = acc[q][r];
+        for (int q = 0; q < 4; ++q) P[row * ld + 16 * q + lr] = (TS)acc[q][r];
     }
     // rows past M hold exact zeros (zero operands) and add nothing
 #pragma unroll
@@ -622,7 +636,8 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(double* __restrict__ P, i
 
 // After the unblocked kernel factored Q1 (status 2): its R' times R1 (upper
 // triangular products, terms in order), written back into the panel's top rows.
-__global__ void __launch_bounds__(256) k_cq_fix(double* __restrict__ P, int64_t ld, const double* __restrict__ Rc,
+template <typename TS>
+__global__ void __launch_bounds__(256) k_cq_fix(TS* __restrict__ P, int64_t ld, const double* __restrict__ Rc,
                                                 const int* __restrict__ status) {
   if (*status != 2) return;
   __shared__ double A[kNb][kNb + 1];
@@ -630,7 +645,7 @@ __global__ void __launch_bounds__(256) k_cq_fix(double* __restrict__ P, int64_t 
   const int t = threadIdx.x;
   for (int e = t; e < kNb * kNb; e += 256) {
     const int r = e / kNb, c = e % kNb;
-    A[r][c] = c >= r ? P[(int64_t)r * ld + c] : 0.0;
+    A[r][c] = c >= r ? (double)P[(int64_t)r * ld + c] : 0.0;
     B[r][c] = Rc[e];
   }
   __syncthreads();
@@ -639,7 +654,7 @@ __global__ void __launch_bounds__(256) k_cq_fix(double* __restrict__ P, int64_t 
     if (c < r) continue;
     double sacc = 0.0;
     for (int k = r; k <= c; ++k) sacc = fma(A[r][k], B[k][c], sacc);
-    P[(int64_t)r * ld + c] = sacc;
+    P[(int64_t)r * ld + c] = (TS)sacc;
   }
 }
 
@@ -651,44 +666,62 @@ int64_t cholqr_workspace_doubles(int64_t M) {
 }
 
 // Enqueues CholeskyQR2 and the reconstruction on the 64-column panel P
-// (M >= 64 rows); ws holds cholqr_workspace_doubles(M) doubles.  A pass whose
-// Cholesky pivot ratio falls below min_ratio1 (first pass) or min_ratio2
-// (second) sets the status.  The caller then launches the unblocked kernel
-// gated on *status != 0, and cholqr_fix.
-rfmls_status run_cholqr_panel(rfmls_handle* h, double* P, int64_t ld, int64_t M, double* tau, double* ws,
-                              int* status, double min_ratio1, double min_ratio2) {
+// (M >= 64 rows, stored as TS, all arithmetic in float64); ws holds
+// cholqr_workspace_doubles(M) doubles.  A pass whose Cholesky pivot ratio falls
+// below min_ratio1 (first pass) or min_ratio2 (second) sets the status.  The
+// caller then launches the unblocked kernel gated on *status != 0, and
+// cholqr_fix.
+template <typename TS>
+static rfmls_status cholqr_panel(rfmls_handle* h, TS* P, int64_t ld, int64_t M, TS* tau, double* ws, int* status,
+                                 double min_ratio1, double min_ratio2) {
   hipStream_t st = h->stream;
   const int64_t nslab = (M + kSlab - 1) / kSlab;
   double* Gpart = ws;
   double* G = Gpart + nslab * kNb * kNb;
   double* Wk = G + kNb * kNb;
   double* Rc = Wk + kNb * kNb;
-  hipLaunchKernelGGL(k_cq_gram, dim3((unsigned)nslab), dim3(256), 0, st, (const double*)P, ld, M, Gpart,
+  hipLaunchKernelGGL(k_cq_gram<TS>, dim3((unsigned)nslab), dim3(256), 0, st, (const TS*)P, ld, M, Gpart,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
                      1);
-  hipLaunchKernelGGL(k_cq_factor, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 1,
+  hipLaunchKernelGGL(k_cq_factor<TS>, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 1,
                      min_ratio1);
-  hipLaunchKernelGGL(k_cq_apply_gram, dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M, (const double*)Wk, Gpart,
+  hipLaunchKernelGGL(k_cq_apply_gram<TS>, dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M, (const double*)Wk, Gpart,
                      (const int*)status);
   hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
                      0);
-  hipLaunchKernelGGL(k_cq_factor, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 2,
+  hipLaunchKernelGGL(k_cq_factor<TS>, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 2,
                      min_ratio2);
   if (M > kNb)
-    hipLaunchKernelGGL(k_cq_apply, dim3((unsigned)((M - kNb + 63) / 64)), dim3(256), 0, st, P, ld, (int64_t)kNb, M,
-                       (const double*)Wk, (const int*)status);
+    hipLaunchKernelGGL(k_cq_apply<TS>, dim3((unsigned)((M - kNb + 63) / 64)), dim3(256), 0, st, P, ld, (int64_t)kNb,
+                       M, (const double*)Wk, (const int*)status);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
 
+rfmls_status run_cholqr_panel(rfmls_handle* h, double* P, int64_t ld, int64_t M, double* tau, double* ws,
+                              int* status, double min_ratio1, double min_ratio2) {
+  return cholqr_panel<double>(h, P, ld, M, tau, ws, status, min_ratio1, min_ratio2);
+}
+rfmls_status run_cholqr_panel(rfmls_handle* h, float* P, int64_t ld, int64_t M, float* tau, double* ws, int* status,
+                              double min_ratio1, double min_ratio2) {
+  return cholqr_panel<float>(h, P, ld, M, tau, ws, status, min_ratio1, min_ratio2);
+}
+
 // Status 2 only: the panel's R (from the unblocked kernel, on Q1) times R1.
-rfmls_status cholqr_fix(rfmls_handle* h, double* P, int64_t ld, int64_t M, const double* ws, const int* status) {
+template <typename TS>
+static rfmls_status cholqr_fix_t(rfmls_handle* h, TS* P, int64_t ld, int64_t M, const double* ws, const int* status) {
   const int64_t nslab = (M + kSlab - 1) / kSlab;
   const double* Rc = ws + nslab * kNb * kNb + 2 * kNb * kNb;
-  hipLaunchKernelGGL(k_cq_fix, dim3(1), dim3(256), 0, h->stream, P, ld, Rc, status);
+  hipLaunchKernelGGL(k_cq_fix<TS>, dim3(1), dim3(256), 0, h->stream, P, ld, Rc, status);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
+}
+rfmls_status cholqr_fix(rfmls_handle* h, double* P, int64_t ld, int64_t M, const double* ws, const int* status) {
+  return cholqr_fix_t<double>(h, P, ld, M, ws, status);
+}
+rfmls_status cholqr_fix(rfmls_handle* h, float* P, int64_t ld, int64_t M, const double* ws, const int* status) {
+  return cholqr_fix_t<float>(h, P, ld, M, ws, status);
 }
 
 }  // namespace rfmls

@@ -277,11 +277,14 @@ rfmls_status capture_graph(rfmls_handle* h, IterGraph* g, F&& body) {
 
 // Launch entry points implemented in the individual .hip files -----------------
 namespace rfmls {
-// CholeskyQR2 panel with Householder reconstruction (cholqr.hip), float64
+// CholeskyQR2 panel with Householder reconstruction (cholqr.hip), float64 or float32 storage
 int64_t cholqr_workspace_doubles(int64_t M);
 rfmls_status run_cholqr_panel(rfmls_handle* h, double* P, int64_t ld, int64_t M, double* tau, double* ws,
                               int* status, double min_ratio1, double min_ratio2);
+rfmls_status run_cholqr_panel(rfmls_handle* h, float* P, int64_t ld, int64_t M, float* tau, double* ws, int* status,
+                              double min_ratio1, double min_ratio2);
 rfmls_status cholqr_fix(rfmls_handle* h, double* P, int64_t ld, int64_t M, const double* ws, const int* status);
+rfmls_status cholqr_fix(rfmls_handle* h, float* P, int64_t ld, int64_t M, const double* ws, const int* status);
 rfmls_status launch_hash_sign(rfmls_handle* h, int64_t m, int64_t s, uint64_t seed, int32_t* hash,
                               int8_t* sign);
 rfmls_status run_sketch(rfmls_handle* h, const rfmls_csr* A, int64_t s, const int32_t* hash,

@@ -21,8 +21,6 @@
 //   T_o from the Gram: diagonal 64-blocks are the panels' T, off-diagonal
 //   blocks T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
 // All reductions run in a fixed order, so the factorisation is deterministic.
-#include <type_traits>
-
 #include "common.h"
 #include "gemm.h"
 
@@ -576,12 +574,12 @@ rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw,
     // read and written once (the method's work, whichever way it is factored)
     const double pf = 4.0 * (double)M * jb * (jb + 1) / 2.0;
     if (cq_ws && jb == kMaxNb && M >= kCholqrMinRows) {
-      // float64 64-column panels: CholeskyQR2 + reconstruction; the unblocked
-      // kernel below then runs only for a panel it flagged
+      // 64-column panels: CholeskyQR2 + reconstruction in float64 arithmetic;
+      // the unblocked kernel below then runs only for a panel it flagged
       Trace tr(h, "qr_panel_cq", 2.0 * sizeof(T) * (double)M * jb, pf);
       const double thr1 = h->qr_panel == 2 ? 2.0 : kCholqrMinPivot;
       const double thr2 = h->qr_panel == 3 ? 2.0 : kCholqrMinPivot;
-      RFMLS_CHECK(run_cholqr_panel(h, (double*)P, ld, M, (double*)tau_p, cq_ws, cq_status, thr1, thr2));
+      RFMLS_CHECK(run_cholqr_panel(h, P, ld, M, tau_p, cq_ws, cq_status, thr1, thr2));
       run_if = cq_status;
     }
     void* args[] = {(void*)&P,     (void*)&ld, (void*)&M,            (void*)&jb,   (void*)&rpw_i,
@@ -592,7 +590,7 @@ rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw,
                run_if ? 0.0 : pf);
       RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
     }
-    if (run_if) RFMLS_CHECK(cholqr_fix(h, (double*)P, ld, M, cq_ws, cq_status));
+    if (run_if) RFMLS_CHECK(cholqr_fix(h, P, ld, M, cq_ws, cq_status));
     const int64_t rem = k0 + bw - (p0 + jb);
     if (rem <= 0) continue;
     const int64_t ncols = jb + rem;
@@ -834,11 +832,11 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   const int64_t kop = pad32(kOuter);
   const size_t in_wz = (size_t)nsp_in_max * kMaxNb * kop, in_w = (size_t)kMaxNb * kop;
   RFMLS_CHECK(workspace(h, WS_QR_INNER, sizeof(T) * (in_wz + 2 * in_w), &p_in));
-  // CholeskyQR2 panels (float64; rfmls_qr_panel_mode): workspace for the
-  // largest panel and one status word after it
+  // CholeskyQR2 panels (rfmls_qr_panel_mode): workspace for the largest
+  // panel and one status word after it
   double* cq_ws = nullptr;
   int* cq_status = nullptr;
-  if (std::is_same<T, double>::value && h->qr_panel != 1 && s >= kCholqrMinRows) {
+  if (h->qr_panel != 1 && s >= kCholqrMinRows) {
     const int64_t nd = cholqr_workspace_doubles(s);
     void* p_cq;
     RFMLS_CHECK(workspace(h, WS_CHOLQR, sizeof(double) * (size_t)(nd + 8), &p_cq));
@@ -846,7 +844,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     cq_status = (int*)(cq_ws + nd);
   }
   // only panels that never wait on each other's workgroups may run beside the
-  // trailing products: float64 CholeskyQR2 in its normal mode
+  // trailing products: CholeskyQR2 in its normal mode
   const bool lookahead = h->qr_lookahead && cq_ws && h->qr_panel == 0;
   if (lookahead) RFMLS_CHECK(lookahead_stream(h));
   hipStream_t st = h->stream;

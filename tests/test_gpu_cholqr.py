@@ -1,13 +1,14 @@
-"""The CholeskyQR2 panels of the float64 QR (with Householder reconstruction)
-against the unblocked Householder panels and the oracle.
+"""The CholeskyQR2 panels of the QR (with Householder reconstruction) against
+the unblocked Householder panels and the oracle.
 
 Mode 0 (default) factors 64-column panels of at least 1024 rows by CholeskyQR2
-on column-scaled Grams and reconstructs their Householder vectors; mode 1 uses
-the unblocked kernel throughout.  Both must satisfy R^T R = (SA)^T SA to a few
-n u, agree with each other and with the oracle's R to the sensitivity of R
-(about cond(SA) u), and give the same solve.  Modes 2 and 3 force the first or
-second Cholesky pass of every eligible panel to fail: the first fallback leaves
-the panel untouched for the unblocked kernel (bitwise mode 1's R), the second
+on column-scaled Grams and reconstructs their Householder vectors, in float64
+arithmetic for float64 and float32 panels alike; mode 1 uses the unblocked
+kernel throughout.  Both must satisfy R^T R = (SA)^T SA to a few n u, agree
+with each other and with the oracle's R to the sensitivity of R (about
+cond(SA) u), and give the same solve.  Modes 2 and 3 force the first or second
+Cholesky pass of every eligible panel to fail: the first fallback leaves the
+panel untouched for the unblocked kernel (bitwise mode 1's R), the second
 factors Q1 and multiplies by R1."""
 
 import numpy as np
@@ -24,16 +25,16 @@ R = pytest.importorskip("paper_2409_15818_amd")
 SEED = 2
 
 
-def _R(handle, SAo, mode):
+def _R(handle, SAo, mode, dtype="f64"):
     R.rfmls_qr_panel_mode(handle, mode)
     try:
-        SA = torch.tensor(SAo, device="cuda")
-        P = R.rfmls_precond(handle, SA, "f64", "f64")
+        SA = torch.tensor(SAo.astype(np.float64 if dtype == "f64" else np.float32), device="cuda")
+        P = R.rfmls_precond(handle, SA, dtype, dtype)
         Rg = R.rfmls_precond_export_R(handle, P).cpu().numpy()
         P.free()
     finally:
         R.rfmls_qr_panel_mode(handle, 0)
-    return Rg
+    return Rg.astype(np.float64)
 
 
 def _ident(Rg, SAo):
@@ -73,6 +74,55 @@ def test_cholqr_panels_match_householder_panels(handle, case):
     d0o = (np.abs(R0 - Ro) / scale).max()
     print(f"[cholqr] {label}: |R_cq - R_hh| {d01:.2e}, |R_cq - R_oracle| {d0o:.2e}", flush=True)
     assert d01 < rtol and d0o < rtol
+
+
+def _cases32():
+    rng = np.random.default_rng(5)
+    yield "gaussian 4096x64", rng.standard_normal((4096, 64))
+    yield "gaussian 6000x200 column scales 1e3", rng.standard_normal((6000, 200)) * np.geomspace(1.0, 1e3, 200)[None, :]
+    for name in ("poisson2d_3x3",):
+        S, s = build_config(name)
+        h, sign = countsketch.hash_sign(S.m, s, SEED)
+        SAo, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
+        yield name, SAo
+
+
+@pytest.mark.parametrize("case", list(_cases32()), ids=lambda c: c[0])
+def test_float32_cholqr_panels(handle, case):
+    """Float32 panels through CholeskyQR2 in float64 arithmetic: R^T R = (SA)^T SA
+    to the float32 rounding of the stored factor (SA rounded to float32 is the
+    input both ways), and R against the float32 unblocked kernel's and the float64
+    oracle's to R's sensitivity at float32 (about cond u32 per row's scale)."""
+    label, SAo = case
+    SA32 = SAo.astype(np.float32).astype(np.float64)
+    n = SAo.shape[1]
+    print(f"[cholqr32] {label} {SAo.shape}", flush=True)
+    R0 = _R(handle, SAo, 0, "f32")
+    R1 = _R(handle, SAo, 1, "f32")
+    u32 = 6e-8
+    assert np.all(np.diag(R0) > 0) and not np.tril(R0, -1).any()
+    e0, e1 = _ident(R0, SA32), _ident(R1, SA32)
+    print(f"[cholqr32] {label}: identity cholqr {e0:.2e} householder {e1:.2e}", flush=True)
+    assert e0 < 20 * n * u32 and e1 < 20 * n * u32
+    Ro = oqr.r_factor(SA32, check_rank=False)
+    scale = np.abs(Ro).max(axis=1, keepdims=True)
+    d0o = (np.abs(R0 - Ro) / scale).max()
+    d1o = (np.abs(R1 - Ro) / scale).max()
+    print(f"[cholqr32] {label}: |R_cq - R_oracle| {d0o:.2e}, |R_hh - R_oracle| {d1o:.2e}", flush=True)
+    # the float64-arithmetic panel is at least as close to the float64 R as the float32 kernel
+    assert d0o <= max(2.0 * d1o, 1e-6)
+
+
+def test_float32_cholqr_fallback_paths(handle):
+    SAo = dense_with_condition(3000, 128, 1e3, seed=8)
+    R1 = _R(handle, SAo, 1, "f32")
+    R2 = _R(handle, SAo, 2, "f32")
+    R3 = _R(handle, SAo, 3, "f32")
+    assert np.array_equal(R2, R1)
+    SA32 = SAo.astype(np.float32).astype(np.float64)
+    assert _ident(R3, SA32) < 20 * 128 * 6e-8
+    scale = np.abs(R1).max(axis=1, keepdims=True)
+    assert (np.abs(R3 - R1) / scale).max() < 1e-4
 
 
 def test_cholqr_fallback_paths(handle):
