@@ -167,6 +167,7 @@ enum WsSlot {
   WS_GEMV,
   WS_SVD,
   WS_SPMM_PART,
+  WS_SPMM_SPLIT,
   WS_SVD2,
   WS_APPLYQ,
   WS_MISC,

@@ -7,7 +7,8 @@
 //                  tile of X meets a 64 x 32 block of V on the matrix cores
 //                  (v_mfma_f64_16x16x4f64), so X is streamed once per
 //                  iteration for all 32 columns instead of 32 times
-//   U = A Z - U a  CSR SpMM: one wavefront per row, lanes over (column, entry)
+//   U = A Z - U a  CSR SpMM: 64-row groups times LDS-staged 32-wide input windows
+//                  on the matrix cores
 //   Q = A^T U      the same with the transpose
 //   V = X^T Q - V b
 // Vectors are interleaved row-major blocks (element (i, c) at i * 32 + c).
@@ -222,16 +223,66 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// CSR SpMM with LDS-staged input windows:
+// Entries [*b, *e) of row r in split z of nsplit: the columns in the z-th of
+// nsplit ranges cut at equal-count points of the group's first row r0 (binary
+// searches; malformed rows give some range, never one outside the row).
+__device__ __forceinline__ void spmm_split_range(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                 int64_t r0, int64_t r, int nsplit, int z, int64_t* b_out,
+                                                 int64_t* e_out) {
+  const int64_t b = rp[r], e = rp[r + 1];
+  const int64_t f0 = rp[r0], len0 = rp[r0 + 1] - rp[r0];
+  const int32_t lo = z == 0 ? INT32_MIN : (len0 > 0 ? col[f0 + (int64_t)z * len0 / nsplit] : INT32_MAX);
+  const int32_t hi = z == nsplit - 1 ? INT32_MAX : (len0 > 0 ? col[f0 + (int64_t)(z + 1) * len0 / nsplit] : INT32_MAX);
+  int64_t a = b, c2 = e;
+  while (a < c2) {
+    const int64_t mid = (a + c2) / 2;
+    if (col[mid] < lo) a = mid + 1;
+    else c2 = mid;
+  }
+  int64_t a2 = a, c3 = e;
+  if (hi != INT32_MAX) {
+    while (a2 < c3) {
+      const int64_t mid = (a2 + c3) / 2;
+      if (col[mid] < hi) a2 = mid + 1;
+      else c3 = mid;
+    }
+  } else {
+    a2 = e;
+  }
+  *b_out = a;
+  *e_out = a2;
+}
+
+// The split cursors of every row, once per matrix: splits[r][2 z] and
+// splits[r][2 z + 1] bound split z of row r, the range spmm_split_range gives
+// for row r's 64-row group.
+__global__ void k_spmm_splits(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t rows,
+                              int nsplit, int group, int64_t* __restrict__ splits) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t r0 = r / group * group;
+  for (int z = 0; z < nsplit; ++z) {
+    int64_t b, e;
+    spmm_split_range(rp, col, r0, r, nsplit, z, &b, &e);
+    splits[(r * nsplit + z) * 2] = b;
+    splits[(r * nsplit + z) * 2 + 1] = e;
+  }
+}
+
+// CSR SpMM on the matrix cores:
 //   out[row][c] = sA (M Xin)[row][c] - coef_c prev[row][c],  c < 32,
-// plus per-column partial sums of squares of out.  A workgroup takes kGroup
-// consecutive rows and walks their (ascending) column indices in windows of
-// kWin input rows: each window's 32-wide input rows are staged in LDS once,
-// with the group's entries that fall in it, and every row of the group then
-// accumulates from LDS.  Rows of one RFM box share their column runs (the
-// transpose's rows even share whole patterns), so a staged window serves the
-// whole group instead of being gathered from L2 once per nonzero.  Entries
-// are accumulated in CSR order, so results are deterministic.
+// plus per-column partial sums of squares of out.  A workgroup takes kSpmmGroup
+// (64) consecutive rows, wavefront w rows 16 w .. 16 w + 15, and walks their
+// (ascending) column indices in windows of W input rows, each starting at a
+// multiple of 4: the window's 32-wide input rows are staged in LDS, the group's
+// entries that fall in it are scattered into a dense 64 x W tile (zeros
+// elsewhere), and each wavefront multiplies its 16 x W slab by the W x 32
+// window (v_mfma_f64_16x16x4f64, two 16 x 16 output tiles).  Rows of one RFM box
+// share their column runs, so the tile is nearly dense and every staged input
+// row serves 64 rows through the matrix cores instead of one LDS gather per
+// entry and column.  Column j always falls in the K step of its aligned quad
+// j / 4 (windows start at multiples of 4), so every output is the same ordered
+// sum of quads whatever W is: the window width changes no result.
 // Malformed input (columns out of order or out of range) cannot make the
 // kernel read outside Xin or LDS: such entries end a window's prefix early.
 //
@@ -240,176 +291,198 @@ __global__ void __launch_bounds__(kThreads)
 // ranges cut at equal-count points of the group's first row, and writes its
 // raw sums to part[z][row][32]; k_spmm_merge adds the nsplit parts in order and
 // applies the scaling, the subtraction and the sums of squares.
-constexpr int kGroup = 16;
-constexpr int kWin = 128;
+constexpr int kSpmmGroup = 64;
 
-template <int kGroup = rfmls::kGroup, int kWin = rfmls::kWin>
+template <int W>
 __global__ void __launch_bounds__(kThreads)
     k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
            const double* __restrict__ val, int64_t rows, int64_t ncols, const double* __restrict__ Xin,
            double sA, double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
            double* out, double* __restrict__ sq, const BlockState* __restrict__ st, int nsplit,
-           double* __restrict__ part) {
+           double* __restrict__ part, const int64_t* __restrict__ splits) {
+  static_assert(W % 32 == 0 && W <= 128, "window");
   if (st && all_done(st)) return;
-  __shared__ double Xs[kWin][kBlk];
-  __shared__ double Vs[kGroup][kWin];
-  __shared__ int Cs[kGroup][kWin];
-  __shared__ int64_t cur[kGroup], endp[kGroup];
-  __shared__ int cnt[kGroup];
-  __shared__ int wmin[kGroup];
-  __shared__ double red[kThreads / kBlk][kBlk];
+  __shared__ double Xs[W][kBlk];
+  __shared__ double At[kSpmmGroup][W + 1];
+  __shared__ int64_t cur[kSpmmGroup], endp[kSpmmGroup];
+  __shared__ int wmin[4];
+  __shared__ int w0_s;
+  __shared__ double red[kThreads / 16][kBlk];
   const int tid = threadIdx.x;
-  constexpr int kSlots = kThreads / kBlk;  // 8 row slots of 32 columns
-  constexpr int RPS = kGroup / kSlots;      // rows per slot: slot, slot + 8, ...
-  static_assert(kGroup % kSlots == 0 && kThreads % kGroup == 0, "row group");
-  const int c = tid & (kBlk - 1), slot = tid / kBlk;
-  const int er = tid / (kThreads / kGroup), el = tid % (kThreads / kGroup);  // entry staging: row er, lane el
-  double cf = hcoef;
-  if (coef) cf *= coef[c * cstride];
-  const bool act = !st || !st->col[c].done;
-  double ss = 0.0;
-  const int64_t ngroups = (rows + kGroup - 1) / kGroup;
+  const int lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  double cf[2];
+  bool act[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = 16 * q + lr;
+    cf[q] = coef ? hcoef * coef[c * cstride] : hcoef;
+    act[q] = !st || !st->col[c].done;
+  }
+  double ss[2] = {0.0, 0.0};
+  const int64_t ngroups = (rows + kSpmmGroup - 1) / kSpmmGroup;
   for (int64_t wi = blockIdx.x; wi < ngroups * nsplit; wi += gridDim.x) {
     const int64_t gi = wi / nsplit;
     const int z = (int)(wi % nsplit);
-    const int64_t r0 = gi * kGroup;
-    if (tid < kGroup) {
+    const int64_t r0 = gi * kSpmmGroup;
+    if (tid < kSpmmGroup) {
       const int64_t r = r0 + tid;
       int64_t b = r < rows ? rp[r] : 0, e = r < rows ? rp[r + 1] : 0;
-      if (nsplit > 1) {
-        // column range [lo, hi) of split z, cut at equal-count points of row r0
-        const int64_t f0 = rp[r0], len0 = rp[r0 + 1] - rp[r0];
-        const int32_t lo = z == 0 ? INT32_MIN : (len0 > 0 ? col[f0 + (int64_t)z * len0 / nsplit] : INT32_MAX);
-        const int32_t hi = z == nsplit - 1 ? INT32_MAX
-                                           : (len0 > 0 ? col[f0 + (int64_t)(z + 1) * len0 / nsplit] : INT32_MAX);
-        // first entries of this row at or beyond lo and beyond hi (binary searches)
-        int64_t a = b, c2 = e;
-        while (a < c2) {
-          const int64_t mid = (a + c2) / 2;
-          if (col[mid] < lo) a = mid + 1;
-          else c2 = mid;
-        }
-        int64_t a2 = a, c3 = e;
-        if (hi != INT32_MAX) {
-          while (a2 < c3) {
-            const int64_t mid = (a2 + c3) / 2;
-            if (col[mid] < hi) a2 = mid + 1;
-            else c3 = mid;
-          }
+      if (nsplit > 1 && r < rows) {
+        if (splits) {
+          b = splits[(r * nsplit + z) * 2];
+          e = splits[(r * nsplit + z) * 2 + 1];
         } else {
-          a2 = e;
+          spmm_split_range(rp, col, r0, r, nsplit, z, &b, &e);
         }
-        b = a;
-        e = a2;
       }
       cur[tid] = b;
       endp[tid] = e;
     }
-    double acc[RPS];
+    v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+    __syncthreads();
+    if (w == 0) {
+      // first window: the smallest first column of the group, down to a multiple of 4
+      int m0 = cur[lane] < endp[lane] ? col[cur[lane]] : INT32_MAX;
 #pragma unroll
-    for (int h2 = 0; h2 < RPS; ++h2) acc[h2] = 0.0;
-    for (;;) {
-      __syncthreads();
-      if (tid < kGroup) wmin[tid] = cur[tid] < endp[tid] ? col[cur[tid]] : INT32_MAX;
-      __syncthreads();
-      int w0 = INT32_MAX;
-#pragma unroll
-      for (int t = 0; t < kGroup; ++t) w0 = wmin[t] < w0 ? wmin[t] : w0;
-      if (w0 == INT32_MAX) break;  // uniform: every thread computed the same w0
-      // stage the input rows [w0, w0 + kWin) (coalesced, 32 doubles per row)
-      for (int e = tid; e < kWin * kBlk; e += kThreads) {
-        const int64_t r = (int64_t)w0 + e / kBlk;
-        Xs[e / kBlk][e % kBlk] = (r >= 0 && r < ncols) ? Xin[r * kBlk + (e % kBlk)] : 0.0;
+      for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(m0, off, 64);
+        m0 = o < m0 ? o : m0;
       }
-      // stage each row's entries in the window; cnt = length of the in-window prefix
-      if (el == 0) cnt[er] = (int)(endp[er] - cur[er] < kWin ? endp[er] - cur[er] : kWin);
-      __syncthreads();
-      {
-        const int64_t base = cur[er];
-        int first_bad = kWin;
-        for (int j = el; j < kWin; j += kThreads / kGroup) {
-          const int64_t e = base + j;
-          bool ok = e < endp[er];
-          int cc = 0;
-          if (ok) {
-            cc = col[e] - w0;
-            ok = cc >= 0 && cc < kWin;
-          }
-          if (ok) {
-            Vs[er][j] = val[e];
-            Cs[er][j] = cc;
-          } else if (j < first_bad) {
-            first_bad = j;
-          }
-        }
-        atomicMin(&cnt[er], first_bad);
-      }
-      __syncthreads();
-      {
-        // 8 entries of each of the slot's rows at a time: all LDS loads issued
-        // before the (in-order) accumulation, so the loads overlap
-        int nr[RPS];
-        int nn = kWin;
-#pragma unroll
-        for (int h2 = 0; h2 < RPS; ++h2) {
-          nr[h2] = cnt[slot + kSlots * h2];
-          nn = nr[h2] < nn ? nr[h2] : nn;
-        }
-        int j = 0;
-        for (; j + 8 <= nn; j += 8) {
-          int cx[RPS][8];
-          double vx[RPS][8], xx[RPS][8];
-#pragma unroll
-          for (int h2 = 0; h2 < RPS; ++h2)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              cx[h2][q] = Cs[slot + kSlots * h2][j + q];
-              vx[h2][q] = Vs[slot + kSlots * h2][j + q];
-            }
-#pragma unroll
-          for (int h2 = 0; h2 < RPS; ++h2)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) xx[h2][q] = Xs[cx[h2][q]][c];
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int h2 = 0; h2 < RPS; ++h2) acc[h2] += vx[h2][q] * xx[h2][q];
-        }
-#pragma unroll
-        for (int h2 = 0; h2 < RPS; ++h2) {
-          const int t = slot + kSlots * h2;
-          for (int jj = j; jj < nr[h2]; ++jj) acc[h2] += Vs[t][jj] * Xs[Cs[t][jj]][c];
-        }
-      }
-      __syncthreads();
-      if (tid < kGroup) cur[tid] += cnt[tid];
+      if (lane == 0) w0_s = m0;
     }
-    // write the group's rows (a split group: its raw partial sums)
+    __syncthreads();
+    int w0 = w0_s == INT32_MAX ? INT32_MAX : (w0_s & ~3);
+    // Window data in registers: the input rows [w0, w0 + W) (coalesced, 32
+    // doubles per row) and, per wavefront, the next W entries of each of its 16
+    // rows (64 lanes over consecutive entries).  The next window's are loaded
+    // while the matrix cores work on the current one.
+    constexpr int kXPer = W * kBlk / kThreads;
+    constexpr int kH = (W + 63) / 64;
+    double xr[kXPer];
+    int cj[16][kH];
+    double vj[16][kH];
+    bool inr[16][kH];
+    auto load = [&](int ws) {
+#pragma unroll
+      for (int q = 0; q < kXPer; ++q) {
+        const int e = tid + q * kThreads;
+        const int64_t r = (int64_t)ws + e / kBlk;
+        xr[q] = (r >= 0 && r < ncols) ? Xin[r * kBlk + (e % kBlk)] : 0.0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int row = 16 * w + rr;
+        const int64_t base = cur[row], end = endp[row];
+#pragma unroll
+        for (int h = 0; h < kH; ++h) {
+          const int j = lane + 64 * h;
+          const int64_t e = base + j;
+          inr[rr][h] = j < W && e < end;
+          cj[rr][h] = inr[rr][h] ? col[e] : 0;
+          vj[rr][h] = inr[rr][h] ? val[e] : 0.0;
+        }
+      }
+    };
+    if (w0 != INT32_MAX) load(w0);
+    while (w0 != INT32_MAX) {  // uniform
+      // the tile starts empty (the previous window's products are done)
+      for (int e = tid; e < kSpmmGroup * W; e += kThreads) At[e / W][e % W] = 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kXPer; ++q) {
+        const int e = tid + q * kThreads;
+        Xs[e / kBlk][e % kBlk] = xr[q];
+      }
+      // each row's in-window prefix (its entries in order until the first one
+      // outside the window) into the tile; the row's cursor moves past it, and
+      // its next column is the first entry left (or, after W entries in a row,
+      // at least w0 + W: W distinct ascending columns filled the window)
+      const int lb = (int)((int64_t)w0 + W < (int64_t)INT32_MAX ? (int64_t)w0 + W : (int64_t)INT32_MAX - 1);
+      int nxt = INT32_MAX;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int row = 16 * w + rr;
+        int fb = W;
+#pragma unroll
+        for (int h = 0; h < kH; ++h) {
+          const int j = lane + 64 * h;
+          const int cc = cj[rr][h] - w0;
+          const bool ok = inr[rr][h] && cc >= 0 && cc < W;
+          const unsigned long long bad = __ballot(j < W && !ok);
+          if (bad) {
+            const int f = 64 * h + __builtin_ctzll(bad);
+            fb = f < fb ? f : fb;
+          }
+        }
+        // the row's next column: none if the row is finished; its first entry
+        // left if the window took none of it (lane 0's column, a scalar read);
+        // else at least w0 + W (it took entries up to the first that is not in
+        // the window, whose column, the columns ascending, lies beyond it)
+        const int64_t rbase = cur[row], rend = endp[row];
+        int rn;
+        if (rbase + fb >= rend) rn = INT32_MAX;
+        else if (fb == 0) rn = __builtin_amdgcn_readlane(cj[rr][0], 0);
+        else rn = lb;
+        nxt = rn < nxt ? rn : nxt;
+#pragma unroll
+        for (int h = 0; h < kH; ++h) {
+          const int j = lane + 64 * h;
+          if (j < fb) At[row][cj[rr][h] - w0] = vj[rr][h];
+        }
+        if (lane == 0) cur[row] = rbase + fb;  // read back by this wavefront after the barrier below
+      }
+      if (lane == 0) wmin[w] = nxt;
+      __syncthreads();
+      int wn = wmin[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) wn = wmin[q] < wn ? wmin[q] : wn;
+      wn = wn == INT32_MAX ? INT32_MAX : (wn & ~3);
+      if (wn != INT32_MAX) load(wn);
+      // the wavefront's 16 x W slab times the W x 32 window
+#pragma unroll 4
+      for (int s4 = 0; s4 < W / 4; ++s4) {
+        const double a = At[16 * w + lr][4 * s4 + lk];
+        const double b0 = Xs[4 * s4 + lk][lr], b1 = Xs[4 * s4 + lk][16 + lr];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[1], 0, 0, 0);
+      }
+      w0 = wn;
+      __syncthreads();
+    }
+    // register r of tile q: row 16 w + lk + 4 r, column 16 q + lr
     if (nsplit > 1) {
 #pragma unroll
-      for (int h2 = 0; h2 < RPS; ++h2) {
-        const int64_t row = r0 + slot + kSlots * h2;
-        if (row < rows) part[((int64_t)z * rows + row) * kBlk + c] = acc[h2];
-      }
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + 16 * w + lk + 4 * r;
+          if (row < rows) part[((int64_t)z * rows + row) * kBlk + 16 * q + lr] = acc[q][r];
+        }
       continue;
     }
 #pragma unroll
-    for (int h2 = 0; h2 < RPS; ++h2) {
-      const int64_t row = r0 + slot + kSlots * h2;
-      if (row < rows) {
-        double o = sA * acc[h2];
-        if (prev && cf != 0.0) o -= cf * prev[row * kBlk + c];
-        if (act) out[row * kBlk + c] = o;
-        ss += o * o;
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 16 * w + lk + 4 * r;
+        const int c = 16 * q + lr;
+        if (row < rows) {
+          double o = sA * acc[q][r];
+          if (prev && cf[q] != 0.0) o -= cf[q] * prev[row * kBlk + c];
+          if (act[q]) out[row * kBlk + c] = o;
+          ss[q] += o * o;
+        }
       }
-    }
   }
   if (sq) {
-    red[slot][c] = ss;
+    // per column: the 16 lane groups (4 per wavefront) in order
+#pragma unroll
+    for (int q = 0; q < 2; ++q) red[4 * w + lk][16 * q + lr] = ss[q];
     __syncthreads();
     if (tid < kBlk) {
       double t = 0.0;
-      for (int q = 0; q < kThreads / kBlk; ++q) t += red[q][tid];
+      for (int g = 0; g < kThreads / 16; ++g) t += red[g][tid];
       sq[blockIdx.x * kBlk + tid] = t;
     }
   }
@@ -752,56 +825,42 @@ unsigned rows_grid(int64_t rows) {  // blocks of 8 rows x 32 columns, grid-strid
   const int64_t b = (rows + (kThreads / kBlk) - 1) / (kThreads / kBlk);
   return (unsigned)(b < kRowBlocks ? (b > 0 ? b : 1) : kRowBlocks);
 }
-unsigned spmm_grid(int64_t rows) {  // row groups of 16, grid-stride beyond kSpmmBlocks
-  const int64_t b = (rows + kGroup - 1) / kGroup;
+unsigned spmm_grid(int64_t rows) {  // 16-row groups, grid-stride beyond kSpmmBlocks
+  const int64_t b = (rows + 15) / 16;
   return (unsigned)(b < kSpmmBlocks ? (b > 0 ? b : 1) : kSpmmBlocks);
 }
 
-// SpMM launch shapes.  The row-group height follows the average row length
-// (measured on gfx950, 32 columns): short rows (the RFM matrix, 200-400
-// entries) in groups of 16, long rows (its transpose, ~2000 entries) in groups
-// of 8, whose smaller LDS footprint keeps more blocks resident (the kernel is
-// latency-bound); grids stop at about the resident block count.  The window
-// width (columns of the input block staged in LDS at a time) is chosen per
-// matrix by the autotuner below: it changes neither the order of any sum nor
-// the rows each block handles (so not the norm partials either), so every
-// candidate gives bitwise the same result.
+// SpMM launch shapes: 64-row groups; the window width (columns of the input
+// block staged in LDS at a time) is chosen per matrix by the autotuner below.
+// It changes neither the order of any sum nor the rows each block handles (so
+// not the norm partials either), so every candidate gives bitwise the same
+// result.  Grids stop at kSpmmGrid blocks (grid-stride over the groups beyond).
+constexpr unsigned kSpmmGrid = 1536;
 struct SpmmShape {
   const void* fn;
   int group, win;
   unsigned max_blocks;  // grid cap (grid-stride over the groups beyond it)
 };
-static int spmm_group(const rfmls_csr* M) { return (M->m > 0 && M->nnz / M->m > 512) ? 8 : 16; }
 // the hand-picked shape (used when tuning is off, and the tuner's reference)
-SpmmShape spmm_shape(const rfmls_csr* M) {
-  if (spmm_group(M) == 8) return {(const void*)k_spmm<8, 32>, 8, 32, 1792};
-  return {(const void*)k_spmm<16, 64>, 16, 64, 1024};
-}
+SpmmShape spmm_shape(const rfmls_csr*) { return {(const void*)k_spmm<64>, kSpmmGroup, 64, kSpmmGrid}; }
 static std::vector<SpmmShape> spmm_candidates(const rfmls_csr* M, int /*num_cus*/) {
   std::vector<SpmmShape> c;
   c.push_back(spmm_shape(M));
-  if (spmm_group(M) == 8) {
-    c.push_back({(const void*)k_spmm<8, 64>, 8, 64, 1792});
-    c.push_back({(const void*)k_spmm<8, 128>, 8, 128, 1792});
-    c.push_back({(const void*)k_spmm<8, 16>, 8, 16, 1792});
-  } else {
-    c.push_back({(const void*)k_spmm<16, 32>, 16, 32, 1024});
-    c.push_back({(const void*)k_spmm<16, 128>, 16, 128, 1024});
-  }
+  c.push_back({(const void*)k_spmm<32>, kSpmmGroup, 32, kSpmmGrid});
+  c.push_back({(const void*)k_spmm<128>, kSpmmGroup, 128, kSpmmGrid});
   return c;
 }
 // Split row groups of a matrix with fewer than 4 groups per compute unit and
-// long rows (at least 8 windows per split) so that the grid covers the chip:
-// nsplit = ceil(4 CUs / groups), at most 8.
+// long rows (at least 4 windows of 64 per split) so that the grid covers the
+// chip: nsplit = ceil(4 CUs / groups), at most 8.
 int spmm_split(const rfmls_csr* M, int num_cus) {
-  const SpmmShape sh = spmm_shape(M);
-  const int64_t ng = (M->m + sh.group - 1) / sh.group;
+  const int64_t ng = (M->m + kSpmmGroup - 1) / kSpmmGroup;
   const int64_t target = 4 * (int64_t)num_cus;
-  if (ng <= 0 || ng >= target || M->nnz / M->m < 8 * 32) return 1;
+  if (ng <= 0 || ng >= target || M->nnz / M->m < 8 * 64) return 1;
   const int64_t sp = (target + ng - 1) / ng;
-  const int64_t win = M->nnz / M->m / 32;  // windows of a row at the long-row shape
+  const int64_t win = M->nnz / M->m / 64;  // windows of 64 columns of a row
   int64_t k = sp < 8 ? sp : 8;
-  while (k > 1 && win / k < 8) --k;
+  while (k > 1 && win / k < 4) --k;
   return (int)k;
 }
 struct BCtx {
@@ -813,6 +872,8 @@ struct BCtx {
   double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX, *Sm, *Sn;
   double *sqA, *sqB, *sqY, *sqW, *part;
   double* spart;  // partial sums of split SpMM groups (nsplit x rows x 32)
+  const int64_t* splitA = nullptr;   // split cursors of A's rows (k_spmm_splits), if A is split
+  const int64_t* splitAT = nullptr;  // the same for A^T
   BlockState* dst;
   IterGraph* graph = nullptr;  // captured poll interval of the loop, or null: eager launches
 };
@@ -968,9 +1029,10 @@ static rfmls_status spmm_launch(BCtx& c, const rfmls_csr* M, const SpmmShape& sh
            2.0 * kBlk * (double)M->nnz);
   int kStride_v = kStride;
   double* spart = c.spart;
+  const int64_t* splits = nsplit > 1 ? (M == c.A ? c.splitA : (M == c.AT ? c.splitAT : nullptr)) : nullptr;
   void* args[] = {(void*)&M->row_ptr, (void*)&M->col, (void*)&M->val, (void*)&M->m, (void*)&M->n,
                   (void*)&x, (void*)&sA, (void*)&hcoef, (void*)&coef, (void*)&kStride_v, (void*)&prev,
-                  (void*)&out, (void*)&sq, (void*)&stp, (void*)&nsplit, (void*)&spart};
+                  (void*)&out, (void*)&sq, (void*)&stp, (void*)&nsplit, (void*)&spart, (void*)&splits};
   RFMLS_HIP(c.h, hipLaunchKernel(sh.fn, dim3(nb), dim3(kThreads), args, 0, c.st));
   if (nsplit > 1) {
     const unsigned gm = rows_grid(M->m);
@@ -1120,6 +1182,28 @@ static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_c
     void* pp;
     RFMLS_CHECK(workspace(h, WS_SPMM_PART, sizeof(double) * (size_t)need * kBlk, &pp));
     c.spart = (double*)pp;
+  }
+  {
+    // split cursors, computed once here instead of by every work item
+    const int sa = spmm_split(A, h->num_cus), st = AT != A ? spmm_split(AT, h->num_cus) : 1;
+    const int64_t na = sa > 1 ? 2 * sa * A->m : 0, nt = st > 1 ? 2 * st * AT->m : 0;
+    if (na + nt > 0) {
+      void* pt;
+      RFMLS_CHECK(workspace(h, WS_SPMM_SPLIT, sizeof(int64_t) * (size_t)(na + nt), &pt));
+      int64_t* tab = (int64_t*)pt;
+      if (na > 0) {
+        hipLaunchKernelGGL(k_spmm_splits, dim3(ceil_div(A->m, 256)), dim3(256), 0, c.st, A->row_ptr, A->col, A->m, sa,
+                           kSpmmGroup, tab);
+        c.splitA = tab;
+      }
+      if (nt > 0) {
+        hipLaunchKernelGGL(k_spmm_splits, dim3(ceil_div(AT->m, 256)), dim3(256), 0, c.st, AT->row_ptr, AT->col,
+                           AT->m, st, kSpmmGroup, tab + na);
+        c.splitAT = tab + na;
+      }
+      RFMLS_HIP(h, hipGetLastError());
+    }
+    if (AT == A) c.splitAT = c.splitA;
   }
   void* ps;
   RFMLS_CHECK(workspace(h, WS_LSQR_BSTATE, sizeof(BlockState), &ps));
