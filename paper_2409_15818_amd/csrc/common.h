@@ -167,7 +167,10 @@ enum WsSlot {
   WS_GEMV,
   WS_SVD,
   WS_SPMM_PART,
-  WS_SPMM_SPLIT,
+  WS_SPMM_WPTR_A,
+  WS_SPMM_WDESC_A,
+  WS_SPMM_WPTR_AT,
+  WS_SPMM_WDESC_AT,
   WS_SVD2,
   WS_APPLYQ,
   WS_MISC,

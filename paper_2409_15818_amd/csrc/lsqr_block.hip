@@ -32,7 +32,7 @@ constexpr int kSpmmMaxBlocks = 2048;  // capacity of the per-column partial-sum 
 // stride loops), and the single-block kernels that fold the partials into the
 // column scalars use 1024 threads (32 columns x 32 slices).
 constexpr int kSpmmBlocks = 512;
-constexpr int kRowBlocks = 256;
+constexpr int kRowBlocks = 1024;  // 8-row blocks: enough loads in flight for the row-wise passes
 constexpr int kRedThreads = 1024;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -207,7 +207,17 @@ __global__ void __launch_bounds__(kThreads)
     const int r = (int)(i % kTile);
     const int64_t nk = trans ? (col_end(I, nt, full) + C - 1) / C : (nt - row_first(I, full) + C - 1) / C;
     double s = 0.0;
-    for (int64_t kq = 0; kq < nk; ++kq) s += part[((I * maxk + kq) * kTile + r) * kBlk + c];
+    // the partials in chunk order; the loads of eight at a time are in flight together
+    const double* pp = part + ((I * maxk) * kTile + r) * kBlk + c;
+    int64_t kq = 0;
+    for (; kq + 8 <= nk; kq += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = pp[(kq + q) * kTile * kBlk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; kq < nk; ++kq) s += pp[kq * kTile * kBlk];
     if (prev && cf != 0.0) s -= cf * prev[i * kBlk + c];
     if (act) out[i * kBlk + c] = s;
     ss += s * s;
@@ -253,38 +263,27 @@ __device__ __forceinline__ void spmm_split_range(const int64_t* __restrict__ rp,
   *e_out = a2;
 }
 
-// The split cursors of every row, once per matrix: splits[r][2 z] and
-// splits[r][2 z + 1] bound split z of row r, the range spmm_split_range gives
-// for row r's 64-row group.
-__global__ void k_spmm_splits(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t rows,
-                              int nsplit, int group, int64_t* __restrict__ splits) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const int64_t r0 = r / group * group;
-  for (int z = 0; z < nsplit; ++z) {
-    int64_t b, e;
-    spmm_split_range(rp, col, r0, r, nsplit, z, &b, &e);
-    splits[(r * nsplit + z) * 2] = b;
-    splits[(r * nsplit + z) * 2 + 1] = e;
-  }
-}
-
 // CSR SpMM on the matrix cores:
 //   out[row][c] = sA (M Xin)[row][c] - coef_c prev[row][c],  c < 32,
-// plus per-column partial sums of squares of out.  A workgroup takes kSpmmGroup
-// (64) consecutive rows, wavefront w rows 16 w .. 16 w + 15, and walks their
-// (ascending) column indices in windows of W input rows, each starting at a
-// multiple of 4: the window's 32-wide input rows are staged in LDS, the group's
-// entries that fall in it are scattered into a dense 64 x W tile (zeros
-// elsewhere), and each wavefront multiplies its 16 x W slab by the W x 32
-// window (v_mfma_f64_16x16x4f64, two 16 x 16 output tiles).  Rows of one RFM box
-// share their column runs, so the tile is nearly dense and every staged input
-// row serves 64 rows through the matrix cores instead of one LDS gather per
-// entry and column.  Column j always falls in the K step of its aligned quad
-// j / 4 (windows start at multiples of 4), so every output is the same ordered
-// sum of quads whatever W is: the window width changes no result.
-// Malformed input (columns out of order or out of range) cannot make the
-// kernel read outside Xin or LDS: such entries end a window's prefix early.
+// plus per-column partial sums of squares of out.  Rows go in groups of
+// kSpmmGroup (64), wavefront w of a workgroup rows 16 w .. 16 w + 15; a group's
+// (ascending) column indices are walked in windows of W input rows, each
+// starting at a multiple of 4: the window's 32-wide input rows are staged in
+// LDS, the group's entries that fall in it are scattered into a dense 64 x W
+// tile (zeros elsewhere), and each wavefront multiplies its 16 x W slab by the
+// W x 32 window (v_mfma_f64_16x16x4f64, two 16 x 16 output tiles).  Rows of one
+// RFM box share their column runs, so the tile is nearly dense and every staged
+// input row serves 64 rows through the matrix cores.  Column j always falls in
+// the K step of its aligned quad j / 4, so every output is the same ordered sum
+// of quads whatever W is: the window width changes no result.
+//
+// The walk depends only on the matrix, so k_spmm_walk runs it once per solve
+// and records descriptors: per work item its windows, per window its start
+// column, per window and row the row's first entry in it and their number (the
+// row's entries in order until the first one outside the window).  k_spmm then
+// only loads and multiplies.  Malformed input (columns out of order or out of
+// range) ends a prefix early and cannot make either kernel read outside Xin or
+// LDS.
 //
 // Split groups (nsplit > 1, for matrices with few long rows): work item
 // (group, z) takes only the entries whose column lies in the z-th of nsplit
@@ -292,34 +291,25 @@ __global__ void k_spmm_splits(const int64_t* __restrict__ rp, const int32_t* __r
 // raw sums to part[z][row][32]; k_spmm_merge adds the nsplit parts in order and
 // applies the scaling, the subtraction and the sums of squares.
 constexpr int kSpmmGroup = 64;
+constexpr int kDescCntShift = 48;  // descriptor: first entry | count << 48
 
-template <int W>
+// One pass of the window walk over every work item.  Count pass: wcount[item]
+// = its number of windows.  Fill pass (wptr = exclusive scan of the counts):
+// window k of the item (global index wptr[item] + k) gets its start in
+// wstart[k] and, for each of the group's 64 rows, the descriptor in
+// wdesc[k * 64 + row].
+template <int W, bool Fill>
 __global__ void __launch_bounds__(kThreads)
-    k_spmm(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-           const double* __restrict__ val, int64_t rows, int64_t ncols, const double* __restrict__ Xin,
-           double sA, double hcoef, const double* __restrict__ coef, int cstride, const double* prev,
-           double* out, double* __restrict__ sq, const BlockState* __restrict__ st, int nsplit,
-           double* __restrict__ part, const int64_t* __restrict__ splits) {
+    k_spmm_walk(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t rows, int nsplit,
+                int32_t* __restrict__ wcount, const int64_t* __restrict__ wptr, int32_t* __restrict__ wstart,
+                int64_t* __restrict__ wdesc) {
   static_assert(W % 32 == 0 && W <= 128, "window");
-  if (st && all_done(st)) return;
-  __shared__ double Xs[W][kBlk];
-  __shared__ double At[kSpmmGroup][W + 1];
+  constexpr int kH = (W + 63) / 64;
   __shared__ int64_t cur[kSpmmGroup], endp[kSpmmGroup];
   __shared__ int wmin[4];
   __shared__ int w0_s;
-  __shared__ double red[kThreads / 16][kBlk];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  double cf[2];
-  bool act[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int c = 16 * q + lr;
-    cf[q] = coef ? hcoef * coef[c * cstride] : hcoef;
-    act[q] = !st || !st->col[c].done;
-  }
-  double ss[2] = {0.0, 0.0};
   const int64_t ngroups = (rows + kSpmmGroup - 1) / kSpmmGroup;
   for (int64_t wi = blockIdx.x; wi < ngroups * nsplit; wi += gridDim.x) {
     const int64_t gi = wi / nsplit;
@@ -328,21 +318,13 @@ __global__ void __launch_bounds__(kThreads)
     if (tid < kSpmmGroup) {
       const int64_t r = r0 + tid;
       int64_t b = r < rows ? rp[r] : 0, e = r < rows ? rp[r + 1] : 0;
-      if (nsplit > 1 && r < rows) {
-        if (splits) {
-          b = splits[(r * nsplit + z) * 2];
-          e = splits[(r * nsplit + z) * 2 + 1];
-        } else {
-          spmm_split_range(rp, col, r0, r, nsplit, z, &b, &e);
-        }
-      }
+      if (nsplit > 1 && r < rows) spmm_split_range(rp, col, r0, r, nsplit, z, &b, &e);
       cur[tid] = b;
       endp[tid] = e;
     }
-    v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
     __syncthreads();
     if (w == 0) {
-      // first window: the smallest first column of the group, down to a multiple of 4
+      // first window: the smallest first column of the group
       int m0 = cur[lane] < endp[lane] ? col[cur[lane]] : INT32_MAX;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -353,39 +335,127 @@ __global__ void __launch_bounds__(kThreads)
     }
     __syncthreads();
     int w0 = w0_s == INT32_MAX ? INT32_MAX : (w0_s & ~3);
-    // Window data in registers: the input rows [w0, w0 + W) (coalesced, 32
-    // doubles per row) and, per wavefront, the next W entries of each of its 16
-    // rows (64 lanes over consecutive entries).  The next window's are loaded
-    // while the matrix cores work on the current one.
-    constexpr int kXPer = W * kBlk / kThreads;
-    constexpr int kH = (W + 63) / 64;
-    double xr[kXPer];
-    int cj[16][kH];
-    double vj[16][kH];
-    bool inr[16][kH];
-    auto load = [&](int ws) {
-#pragma unroll
-      for (int q = 0; q < kXPer; ++q) {
-        const int e = tid + q * kThreads;
-        const int64_t r = (int64_t)ws + e / kBlk;
-        xr[q] = (r >= 0 && r < ncols) ? Xin[r * kBlk + (e % kBlk)] : 0.0;
-      }
-#pragma unroll
+    int64_t k = Fill ? wptr[wi] : 0;
+    while (w0 != INT32_MAX) {  // uniform
+      // each row's in-window prefix: its entries in order until the first one
+      // outside the window; its next column is none if the row is finished,
+      // its first entry left if the window took none of it, else at least
+      // w0 + W (it took entries up to the first that is not in the window,
+      // whose column, the columns ascending, lies beyond it)
+      const int lb = (int)((int64_t)w0 + W < (int64_t)INT32_MAX ? (int64_t)w0 + W : (int64_t)INT32_MAX - 1);
+      int nxt = INT32_MAX;
       for (int rr = 0; rr < 16; ++rr) {
         const int row = 16 * w + rr;
         const int64_t base = cur[row], end = endp[row];
+        int fb = W, c0 = 0;
 #pragma unroll
         for (int h = 0; h < kH; ++h) {
           const int j = lane + 64 * h;
           const int64_t e = base + j;
-          inr[rr][h] = j < W && e < end;
-          cj[rr][h] = inr[rr][h] ? col[e] : 0;
-          vj[rr][h] = inr[rr][h] ? val[e] : 0.0;
+          const bool in = j < W && e < end;
+          const int cj = in ? col[e] : 0;
+          if (h == 0) c0 = cj;
+          const int cc = cj - w0;
+          const bool ok = in && cc >= 0 && cc < W;
+          const unsigned long long bad = __ballot(j < W && !ok);
+          if (bad) {
+            const int f = 64 * h + __builtin_ctzll(bad);
+            fb = f < fb ? f : fb;
+          }
+        }
+        int rn;
+        if (base + fb >= end) rn = INT32_MAX;
+        else if (fb == 0) rn = __builtin_amdgcn_readlane(c0, 0);
+        else rn = lb;
+        nxt = rn < nxt ? rn : nxt;
+        if (lane == 0) {
+          if (Fill) wdesc[k * kSpmmGroup + row] = base | ((int64_t)fb << kDescCntShift);
+          cur[row] = base + fb;
         }
       }
-    };
-    if (w0 != INT32_MAX) load(w0);
-    while (w0 != INT32_MAX) {  // uniform
+      if (lane == 0) wmin[w] = nxt;
+      if (Fill && tid == 0) wstart[k] = w0;
+      __syncthreads();
+      int wn = wmin[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) wn = wmin[q] < wn ? wmin[q] : wn;
+      w0 = wn == INT32_MAX ? INT32_MAX : (wn & ~3);
+      ++k;
+      __syncthreads();
+    }
+    if (!Fill && tid == 0) wcount[wi] = (int32_t)k;
+  }
+}
+
+template <int W>
+__global__ void __launch_bounds__(kThreads)
+    k_spmm(const int32_t* __restrict__ col, const double* __restrict__ val, int64_t rows, int64_t ncols,
+           const double* __restrict__ Xin, double sA, double hcoef, const double* __restrict__ coef, int cstride,
+           const double* prev, double* out, double* __restrict__ sq, const BlockState* __restrict__ st, int nsplit,
+           double* __restrict__ part, const int64_t* __restrict__ wptr, const int32_t* __restrict__ wstart,
+           const int64_t* __restrict__ wdesc) {
+  static_assert(W % 32 == 0 && W <= 128, "window");
+  if (st && all_done(st)) return;
+  __shared__ double Xs[W][kBlk];
+  __shared__ double At[kSpmmGroup][W + 1];
+  __shared__ double red[kThreads / 16][kBlk];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  double cf[2];
+  bool act[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = 16 * q + lr;
+    cf[q] = coef ? hcoef * coef[c * cstride] : hcoef;
+    act[q] = !st || !st->col[c].done;
+  }
+  double ss[2] = {0.0, 0.0};
+  // Window data in registers: the input rows [w0, w0 + W) (coalesced, 32
+  // doubles per row) and, per wavefront, each of its 16 rows' entries in the
+  // window (64 lanes over consecutive entries).  The next window's are loaded
+  // while the matrix cores work on the current one.
+  constexpr int kXPer = W * kBlk / kThreads;
+  constexpr int kH = (W + 63) / 64;
+  double xr[kXPer];
+  int cj[16][kH];
+  double vj[16][kH];
+  int w0 = 0;
+  auto load = [&](int64_t k) {
+    w0 = wstart[k];
+#pragma unroll
+    for (int q = 0; q < kXPer; ++q) {
+      const int e = tid + q * kThreads;
+      const int64_t r = (int64_t)w0 + e / kBlk;
+      xr[q] = (r >= 0 && r < ncols) ? Xin[r * kBlk + (e % kBlk)] : 0.0;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const int64_t d = wdesc[k * kSpmmGroup + 16 * w + rr];
+      const int64_t base = d & ((1ll << kDescCntShift) - 1);
+      const int cnt = (int)(d >> kDescCntShift);
+#pragma unroll
+      for (int h = 0; h < kH; ++h) {
+        const int j = lane + 64 * h;
+        const bool in = j < cnt;
+        cj[rr][h] = in ? col[base + j] : -1;
+        vj[rr][h] = in ? val[base + j] : 0.0;
+      }
+    }
+  };
+  const int64_t items = ((rows + kSpmmGroup - 1) / kSpmmGroup) * nsplit;
+  // the last items first: a matrix's last rows (the RFM's interface rows, two
+  // boxes' columns each) have the most windows, and blocks are dispatched in order
+  for (int64_t wb = blockIdx.x; wb < items; wb += gridDim.x) {
+    const int64_t wi = items - 1 - wb;
+    const int64_t gi = wi / nsplit;
+    const int z = (int)(wi % nsplit);
+    const int64_t r0 = gi * kSpmmGroup;
+    const int64_t kb = wptr[wi], ke = wptr[wi + 1];
+    v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+    if (kb < ke) load(kb);
+    for (int64_t k = kb; k < ke; ++k) {
       // the tile starts empty (the previous window's products are done)
       for (int e = tid; e < kSpmmGroup * W; e += kThreads) At[e / W][e % W] = 0.0;
       __syncthreads();
@@ -394,51 +464,13 @@ __global__ void __launch_bounds__(kThreads)
         const int e = tid + q * kThreads;
         Xs[e / kBlk][e % kBlk] = xr[q];
       }
-      // each row's in-window prefix (its entries in order until the first one
-      // outside the window) into the tile; the row's cursor moves past it, and
-      // its next column is the first entry left (or, after W entries in a row,
-      // at least w0 + W: W distinct ascending columns filled the window)
-      const int lb = (int)((int64_t)w0 + W < (int64_t)INT32_MAX ? (int64_t)w0 + W : (int64_t)INT32_MAX - 1);
-      int nxt = INT32_MAX;
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int row = 16 * w + rr;
-        int fb = W;
+      for (int rr = 0; rr < 16; ++rr)
 #pragma unroll
-        for (int h = 0; h < kH; ++h) {
-          const int j = lane + 64 * h;
-          const int cc = cj[rr][h] - w0;
-          const bool ok = inr[rr][h] && cc >= 0 && cc < W;
-          const unsigned long long bad = __ballot(j < W && !ok);
-          if (bad) {
-            const int f = 64 * h + __builtin_ctzll(bad);
-            fb = f < fb ? f : fb;
-          }
-        }
-        // the row's next column: none if the row is finished; its first entry
-        // left if the window took none of it (lane 0's column, a scalar read);
-        // else at least w0 + W (it took entries up to the first that is not in
-        // the window, whose column, the columns ascending, lies beyond it)
-        const int64_t rbase = cur[row], rend = endp[row];
-        int rn;
-        if (rbase + fb >= rend) rn = INT32_MAX;
-        else if (fb == 0) rn = __builtin_amdgcn_readlane(cj[rr][0], 0);
-        else rn = lb;
-        nxt = rn < nxt ? rn : nxt;
-#pragma unroll
-        for (int h = 0; h < kH; ++h) {
-          const int j = lane + 64 * h;
-          if (j < fb) At[row][cj[rr][h] - w0] = vj[rr][h];
-        }
-        if (lane == 0) cur[row] = rbase + fb;  // read back by this wavefront after the barrier below
-      }
-      if (lane == 0) wmin[w] = nxt;
+        for (int h = 0; h < kH; ++h)
+          if (cj[rr][h] >= 0) At[16 * w + rr][cj[rr][h] - w0] = vj[rr][h];
       __syncthreads();
-      int wn = wmin[0];
-#pragma unroll
-      for (int q = 1; q < 4; ++q) wn = wmin[q] < wn ? wmin[q] : wn;
-      wn = wn == INT32_MAX ? INT32_MAX : (wn & ~3);
-      if (wn != INT32_MAX) load(wn);
+      if (k + 1 < ke) load(k + 1);
       // the wavefront's 16 x W slab times the W x 32 window
 #pragma unroll 4
       for (int s4 = 0; s4 < W / 4; ++s4) {
@@ -447,7 +479,6 @@ __global__ void __launch_bounds__(kThreads)
         acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[1], 0, 0, 0);
       }
-      w0 = wn;
       __syncthreads();
     }
     // register r of tile q: row 16 w + lk + 4 r, column 16 q + lr
@@ -834,8 +865,9 @@ unsigned spmm_grid(int64_t rows) {  // 16-row groups, grid-stride beyond kSpmmBl
 // block staged in LDS at a time) is chosen per matrix by the autotuner below.
 // It changes neither the order of any sum nor the rows each block handles (so
 // not the norm partials either), so every candidate gives bitwise the same
-// result.  Grids stop at kSpmmGrid blocks (grid-stride over the groups beyond).
-constexpr unsigned kSpmmGrid = 1536;
+// result.  Grids stop at kSpmmGrid blocks (grid-stride over the groups beyond):
+// up to 2048 groups one block each.
+constexpr unsigned kSpmmGrid = kSpmmMaxBlocks;
 struct SpmmShape {
   const void* fn;
   int group, win;
@@ -863,6 +895,16 @@ int spmm_split(const rfmls_csr* M, int num_cus) {
   while (k > 1 && win / k < 4) --k;
   return (int)k;
 }
+// Window descriptors of one matrix for the window width W (built by
+// spmm_build_desc, see k_spmm_walk).
+struct SpmmDesc {
+  int W = 0;  // 0: not built
+  int nsplit = 1;
+  int64_t items = 0, nwin = 0;
+  int64_t* wptr = nullptr;    // items + 1 window offsets
+  int32_t* wstart = nullptr;  // nwin window starts
+  int64_t* wdesc = nullptr;   // nwin x 64 row descriptors
+};
 struct BCtx {
   rfmls_handle* h;
   const rfmls_csr* A;
@@ -872,8 +914,7 @@ struct BCtx {
   double *U, *V, *W, *Y, *Z, *Q, *T, *Rr, *Xb, *Bb, *DX, *Sm, *Sn;
   double *sqA, *sqB, *sqY, *sqW, *part;
   double* spart;  // partial sums of split SpMM groups (nsplit x rows x 32)
-  const int64_t* splitA = nullptr;   // split cursors of A's rows (k_spmm_splits), if A is split
-  const int64_t* splitAT = nullptr;  // the same for A^T
+  SpmmDesc dA, dAT;  // SpMM window descriptors of A and A^T (k_spmm_walk)
   BlockState* dst;
   IterGraph* graph = nullptr;  // captured poll interval of the loop, or null: eager launches
 };
@@ -942,6 +983,64 @@ static bool spmm_lookup(rfmls_handle* h, const rfmls_csr* M, SpmmShape* out) {
   return false;
 }
 
+// Window descriptors of M (A or A^T of the context) for width W: a count pass
+// of the window walk, the scan of the counts, one host read of the total,
+// and the fill pass.  Synchronises the stream; refused while a graph is
+// being captured (the solve loops prepare them before capturing).
+template <int W>
+static void spmm_walk_launch(BCtx& c, const rfmls_csr* M, int nsplit, unsigned grid, int32_t* cnt, int64_t* wptr,
+                             int32_t* wstart, int64_t* wdesc, bool fill) {
+  if (fill)
+    hipLaunchKernelGGL((k_spmm_walk<W, true>), dim3(grid), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->m, nsplit,
+                       cnt, (const int64_t*)wptr, wstart, wdesc);
+  else
+    hipLaunchKernelGGL((k_spmm_walk<W, false>), dim3(grid), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->m, nsplit,
+                       cnt, (const int64_t*)wptr, wstart, wdesc);
+}
+static rfmls_status spmm_build_desc(BCtx& c, const rfmls_csr* M, int W, SpmmDesc* d) {
+  rfmls_handle* h = c.h;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c.st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(h, RFMLS_E_HIP, "SpMM: window descriptors requested while capturing a graph");
+  const bool isA = M == c.A;
+  const int nsplit = spmm_split(M, h->num_cus);
+  const int64_t items = ((M->m + kSpmmGroup - 1) / kSpmmGroup) * nsplit;
+  const unsigned grid = (unsigned)(items < 4096 ? (items > 0 ? items : 1) : 4096);
+  void* p1;
+  RFMLS_CHECK(workspace(h, isA ? WS_SPMM_WPTR_A : WS_SPMM_WPTR_AT,
+                        sizeof(int64_t) * (size_t)(items + 1) + sizeof(int32_t) * (size_t)(items + 1), &p1));
+  int64_t* wptr = (int64_t*)p1;
+  int32_t* cnt = (int32_t*)(wptr + items + 1);
+  auto walk = [&](bool fill, int32_t* ws, int64_t* wd) {
+    if (W == 32) spmm_walk_launch<32>(c, M, nsplit, grid, cnt, wptr, ws, wd, fill);
+    else if (W == 128) spmm_walk_launch<128>(c, M, nsplit, grid, cnt, wptr, ws, wd, fill);
+    else spmm_walk_launch<64>(c, M, nsplit, grid, cnt, wptr, ws, wd, fill);
+  };
+  walk(false, nullptr, nullptr);
+  RFMLS_CHECK(scan_counts(h, cnt, items, wptr));
+  int64_t nwin = 0;
+  RFMLS_HIP(h, hipMemcpyAsync(&nwin, wptr + items, sizeof(int64_t), hipMemcpyDeviceToHost, c.st));
+  RFMLS_HIP(h, hipStreamSynchronize(c.st));
+  void* p2;
+  RFMLS_CHECK(workspace(h, isA ? WS_SPMM_WDESC_A : WS_SPMM_WDESC_AT,
+                        sizeof(int64_t) * (size_t)(nwin > 0 ? nwin : 1) * kSpmmGroup +
+                            sizeof(int32_t) * (size_t)(nwin > 0 ? nwin : 1) + 64,
+                        &p2));
+  int64_t* wdesc = (int64_t*)p2;
+  int32_t* wstart = (int32_t*)(wdesc + (nwin > 0 ? nwin : 1) * kSpmmGroup);
+  walk(true, wstart, wdesc);
+  RFMLS_HIP(h, hipGetLastError());
+  d->W = W;
+  d->nsplit = nsplit;
+  d->items = items;
+  d->nwin = nwin;
+  d->wptr = wptr;
+  d->wstart = wstart;
+  d->wdesc = wdesc;
+  if (c.AT == c.A) c.dAT = c.dA = *d;
+  return RFMLS_OK;
+}
+
 static rfmls_status spmm_launch(BCtx& c, const rfmls_csr* M, const SpmmShape& sh, const double* x, double sA,
                                 double hcoef, const double* coef, const double* prev, double* out, double* sq,
                                 const BlockState* stp, int* nblk);
@@ -1001,10 +1100,17 @@ static rfmls_status spmm_tune(BCtx& c, const rfmls_csr* M, double* xin, double* 
   return RFMLS_OK;
 }
 
-// Tunes the products with A and A^T (before any capture of the loop).
+// Tunes the products with A and A^T and builds the window descriptors of the
+// shapes the loop will use (before any capture of the loop).
 static rfmls_status spmm_tune_both(BCtx& c) {
   RFMLS_CHECK(spmm_tune(c, c.A, c.Z, c.T, c.sqA));
   if (c.AT != c.A) RFMLS_CHECK(spmm_tune(c, c.AT, c.T, c.Sn, c.sqA));
+  for (const rfmls_csr* M : {c.A, c.AT}) {
+    SpmmShape sh;
+    if (!spmm_lookup(c.h, M, &sh)) sh = spmm_shape(M);
+    SpmmDesc* d = M == c.A ? &c.dA : &c.dAT;
+    if (d->W != sh.win) RFMLS_CHECK(spmm_build_desc(c, M, sh.win, d));
+  }
   return RFMLS_OK;
 }
 
@@ -1029,10 +1135,15 @@ static rfmls_status spmm_launch(BCtx& c, const rfmls_csr* M, const SpmmShape& sh
            2.0 * kBlk * (double)M->nnz);
   int kStride_v = kStride;
   double* spart = c.spart;
-  const int64_t* splits = nsplit > 1 ? (M == c.A ? c.splitA : (M == c.AT ? c.splitAT : nullptr)) : nullptr;
-  void* args[] = {(void*)&M->row_ptr, (void*)&M->col, (void*)&M->val, (void*)&M->m, (void*)&M->n,
+  SpmmDesc* dsc = M == c.A ? &c.dA : &c.dAT;
+  if (dsc->W != sh.win) RFMLS_CHECK(spmm_build_desc(c, M, sh.win, dsc));
+  const int64_t* wptr = dsc->wptr;
+  const int32_t* wstart = dsc->wstart;
+  const int64_t* wdesc = dsc->wdesc;
+  void* args[] = {(void*)&M->col, (void*)&M->val, (void*)&M->m, (void*)&M->n,
                   (void*)&x, (void*)&sA, (void*)&hcoef, (void*)&coef, (void*)&kStride_v, (void*)&prev,
-                  (void*)&out, (void*)&sq, (void*)&stp, (void*)&nsplit, (void*)&spart, (void*)&splits};
+                  (void*)&out, (void*)&sq, (void*)&stp, (void*)&nsplit, (void*)&spart, (void*)&wptr,
+                  (void*)&wstart, (void*)&wdesc};
   RFMLS_HIP(c.h, hipLaunchKernel(sh.fn, dim3(nb), dim3(kThreads), args, 0, c.st));
   if (nsplit > 1) {
     const unsigned gm = rows_grid(M->m);
@@ -1182,28 +1293,6 @@ static rfmls_status make_bctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_c
     void* pp;
     RFMLS_CHECK(workspace(h, WS_SPMM_PART, sizeof(double) * (size_t)need * kBlk, &pp));
     c.spart = (double*)pp;
-  }
-  {
-    // split cursors, computed once here instead of by every work item
-    const int sa = spmm_split(A, h->num_cus), st = AT != A ? spmm_split(AT, h->num_cus) : 1;
-    const int64_t na = sa > 1 ? 2 * sa * A->m : 0, nt = st > 1 ? 2 * st * AT->m : 0;
-    if (na + nt > 0) {
-      void* pt;
-      RFMLS_CHECK(workspace(h, WS_SPMM_SPLIT, sizeof(int64_t) * (size_t)(na + nt), &pt));
-      int64_t* tab = (int64_t*)pt;
-      if (na > 0) {
-        hipLaunchKernelGGL(k_spmm_splits, dim3(ceil_div(A->m, 256)), dim3(256), 0, c.st, A->row_ptr, A->col, A->m, sa,
-                           kSpmmGroup, tab);
-        c.splitA = tab;
-      }
-      if (nt > 0) {
-        hipLaunchKernelGGL(k_spmm_splits, dim3(ceil_div(AT->m, 256)), dim3(256), 0, c.st, AT->row_ptr, AT->col,
-                           AT->m, st, kSpmmGroup, tab + na);
-        c.splitAT = tab + na;
-      }
-      RFMLS_HIP(h, hipGetLastError());
-    }
-    if (AT == A) c.splitAT = c.splitA;
   }
   void* ps;
   RFMLS_CHECK(workspace(h, WS_LSQR_BSTATE, sizeof(BlockState), &ps));
