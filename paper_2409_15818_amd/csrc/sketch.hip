@@ -253,7 +253,12 @@ __global__ void __launch_bounds__(kSketchThreads)
       const int32_t i = perm[q];
       const double sg = (double)sign[i];
       const int64_t lo = row_ptr[i], hi = row_ptr[i + 1];
-      for (int64_t e = lo + t; e < hi; e += kSketchThreads) acc[wpos(col[e])] += sg * val[e];
+      for (int64_t e = lo + t; e < hi; e += kSketchThreads) {
+        // a column outside the row's span (a row against the ascending-column
+        // contract) is dropped rather than written outside the window
+        const int pw = wpos(col[e]);
+        if (pw >= 0) acc[pw] += sg * val[e];
+      }
       __syncthreads();
     }
     // the window's segments (a segment across two intervals is written twice, alike)

@@ -410,6 +410,30 @@ def test_form_B_is_A_times_stored_inverse(handle, name, store):
         assert np.abs(Bg - Bo).max() <= 1e-11 * np.abs(Bo).max()
 
 
+def test_form_B_with_rows_out_of_column_order(handle):
+    """The lockstep SpMM's window walk takes each row's entries in stored order
+    until the first one outside the current window, so a row stored against the
+    ascending-column contract is still multiplied entry by entry (each once, in
+    a different order): B from the shuffled rows equals B from the sorted ones
+    within the rounding of the sums."""
+    m, n = 700, 150
+    Ad = dense_with_condition(m, n, 1e3, seed=33)
+    rp, col, val = csr_from_dense(Ad, keep_zeros=True)
+    A = gpu_csr(rp, col, val, m, n)
+    P = R.rfmls_precond(handle, R.rfmls_sketch(handle, A, 4 * n, SEED)[0], "f64", "f64")
+    Bs = R.rfmls_form_B(handle, A, P).cpu().numpy()
+    rng = np.random.default_rng(34)
+    col2, val2 = col.copy(), val.copy()
+    for i in range(m):
+        p = rng.permutation(rp[i + 1] - rp[i]) + rp[i]
+        col2[rp[i]:rp[i + 1]] = col[p]
+        val2[rp[i]:rp[i + 1]] = val[p]
+    Bu = R.rfmls_form_B(handle, gpu_csr(rp, col2, val2, m, n), P).cpu().numpy()
+    Xg = R.rfmls_precond_export_Rinv(handle, P).cpu().numpy()
+    bound = 4 * n * 1.1e-16 * (np.abs(Ad) @ np.abs(Xg))
+    assert np.all(np.abs(Bu - Bs) <= bound + 1e-300)
+
+
 @pytest.mark.parametrize("name", SMALL)
 @pytest.mark.parametrize("start", ["zero", "sketch"])
 def test_pipeline_with_explicit_operator(handle, name, start):
