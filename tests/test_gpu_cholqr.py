@@ -209,3 +209,41 @@ def test_lookahead_solve_matches_oracle(handle):
     orc = pipeline.solve(S.row_ptr, S.col, S.val, S.b[0], S.m, S.n, s, SEED, refine=1)
     assert abs(res.info[0]["normr"] - orc["normr"]) <= 1e-10 * orc["normr"]
     assert abs(res.info[0]["itn_first"] - orc["itn_sweeps"][0]) <= 2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1024, 64), (1050, 128), (1300, 320), (2100, 130)])
+def test_cholqr_at_the_row_threshold(handle, dtype, shape):
+    """Panels of at least 1024 rows go through CholeskyQR2, shorter ones and ragged
+    last panels through the unblocked kernel, within one factorisation (1050 x 128:
+    panel 0 of 1050 rows, panel 1 of 986; 1300 x 320: five panels down to 1044 rows
+    in slabs with a ragged last one; 2100 x 130: a 2-column last panel).  Both ways
+    R^T R = (SA)^T SA, and R agrees with the unblocked kernel's."""
+    m, n = shape
+    SAo = np.random.default_rng(m + n).standard_normal((m, n))
+    SAq = SAo.astype(np.float64 if dtype == "f64" else np.float32).astype(np.float64)
+    u = 1.1e-16 if dtype == "f64" else 6e-8
+    R0 = _R(handle, SAo, 0, dtype)
+    R1 = _R(handle, SAo, 1, dtype)
+    assert np.all(np.diag(R0) > 0) and not np.tril(R0, -1).any()
+    assert _ident(R0, SAq) < 20 * n * u
+    scale = np.abs(R1).max(axis=1, keepdims=True)
+    assert (np.abs(R0 - R1) / scale).max() < (1e-11 if dtype == "f64" else 1e-4)
+
+
+def test_lookahead_float32_bitwise(handle):
+    """Look-ahead with float32 panels (CholeskyQR2 in float64 arithmetic): the same
+    factored matrix as the plain schedule, bit for bit."""
+    SAo = np.random.default_rng(41).standard_normal((3000, 800)).astype(np.float32)
+    F = []
+    for la in (False, True):
+        R.rfmls_qr_lookahead(handle, la)
+        try:
+            SA = torch.tensor(SAo, device="cuda")
+            P = R.rfmls_precond(handle, SA, "f32", "f32")
+            torch.cuda.synchronize()
+            F.append(SA.cpu().numpy().copy())
+            P.free()
+        finally:
+            R.rfmls_qr_lookahead(handle, False)
+    assert np.array_equal(F[0], F[1])
