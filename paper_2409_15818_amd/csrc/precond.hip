@@ -173,12 +173,19 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   const int64_t o = I * kTile;
   const int b = (int)(n - o < kTile ? n - o : kTile);
   const int t = threadIdx.x;
-  for (int e = t; e < kTile * kTile; e += kInvCols * kInvLanes) {
+  // Every load below reads a clamped, in-range address unconditionally and the
+  // unused values are dropped by a select, so all of a thread's loads are in
+  // flight together (a conditional load per element made the compiler wait for
+  // each one before the next: 16 serial memory round trips).
+  constexpr int kLoads = kTile * kTile / (kInvCols * kInvLanes);
+  double rt[kLoads];
+#pragma unroll
+  for (int s = 0; s < kLoads; ++s) {
+    const int e = t + s * kInvCols * kInvLanes;
     const int i = e / kTile, k = e % kTile;
-    // zeros below the diagonal: the update loop below then needs no per-row test
-    Rs[i][k] = (i < b && k < b && k >= i) ? R[(o + i) * n + o + k] : (i == k ? 1.0 : 0.0);
+    rt[s] = R[(o + min(i, b - 1)) * n + o + min(k, b - 1)];
   }
-  if (t < kTile) rinv[t] = t < b ? 1.0 / R[(o + t) * n + o + t] : 1.0;
+  const double rdiag = R[(o + min(t % kTile, b - 1)) * (n + 1)];
   const int q = t % kInvLanes;  // this lane holds rows q*16 .. q*16 + 15
   const int r0 = q * kInvRows;
   const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t / kInvLanes;
@@ -189,17 +196,32 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   if (live && j >= o + kTile && Pn) {
     const int64_t jc = j - o - kTile;
 #pragma unroll
-    for (int l = 0; l < kInvRows; ++l) v[l] = r0 + l < b ? -Pn[(int64_t)(r0 + l) * ldn + jc] : 0.0;
+    for (int l = 0; l < kInvRows; ++l) {
+      const double p = Pn[(int64_t)min(r0 + l, b - 1) * ldn + jc];
+      v[l] = r0 + l < b ? -p : 0.0;
+    }
   }
-  if (live && j >= e2) {
+  // far partials exist only for outer blocks that end before n, whose block
+  // rows are all full (b == kTile), so no row test is needed here
+  if (live && j >= e2 && b == kTile) {
     const int64_t jf = j - e2;
     for (int z = 0; z < nzf; ++z) {
       const double* Pz = Pf + (int64_t)z * zsf + roff * ldf + jf;
+      double pz[kInvRows];
 #pragma unroll
-      for (int l = 0; l < kInvRows; ++l)
-        if (r0 + l < b) v[l] -= Pz[(int64_t)(r0 + l) * ldf];
+      for (int l = 0; l < kInvRows; ++l) pz[l] = Pz[(int64_t)(r0 + l) * ldf];
+#pragma unroll
+      for (int l = 0; l < kInvRows; ++l) v[l] -= pz[l];
     }
   }
+#pragma unroll
+  for (int s = 0; s < kLoads; ++s) {
+    const int e = t + s * kInvCols * kInvLanes;
+    const int i = e / kTile, k = e % kTile;
+    // zeros below the diagonal: the update loop below then needs no per-row test
+    Rs[i][k] = (i < b && k < b && k >= i) ? rt[s] : (i == k ? 1.0 : 0.0);
+  }
+  if (t < kTile) rinv[t] = t < b ? 1.0 / rdiag : 1.0;
   __syncthreads();
   // rows >= b are the identity with v = 0 and stay 0
 #pragma unroll
