@@ -88,37 +88,54 @@ __global__ void __launch_bounds__(256) k_diag_stats(const double* __restrict__ R
 
 // Column-relative pivots rho_j = |r_jj| / ||R[:, j]|| (||R[:, j]|| = ||SA[:, j]||):
 // the distance of column j of SA from the span of the columns before it,
-// relative to its length.  A block takes 64 columns; its four wavefronts sum
-// every fourth row (a row's 64 loads are coalesced), the four partial sums are
-// added in a fixed order; per-block minima into part[blockIdx.x].
-__global__ void __launch_bounds__(256) k_col_rho(const double* __restrict__ R, int64_t n,
-                                                 double* __restrict__ part) {
-  __shared__ double ssum[4][64];
-  __shared__ double smin[64];
+// relative to its length.  k_col_sumsq: block (x, z) takes 64 columns and the
+// z-th chunk of kRhoRows rows; its four wavefronts sum every fourth row (a
+// row's 64 loads are coalesced, four rows in flight per wavefront) and the
+// four partial sums are added in a fixed order into ss[z][j].  k_col_rho then
+// adds the chunks in order and writes per-block minima into part[blockIdx.x].
+constexpr int64_t kRhoRows = 512;
+__global__ void __launch_bounds__(256) k_col_sumsq(const double* __restrict__ R, int64_t n,
+                                                   double* __restrict__ ss) {
+  __shared__ double psum[4][64];
   const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + c;
-  double ss = 0.0;
-  if (j < n)
-    for (int64_t i = q; i <= j; i += 4) {
+  const int64_t i0 = (int64_t)blockIdx.y * kRhoRows;
+  double acc = 0.0;
+  if (j < n) {
+    // rows i0 + q, i0 + q + 4, ... up to min(j, i0 + kRhoRows - 1)
+    const int64_t iend = j + 1 < i0 + kRhoRows ? j + 1 : i0 + kRhoRows;
+    int64_t i = i0 + q;
+    for (; i + 12 < iend; i += 16) {
+      const double v0 = R[i * n + j], v1 = R[(i + 4) * n + j], v2 = R[(i + 8) * n + j], v3 = R[(i + 12) * n + j];
+      acc = fma(v0, v0, acc);
+      acc = fma(v1, v1, acc);
+      acc = fma(v2, v2, acc);
+      acc = fma(v3, v3, acc);
+    }
+    for (; i < iend; i += 4) {
       const double v = R[i * n + j];
-      ss += v * v;
+      acc = fma(v, v, acc);
     }
-  ssum[q][c] = ss;
-  __syncthreads();
-  if (q == 0) {
-    double rho = INFINITY;
-    if (j < n) {
-      const double t = (ssum[0][c] + ssum[1][c]) + (ssum[2][c] + ssum[3][c]);
-      rho = t > 0.0 ? fabs(R[j * n + j]) / sqrt(t) : 0.0;
-    }
-    smin[c] = rho;
   }
+  psum[q][c] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double mn = INFINITY;
-    for (int k = 0; k < 64; ++k) mn = fmin(mn, smin[k]);
-    part[blockIdx.x] = mn;
+  if (q == 0 && j < n) ss[(int64_t)blockIdx.y * n + j] = (psum[0][c] + psum[1][c]) + (psum[2][c] + psum[3][c]);
+}
+
+__global__ void __launch_bounds__(64) k_col_rho(const double* __restrict__ R, int64_t n,
+                                                const double* __restrict__ ss, double* __restrict__ part) {
+  const int c = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  double rho = INFINITY;
+  if (j < n) {
+    double t = 0.0;
+    const int64_t nz = j / kRhoRows + 1;  // the chunks holding rows 0 .. j
+    for (int64_t z = 0; z < nz; ++z) t += ss[z * n + j];
+    rho = t > 0.0 ? fabs(R[j * n + j]) / sqrt(t) : 0.0;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rho = fmin(rho, __shfl_xor(rho, off, 64));
+  if (c == 0) part[blockIdx.x] = rho;
 }
 
 __global__ void __launch_bounds__(256) k_min_partials(const double* __restrict__ part, int np,
@@ -140,8 +157,9 @@ __global__ void __launch_bounds__(256) k_min_partials(const double* __restrict__
 // lower triangle gets the exact zeros back substitution leaves there (0 / r_ii
 // below a unit right-hand side); the GEMMs above read those as stored.
 // Right-hand side: e_j restricted to the block row, minus R_{I,>I} X_{>I}, which
-// arrives in two parts (see invert_upper): Pn (b x (n - o - 64), one slice) from
-// the rows of X solved earlier inside the same outer block, and nzf split-K
+// arrives in two parts (see invert_upper): nzn split-K slices of Pn (each
+// b x (n - o - 64), stride zsn) from the rows of X solved earlier inside the
+// same outer block, summed in slice order, and nzf split-K
 // slices of Pf (rows roff .. roff + b of a (rows of the outer block) x (n - e2)
 // partial) from the rows beyond the outer block, for columns j >= e2.  Then
 // R_II x = rhs by back substitution, column-oriented (x_i = rhs_i * (1 / r_ii),
@@ -166,7 +184,7 @@ __device__ __forceinline__ double quad_bcast(double v) {
 
 __global__ void __launch_bounds__(kInvCols * kInvLanes)
     k_inv_blockrow(const double* __restrict__ R, int64_t n, int64_t I, const double* __restrict__ Pn,
-                   int64_t ldn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
+                   int64_t ldn, int nzn, int64_t zsn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
                    int64_t roff, int64_t e2, double* __restrict__ X) {
   __shared__ double Rs[kTile][kTile + 1];
   __shared__ double rinv[kTile];  // 1 / r_ii, formed once so no division sits on the chain
@@ -195,11 +213,18 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   for (int l = 0; l < kInvRows; ++l) v[l] = (live && j == o + r0 + l) ? 1.0 : 0.0;
   if (live && j >= o + kTile && Pn) {
     const int64_t jc = j - o - kTile;
+    double pn[kInvRows];
 #pragma unroll
-    for (int l = 0; l < kInvRows; ++l) {
-      const double p = Pn[(int64_t)min(r0 + l, b - 1) * ldn + jc];
-      v[l] = r0 + l < b ? -p : 0.0;
+    for (int l = 0; l < kInvRows; ++l) pn[l] = Pn[(int64_t)min(r0 + l, b - 1) * ldn + jc];
+    for (int z = 1; z < nzn; ++z) {
+      double pz[kInvRows];
+#pragma unroll
+      for (int l = 0; l < kInvRows; ++l) pz[l] = Pn[(int64_t)z * zsn + (int64_t)min(r0 + l, b - 1) * ldn + jc];
+#pragma unroll
+      for (int l = 0; l < kInvRows; ++l) pn[l] += pz[l];
     }
+#pragma unroll
+    for (int l = 0; l < kInvRows; ++l) v[l] = r0 + l < b ? -pn[l] : 0.0;
   }
   // far partials exist only for outer blocks that end before n, whose block
   // rows are all full (b == kTile), so no row test is needed here
@@ -223,20 +248,40 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   }
   if (t < kTile) rinv[t] = t < b ? 1.0 / rdiag : 1.0;
   __syncthreads();
-  // rows >= b are the identity with v = 0 and stay 0
+  // Rows >= b are the identity with v = 0 and stay 0.  The 64 rows go in four
+  // groups of 16 from the bottom.  Group qi: the lanes holding it (q == qi)
+  // solve its 16 rows among themselves, x_i = v_i / r_ii and v_k -= r_ki x_i for
+  // the rows k < i of the group, a chain of 16 steps inside one lane (every
+  // lane runs it on a copy; only the owners keep the result); the 16 x_i then
+  // go to the whole quad by DPP, and the lanes holding rows above the group
+  // (q < qi) apply them, i from high to low.  Every element sees the same
+  // updates in the same order as a one-lane-per-column substitution.
 #pragma unroll
   for (int qi = kInvLanes - 1; qi >= 0; --qi) {
+    const int g0 = qi * kInvRows;
+    double w[kInvRows];
+#pragma unroll
+    for (int l = 0; l < kInvRows; ++l) w[l] = v[l];
 #pragma unroll
     for (int li = kInvRows - 1; li >= 0; --li) {
-      const int i = qi * kInvRows + li;
-      // x_i on the lane that holds row i, then on the whole quad
-      double xi = v[li] * rinv[i];
-      xi = qi == 0 ? quad_bcast<0>(xi) : qi == 1 ? quad_bcast<1>(xi) : qi == 2 ? quad_bcast<2>(xi) : quad_bcast<3>(xi);
-      // rhs_k -= r_ki x_i on every row this lane holds: rows k > i meet the
-      // stored zeros (v_k - 0 = v_k), row i is overwritten by x_i just after
+      const double xi = w[li] * rinv[g0 + li];
 #pragma unroll
-      for (int l = 0; l < kInvRows; ++l) v[l] -= Rs[r0 + l][i] * xi;
-      if (q == qi) v[li] = xi;
+      for (int l = 0; l < li; ++l) w[l] -= Rs[g0 + l][g0 + li] * xi;
+      w[li] = xi;
+    }
+    double xb[kInvRows];
+#pragma unroll
+    for (int li = 0; li < kInvRows; ++li)
+      xb[li] = qi == 0 ? quad_bcast<0>(w[li]) : qi == 1 ? quad_bcast<1>(w[li]) : qi == 2 ? quad_bcast<2>(w[li])
+                                                                                          : quad_bcast<3>(w[li]);
+    if (q == qi) {
+#pragma unroll
+      for (int l = 0; l < kInvRows; ++l) v[l] = w[l];
+    } else if (q < qi) {
+#pragma unroll
+      for (int li = kInvRows - 1; li >= 0; --li)
+#pragma unroll
+        for (int l = 0; l < kInvRows; ++l) v[l] -= Rs[r0 + l][g0 + li] * xb[li];
     }
   }
   if (live) {
@@ -299,7 +344,9 @@ __global__ void k_unpack_tiles(const TS* __restrict__ pk, int64_t n, int64_t nt,
 // by kInvTiles tile rows.  Measured (total of the three kernels, 12,800 /
 // 25,600 columns): 40 / 188 ms at 4 tiles, 39 / 180 ms at 16, 42 / 180 ms at 32
 // (the near products grow as fast as the far one shrinks).  Pf holds up to 4
-// split-K slices of (e2 - o2) x (n - e2); Pn one 64 x n slice.
+// split-K slices of (e2 - o2) x (n - e2); Pn up to 4 split-K slices of 64 x n
+// (the near product has one tile row, so its K range is split until the
+// output tiles times the slices give about two blocks per compute unit).
 constexpr int64_t kInvTiles = 16;
 constexpr int64_t kInvOuter = kInvTiles * kTile;
 
@@ -349,6 +396,8 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       const int64_t b = n - o < kTile ? n - o : kTile;
       const int64_t kn = e2 - o - b;  // solved rows of this outer block below row block I
       const int64_t ldn = n - o - kTile > 0 ? n - o - kTile : 1;
+      int nzn = 0;
+      const int64_t zsn = kTile * ldn;
       if (kn > 0) {
         GemmArgs<double> g;
         g.M = b;
@@ -362,16 +411,30 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
         g.ldc = ldn;
         g.b_upper = 1;
         g.b_lower_zero = 1;
-        Trace tr(h, "inv_gemm_near", 8.0 * ((double)b * kn + (double)kn * g.N + (double)b * g.N),
+        // one tile row: split K (slices of at least 64 rows, at most 4) until
+        // the tiles times the slices give about two blocks per compute unit
+        const int64_t tiles = (g.N + kTile - 1) / kTile;
+        int64_t want = (2 * (int64_t)h->num_cus + tiles - 1) / tiles;
+        if (want > 4) want = 4;
+        int64_t ksn = (kn + want - 1) / want;
+        ksn = (ksn + kTile - 1) / kTile * kTile;
+        nzn = (int)((kn + ksn - 1) / ksn);
+        if (nzn > 1) {
+          g.ksplit = ksn;
+          g.c_zstride = zsn;
+        }
+        if (nzn < 1) nzn = 1;
+        Trace tr(h, "inv_gemm_near", 8.0 * ((double)b * kn + (double)kn * g.N + (double)nzn * b * g.N),
                  2.0 * (double)b * kn * (double)g.N);
         RFMLS_HIP(h, (gemm_clean<double, GemmRole::Inverse>(g, h->stream)));
       }
       {
-        Trace tr(h, "inv_blockrow", 8.0 * ((double)(nzf + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
+        Trace tr(h, "inv_blockrow",
+                 8.0 * ((double)(nzf + nzn + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
                  (double)kTile * kTile * (double)(n - o));
         hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols * kInvLanes), 0, h->stream, R,
-                           n, I, kn > 0 ? (const double*)Pn : (const double*)nullptr, ldn, (const double*)Pf,
-                           nzf, ldf, zsf, o - o2, e2, X);
+                           n, I, kn > 0 ? (const double*)Pn : (const double*)nullptr, ldn, nzn, zsn,
+                           (const double*)Pf, nzf, ldf, zsf, o - o2, e2, X);
       }
       RFMLS_HIP(h, hipGetLastError());
     }
@@ -387,11 +450,15 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
                             int check_precision) {
   const int64_t n = P->n;
   const unsigned ncb = ceil_div(n, 64);
+  const unsigned nzr = ceil_div(n, kRhoRows);
   void* p_stats;
-  RFMLS_CHECK(workspace(h, WS_MISC, sizeof(double) * (8 + (size_t)ncb), &p_stats));
+  RFMLS_CHECK(workspace(h, WS_MISC, sizeof(double) * (8 + (size_t)ncb + (size_t)nzr * (size_t)n), &p_stats));
   double* dstats = (double*)p_stats;
+  double* dss = dstats + 8 + ncb;
   hipLaunchKernelGGL(k_diag_stats, dim3(1), dim3(256), 0, h->stream, P->Rdense, n, dstats);
-  hipLaunchKernelGGL(k_col_rho, dim3(ncb), dim3(256), 0, h->stream, (const double*)P->Rdense, n, dstats + 8);
+  hipLaunchKernelGGL(k_col_sumsq, dim3(ncb, nzr), dim3(256), 0, h->stream, (const double*)P->Rdense, n, dss);
+  hipLaunchKernelGGL(k_col_rho, dim3(ncb), dim3(64), 0, h->stream, (const double*)P->Rdense, n, (const double*)dss,
+                     dstats + 8);
   hipLaunchKernelGGL(k_min_partials, dim3(1), dim3(256), 0, h->stream, (const double*)(dstats + 8), (int)ncb,
                      dstats + 3);
   double stats[4] = {0, 0, 0, 0};
@@ -420,8 +487,8 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   void* p_w;
   RFMLS_CHECK(workspace(h, WS_TRSM, sizeof(double) * (size_t)n * (size_t)n, &p_x));
   const int64_t kslice = 512;
-  // 4 far slices of kInvOuter x n and one near slice of 64 x n
-  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + kTile) * (size_t)n, &p_w));
+  // 4 far slices of kInvOuter x n and 4 near slices of 64 x n
+  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + 4 * kTile) * (size_t)n, &p_w));
   double* X = (double*)p_x;
   RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
                            P->nt, kslice));
