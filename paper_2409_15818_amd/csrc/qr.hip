@@ -588,7 +588,15 @@ rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw,
     {
       Trace tr(h, run_if ? "qr_panel_fallback" : "qr_panel", run_if ? 0.0 : 2.0 * sizeof(T) * (double)M * jb,
                run_if ? 0.0 : pf);
-      RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
+      // The gated launch after CholeskyQR2 on the main stream is an ordinary
+      // launch: nothing else runs beside it, so its G <= one-per-CU workgroups
+      // are all resident when it does run (its waits are bounded either way),
+      // and the cooperative launch's own overhead (about 15 us per panel,
+      // 200 panels on the 8x8-box sketch) is not paid when it does nothing.
+      if (run_if && !h->qr_lookahead)
+        RFMLS_HIP(h, hipLaunchKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
+      else
+        RFMLS_HIP(h, hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, st));
     }
     if (run_if) RFMLS_CHECK(cholqr_fix(h, P, ld, M, cq_ws, cq_status));
     const int64_t rem = k0 + bw - (p0 + jb);
