@@ -44,6 +44,8 @@ __global__ void __launch_bounds__(kThreads)
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  // two tiles' loads in flight per iteration (sums in the same order)
+#pragma unroll 2
   for (int64_t J = J0; J < J1; ++J) {
     const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
     const int64_t gc = J * kTile + lane;
@@ -77,6 +79,7 @@ __global__ void __launch_bounds__(kThreads)
   // needs per tile are then scalar loads, with no branch for the bound test
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double acc0 = 0.0, acc1 = 0.0;  // two chains over alternate rows
+#pragma unroll 2
   for (int64_t I = I0; I < I1; ++I) {
     const TS* t = Xpk + ptile(I, J, nt, full) * (int64_t)(kTile * kTile);
 #pragma unroll
