@@ -344,9 +344,12 @@ __global__ void k_unpack_tiles(const TS* __restrict__ pk, int64_t n, int64_t nt,
 // by kInvTiles tile rows.  Measured (total of the three kernels, 12,800 /
 // 25,600 columns): 40 / 188 ms at 4 tiles, 39 / 180 ms at 16, 42 / 180 ms at 32
 // (the near products grow as fast as the far one shrinks).  Pf holds up to 4
-// split-K slices of (e2 - o2) x (n - e2); Pn up to 4 split-K slices of 64 x n
-// (the near product has one tile row, so its K range is split until the
-// output tiles times the slices give about two blocks per compute unit).
+// split-K slices of (e2 - o2) x (n - e2); Pn up to 2 split-K slices of 64 x n
+// (the near product has one tile row, so its K range is split in two where
+// its output tiles alone give fewer than about two blocks per compute unit;
+// measured against 1 and 4 slices: 340 vs 342 / 342 ms for QR + inverse on
+// the 8x8-box system, 696 vs 699 / 695 ms on the 4^3-box float32 one, since
+// every slice is one more memory round trip for the block-row kernel).
 constexpr int64_t kInvTiles = 16;
 constexpr int64_t kInvOuter = kInvTiles * kTile;
 
@@ -411,11 +414,11 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
         g.ldc = ldn;
         g.b_upper = 1;
         g.b_lower_zero = 1;
-        // one tile row: split K (slices of at least 64 rows, at most 4) until
+        // one tile row: split K (slices of at least 64 rows, at most 2) until
         // the tiles times the slices give about two blocks per compute unit
         const int64_t tiles = (g.N + kTile - 1) / kTile;
         int64_t want = (2 * (int64_t)h->num_cus + tiles - 1) / tiles;
-        if (want > 4) want = 4;
+        if (want > 2) want = 2;
         int64_t ksn = (kn + want - 1) / want;
         ksn = (ksn + kTile - 1) / kTile * kTile;
         nzn = (int)((kn + ksn - 1) / ksn);
@@ -487,8 +490,8 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   void* p_w;
   RFMLS_CHECK(workspace(h, WS_TRSM, sizeof(double) * (size_t)n * (size_t)n, &p_x));
   const int64_t kslice = 512;
-  // 4 far slices of kInvOuter x n and 4 near slices of 64 x n
-  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + 4 * kTile) * (size_t)n, &p_w));
+  // 4 far slices of kInvOuter x n and 2 near slices of 64 x n
+  RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + 2 * kTile) * (size_t)n, &p_w));
   double* X = (double*)p_x;
   RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
                            P->nt, kslice));
