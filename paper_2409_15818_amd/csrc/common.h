@@ -312,7 +312,7 @@ rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, co
 // check_precision the float32 column-relative pivot), records its statistics,
 // then forms and packs X = R^{-1}
 rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit,
-                            int check_precision);
+                            int check_precision, int invert_f32 = 0);
 // tables of the tiled products and the packed tiles of X (row-major n x n
 // dense, float64) in P->store precision, for either packing (P->full)
 rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X);

@@ -182,10 +182,13 @@ __device__ __forceinline__ double quad_bcast(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// T: storage of R, the partials and X (float64, or float32 for a factor
+// computed and stored in float32); the substitution runs in float64.
+template <typename T>
 __global__ void __launch_bounds__(kInvCols * kInvLanes)
-    k_inv_blockrow(const double* __restrict__ R, int64_t n, int64_t I, const double* __restrict__ Pn,
-                   int64_t ldn, int nzn, int64_t zsn, const double* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
-                   int64_t roff, int64_t e2, double* __restrict__ X) {
+    k_inv_blockrow(const T* __restrict__ R, int64_t n, int64_t I, const T* __restrict__ Pn,
+                   int64_t ldn, int nzn, int64_t zsn, const T* __restrict__ Pf, int nzf, int64_t ldf, int64_t zsf,
+                   int64_t roff, int64_t e2, T* __restrict__ X) {
   __shared__ double Rs[kTile][kTile + 1];
   __shared__ double rinv[kTile];  // 1 / r_ii, formed once so no division sits on the chain
   const int64_t o = I * kTile;
@@ -201,9 +204,9 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   for (int s = 0; s < kLoads; ++s) {
     const int e = t + s * kInvCols * kInvLanes;
     const int i = e / kTile, k = e % kTile;
-    rt[s] = R[(o + min(i, b - 1)) * n + o + min(k, b - 1)];
+    rt[s] = (double)R[(o + min(i, b - 1)) * n + o + min(k, b - 1)];
   }
-  const double rdiag = R[(o + min(t % kTile, b - 1)) * (n + 1)];
+  const double rdiag = (double)R[(o + min(t % kTile, b - 1)) * (n + 1)];
   const int q = t % kInvLanes;  // this lane holds rows q*16 .. q*16 + 15
   const int r0 = q * kInvRows;
   const int64_t j = o + (int64_t)blockIdx.x * kInvCols + t / kInvLanes;
@@ -215,11 +218,11 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
     const int64_t jc = j - o - kTile;
     double pn[kInvRows];
 #pragma unroll
-    for (int l = 0; l < kInvRows; ++l) pn[l] = Pn[(int64_t)min(r0 + l, b - 1) * ldn + jc];
+    for (int l = 0; l < kInvRows; ++l) pn[l] = (double)Pn[(int64_t)min(r0 + l, b - 1) * ldn + jc];
     for (int z = 1; z < nzn; ++z) {
       double pz[kInvRows];
 #pragma unroll
-      for (int l = 0; l < kInvRows; ++l) pz[l] = Pn[(int64_t)z * zsn + (int64_t)min(r0 + l, b - 1) * ldn + jc];
+      for (int l = 0; l < kInvRows; ++l) pz[l] = (double)Pn[(int64_t)z * zsn + (int64_t)min(r0 + l, b - 1) * ldn + jc];
 #pragma unroll
       for (int l = 0; l < kInvRows; ++l) pn[l] += pz[l];
     }
@@ -231,10 +234,10 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   if (live && j >= e2 && b == kTile) {
     const int64_t jf = j - e2;
     for (int z = 0; z < nzf; ++z) {
-      const double* Pz = Pf + (int64_t)z * zsf + roff * ldf + jf;
+      const T* Pz = Pf + (int64_t)z * zsf + roff * ldf + jf;
       double pz[kInvRows];
 #pragma unroll
-      for (int l = 0; l < kInvRows; ++l) pz[l] = Pz[(int64_t)(r0 + l) * ldf];
+      for (int l = 0; l < kInvRows; ++l) pz[l] = (double)Pz[(int64_t)(r0 + l) * ldf];
 #pragma unroll
       for (int l = 0; l < kInvRows; ++l) v[l] -= pz[l];
     }
@@ -287,12 +290,12 @@ __global__ void __launch_bounds__(kInvCols * kInvLanes)
   if (live) {
 #pragma unroll
     for (int l = 0; l < kInvRows; ++l)
-      if (r0 + l < b) X[(o + r0 + l) * n + j] = v[l];
+      if (r0 + l < b) X[(o + r0 + l) * n + j] = (T)v[l];
   }
 }
 
-template <typename TS>
-__global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt, int full,
+template <typename TS, typename TX = double>
+__global__ void k_pack_tiles(const TX* __restrict__ X, int64_t n, int64_t nt, int full,
                              TS* __restrict__ pk) {
   // blockIdx.x = tile index in packed order; decode (I, J)
   const int64_t t = blockIdx.x;
@@ -316,7 +319,7 @@ __global__ void k_pack_tiles(const double* __restrict__ X, int64_t n, int64_t nt
     const int r = e / kTile, c = e % kTile;
     const int64_t gi = I * kTile + r, gj = J * kTile + c;
     double v = 0.0;
-    if (gi < n && gj < n && (full || gj >= gi)) v = X[gi * n + gj];
+    if (gi < n && gj < n && (full || gj >= gi)) v = (double)X[gi * n + gj];
     out[e] = (TS)v;
   }
 }
@@ -353,8 +356,9 @@ __global__ void k_unpack_tiles(const TS* __restrict__ pk, int64_t n, int64_t nt,
 constexpr int64_t kInvTiles = 16;
 constexpr int64_t kInvOuter = kInvTiles * kTile;
 
-rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* Pf, double* Pn,
-                          int64_t n, int64_t nt, int64_t kslice) {
+template <typename T>
+rfmls_status invert_upper(rfmls_handle* h, const T* R, T* X, T* Pf, T* Pn, int64_t n, int64_t nt,
+                          int64_t kslice) {
   const int64_t nt2 = (nt + kInvTiles - 1) / kInvTiles;
   for (int64_t I2 = nt2 - 1; I2 >= 0; --I2) {
     const int64_t o2 = I2 * kInvOuter;
@@ -373,7 +377,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       if ((far + ks - 1) / ks > 4) ks = (far + 3) / 4;
       ks = (ks + 15) / 16 * 16;
       nzf = (int)((far + ks - 1) / ks);
-      GemmArgs<double> g;
+      GemmArgs<T> g;
       g.M = e2 - o2;
       g.N = far;
       g.K = far;
@@ -390,9 +394,9 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       // so the strip comes from HBM once: 46 -> 60 TFLOP/s at 24,576 columns
       g.tile_order = 1;
       g.c_zstride = zsf;
-      Trace tr(h, "inv_gemm", 8.0 * ((double)(e2 - o2) * far + 0.5 * (double)far * far + (double)nzf * (e2 - o2) * far),
+      Trace tr(h, "inv_gemm", (double)sizeof(T) * ((double)(e2 - o2) * far + 0.5 * (double)far * far + (double)nzf * (e2 - o2) * far),
                (double)(e2 - o2) * (double)far * (double)far);
-      RFMLS_HIP(h, (gemm_clean<double, GemmRole::Inverse>(g, h->stream)));
+      RFMLS_HIP(h, (gemm_clean<T, GemmRole::Inverse>(g, h->stream)));
     }
     for (int64_t I = (e2 - 1) / kTile; I >= I2 * kInvTiles; --I) {
       const int64_t o = I * kTile;
@@ -402,7 +406,7 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
       int nzn = 0;
       const int64_t zsn = kTile * ldn;
       if (kn > 0) {
-        GemmArgs<double> g;
+        GemmArgs<T> g;
         g.M = b;
         g.N = n - o - kTile;
         g.K = kn;
@@ -427,17 +431,17 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
           g.c_zstride = zsn;
         }
         if (nzn < 1) nzn = 1;
-        Trace tr(h, "inv_gemm_near", 8.0 * ((double)b * kn + (double)kn * g.N + (double)nzn * b * g.N),
+        Trace tr(h, "inv_gemm_near", (double)sizeof(T) * ((double)b * kn + (double)kn * g.N + (double)nzn * b * g.N),
                  2.0 * (double)b * kn * (double)g.N);
-        RFMLS_HIP(h, (gemm_clean<double, GemmRole::Inverse>(g, h->stream)));
+        RFMLS_HIP(h, (gemm_clean<T, GemmRole::Inverse>(g, h->stream)));
       }
       {
         Trace tr(h, "inv_blockrow",
-                 8.0 * ((double)(nzf + nzn + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
+                 (double)sizeof(T) * ((double)(nzf + nzn + 1) * kTile * (double)(n - o) + (double)kTile * (n - o)),
                  (double)kTile * kTile * (double)(n - o));
-        hipLaunchKernelGGL(k_inv_blockrow, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols * kInvLanes), 0, h->stream, R,
-                           n, I, kn > 0 ? (const double*)Pn : (const double*)nullptr, ldn, nzn, zsn,
-                           (const double*)Pf, nzf, ldf, zsf, o - o2, e2, X);
+        hipLaunchKernelGGL(k_inv_blockrow<T>, dim3(ceil_div(n - o, kInvCols)), dim3(kInvCols * kInvLanes), 0, h->stream, R,
+                           n, I, kn > 0 ? (const T*)Pn : (const T*)nullptr, ldn, nzn, zsn,
+                           (const T*)Pf, nzf, ldf, zsf, o - o2, e2, X);
       }
       RFMLS_HIP(h, hipGetLastError());
     }
@@ -447,10 +451,21 @@ rfmls_status invert_upper(rfmls_handle* h, const double* R, double* X, double* P
 
 }  // namespace
 
+__global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+template <typename TX>
+static rfmls_status pack_precond_t(rfmls_handle* h, rfmls_precond_t* P, const TX* X);
+
 // Shared tail of rfmls_precond / rfmls_precond_import_R: R (normalised,
-// float64 row-major n x n) is in P->Rdense.
+// float64 row-major n x n) is in P->Rdense.  invert_f32 (a factor computed
+// and stored in float32): X = R^{-1} is formed from R rounded to float32, its
+// products on the float32 matrix cores, the block-row substitutions in
+// float64 arithmetic on float32 operands.
 rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank, double unit,
-                            int check_precision) {
+                            int check_precision, int invert_f32) {
   const int64_t n = P->n;
   const unsigned ncb = ceil_div(n, 64);
   const unsigned nzr = ceil_div(n, kRhoRows);
@@ -492,13 +507,34 @@ rfmls_status finish_precond(rfmls_handle* h, rfmls_precond_t* P, int check_rank,
   const int64_t kslice = 512;
   // 4 far slices of kInvOuter x n and 2 near slices of 64 x n
   RFMLS_CHECK(workspace(h, WS_QR_W, sizeof(double) * (size_t)(4 * kInvOuter + 2 * kTile) * (size_t)n, &p_w));
+  if (invert_f32) {
+    // X and R in float32 share the float64 n x n slot
+    float* X32 = (float*)p_x;
+    float* R32 = X32 + (size_t)n * (size_t)n;
+    float* W32 = (float*)p_w;
+    const unsigned g = ceil_div(n * n, 256) < 8192 ? ceil_div(n * n, 256) : 8192;
+    hipLaunchKernelGGL(k_to_float, dim3(g), dim3(256), 0, h->stream, (const double*)P->Rdense, R32, n * n);
+    RFMLS_HIP(h, hipGetLastError());
+    // X starts as zeros: the float32 products use 128-column tiles, whose K
+    // range for a tile column reaches the 64 x 64 block below the diagonal
+    // block, so X's lower triangle must hold zeros everywhere, not only inside
+    // the diagonal blocks
+    RFMLS_HIP(h, hipMemsetAsync(X32, 0, sizeof(float) * (size_t)n * (size_t)n, h->stream));
+    RFMLS_CHECK(invert_upper<float>(h, R32, X32, W32, W32 + (size_t)4 * kInvOuter * n, n, P->nt, kslice));
+    return pack_precond_t<float>(h, P, X32);
+  }
   double* X = (double*)p_x;
-  RFMLS_CHECK(invert_upper(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
-                           P->nt, kslice));
+  RFMLS_CHECK(invert_upper<double>(h, P->Rdense, X, (double*)p_w, (double*)p_w + (size_t)4 * kInvOuter * n, n,
+                                   P->nt, kslice));
   return pack_precond(h, P, X);
 }
 
 rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X) {
+  return pack_precond_t<double>(h, P, X);
+}
+
+template <typename TX>
+static rfmls_status pack_precond_t(rfmls_handle* h, rfmls_precond_t* P, const TX* X) {
   const int64_t n = P->n;
   const int full = P->full;
   const int64_t ntiles = stored_tiles(P->nt, full);
@@ -523,10 +559,10 @@ rfmls_status pack_precond(rfmls_handle* h, rfmls_precond_t* P, const double* X) 
   }
   RFMLS_HIP(h, hipMalloc(&P->Xpk, esz * (size_t)ntiles * kTile * kTile));
   if (P->store == RFMLS_F64)
-    hipLaunchKernelGGL(k_pack_tiles<double>, dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
+    hipLaunchKernelGGL((k_pack_tiles<double, TX>), dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
                        P->nt, full, (double*)P->Xpk);
   else
-    hipLaunchKernelGGL(k_pack_tiles<float>, dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
+    hipLaunchKernelGGL((k_pack_tiles<float, TX>), dim3((unsigned)ntiles), dim3(256), 0, h->stream, X, n,
                        P->nt, full, (float*)P->Xpk);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
@@ -599,7 +635,14 @@ rfmls_status run_build_precond(rfmls_handle* h, int64_t n, rfmls_dtype qr_dt, co
                        P->Rdense);
   RFMLS_HIP(h, hipGetLastError());
   const double unit = qr_dt == RFMLS_F64 ? 1.1102230246251565e-16 : 5.960464477539063e-08;
-  return finish_precond(h, P, check_rank, unit, qr_dt == RFMLS_F32 || store == RFMLS_F32);
+  // A float32 factor of at least 16,384 columns is also inverted in float32:
+  // its n^3/3 products then run at the float32 rate.  The float32 inverse
+  // preconditions slightly worse (4^3-box system, n = 25,600: 102 instead of 90
+  // iterations, inverse 81 -> 48 ms, solve 0.785 -> 0.760 s; on the 2^3-box
+  // Helmholtz system, n = 3,200, the extra iterations cost more than the
+  // smaller inverse saves: 36.6 -> 37.2 ms).
+  const bool inv32 = qr_dt == RFMLS_F32 && store == RFMLS_F32 && n >= 16384;
+  return finish_precond(h, P, check_rank, unit, qr_dt == RFMLS_F32 || store == RFMLS_F32, inv32);
 }
 
 }  // namespace rfmls
