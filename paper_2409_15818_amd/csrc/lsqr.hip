@@ -281,7 +281,10 @@ __global__ void k_lsqr_start(LsqrDev* st) {
   st->istop = 7;
   st->pending = 0;
   st->done = 0;
-  if (!(st->beta > 0.0)) {
+  if (!isfinite(st->beta)) {  // a non-finite right-hand side: breakdown, not "x = 0 is exact"
+    st->istop = -3;
+    st->done = 1;
+  } else if (!(st->beta > 0.0)) {
     st->istop = 0;
     st->done = 1;
   }
@@ -293,7 +296,10 @@ __global__ void k_lsqr_start2(LsqrDev* st) {
   st->rhobar = st->alpha;
   st->normr = st->beta;
   st->normar = st->alpha * st->beta;
-  if (!(st->alpha > 0.0)) {
+  if (!isfinite(st->alpha)) {
+    st->istop = -3;
+    st->done = 1;
+  } else if (!(st->alpha > 0.0)) {
     st->istop = 0;
     st->done = 1;
   }

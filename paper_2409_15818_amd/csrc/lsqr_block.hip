@@ -638,7 +638,10 @@ __global__ void k_blk_start(BlockState* st, double atol, double btol, double con
     d.bnorm = beta;
     d.phibar = beta;
     d.istop = 7;
-    if (!(beta > 0.0)) {
+    if (!isfinite(beta)) {  // a non-finite right-hand side: breakdown, not "x = 0 is exact"
+      d.istop = -3;
+      d.done = 1;
+    } else if (!(beta > 0.0)) {
       d.istop = 0;
       d.done = 1;
     }
@@ -656,7 +659,10 @@ __global__ void k_blk_start2(BlockState* st) {
       d.alpha_prev = d.alpha;
       d.normr = d.beta;
       d.normar = d.alpha * d.beta;
-      if (!(d.alpha > 0.0)) {
+      if (!isfinite(d.alpha)) {
+        d.istop = -3;
+        d.done = 1;
+      } else if (!(d.alpha > 0.0)) {
         d.istop = 0;
         d.done = 1;
       }
