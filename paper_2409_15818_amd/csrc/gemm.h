@@ -355,14 +355,16 @@ inline hipError_t launch(const GemmArgs<T>& g, hipStream_t st) {
   } else {
     const unsigned tn = (unsigned)((g.N + 63) / 64), tm = (unsigned)((g.M + 63) / 64);
     dim3 grid(g.tile_order == 1 ? tm : tn, g.tile_order == 1 ? tn : tm, gz);
-    if constexpr (sizeof(T) == 8 && CleanOnly && Role == GemmRole::QrVtC) {
+    if constexpr (sizeof(T) == 8 && CleanOnly && (Role == GemmRole::QrVtC || Role == GemmRole::Inverse)) {
       // float64 W = V^T [V | C] over 4096-row slices: K chunks of 8 and at
       // most four workgroups per compute unit (a dynamic LDS reservation that
       // brings each workgroup to a quarter of the 160 KB): 67.5 -> 71.1
       // TFLOP/s on 256 x 11,776 x 49,920 in isolation (fewer slabs of [V | C]
       // streamed at once per L2); in the pipeline 64.1 -> 66.0 TFLOP/s on the
       // 4^3-box float64 sketch (1.254 -> 1.243 s), within the run-to-run spread
-      // on the 8x8-box one; same K order, so the same bits
+      // on the 8x8-box one.  The blocked inversion's products (long K, split
+      // into slices) take the same shape: 54 -> 57-60 TFLOP/s (8x8-box),
+      // 57-58 -> 60 (4^3-box).  Same K order, so the same bits.
       constexpr size_t kStatic = sizeof(T) * 8 * 2 * (64 + PAD);
       constexpr size_t kCapLds = 163840 / 4 - kStatic;
       hipLaunchKernelGGL((k_gemm<T, 64, 64, 8, 2, 2, Role, CleanOnly>), grid, dim3(256), kCapLds, st, g);
