@@ -154,7 +154,6 @@ enum WsSlot {
   WS_QR_WP,
   WS_QR_T,
   WS_QR_WR,
-  WS_QR_Y,
   WS_QR_INNER,
   WS_TRSM,
   WS_LSQR_VEC,

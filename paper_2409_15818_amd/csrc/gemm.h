@@ -59,7 +59,6 @@ enum class GemmRole : int {
   QrVtC = 2,             // W = V^T [V | C] of an outer block
   QrInnerUpdate = 3,     // the same two products inside an outer block
   QrInnerVtC = 4,
-  QrOuterT = 5,          // block columns of T and T^T W
   Inverse = 6,           // blocked inversion of R
 };
 

@@ -18,8 +18,10 @@
 //                back substitution), C <- C - V (T^T W).
 // Outer block at column k0 (M0 = s - k0 rows, V_o = its kOuter Householder vectors):
 //   W = V_o^T [V_o | C] (split-K GEMM; the first kOuter columns are the Gram V_o^T V_o),
-//   T_o from the Gram: diagonal 64-blocks are the panels' T, off-diagonal
-//   blocks T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq,  then C <- C - V_o (T_o^T W_C).
+//   W' = T_o^T W_C without forming T_o's off-diagonal blocks: T_o's block
+//   recurrence T_o[:q, q] = -T_o[:q, :q] (V_:q^T V_q) T_qq turns the product
+//   into a forward substitution by blocks with the Gram's blocks and the
+//   panels' T (k_qr_outer_wp),  then C <- C - V_o W'.
 // All reductions run in a fixed order, so the factorisation is deterministic.
 #include "common.h"
 #include "gemm.h"
@@ -453,6 +455,103 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// W' = T_o^T W_C for an outer block of NQ 64-column panels, without forming
+// T_o's blocks above the diagonal.  Since T_o[:q0, q] = -T_o[:q0, :q0]
+// G[:q0, q] T_q (G = V_o^T V_o, q the panel at column q0, T_q its T), block
+// row q of T_o^T W_C is
+//   W'_q = T_q^T (W_q - G[:q0, q]^T W'[:q0]),
+// a forward substitution by blocks that every column runs on its own.  G's
+// blocks above the diagonal are read from G (rows ldg apart), each T_q (upper
+// triangular, zeros stored below the diagonal) from the diagonal 64-blocks of
+// Td (rows ldt apart), W_C from W (NQ * 64 rows, ldw apart).  One workgroup
+// per 16 columns; wavefront w forms rows 16 w .. 16 w + 15 of each 64-row
+// block on the matrix cores, in float64 for either storage type, and the rows
+// of W' formed so far stay in LDS.
+template <typename T, int NQ>
+__global__ void __launch_bounds__(256)
+    k_qr_outer_wp(const T* __restrict__ W, int64_t ldw, const T* __restrict__ G, int64_t ldg,
+                  const T* __restrict__ Td, int64_t ldt, int64_t ncol, T* __restrict__ Wp, int64_t ldwp) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  constexpr int SW = 16;
+  __shared__ double Xs[NQ * kMaxNb][SW + 1];  // W' rows formed so far
+  __shared__ double Ys[kMaxNb][SW + 1];       // W_q - G[:q0, q]^T W'[:q0]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int i0 = 16 * w;
+  const int64_t col = (int64_t)blockIdx.x * SW + lr;
+  const bool cin = col < ncol;
+  // operand layout of v_mfma_f64_16x16x4f64: lane (lr, lk) holds A[lr][lk] and
+  // B[lk][lr]; accumulator register r holds D[lk + 4 r][lr]
+  for (int q = 0; q < NQ; ++q) {
+    const int q0 = kMaxNb * q;
+    // G[:q0, q]^T W'[:q0]: A[i][k] = G[k][q0 + i], B[k][c] = W'[k][c], K in
+    // chunks of 64 (the next chunk's operands loaded during this one's
+    // products), two accumulators (even and odd steps)
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const T* ga = G + q0 + i0 + lr;
+    double a[16];
+    if (q0 > 0)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a[j] = (double)ga[(int64_t)(4 * j + lk) * ldg];
+    for (int kc = 0; kc < q0; kc += 64) {
+      double an[16];
+      const bool more = kc + 64 < q0;
+      if (more)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) an[j] = (double)ga[(int64_t)(kc + 64 + 4 * j + lk) * ldg];
+#pragma unroll
+      for (int j = 0; j < 16; j += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], Xs[kc + 4 * j + lk][lr], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1], Xs[kc + 4 * j + 4 + lk][lr], acc1, 0, 0, 0);
+      }
+      if (more)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a[j] = an[j];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + lk + 4 * r;
+      const double wv = cin ? (double)W[(int64_t)(q0 + i) * ldw + col] : 0.0;
+      Ys[i][lr] = wv - (acc0[r] + acc1[r]);
+    }
+    __syncthreads();
+    // W'_q = T_q^T Y: A[i][k] = T_q[k][i], zero for k > i, so the K range of
+    // rows i0 .. i0 + 15 ends at i0 + 16
+    const T* ta = Td + (int64_t)q0 * ldt + q0 + i0 + lr;
+    const int nk = 4 * (w + 1);
+    double tv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tv[j] = (double)ta[(int64_t)(4 * j + lk) * ldt];  // inside the block
+    v4d o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {
+      if (j < nk) {
+        o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[j], Ys[4 * j + lk][lr], o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[j + 1], Ys[4 * j + 4 + lk][lr], o1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + lk + 4 * r;
+      const double v = o0[r] + o1[r];
+      Xs[q0 + i][lr] = v;
+      if (cin) Wp[(int64_t)(q0 + i) * ldwp + col] = (T)v;
+    }
+    __syncthreads();
+  }
+}
+
+// The Gram's 64-blocks above the diagonal (rows ldw apart in W) into the same
+// places of To (rows ldt apart), whose diagonal blocks hold the panels' T:
+// what k_qr_outer_wp needs when a later product reuses the outer block.
+template <typename T>
+__global__ void k_qr_keep_gram(const T* __restrict__ W, int64_t ldw, int bw, T* __restrict__ To, int64_t ldt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)bw * bw) return;
+  const int r = (int)(e / bw), c = (int)(e % bw);
+  if (r / kMaxNb < c / kMaxNb) To[(int64_t)r * ldt + c] = W[(int64_t)r * ldw + c];
+}
+
 // Panel launch shapes (rows per thread Q, rows per block 16 Q), increasing.
 // The largest are the largest that compile without spills at 1024 threads.
 struct PanelShape {
@@ -634,13 +733,12 @@ rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw,
 }
 
 // Buffers of the trailing update: the outer products' slices, W = V^T [.],
-// W' = T_o^T W, and the scratch of T_o's block columns.
+// and W' = T_o^T W.
 template <typename T>
 struct TrailBufs {
   T* Wz;
   T* W;
   T* Wp;
-  T* Y;
 };
 
 // Trailing update C <- C - V T_o^T (V^T C) with the outer block [k0, k0 + bw)
@@ -652,7 +750,7 @@ struct TrailBufs {
 template <typename T>
 rfmls_status qr_block_trailing(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw, int64_t kOuter, T* SA, int64_t ld,
                                int64_t off, int64_t nc, int64_t nc_m, bool gram, const T* tau, T* To,
-                               const TrailBufs<T>& tb) {
+                               const TrailBufs<T>& tb, bool keep_gram = false) {
   hipStream_t st = h->stream;
   const int64_t split_out = 4096;
   const int64_t M0 = s - k0;
@@ -708,61 +806,33 @@ rfmls_status qr_block_trailing(rfmls_handle* h, int64_t s, int64_t k0, int64_t b
                        dim3(256), 0, st, (const T*)tb.Wz, bw * ldw, (int)nsp, zs, tb.W);
   }
   if (gram) {
-    // T_o: its diagonal 64-blocks are the inner panels' T, written by the
-    // panels, except the last panel's (no inner update follows it), built here
-    // from the Gram's diagonal block; then the block columns
-    Trace tr(h, "qr_outer_T", sizeof(T) * 4.0 * (double)bw * bw, 2.0 * (double)bw * bw * bw);
-    {
-      const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
-      const int jq = (int)(bw - q0);
-      hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jq + 15) / 16), dim3(1024), 0, st, (const T*)(tb.W + q0 * ldw + q0),
-                         (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0, (int64_t)kOuter);
-    }
-    for (int64_t q0 = kMaxNb; q0 < bw; q0 += kMaxNb) {
-      const int64_t jq = bw - q0 < kMaxNb ? bw - q0 : kMaxNb;
-      GemmArgs<T> ga;  // Y = T_o[:q0, :q0] * Gram[:q0, q0:q0+jq]
-      ga.M = q0;
-      ga.N = jq;
-      ga.K = q0;
-      ga.A = To;
-      ga.lda = kOuter;
-      ga.a_upper = 1;
-      ga.B = tb.W + q0;
-      ga.ldb = ldw;
-      ga.C = tb.Y;
-      ga.ldc = jq;
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(ga, st)));
-      GemmArgs<T> gb;  // T_o[:q0, q0:q0+jq] = -Y * T_qq
-      gb.M = q0;
-      gb.N = jq;
-      gb.K = jq;
-      gb.A = tb.Y;
-      gb.lda = jq;
-      gb.B = To + q0 * kOuter + q0;
-      gb.ldb = kOuter;
-      gb.b_upper = 1;
-      gb.C = To + q0;
-      gb.ldc = kOuter;
-      gb.alpha = T(-1);
-      RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gb, st)));
-    }
+    // the last panel's T (no inner update followed it) from the Gram's
+    // diagonal block; the other panels wrote theirs into To's diagonal
+    Trace tr(h, "qr_outer_T", sizeof(T) * 2.0 * kMaxNb * kMaxNb, 2.0 * (double)kMaxNb * kMaxNb * kMaxNb / 3.0);
+    const int64_t q0 = (bw - 1) / kMaxNb * kMaxNb;
+    const int jq = (int)(bw - q0);
+    hipLaunchKernelGGL(k_qr_buildT<T>, dim3((jq + 15) / 16), dim3(1024), 0, st, (const T*)(tb.W + q0 * ldw + q0),
+                       (int64_t)0, 1, ldw, jq, (const T*)(tau + q0), To + q0 * kOuter + q0, (int64_t)kOuter);
+    if (keep_gram)
+      hipLaunchKernelGGL(k_qr_keep_gram<T>, dim3((unsigned)ceil_div(bw * bw, 256)), dim3(256), 0, st,
+                         (const T*)tb.W, ldw, (int)bw, To, kOuter);
   }
   {
-    // W' = T_o^T W[:, C's columns]  (T_o^T lower triangular)
-    Trace tr(h, "qr_outer_TtW", sizeof(T) * 2.0 * (double)bw * nc_m, (double)bw * bw * nc_m);
-    GemmArgs<T> gt;
-    gt.M = bw;
-    gt.N = nc;
-    gt.K = bw;
-    gt.A = To;
-    gt.lda = kOuter;
-    gt.transA = 1;
-    gt.a_lower = 1;
-    gt.B = tb.W + vc;
-    gt.ldb = ldw;
-    gt.C = tb.Wp;
-    gt.ldc = ldwp;
-    RFMLS_HIP(h, (gemm<T, GemmRole::QrOuterT>(gt, st)));
+    // W' = T_o^T W[:, C's columns] by forward substitution with the Gram's
+    // blocks (from this product, or kept in To by an earlier one) and the
+    // panels' T
+    Trace tr(h, "qr_outer_Wp", sizeof(T) * 2.0 * (double)bw * nc_m, (double)bw * bw * nc_m);
+    const T* Gp = gram ? tb.W : To;
+    const int64_t ldg = gram ? ldw : kOuter;
+    const unsigned nb = (unsigned)ceil_div(nc, 16);
+    if (bw == 4 * kMaxNb)
+      hipLaunchKernelGGL((k_qr_outer_wp<T, 4>), dim3(nb), dim3(256), 0, st, (const T*)(tb.W + vc), ldw, Gp, ldg,
+                         (const T*)To, kOuter, nc, tb.Wp, ldwp);
+    else if (bw == 8 * kMaxNb)
+      hipLaunchKernelGGL((k_qr_outer_wp<T, 8>), dim3(nb), dim3(256), 0, st, (const T*)(tb.W + vc), ldw, Gp, ldg,
+                         (const T*)To, kOuter, nc, tb.Wp, ldwp);
+    else
+      return fail(h, RFMLS_E_ARG, "outer block of %lld columns", (long long)bw);
   }
   {
     Trace tr(h, gram ? "qr_gemm_update" : "qr_gemm_update_rest",
@@ -823,7 +893,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   // slices (2% faster than 8192 rows on the 8x8-box sketch, net of the longer
   // slice sum) and a ragged tail
   const int64_t nsp_out_max = (s + split_out - 1) / split_out + 2;
-  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_y, *p_in;
+  void *p_tau, *p_part, *p_wz, *p_w, *p_wp, *p_to, *p_in;
   RFMLS_CHECK(workspace(h, WS_QR_TAU, sizeof(T) * 2 * kOuterMax, &p_tau));
   RFMLS_CHECK(workspace(h, WS_QR_PART, sizeof(uint64_t) * ll_words(kPanelMaxBlocks), &p_part));
   // rows of the products W, W' are padded to 32 elements (128-byte aligned
@@ -834,7 +904,6 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   RFMLS_CHECK(workspace(h, WS_QR_WR, sizeof(T) * kOuter * (size_t)npad, &p_w));
   RFMLS_CHECK(workspace(h, WS_QR_WP, sizeof(T) * kOuter * (size_t)npad, &p_wp));
   RFMLS_CHECK(workspace(h, WS_QR_T, sizeof(T) * 2 * kOuter * kOuter, &p_to));
-  RFMLS_CHECK(workspace(h, WS_QR_Y, sizeof(T) * kOuter * kOuter, &p_y));
   // the panels' own product buffers: slices, Gram and T^T W of at most
   // 64 x kOuter each
   const int64_t kop = pad32(kOuter);
@@ -858,7 +927,7 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
   hipStream_t st = h->stream;
   T* tau2[2] = {(T*)p_tau, (T*)p_tau + kOuterMax};
   T* To2[2] = {(T*)p_to, (T*)p_to + kOuter * kOuter};
-  const TrailBufs<T> tb = {(T*)p_wz, (T*)p_w, (T*)p_wp, (T*)p_y};
+  const TrailBufs<T> tb = {(T*)p_wz, (T*)p_w, (T*)p_wp};
   T* in = (T*)p_in;
   uint64_t* ll = (uint64_t*)p_part;
   {
@@ -887,7 +956,8 @@ rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* S
     const PanelBufs<T> pb = bufs(blk), pb1 = bufs(blk + 1);
     if (lookahead && ntr_m > kOuter && cq_block(k1, bw1)) {
       // block k + 1's columns first, its panels on the second stream, the rest here
-      RFMLS_CHECK(qr_block_trailing<T>(h, s, k0, bw, kOuter, SA, ld, 0, kOuter, kOuter, true, pb.tau, pb.To, tb));
+      RFMLS_CHECK(qr_block_trailing<T>(h, s, k0, bw, kOuter, SA, ld, 0, kOuter, kOuter, true, pb.tau, pb.To, tb,
+                                       true));
       RFMLS_HIP(h, hipEventRecord(h->la_event[0], st));
       RFMLS_HIP(h, hipStreamWaitEvent(h->la_stream, h->la_event[0], 0));
       h->stream = h->la_stream;
