@@ -139,8 +139,9 @@ __global__ void __launch_bounds__(256) k_cq_reduce(const double* __restrict__ Gp
 
 // ---------------------------------------------------------------------------
 // 64 x 64 factorisations in LDS by one block of 256 threads, blocked by 16:
-// the 16 x 16 diagonal blocks on one wavefront in registers (values passed by
-// v_readlane), every product of blocks on the matrix cores (lds_mm).
+// the eliminations of a 16-row (or 16-column) block on one wavefront in
+// registers (values passed by v_readlane), every product of blocks on the
+// matrix cores (lds_mm).
 // ---------------------------------------------------------------------------
 constexpr int kB = 16;
 constexpr int kLd = kNb + 1;  // LDS row stride of a 64 x 64 matrix
@@ -214,100 +215,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cholesky A = U^T U of the symmetric positive definite A (upper triangle
-// read), U written over A with its lower triangle set to zero; Z[kb] receives
-// the inverse of diagonal block kb.  Returns false (every thread) on a
-// non-positive or non-finite pivot; pmin / pmax: the extreme pivots u_kk.
-__device__ bool blk_cholesky(Mat& A, Blk* Z, double* pmin, double* pmax) {
-  __shared__ int bad;
-  __shared__ double ext[2];
-  __shared__ double urow[kB][kB + 1];
-  const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  double mn = 1e300, mx = 0.0;
-  __syncthreads();
-  for (int kb = 0; kb < kNb / kB; ++kb) {
-    const int k0 = kb * kB;
-    if (t < 64) {
-      // diagonal block on wavefront 0, lane l < 16 holding its column l.  Step
-      // s: pivot by readlane, r_s = 1/sqrt(pivot), row s of U; the next row's
-      // entry (the next pivot's only dependence) by readlane, the rest of the
-      // row through LDS (uniform reads).
-      const int l = t;
-      const bool act = l < kB;
-      double d[kB], rr[kB];
-#pragma unroll
-      for (int i = 0; i < kB; ++i) d[i] = act ? A[k0 + i][k0 + l] : 0.0;
-#pragma unroll
-      for (int s2 = 0; s2 < kB; ++s2) {
-        const double piv = lane_bcast(d[s2], s2);
-        if (!(piv > 0.0) || !isfinite(piv)) bad = 1;
-        const double r = rsqrt(piv > 0.0 ? piv : 1.0);
-        const double ukk = piv * r;
-        rr[s2] = r;
-        mn = fmin(mn, ukk);
-        mx = fmax(mx, ukk);
-        const double us = (l == s2) ? ukk : (l > s2 ? d[s2] * r : 0.0);
-        d[s2] = us;
-        if (s2 + 1 < kB) {
-          if (act) urow[s2][l] = us;
-          const double un = lane_bcast(us, s2 + 1);
-          d[s2 + 1] = fma(-un, us, d[s2 + 1]);
-          wave_sync();
-#pragma unroll
-          for (int i = s2 + 2; i < kB; ++i) d[i] = fma(-urow[s2][i], us, d[i]);
-        }
-      }
-      // column l of U11^{-1} by a column sweep: z_m = acc_m / u_mm, then
-      // acc_i -= u_im z_m for i < m
-      double acc[kB];
-#pragma unroll
-      for (int i = 0; i < kB; ++i) acc[i] = (i == l) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m2 = kB - 1; m2 >= 0; --m2) {
-        const double zm = (m2 <= l) ? acc[m2] * rr[m2] : 0.0;
-        acc[m2] = zm;
-#pragma unroll
-        for (int i = 0; i < m2; ++i) acc[i] = fma(-urow[i][m2], zm, acc[i]);
-      }
-      if (act)
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          A[k0 + i][k0 + l] = d[i];  // d[i] = 0 below the diagonal
-          Z[kb][i][l] = acc[i];
-        }
-    }
-    __syncthreads();
-    if (bad) break;  // uniform: read after the barrier
-    const int nc = kNb - k0 - kB;
-    if (nc > 0) {
-      // block row U12 = U11^{-T} A12, then A22 -= U12^T U12
-      lds_mm(&A[k0][k0 + kB], kLd, &Z[kb][0][0], kB + 1, true, &A[k0][k0 + kB], kLd, kB, nc, kB, 1.0, 0.0);
-      lds_mm(&A[k0 + kB][k0 + kB], kLd, &A[k0][k0 + kB], kLd, true, &A[k0][k0 + kB], kLd, nc, nc, kB, -1.0, 1.0);
-    }
-  }
-  if (t < 64) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      mn = fmin(mn, __shfl_xor(mn, off, 64));
-      mx = fmax(mx, __shfl_xor(mx, off, 64));
-    }
-    if (t == 0) {
-      ext[0] = mn;
-      ext[1] = mx;
-    }
-  }
-  // lower triangle outside the diagonal blocks
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
-    if ((i >> 4) > (j >> 4)) A[i][j] = 0.0;
-  }
-  __syncthreads();
-  *pmin = ext[0];
-  *pmax = ext[1];
-  return !bad;
-}
-
 // Z[w] = inverse of diagonal block w of the upper triangular U, wavefront w
 // taking block w, lane l < 16 column l, by a column sweep with U's entries read
 // uniformly from LDS.
@@ -332,6 +239,74 @@ __device__ void blk_diag_inverses(const Mat& U, Blk* Z) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) Z[w][i][l] = acc[i];
   __syncthreads();
+}
+
+// Cholesky A = U^T U of the symmetric positive definite A (both triangles
+// read: A is kept whole), U written over A with its lower triangle set to
+// zero; Z[kb] receives the inverse of diagonal block kb.  Returns false
+// (every thread) on a non-positive or non-finite pivot; pmin / pmax: the
+// extreme pivots u_kk.  Block row kb (16 rows, columns k0 = 16 kb .. 63) is
+// factored by wavefront 0 alone, lane l holding column k0 + l: step s takes
+// the pivot from lane s (v_readlane), scales the lanes' row s entries to U's
+// row s and subtracts u_s,i u_s,l from the rows i > s below it, u_s,i read
+// from lane i; the whole block row of U comes out of the one elimination (no
+// product with the diagonal block's inverse) and no LDS round trip sits on the
+// chain.  The trailing block then takes A22 -= U12^T U12 on the matrix cores.
+__device__ bool blk_cholesky(Mat& A, Blk* Z, double* pmin, double* pmax) {
+  __shared__ int bad;
+  __shared__ double ext[2];
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  double mn = 1e300, mx = 0.0;  // uniform on wavefront 0 (pivots by readlane)
+  for (int kb = 0; kb < kNb / kB; ++kb) {
+    const int k0 = kb * kB;
+    if (t < 64) {
+      const int l = t;
+      const bool act = l < kNb - k0;
+      double d[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) d[i] = act ? A[k0 + i][k0 + l] : 0.0;
+      bool badl = false;
+#pragma unroll
+      for (int s2 = 0; s2 < kB; ++s2) {
+        const double piv = lane_bcast(d[s2], s2);
+        if (!(piv > 0.0) || !isfinite(piv)) badl = true;
+        const double r = rsqrt(piv > 0.0 ? piv : 1.0);
+        const double ukk = piv * r;
+        mn = fmin(mn, ukk);
+        mx = fmax(mx, ukk);
+        const double us = l == s2 ? ukk : d[s2] * r;  // u_{s,l} for l >= s
+        d[s2] = l >= s2 ? us : 0.0;
+#pragma unroll
+        for (int i = s2 + 1; i < kB; ++i) d[i] = fma(-lane_bcast(us, i), us, d[i]);
+      }
+      if (act)
+#pragma unroll
+        for (int i = 0; i < kB; ++i) A[k0 + i][k0 + l] = d[i];
+      if (t == 0) {
+        if (badl) bad = 1;
+        ext[0] = mn;
+        ext[1] = mx;
+      }
+    }
+    __syncthreads();
+    if (bad) break;  // uniform: read after the barrier
+    const int nc = kNb - k0 - kB;
+    if (nc > 0)  // A22 -= U12^T U12
+      lds_mm(&A[k0 + kB][k0 + kB], kLd, &A[k0][k0 + kB], kLd, true, &A[k0][k0 + kB], kLd, nc, nc, kB, -1.0, 1.0);
+  }
+  // lower triangle outside the diagonal blocks
+  for (int e = t; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    if ((i >> 4) > (j >> 4)) A[i][j] = 0.0;
+  }
+  __syncthreads();
+  const bool good = !bad;
+  if (good) blk_diag_inverses(A, Z);
+  *pmin = ext[0];
+  *pmax = ext[1];
+  return good;
 }
 
 // W = U^{-1} for the upper triangular U (zero below the diagonal; Z the
@@ -450,6 +425,20 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
   __shared__ double sg[kNb];
   __shared__ int bad0;
   const int t = threadIdx.x;
+  // thread t takes element (t / 64 + 4 q, t % 64), q < 16, of every 64 x 64
+  // operand; each operand's 16 loads are issued together
+  const int er = t >> 6, ec = t & 63;
+  double gv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gv[q] = G[(er + 4 * q) * kNb + ec];
+  if (pass == 2) {
+    // the panel's top block (Q1's) into M3, read after the Cholesky
+    double pv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pv[q] = (double)P[(int64_t)(er + 4 * q) * ld + ec];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) M3[er + 4 * q][ec] = pv[q];
+  }
   if (t < kNb) {
     const double gjj = G[t * kNb + t];
     dsc[t] = pass == 1 ? sqrt(gjj > 0.0 ? gjj : 0.0) : 1.0;
@@ -457,10 +446,13 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
   if (t == 0) bad0 = 0;
   __syncthreads();
   if (t < kNb && !(dsc[t] > 0.0)) bad0 = 1;
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
-    const double di = dsc[i], dj = dsc[j];
-    M0[i][j] = (di > 0.0 && dj > 0.0) ? G[e] * (1.0 / di) * (1.0 / dj) : 0.0;
+  {
+    const double dj = dsc[ec];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double di = dsc[er + 4 * q];
+      M0[er + 4 * q][ec] = (di > 0.0 && dj > 0.0) ? gv[q] * (1.0 / di) * (1.0 / dj) : 0.0;
+    }
   }
   __syncthreads();
   double pmin = 0.0, pmax = 0.0;
@@ -478,23 +470,21 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
     }
     return;
   }
-  // pass 2: M3 = R = U2 R1; M0 = Q1top U2^{-1}
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
-    M2[i][j] = Rc[e];
+  // pass 2: M2 = R = U2 R1 (written over R1); M0 = Q1top U2^{-1}
+  {
+    double rv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) rv[q] = Rc[(er + 4 * q) * kNb + ec];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) M2[er + 4 * q][ec] = rv[q];
   }
   __syncthreads();
-  lds_mm(&M3[0][0], kLd, &M0[0][0], kLd, false, &M2[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
-  for (int e = t; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
-    M2[i][j] = (double)P[(int64_t)i * ld + j];
-  }
-  __syncthreads();
-  lds_mm(&M0[0][0], kLd, &M2[0][0], kLd, false, &M1[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
+  lds_mm(&M2[0][0], kLd, &M0[0][0], kLd, false, &M2[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
+  lds_mm(&M0[0][0], kLd, &M3[0][0], kLd, false, &M1[0][0], kLd, kNb, kNb, kNb, 1.0, 0.0);
   blk_recon_lu(M0, sg);
   for (int e = t; e < kNb * kNb; e += 256) {
     const int i = e / kNb, c = e % kNb;
-    P[(int64_t)i * ld + c] = (TS)(i <= c ? sg[i] * M3[i][c] : M0[i][c]);
+    P[(int64_t)i * ld + c] = (TS)(i <= c ? sg[i] * M2[i][c] : M0[i][c]);
   }
   if (t < kNb) tau[t] = (TS)(-M0[t][t]);
   __syncthreads();
