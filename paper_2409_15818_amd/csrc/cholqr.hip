@@ -70,24 +70,27 @@ __global__ void __launch_bounds__(256) k_cq_gram(const TS* __restrict__ P, int64
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t r0 = (int64_t)blockIdx.x * kSlab + 64 * w;
+  // all 64 rows' operands loaded first (rows past M read row M - 1 and are
+  // replaced by zeros, so the loads carry no branch)
+  double x[16][4];
 #pragma unroll
-  for (int grp = 0; grp < 4; ++grp) {
-    double x[4][4];
+  for (int s = 0; s < 16; ++s) {
+    const int64_t row = r0 + 4 * s + lk;
+    const int64_t rr = row < M ? row : M - 1;
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int64_t row = r0 + 16 * grp + 4 * s4 + lk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[s4][q] = row < M ? (double)P[row * ld + 16 * q + lr] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const double v = (double)P[rr * ld + 16 * q + lr];
+      x[s][q] = row < M ? v : 0.0;
     }
+  }
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      int tile = 0;
+  for (int s = 0; s < 16; ++s) {
+    int tile = 0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = a; b < 4; ++b, ++tile)
-          acc[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s4][a], x[s4][b], acc[tile], 0, 0, 0);
-    }
+      for (int b = a; b < 4; ++b, ++tile)
+        acc[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s][a], x[s][b], acc[tile], 0, 0, 0);
   }
   // tile (a, b): D[lk + 4 r][lr] = G[16 a + lk + 4 r][16 b + lr]
   for (int ww = 0; ww < 4; ++ww) {
@@ -504,10 +507,67 @@ __global__ void __launch_bounds__(256) k_cq_factor(const double* __restrict__ G,
   for (int e = t; e < kNb * kNb; e += 256) Wk[e] = M3[e / kNb][e % kNb];
 }
 
-// Rows [r_begin, M) of P <- P W (W 64 x 64) on the matrix cores, in place:
-// wave w of a block takes 16 rows, reads all 64 of their columns (A operands,
-// in registers) before it writes them.  Runs when *status == 0.
-template <typename TS>
+// A operands of P W for one row: lane (lr, lk) of a wavefront takes row lr of
+// a 16-row group, and step t of the product's K range one of its columns,
+// kcol(t, lk).  With 16-byte loads (V16: the row start and ld allow them)
+// the lane reads E = 16 / sizeof(TS) adjacent columns at a time, so step t
+// takes column 4E (t / E) + E lk + t % E; otherwise column 4 t + lk.  Either
+// way the four lanes of a step hold four distinct columns inside the 4E-column
+// (or 4-column) chunk of the step, all 64 columns are covered once, and the
+// steps t < 4 (q + 1) hold every column <= 16 q + 15.
+template <typename TS, bool V16>
+__device__ __forceinline__ int kcol(int t, int lk) {
+  constexpr int E = 16 / (int)sizeof(TS);
+  return V16 ? 4 * E * (t / E) + E * lk + t % E : 4 * t + lk;
+}
+template <typename TS, bool V16>
+__device__ __forceinline__ void load_arow(double (&a)[16], const TS* __restrict__ row, int lk, bool in) {
+  if constexpr (V16 && sizeof(TS) == 8) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double2 v = *(const double2*)(row + 8 * m + 2 * lk);
+      a[2 * m] = in ? v.x : 0.0;
+      a[2 * m + 1] = in ? v.y : 0.0;
+    }
+  } else if constexpr (V16) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float4 v = *(const float4*)(row + 16 * m + 4 * lk);
+      a[4 * m] = in ? (double)v.x : 0.0;
+      a[4 * m + 1] = in ? (double)v.y : 0.0;
+      a[4 * m + 2] = in ? (double)v.z : 0.0;
+      a[4 * m + 3] = in ? (double)v.w : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const double v = (double)row[4 * t + lk];
+      a[t] = in ? v : 0.0;
+    }
+  }
+}
+// D = A W for a 16-row group, W upper triangular (zeros below its diagonal
+// are skipped: tile q's K range stops at column 16 q + 15).  Accumulator
+// register r of tile q holds D[lk + 4 r][16 q + lr].
+template <typename TS, bool V16>
+__device__ __forceinline__ void group_times_upper(const double (&a)[16], const double (*Ws)[kNb + 1], int lr, int lk,
+                                                  v4d (&acc)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int kk = kcol<TS, V16>(t, lk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (t < 4 * (q + 1)) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
+  }
+}
+
+// Rows [r_begin, M) of P <- P W (W 64 x 64 upper triangular) on the matrix
+// cores, in place: wave w of a block takes 16 rows, reads all 64 of their
+// columns (A operands, in registers) before it writes them.  Runs when
+// *status == 0.
+template <typename TS, bool V16>
 __global__ void __launch_bounds__(256) k_cq_apply(TS* __restrict__ P, int64_t ld, int64_t r_begin, int64_t M,
                                                   const double* __restrict__ W, const int* __restrict__ status) {
   if (*status) return;
@@ -515,22 +575,15 @@ __global__ void __launch_bounds__(256) k_cq_apply(TS* __restrict__ P, int64_t ld
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int e = t; e < kNb * kNb; e += 256) Ws[e / kNb][e % kNb] = W[e];
   const int64_t rbase = r_begin + (int64_t)blockIdx.x * 64 + 16 * w;
   const int64_t ra = rbase + lr;
+  const int64_t rc = ra < M ? ra : M - 1;  // rows past M: row M - 1, replaced by zeros
   double a[16];
-#pragma unroll
-  for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? (double)P[ra * ld + 4 * s4 + lk] : 0.0;
+  load_arow<TS, V16>(a, P + rc * ld, lk, ra < M);
+  for (int e = t; e < kNb * kNb; e += 256) Ws[e / kNb][e % kNb] = W[e];
   __syncthreads();
   v4d acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s4 = 0; s4 < 16; ++s4) {
-    const int kk = 4 * s4 + lk;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
-  }
+  group_times_upper<TS, V16>(a, Ws, lr, lk, acc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t row = rbase + lk + 4 * r;
@@ -541,12 +594,13 @@ __global__ void __launch_bounds__(256) k_cq_apply(TS* __restrict__ P, int64_t ld
 }
 
 // First pass's apply fused with the second pass's Gram: rows
-// [z kSlab, (z + 1) kSlab) of P <- P W (matrix cores, in place) and the
-// partial Gram of the new rows.  Wave w takes four groups of 16 rows from
-// z kSlab + 64 w; a group's product tiles (D[lk + 4 r][16 q + lr] in register
-// r of tile q) are already the Gram's operands for K-step r.  The waves' Gram
-// tiles are added in wave order through LDS.  Runs when *status == 0.
-template <typename TS>
+// [z kSlab, (z + 1) kSlab) of P <- P W (W upper triangular; matrix cores, in
+// place) and the partial Gram of the new rows.  Wave w takes four groups of 16
+// rows from z kSlab + 64 w; a group's product tiles (D[lk + 4 r][16 q + lr] in
+// register r of tile q) are already the Gram's operands for K-step r.  The
+// waves' Gram tiles are added in wave order through LDS.  Runs when
+// *status == 0.
+template <typename TS, bool V16>
 __global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64_t ld, int64_t M,
                                                        const double* __restrict__ W, double* __restrict__ Gpart,
                                                        const int* __restrict__ status) {
@@ -556,27 +610,25 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  // the four groups' operands loaded first (rows past M read row M - 1 and
+  // are replaced by zeros, so the loads carry no branch)
+  double ag[4][16];
+#pragma unroll
+  for (int grp = 0; grp < 4; ++grp) {
+    const int64_t ra = (int64_t)blockIdx.x * kSlab + 64 * w + 16 * grp + lr;
+    const int64_t rc = ra < M ? ra : M - 1;
+    load_arow<TS, V16>(ag[grp], P + rc * ld, lk, ra < M);
+  }
   for (int e = t; e < kNb * kNb; e += 256) Ws[e / kNb][e % kNb] = W[e];
   __syncthreads();
   v4d gacc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) gacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
   for (int grp = 0; grp < 4; ++grp) {
     const int64_t rbase = (int64_t)blockIdx.x * kSlab + 64 * w + 16 * grp;
-    const int64_t ra = rbase + lr;
-    double a[16];
-#pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) a[s4] = ra < M ? (double)P[ra * ld + 4 * s4 + lk] : 0.0;
     v4d acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) {
-      const int kk = 4 * s4 + lk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s4], Ws[kk][16 * q + lr], acc[q], 0, 0, 0);
-    }
+    group_times_upper<TS, V16>(ag[grp], Ws, lr, lk, acc);
     if constexpr (sizeof(TS) < sizeof(double)) {
       // the Gram below is of the rows as stored
 #pragma unroll
@@ -676,15 +728,27 @@ static rfmls_status cholqr_panel(rfmls_handle* h, TS* P, int64_t ld, int64_t M, 
                      1);
   hipLaunchKernelGGL(k_cq_factor<TS>, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 1,
                      min_ratio1);
-  hipLaunchKernelGGL(k_cq_apply_gram<TS>, dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M, (const double*)Wk, Gpart,
-                     (const int*)status);
+  // 16-byte operand loads when every row start allows them
+  const bool v16 = ld % (16 / (int64_t)sizeof(TS)) == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0;
+  if (v16)
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, true>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+                       (const double*)Wk, Gpart, (const int*)status);
+  else
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, false>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+                       (const double*)Wk, Gpart, (const int*)status);
   hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
                      0);
   hipLaunchKernelGGL(k_cq_factor<TS>, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 2,
                      min_ratio2);
-  if (M > kNb)
-    hipLaunchKernelGGL(k_cq_apply<TS>, dim3((unsigned)((M - kNb + 63) / 64)), dim3(256), 0, st, P, ld, (int64_t)kNb,
-                       M, (const double*)Wk, (const int*)status);
+  if (M > kNb) {
+    const dim3 grid((unsigned)((M - kNb + 63) / 64));
+    if (v16)
+      hipLaunchKernelGGL((k_cq_apply<TS, true>), grid, dim3(256), 0, st, P, ld, (int64_t)kNb, M, (const double*)Wk,
+                         (const int*)status);
+    else
+      hipLaunchKernelGGL((k_cq_apply<TS, false>), grid, dim3(256), 0, st, P, ld, (int64_t)kNb, M, (const double*)Wk,
+                         (const int*)status);
+  }
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
 }
