@@ -266,8 +266,9 @@ rfmls_status rfmls_solve(rfmls_handle *h, const rfmls_csr *A, const rfmls_csr *A
  * rfmls_solve with nothing allocated.  Arguments, results and status codes are
  * those of rfmls_solve, with the right-hand sides solved one at a time
  * (opts->lockstep is ignored; the iterates are those of rfmls_solve with
- * lockstep = 0).  The solve's device scratch (work vectors, partial sums and
- * LSQR state, 8 (4m + 8n + 8256) bytes plus 512) is a fixed array of
+ * lockstep = 0).  The solve's device scratch (work vectors, partial sums,
+ * LSQR state and the column-run descriptors of A and A^T: 8 (4m + 8n + 8256)
+ * + 512 + 68 (m + n) bytes) is a fixed array of
  * rfmls_noalloc_scratch_bytes() bytes (32 MiB) that each device the library
  * runs on holds until the process ends; a problem that needs more is rejected
  * with RFMLS_E_ARG before anything is enqueued.  The preconditioner's buffers

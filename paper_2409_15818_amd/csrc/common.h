@@ -158,6 +158,7 @@ enum WsSlot {
   WS_TRSM,
   WS_LSQR_VEC,
   WS_LSQR_SCAL,
+  WS_LSQR_RUNS,
   WS_LSQR_PART,
   WS_LSQR_BLK,
   WS_LSQR_BSTATE,

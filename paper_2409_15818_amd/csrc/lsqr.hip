@@ -188,6 +188,106 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ---------------------------------------------------------------------------
+// Column runs.  The rows of an RFM matrix cover the basis functions of one or
+// two boxes, contiguous column ranges, and the rows of its transpose a few
+// blocks of collocation points.  Row i is described as at most kMaxRuns runs
+// of consecutive columns: run k starts at column rcol[i kMaxRuns + k] and
+// ends before entry rend[i kMaxRuns + k] of the row (counted from rp[i]); the
+// SpMV then reads 8 bytes per entry (its value) instead of 12 and x in
+// contiguous stretches.  nrun[i] = -1 marks a row with more runs, which takes
+// the column-index path.
+// ---------------------------------------------------------------------------
+constexpr int kMaxRuns = 8;
+
+__global__ void __launch_bounds__(kThreads)
+    k_find_runs(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t rows,
+                int32_t* __restrict__ nrun, int32_t* __restrict__ rcol, int32_t* __restrict__ rend) {
+  const int lane = threadIdx.x & (kSpvLanes - 1);
+  const int half = (threadIdx.x & 63) >> 5;
+  const int64_t sub = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kSpvLanes;
+  const int64_t nsub = (int64_t)gridDim.x * (kThreads / kSpvLanes);
+  for (int64_t row = sub; row < rows; row += nsub) {
+    const int64_t lo = rp[row], hi = rp[row + 1];
+    int cnt = 0;  // runs found so far (uniform over the row's 32 lanes)
+    for (int64_t b = lo; b < hi; b += kSpvLanes) {
+      const int64_t e = b + lane;
+      const bool in = e < hi;
+      const int32_t c = in ? col[e] : 0;
+      const int32_t pc = (in && e > lo) ? col[e - 1] : 0;
+      const bool start = in && (e == lo || c != pc + 1);
+      const unsigned bits = (unsigned)(__ballot(start) >> (32 * half));
+      const int idx = cnt + __popc(bits & ((1u << lane) - 1u));
+      if (start && idx < kMaxRuns) {
+        rcol[row * kMaxRuns + idx] = c;
+        if (idx > 0) rend[row * kMaxRuns + idx - 1] = (int32_t)(e - lo);
+      }
+      cnt += __popc(bits);
+    }
+    if (lane == 0) {
+      if (cnt >= 1 && cnt <= kMaxRuns) rend[row * kMaxRuns + cnt - 1] = (int32_t)(hi - lo);
+      nrun[row] = cnt <= kMaxRuns ? cnt : -1;
+    }
+  }
+}
+
+// k_spmv over column runs (rows marked -1 take the column-index path)
+__global__ void __launch_bounds__(kThreads)
+    k_spmv_runs(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                const double* __restrict__ val, int64_t rows, const int32_t* __restrict__ nrun,
+                const int32_t* __restrict__ rcol, const int32_t* __restrict__ rend,
+                const double* __restrict__ x, double sA, double hcoef, const double* __restrict__ dcoef,
+                const double* prev, double* out, double* __restrict__ sq, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double scratch[kThreads / 64];
+  const int lane = threadIdx.x & (kSpvLanes - 1);
+  const int64_t sub = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kSpvLanes;
+  const int64_t nsub = (int64_t)gridDim.x * (kThreads / kSpvLanes);
+  double cf = hcoef;
+  if (dcoef) cf *= *dcoef;
+  double ss = 0.0;
+  for (int64_t row = sub; row < rows; row += nsub) {
+    const int64_t lo = rp[row], hi = rp[row + 1];
+    const int nr = nrun[row];
+    double s0 = 0.0, s1 = 0.0;
+    if (nr < 0) {
+      int64_t e = lo + lane;
+      for (; e + kSpvLanes < hi; e += 2 * kSpvLanes) {
+        s0 += val[e] * x[col[e]];
+        s1 += val[e + kSpvLanes] * x[col[e + kSpvLanes]];
+      }
+      if (e < hi) s0 += val[e] * x[col[e]];
+    } else {
+      const double* vr = val + lo;
+      int32_t off = 0;
+      for (int k = 0; k < nr; ++k) {
+        const int32_t end = rend[row * kMaxRuns + k];
+        const double* xr = x + rcol[row * kMaxRuns + k];  // column of entry off
+        int32_t e = off + lane;
+        for (; e + kSpvLanes < end; e += 2 * kSpvLanes) {
+          s0 += vr[e] * xr[e - off];
+          s1 += vr[e + kSpvLanes] * xr[e + kSpvLanes - off];
+        }
+        if (e < end) s0 += vr[e] * xr[e - off];
+        off = end;
+      }
+    }
+    double t = s0 + s1;
+#pragma unroll
+    for (int o = kSpvLanes / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) {
+      double o = sA * t;
+      if (prev && cf != 0.0) o -= cf * prev[row];
+      out[row] = o;
+      ss += o * o;
+    }
+  }
+  if (sq) {
+    ss = block_sum(ss, scratch);
+    if (threadIdx.x == 0) sq[blockIdx.x] = ss;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Vector helpers
 // ---------------------------------------------------------------------------
 // nrm = sqrt(sum sq[0..nsq)), fixed order; every block computes it, block 0 stores it.
@@ -515,6 +615,9 @@ struct Ctx {
   LsqrDev* dst;
   IterGraph* graph = nullptr;  // captured poll interval of the loop, or null: eager launches
   int nspmvA, nspmvAT, nvec_n, nvec_m;
+  // column runs of A and A^T (null: the column-index SpMV)
+  const int32_t *nrunA = nullptr, *rcolA = nullptr, *rendA = nullptr;
+  const int32_t *nrunAT = nullptr, *rcolAT = nullptr, *rendAT = nullptr;
 };
 
 static unsigned spmv_blocks(int64_t rows) {
@@ -575,14 +678,21 @@ static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA,
                          const double* dcoef, const double* prev, double* out, double* sq,
                          const int* done, int* nblk) {
   const unsigned nb = spmv_blocks(M->m);
+  const int32_t* nrun = M == c.A ? c.nrunA : c.nrunAT;
+  const int32_t* rcol = M == c.A ? c.rcolA : c.rcolAT;
+  const int32_t* rend = M == c.A ? c.rendA : c.rendAT;
   // algorithmic: values and column indices once, row pointers, x gathered once,
   // out written (and prev read when used)
   Trace tr(c.h, M == c.A ? "spmv_A" : "spmv_At",
            12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) + 8.0 * (double)M->n +
                8.0 * (double)M->m * (prev ? 2.0 : 1.0),
            2.0 * (double)M->nnz);
-  hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
-                     x, sA, hcoef, dcoef, prev, out, sq, done);
+  if (nrun)
+    hipLaunchKernelGGL(k_spmv_runs, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, nrun,
+                       rcol, rend, x, sA, hcoef, dcoef, prev, out, sq, done);
+  else
+    hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
+                       x, sA, hcoef, dcoef, prev, out, sq, done);
   if (nblk) *nblk = (int)nb;
   RFMLS_HIP(c.h, hipGetLastError());
   return RFMLS_OK;
@@ -749,8 +859,11 @@ static rfmls_status lsqr_sweep(Ctx& c, const double* rhs, const rfmls_opts* o, i
 static int64_t ctx_doubles(int64_t m, int64_t n) { return 4 * m + 8 * n + 4 * kSpmvMaxBlocks + 64; }
 constexpr int64_t kStateDoubles = (2 * sizeof(LsqrDev) + 255) / 256 * 32;
 
-// base: device memory of at least ctx_doubles + kStateDoubles doubles, or null
-// for the handle's workspace
+// Bytes of the column-run descriptors of `rows` matrix rows.
+static int64_t runs_bytes(int64_t rows) { return (int64_t)sizeof(int32_t) * rows * (1 + 2 * kMaxRuns); }
+
+// base: device memory of at least ctx_doubles + kStateDoubles doubles followed
+// by runs_bytes(m + n) bytes, or null for the handle's workspace
 static rfmls_status make_ctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
                              const rfmls_precond_t* P, Ctx& c, double* base = nullptr) {
   c.h = h;
@@ -795,6 +908,28 @@ static rfmls_status make_ctx(rfmls_handle* h, const rfmls_csr* A, const rfmls_cs
   void* ps = base ? (void*)(base + nvec) : nullptr;
   if (!base) RFMLS_CHECK(workspace(h, WS_LSQR_SCAL, sizeof(LsqrDev) * 2, &ps));
   c.dst = (LsqrDev*)ps;
+  {
+    // column runs of A and A^T, after the state in the caller's scratch or in
+    // the handle's workspace
+    const int64_t ra = A->m, rt = AT ? AT->m : 0;
+    void* pr = base ? (void*)(base + nvec + kStateDoubles) : nullptr;
+    if (!base) RFMLS_CHECK(workspace(h, WS_LSQR_RUNS, (size_t)runs_bytes(ra + rt), &pr));
+    int32_t* q = (int32_t*)pr;
+    auto carve = [&](const rfmls_csr* M, int64_t rows, const int32_t** nr, const int32_t** rc, const int32_t** re) {
+      int32_t* n0 = q;
+      int32_t* c0 = n0 + rows;
+      int32_t* e0 = c0 + rows * kMaxRuns;
+      q = e0 + rows * kMaxRuns;
+      hipLaunchKernelGGL(k_find_runs, dim3(spmv_blocks(rows)), dim3(kThreads), 0, c.st, M->row_ptr, M->col, rows, n0,
+                         c0, e0);
+      *nr = n0;
+      *rc = c0;
+      *re = e0;
+    };
+    if (ra > 0) carve(A, ra, &c.nrunA, &c.rcolA, &c.rendA);
+    if (rt > 0) carve(AT, rt, &c.nrunAT, &c.rcolAT, &c.rendAT);
+    RFMLS_HIP(h, hipGetLastError());
+  }
   return RFMLS_OK;
 }
 
@@ -942,7 +1077,7 @@ rfmls_status noalloc_scratch_init(rfmls_handle* h) {
 int64_t noalloc_scratch_bytes() { return noalloc::kScratchDoubles * (int64_t)sizeof(double); }
 
 int64_t noalloc_needed_bytes(int64_t m, int64_t n) {
-  return (ctx_doubles(m, n) + kStateDoubles) * (int64_t)sizeof(double);
+  return (ctx_doubles(m, n) + kStateDoubles) * (int64_t)sizeof(double) + runs_bytes(m + n);
 }
 
 rfmls_status run_solve_noalloc(rfmls_handle* h, const rfmls_csr* A, const rfmls_csr* AT,
