@@ -581,6 +581,53 @@ def test_solve_small_dense_systems(handle, m, n, s):
     assert np.linalg.norm(res.x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
 
 
+def _rows_with_runs(m, n, rng):
+    """Dense m x n matrix whose rows have 1, 8, 9 or many runs of consecutive
+    nonzero columns (the SpMV's run descriptors hold up to 8 per row; rows with
+    more take the column-index path), plus a diagonal that keeps it full rank."""
+    Ad = np.zeros((m, n))
+    for i in range(m):
+        kind = i % 4
+        if kind == 0:  # one run
+            a = rng.integers(0, n - 20)
+            Ad[i, a:a + rng.integers(1, 20)] = rng.standard_normal(1)
+        elif kind in (1, 2):  # exactly 8 or 9 runs: stretches of 2 split by gaps of 3
+            k = 8 if kind == 1 else 9
+            a = rng.integers(0, n - 5 * k)
+            for r in range(k):
+                Ad[i, a + 5 * r:a + 5 * r + 2] = 1.0
+        else:  # scattered entries
+            cols = rng.choice(n, size=12, replace=False)
+            Ad[i, cols] = 1.0
+        Ad[i, np.nonzero(Ad[i])[0]] *= rng.standard_normal(np.count_nonzero(Ad[i])) + 2.0
+    Ad[np.arange(n), np.arange(n)] += 3.0
+    return Ad
+
+
+def test_solve_rows_with_many_column_runs(handle):
+    """Rows of A (and of A^T) with one, eight, nine and a dozen runs of
+    consecutive columns: the SpMV over run descriptors and its column-index
+    path for rows with more than eight runs, against numpy's least squares."""
+    rng = np.random.default_rng(7)
+    m, n = 1200, 160
+    Ad = _rows_with_runs(m, n, rng)
+    b = rng.standard_normal(m)
+    rp, col, val = csr_from_dense(Ad)
+    runs = [1 + int(np.sum(np.diff(col[rp[i]:rp[i + 1]]) != 1)) for i in range(m)]
+    assert {1, 8, 9} <= set(runs) and max(runs) > 9
+    A = gpu_csr(rp, col, val, m, n)
+    print("[parity] rows with 1 / 8 / 9 / 12 column runs, 1200 x 160", flush=True)
+    res = R.csqrp_lsqr(handle, A, torch.tensor(b, device="cuda"), 400, 1)
+    x_ref = np.linalg.lstsq(Ad, b, rcond=None)[0]
+    r_ref = np.linalg.norm(b - Ad @ x_ref)
+    assert res.status == 0
+    assert abs(res.info[0]["normr"] - r_ref) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(res.x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    # the true residual the solve reports is b - A x of its own x
+    x = res.x.cpu().numpy().reshape(-1)
+    assert np.allclose(res.residual.cpu().numpy().reshape(-1), b - Ad @ x, rtol=0, atol=1e-12 * np.linalg.norm(b))
+
+
 def test_degenerate_right_hand_sides(handle):
     S, s, A = system("poisson2d_2x2")
     AT = R.rfmls_transpose(handle, A)
