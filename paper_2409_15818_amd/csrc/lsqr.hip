@@ -685,10 +685,12 @@ static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA,
   const int32_t* nrun = M == c.A ? c.nrunA : c.nrunAT;
   const int32_t* rcol = M == c.A ? c.rcolA : c.rcolAT;
   const int32_t* rend = M == c.A ? c.rendA : c.rendAT;
-  // algorithmic: values and column indices once, row pointers, x gathered once,
-  // out written (and prev read when used)
+  // algorithmic: values once (and the column indices, unless the rows are
+  // described by their column runs: then a run count and at least one run per
+  // row), row pointers, x gathered once, out written (and prev read when used)
+  const double idx_bytes = nrun ? 4.0 * (double)M->m * (1 + 2) : 4.0 * (double)M->nnz;
   Trace tr(c.h, M == c.A ? "spmv_A" : "spmv_At",
-           12.0 * (double)M->nnz + 8.0 * (double)(M->m + 1) + 8.0 * (double)M->n +
+           8.0 * (double)M->nnz + idx_bytes + 8.0 * (double)(M->m + 1) + 8.0 * (double)M->n +
                8.0 * (double)M->m * (prev ? 2.0 : 1.0),
            2.0 * (double)M->nnz);
   if (nrun)
