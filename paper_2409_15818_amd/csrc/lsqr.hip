@@ -198,6 +198,11 @@ __global__ void __launch_bounds__(kThreads)
 // the column-index path.
 // ---------------------------------------------------------------------------
 constexpr int kMaxRuns = 8;
+// lanes per row of the run SpMV for matrices whose rows average fewer than
+// 512 entries (more rows in flight per wavefront: spmv_A 0.054 -> 0.048 ms on
+// the 8x8-box system's 216-entry rows, 0.060 -> 0.055 ms on the Helmholtz
+// system's 446-entry rows; 4 lanes and 16 were slower); longer rows keep 32
+constexpr int kSpvLanesShort = 8;
 
 __global__ void __launch_bounds__(kThreads)
     k_find_runs(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t rows,
@@ -230,7 +235,11 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// k_spmv over column runs (rows marked -1 take the column-index path)
+// k_spmv over column runs (rows marked -1 take the column-index path), L
+// lanes per row.  A row's pointers, run count and first run are loaded
+// together, and the next row's while this one is summed, so a row costs one
+// memory latency instead of three.
+template <int L>
 __global__ void __launch_bounds__(kThreads)
     k_spmv_runs(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                 const double* __restrict__ val, int64_t rows, const int32_t* __restrict__ nrun,
@@ -239,51 +248,75 @@ __global__ void __launch_bounds__(kThreads)
                 const double* prev, double* out, double* __restrict__ sq, const int* __restrict__ done) {
   if (done && *done) return;
   __shared__ double scratch[kThreads / 64];
-  const int lane = threadIdx.x & (kSpvLanes - 1);
-  const int64_t sub = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kSpvLanes;
-  const int64_t nsub = (int64_t)gridDim.x * (kThreads / kSpvLanes);
+  const int lane = threadIdx.x & (L - 1);
+  const int64_t sub = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / L;
+  const int64_t nsub = (int64_t)gridDim.x * (kThreads / L);
   double cf = hcoef;
   if (dcoef) cf *= *dcoef;
   double ss = 0.0;
+  int64_t lo = 0, hi = 0;
+  int nr = 0;
+  int32_t e0 = 0, c0 = 0;
+  if (sub < rows) {
+    lo = rp[sub];
+    hi = rp[sub + 1];
+    nr = nrun[sub];
+    e0 = rend[sub * kMaxRuns];
+    c0 = rcol[sub * kMaxRuns];
+  }
   for (int64_t row = sub; row < rows; row += nsub) {
-    const int64_t lo = rp[row], hi = rp[row + 1];
-    const int nr = nrun[row];
+    const int64_t nrow = row + nsub;
+    int64_t nlo = 0, nhi = 0;
+    int nnr = 0;
+    int32_t ne0 = 0, nc0 = 0;
+    if (nrow < rows) {
+      nlo = rp[nrow];
+      nhi = rp[nrow + 1];
+      nnr = nrun[nrow];
+      ne0 = rend[nrow * kMaxRuns];
+      nc0 = rcol[nrow * kMaxRuns];
+    }
     double s0 = 0.0, s1 = 0.0;
     if (nr < 0) {
       int64_t e = lo + lane;
-      for (; e + kSpvLanes < hi; e += 2 * kSpvLanes) {
+      for (; e + L < hi; e += 2 * L) {
         s0 += val[e] * x[col[e]];
-        s1 += val[e + kSpvLanes] * x[col[e + kSpvLanes]];
+        s1 += val[e + L] * x[col[e + L]];
       }
       if (e < hi) s0 += val[e] * x[col[e]];
     } else {
       const double* vr = val + lo;
       int32_t off = 0;
       for (int k = 0; k < nr; ++k) {
-        const int32_t end = rend[row * kMaxRuns + k];
-        const double* xr = x + rcol[row * kMaxRuns + k];  // column of entry off
+        const int32_t end = k == 0 ? e0 : rend[row * kMaxRuns + k];
+        const double* xr = x + (k == 0 ? c0 : rcol[row * kMaxRuns + k]);  // column of entry off
         // four entries per lane in flight (the transposes' rows run to
         // thousands of entries: 0.085 -> 0.064 ms on the Helmholtz A^T)
         int32_t e = off + lane;
-        for (; e + 3 * kSpvLanes < end; e += 4 * kSpvLanes) {
+        for (; e + 3 * L < end; e += 4 * L) {
           s0 += vr[e] * xr[e - off];
-          s1 += vr[e + kSpvLanes] * xr[e + kSpvLanes - off];
-          s0 += vr[e + 2 * kSpvLanes] * xr[e + 2 * kSpvLanes - off];
-          s1 += vr[e + 3 * kSpvLanes] * xr[e + 3 * kSpvLanes - off];
+          s1 += vr[e + L] * xr[e + L - off];
+          s0 += vr[e + 2 * L] * xr[e + 2 * L - off];
+          s1 += vr[e + 3 * L] * xr[e + 3 * L - off];
         }
-        for (; e < end; e += kSpvLanes) s0 += vr[e] * xr[e - off];
+        for (; e < end; e += L) s0 += vr[e] * xr[e - off];
         off = end;
       }
     }
     double t = s0 + s1;
 #pragma unroll
-    for (int o = kSpvLanes / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    for (int o = L / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (lane == 0) {
       double o = sA * t;
       if (prev && cf != 0.0) o -= cf * prev[row];
       out[row] = o;
       ss += o * o;
     }
+    lo = nlo;
+    hi = nhi;
+    nr = nnr;
+    e0 = ne0;
+    c0 = nc0;
   }
   if (sq) {
     ss = block_sum(ss, scratch);
@@ -693,9 +726,18 @@ static rfmls_status spmv(Ctx& c, const rfmls_csr* M, const double* x, double sA,
            8.0 * (double)M->nnz + idx_bytes + 8.0 * (double)(M->m + 1) + 8.0 * (double)M->n +
                8.0 * (double)M->m * (prev ? 2.0 : 1.0),
            2.0 * (double)M->nnz);
+  if (nrun && M->nnz < 512 * M->m) {
+    const int64_t b = (M->m + kThreads / kSpvLanesShort - 1) / (kThreads / kSpvLanesShort);
+    const unsigned nbs = (unsigned)(b < kSpmvMaxBlocks ? (b > 0 ? b : 1) : kSpmvMaxBlocks);
+    hipLaunchKernelGGL(k_spmv_runs<kSpvLanesShort>, dim3(nbs), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val,
+                       M->m, nrun, rcol, rend, x, sA, hcoef, dcoef, prev, out, sq, done);
+    if (nblk) *nblk = (int)nbs;
+    RFMLS_HIP(c.h, hipGetLastError());
+    return RFMLS_OK;
+  }
   if (nrun)
-    hipLaunchKernelGGL(k_spmv_runs, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m, nrun,
-                       rcol, rend, x, sA, hcoef, dcoef, prev, out, sq, done);
+    hipLaunchKernelGGL(k_spmv_runs<kSpvLanes>, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
+                       nrun, rcol, rend, x, sA, hcoef, dcoef, prev, out, sq, done);
   else
     hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kThreads), 0, c.st, M->row_ptr, M->col, M->val, M->m,
                        x, sA, hcoef, dcoef, prev, out, sq, done);
