@@ -4,8 +4,8 @@
 //
 // Products used by one iteration:
 //   z = X v            triangular product with the packed X = R^{-1}  (k_trmv_*)
-//   u^ = A z - a u     CSR SpMV, one wavefront per row                 (k_spmv)
-//   q = A^T u          CSR SpMV with the explicit transpose            (k_spmv)
+//   u^ = A z - a u     SpMV over each row's column runs                (k_spmv_runs)
+//   q = A^T u          the same with the explicit transpose            (k_spmv_runs)
 //   v^ = X^T q - b v   transposed triangular product                   (k_trmvT_*)
 // followed by the plane rotation and the updates of y and w.  Norms are
 // reduced in a fixed order (per-block partials, then a fixed tree), so runs
