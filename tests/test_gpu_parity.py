@@ -165,6 +165,26 @@ def test_transpose_empty_rows_and_columns(handle):
     assert np.array_equal(ref, Ad.T)
 
 
+def test_transpose_wide_scattered_matrix(handle):
+    """A transpose of a wide matrix with scattered entries: row chunks that
+    reach thousands of distinct columns, over two column windows of 16,384
+    columns, against scipy."""
+    rng = np.random.default_rng(9)
+    m, n, per = 2000, 20000, 200
+    cols = np.concatenate([np.sort(rng.choice(n, size=per, replace=False)) for _ in range(m)])
+    vals = rng.standard_normal(m * per)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(np.full(m, per))
+    A = gpu_csr(rp, cols.astype(np.int32), vals, m, n)
+    print("[parity] transpose of a 2000 x 20000 matrix, 200 scattered entries per row", flush=True)
+    AT = R.rfmls_transpose(handle, A)
+    ref = pipeline.csr(rp, cols.astype(np.int32), vals, m, n).T.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(AT.row_ptr.cpu().numpy(), ref.indptr)
+    assert np.array_equal(AT.col.cpu().numpy(), ref.indices)
+    assert np.array_equal(AT.val.cpu().numpy(), ref.data)
+
+
 # ------------------------------------------------------------------ QR / R^{-1}
 def _qr_case(handle, SAo, dtype):
     SA = torch.tensor(SAo.astype(np.float32 if dtype == "f32" else np.float64), device="cuda")
