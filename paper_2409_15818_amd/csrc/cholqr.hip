@@ -41,7 +41,13 @@ namespace rfmls {
 namespace {
 
 constexpr int kNb = 64;      // panel width
-constexpr int kSlab = 256;   // rows per partial Gram
+constexpr int kSlab = 256;   // rows per partial Gram (tall panels)
+// Panels under this many rows take 128-row slabs (two 16-row groups per
+// wavefront): twice the workgroups, so a short panel's Gram and apply passes
+// use more of the GPU, their partial Grams still few enough to sum (Helmholtz
+// sketch, 12,800 rows: 0.155 -> 0.146 ms per panel; 64-row slabs 0.147).
+constexpr int64_t kShortPanelRows = 32768;
+inline int64_t slab_rows(int64_t M) { return M >= kShortPanelRows ? kSlab : 128; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -52,13 +58,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // l = 16 lk + lr holds A[lr][lk] and B[lk][lr]; accumulator register r holds
 // D[lk + 4 r][lr].
 
-// Partial Gram of rows [z kSlab, (z + 1) kSlab) of P on the matrix cores.  Wave
-// w takes the 64 rows starting at z kSlab + 64 w and accumulates the ten upper
+// Partial Gram of rows [z S, (z + 1) S) of P (S = 64 NG) on the matrix cores.
+// Wave w takes the 16 NG rows from z S + 16 NG w and accumulates the ten upper
 // 16 x 16 tiles of their Gram; each lane loads its operands straight from P
 // (lane (lr, lk) reads row 4 s + lk, columns 16 q + lr: every 16 lanes read
 // 128 contiguous bytes), no LDS staging.  The four waves' tiles are then added
 // in wave order through LDS and the full symmetric 64 x 64 partial written.
-template <typename TS>
+template <typename TS, int NG>
 __global__ void __launch_bounds__(256) k_cq_gram(const TS* __restrict__ P, int64_t ld, int64_t M,
                                                  double* __restrict__ Gpart, const int* __restrict__ status) {
   if (status && *status) return;
@@ -69,12 +75,12 @@ __global__ void __launch_bounds__(256) k_cq_gram(const TS* __restrict__ P, int64
   v4d acc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int64_t r0 = (int64_t)blockIdx.x * kSlab + 64 * w;
-  // all 64 rows' operands loaded first (rows past M read row M - 1 and are
-  // replaced by zeros, so the loads carry no branch)
-  double x[16][4];
+  const int64_t r0 = (int64_t)blockIdx.x * (64 * NG) + 16 * NG * w;
+  // all the wavefront's rows' operands loaded first (rows past M read row
+  // M - 1 and are replaced by zeros, so the loads carry no branch)
+  double x[4 * NG][4];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
+  for (int s = 0; s < 4 * NG; ++s) {
     const int64_t row = r0 + 4 * s + lk;
     const int64_t rr = row < M ? row : M - 1;
 #pragma unroll
@@ -84,7 +90,7 @@ __global__ void __launch_bounds__(256) k_cq_gram(const TS* __restrict__ P, int64
     }
   }
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
+  for (int s = 0; s < 4 * NG; ++s) {
     int tile = 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -594,13 +600,13 @@ __global__ void __launch_bounds__(256) k_cq_apply(TS* __restrict__ P, int64_t ld
 }
 
 // First pass's apply fused with the second pass's Gram: rows
-// [z kSlab, (z + 1) kSlab) of P <- P W (W upper triangular; matrix cores, in
-// place) and the partial Gram of the new rows.  Wave w takes four groups of 16
-// rows from z kSlab + 64 w; a group's product tiles (D[lk + 4 r][16 q + lr] in
+// [z S, (z + 1) S) of P (S = 64 NG) <- P W (W upper triangular; matrix cores,
+// in place) and the partial Gram of the new rows.  Wave w takes NG groups of 16
+// rows from z S + 16 NG w; a group's product tiles (D[lk + 4 r][16 q + lr] in
 // register r of tile q) are already the Gram's operands for K-step r.  The
 // waves' Gram tiles are added in wave order through LDS.  Runs when
 // *status == 0.
-template <typename TS, bool V16>
+template <typename TS, bool V16, int NG>
 __global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64_t ld, int64_t M,
                                                        const double* __restrict__ W, double* __restrict__ Gpart,
                                                        const int* __restrict__ status) {
@@ -612,10 +618,10 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64
   const int lr = lane & 15, lk = lane >> 4;
   // the four groups' operands loaded first (rows past M read row M - 1 and
   // are replaced by zeros, so the loads carry no branch)
-  double ag[4][16];
+  double ag[NG][16];
 #pragma unroll
-  for (int grp = 0; grp < 4; ++grp) {
-    const int64_t ra = (int64_t)blockIdx.x * kSlab + 64 * w + 16 * grp + lr;
+  for (int grp = 0; grp < NG; ++grp) {
+    const int64_t ra = (int64_t)blockIdx.x * (64 * NG) + 16 * NG * w + 16 * grp + lr;
     const int64_t rc = ra < M ? ra : M - 1;
     load_arow<TS, V16>(ag[grp], P + rc * ld, lk, ra < M);
   }
@@ -625,8 +631,8 @@ __global__ void __launch_bounds__(256) k_cq_apply_gram(TS* __restrict__ P, int64
 #pragma unroll
   for (int q = 0; q < 10; ++q) gacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int grp = 0; grp < 4; ++grp) {
-    const int64_t rbase = (int64_t)blockIdx.x * kSlab + 64 * w + 16 * grp;
+  for (int grp = 0; grp < NG; ++grp) {
+    const int64_t rbase = (int64_t)blockIdx.x * (64 * NG) + 16 * NG * w + 16 * grp;
     v4d acc[4];
     group_times_upper<TS, V16>(ag[grp], Ws, lr, lk, acc);
     if constexpr (sizeof(TS) < sizeof(double)) {
@@ -702,9 +708,14 @@ __global__ void __launch_bounds__(256) k_cq_fix(TS* __restrict__ P, int64_t ld, 
 
 }  // namespace
 
+// Partial Grams of an M-row panel.
+static int64_t cq_nslab(int64_t M) { return (M + slab_rows(M) - 1) / slab_rows(M); }
+
 int64_t cholqr_workspace_doubles(int64_t M) {
-  const int64_t nslab = (M + kSlab - 1) / kSlab;
-  return nslab * kNb * kNb + 3 * kNb * kNb + 64;
+  // room for the most partials of any panel of at most M rows
+  const int64_t ms = M < kShortPanelRows - 1 ? M : kShortPanelRows - 1;
+  const int64_t a = cq_nslab(M), b = cq_nslab(ms);
+  return (a > b ? a : b) * kNb * kNb + 3 * kNb * kNb + 64;
 }
 
 // Enqueues CholeskyQR2 and the reconstruction on the 64-column panel P
@@ -717,24 +728,36 @@ template <typename TS>
 static rfmls_status cholqr_panel(rfmls_handle* h, TS* P, int64_t ld, int64_t M, TS* tau, double* ws, int* status,
                                  double min_ratio1, double min_ratio2) {
   hipStream_t st = h->stream;
-  const int64_t nslab = (M + kSlab - 1) / kSlab;
+  const int64_t nslab = cq_nslab(M);
+  const bool tall = slab_rows(M) == kSlab;
+  // G, Wk and Rc sit after the most partials any panel of this QR writes
   double* Gpart = ws;
-  double* G = Gpart + nslab * kNb * kNb;
+  double* G = ws + (cholqr_workspace_doubles(M) - 3 * kNb * kNb - 64);
   double* Wk = G + kNb * kNb;
   double* Rc = Wk + kNb * kNb;
-  hipLaunchKernelGGL(k_cq_gram<TS>, dim3((unsigned)nslab), dim3(256), 0, st, (const TS*)P, ld, M, Gpart,
-                     (const int*)nullptr);
+  if (tall)
+    hipLaunchKernelGGL((k_cq_gram<TS, 4>), dim3((unsigned)nslab), dim3(256), 0, st, (const TS*)P, ld, M, Gpart,
+                       (const int*)nullptr);
+  else
+    hipLaunchKernelGGL((k_cq_gram<TS, 2>), dim3((unsigned)nslab), dim3(256), 0, st, (const TS*)P, ld, M, Gpart,
+                       (const int*)nullptr);
   hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
                      1);
   hipLaunchKernelGGL(k_cq_factor<TS>, dim3(1), dim3(256), 0, st, (const double*)G, Wk, Rc, P, ld, tau, status, 1,
                      min_ratio1);
   // 16-byte operand loads when every row start allows them
   const bool v16 = ld % (16 / (int64_t)sizeof(TS)) == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0;
-  if (v16)
-    hipLaunchKernelGGL((k_cq_apply_gram<TS, true>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+  if (v16 && tall)
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, true, 4>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+                       (const double*)Wk, Gpart, (const int*)status);
+  else if (v16)
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, true, 2>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+                       (const double*)Wk, Gpart, (const int*)status);
+  else if (tall)
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, false, 4>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
                        (const double*)Wk, Gpart, (const int*)status);
   else
-    hipLaunchKernelGGL((k_cq_apply_gram<TS, false>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
+    hipLaunchKernelGGL((k_cq_apply_gram<TS, false, 2>), dim3((unsigned)nslab), dim3(256), 0, st, P, ld, M,
                        (const double*)Wk, Gpart, (const int*)status);
   hipLaunchKernelGGL(k_cq_reduce, dim3(kNb * kNb / 16), dim3(256), 0, st, (const double*)Gpart, (int)nslab, G, status,
                      0);
@@ -765,8 +788,7 @@ rfmls_status run_cholqr_panel(rfmls_handle* h, float* P, int64_t ld, int64_t M, 
 // Status 2 only: the panel's R (from the unblocked kernel, on Q1) times R1.
 template <typename TS>
 static rfmls_status cholqr_fix_t(rfmls_handle* h, TS* P, int64_t ld, int64_t M, const double* ws, const int* status) {
-  const int64_t nslab = (M + kSlab - 1) / kSlab;
-  const double* Rc = ws + nslab * kNb * kNb + 2 * kNb * kNb;
+  const double* Rc = ws + (cholqr_workspace_doubles(M) - 3 * kNb * kNb - 64) + 2 * kNb * kNb;
   hipLaunchKernelGGL(k_cq_fix<TS>, dim3(1), dim3(256), 0, h->stream, P, ld, Rc, status);
   RFMLS_HIP(h, hipGetLastError());
   return RFMLS_OK;
