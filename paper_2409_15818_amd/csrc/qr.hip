@@ -401,13 +401,13 @@ __global__ void k_zero_u64(uint64_t* p, int64_t n) {
 
 // Outer block width: 512 columns for float32, whose trailing update then
 // reads and writes the trailing matrix half as often (4^3-box sketch: 2.5% less
-// QR time than 256), and for float64 from 16,384 columns on (4^3-box, 25,600
-// columns: 1.3% less solve time); narrower float64 systems keep 256, where the
-// inner 64-column products, which grow with the width, cancel the gain (8x8-box,
-// 12,800 columns: equal).
+// QR time than 256), and for float64 from 12,800 columns on (4^3-box, 25,600
+// columns: 1.3% less solve time; 8x8-box, 12,800 columns: QR phase 327.8 ->
+// 325.1 ms, the trailing products' 9 ms saved less the inner 64-column
+// products, which grow with the width); narrower float64 systems keep 256.
 constexpr int64_t kOuterMax = 512;
 template <typename T>
-int64_t outer_width(int64_t n) { return sizeof(T) == 4 || n >= 16384 ? 512 : 256; }
+int64_t outer_width(int64_t n) { return sizeof(T) == 4 || n >= 12800 ? 512 : 256; }
 inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
 // W' = T^T W_C for one panel: W = V^T [V | C] (nb x ldw, its leading nb

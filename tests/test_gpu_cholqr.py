@@ -171,23 +171,34 @@ def _qr_factors(handle, SAo, lookahead, mode=0):
     return out
 
 
-def _lookahead_cases():
-    rng = np.random.default_rng(11)
-    # four and five outer blocks of 256 columns, the last one ragged
-    yield "gaussian 6000x1024", rng.standard_normal((6000, 1024))
-    yield "gaussian 4000x1100", rng.standard_normal((4000, 1100)) * np.geomspace(1.0, 1e4, 1100)[None, :]
+def _sketch_4x4():
     S, s = build_config("poisson2d_4x4")
     h, sign = countsketch.hash_sign(S.m, s, SEED)
     SAo, _ = countsketch.sketch_dense(S.row_ptr, S.col, S.val, h, sign, s, S.n)
-    yield "poisson2d_4x4", SAo
+    return SAo
 
 
-@pytest.mark.parametrize("case", list(_lookahead_cases()), ids=lambda c: c[0])
+# (label, matrix maker): the matrices are made when the test runs, not when
+# it is collected
+LOOKAHEAD_CASES = [
+    # four and five outer blocks of 256 columns, the last one ragged
+    ("gaussian 6000x1024", lambda: np.random.default_rng(11).standard_normal((6000, 1024))),
+    ("gaussian 4000x1100",
+     lambda: np.random.default_rng(12).standard_normal((4000, 1100)) * np.geomspace(1.0, 1e4, 1100)[None, :]),
+    ("poisson2d_4x4", _sketch_4x4),
+    # float64 from 12,800 columns on: 25 outer blocks of 512 columns and a
+    # 64-column last one, whose 200-row panel takes the unblocked kernel
+    ("gaussian 13000x12864", lambda: np.random.default_rng(13).standard_normal((13000, 12864))),
+]
+
+
+@pytest.mark.parametrize("case", LOOKAHEAD_CASES, ids=lambda c: c[0])
 def test_lookahead_gives_bitwise_the_same_factorisation(handle, case):
     """The look-ahead schedule splits the trailing update by columns and runs the
     next block's panels on a second stream: every column's sums keep their order,
     so the whole factored matrix (R and the Householder vectors) is bitwise equal."""
-    label, SAo = case
+    label, make = case
+    SAo = make()
     print(f"[lookahead] {label} {SAo.shape}", flush=True)
     F0 = _qr_factors(handle, SAo, False)
     F1 = _qr_factors(handle, SAo, True)

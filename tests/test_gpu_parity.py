@@ -214,7 +214,7 @@ def test_qr_defining_identity(handle, s, n, dtype):
 
 
 def test_qr_wide_float64_outer_blocks(handle):
-    """From 16,384 columns the float64 QR takes 512-column outer blocks: a
+    """From 12,800 columns the float64 QR takes 512-column outer blocks: a
     16,600 x 16,448 matrix (32 whole blocks and a 64-column last one, 4096-row
     split-K slices with a ragged tail) checked by the identity every QR meets,
     R^T R = (SA)^T (SA), on sampled columns (panel, block and slice borders)."""
