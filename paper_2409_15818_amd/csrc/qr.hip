@@ -410,6 +410,21 @@ template <typename T>
 int64_t outer_width(int64_t n) { return sizeof(T) == 4 || n >= 12800 ? 512 : 256; }
 inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
 
+// Row slices of an inner panel's split-K product V^T [V | C]: its output is
+// only 64 rows by at most kOuter columns, so the slices are what fills the
+// GPU.  256-row slices from 32,768 rows on, 128 below (8x8-box sketch, QR
+// phase 325.4 -> 323.6 ms against 512-row slices; Helmholtz sketch, 12,800
+// rows, 20.35 -> 19.74 ms; 128-row slices on the 8x8-box sketch 325-327 ms,
+// the slice sums' extra reads outweighing the fuller grid).
+inline int64_t inner_split(int64_t M) { return M >= 32768 ? 256 : 128; }
+// most slices any panel of an s-row sketch takes
+inline int64_t inner_slices_max(int64_t s) {
+  const int64_t a = (s + inner_split(s) - 1) / inner_split(s);
+  const int64_t ms = s < 32767 ? s : 32767;
+  const int64_t b = (ms + 127) / 128;
+  return a > b ? a : b;
+}
+
 // W' = T^T W_C for one panel: W = V^T [V | C] (nb x ldw, its leading nb
 // columns the Gram, W_C the ncol columns after them) and the panel's T (nb x
 // nb upper triangular, rows ldt apart).  One workgroup per 32 columns; thread
@@ -656,10 +671,10 @@ template <typename T>
 rfmls_status qr_block_panels(rfmls_handle* h, int64_t s, int64_t k0, int64_t bw, int64_t kOuter, T* SA, int64_t ld,
                              const PanelBufs<T>& pb, uint64_t* ll, double* cq_ws, int* cq_status, T* tau_out) {
   hipStream_t st = h->stream;
-  const int64_t split_in = 512;
   for (int64_t p0 = k0; p0 < k0 + bw; p0 += kMaxNb) {
     const int jb = (int)(k0 + bw - p0 < kMaxNb ? k0 + bw - p0 : kMaxNb);
     const int64_t M = s - p0;
+    const int64_t split_in = inner_split(M);
     PanelShape sh;
     int64_t G = 0;
     RFMLS_CHECK(pick_panel_shape<T>(h, M, &sh, &G));
@@ -887,8 +902,8 @@ rfmls_status lookahead_stream(rfmls_handle* h) {
 template <typename T>
 rfmls_status qr_impl(rfmls_handle* h, int64_t s, int64_t n, int64_t n_room, T* SA, int64_t ld, T* tau_out) {
   const int64_t kOuter = outer_width<T>(n);
-  const int64_t split_in = 512, split_out = 4096;
-  const int64_t nsp_in_max = (s + split_in - 1) / split_in;
+  const int64_t split_out = 4096;
+  const int64_t nsp_in_max = inner_slices_max(s);
   // slices of the outer V^T [V | C]: the masked top rows, the clean 4096-row
   // slices (2% faster than 8192 rows on the 8x8-box sketch, net of the longer
   // slice sum) and a ragged tail

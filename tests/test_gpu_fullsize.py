@@ -217,8 +217,12 @@ def test_fullsize_float32_factor_refused_on_8x8(handle, qd, rd):
 
 def test_fullsize_float32_factor_accepted_on_4x4x4(handle):
     """The float32 factor passes the precision check, and its X = R^-1 (formed in
-    float32 from 16,384 columns on) has the left residual of a substitution-based
-    inverse: |X R - I| <= c n u32 |X| |R| on sampled columns."""
+    float32 from 16,384 columns on) has the right residual of a substitution:
+    |R X - I| <= n u32 |R| |X| on sampled columns.  The block rows of X solve
+    R_II X_I = E_I - R_IJ X_J with float32 products over at most n terms and are
+    rounded to float32 once, which bounds that residual to first order; it is
+    also the residual that preconditioning needs, since SA X = Q (R X).  Both
+    sides are evaluated in float64, so the check's own products add nothing."""
     S, s, A = _system("poisson3d_4x4x4")
     SA, _, _, _ = R.rfmls_sketch(handle, A, s, SEED, dtype="f32")
     P = R.rfmls_precond(handle, SA, "f32", "f32")
@@ -226,16 +230,17 @@ def test_fullsize_float32_factor_accepted_on_4x4x4(handle):
     print(f"[fullsize] 4x4x4 float32 factor {st}", flush=True)
     assert st["rho_min"] > 16 * 2.0 ** -24
     del SA
-    Rm = R.rfmls_precond_export_R(handle, P)
+    Rm = R.rfmls_precond_export_R(handle, P).double()
     X = R.rfmls_precond_export_Rinv(handle, P)
     n = P.n
     cols = torch.tensor([0, 63, 64, 1023, 1024, 9000, n // 2, n - 65, n - 1], device=Rm.device)
-    Rc = Rm[:, cols].contiguous()
-    res = X @ Rc
+    Xc = X[:, cols].double()
+    del X
+    res = Rm @ Xc
     res[cols, torch.arange(len(cols), device=Rm.device)] -= 1.0
-    bound = X.abs() @ Rc.abs()
+    bound = Rm.abs() @ Xc.abs()
     ratio = (res.abs() / (n * 2.0 ** -24 * bound + 1e-300)).max().item()
-    print(f"[fullsize] 4x4x4 float32 inverse: max |XR - I| / (n u32 |X||R|) = {ratio:.3g}", flush=True)
+    print(f"[fullsize] 4x4x4 float32 inverse: max |RX - I| / (n u32 |R||X|) = {ratio:.3g}", flush=True)
     assert ratio < 1.0
-    del X, Rm, Rc, res, bound
+    del Rm, Xc, res, bound
     P.free()
