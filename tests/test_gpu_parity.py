@@ -236,6 +236,35 @@ def test_qr_wide_float64_outer_blocks(handle):
     assert err < 20 * n * 1.1e-16, err
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_qr_slice_heights_across_32768_rows(handle, dtype):
+    """The split-K products slice their rows by the rows left: 256 (inner) and
+    4096 (outer) from 32,768 rows on, 128 and 1,024 below.  In a 33,000 x 1,600
+    sketch the panel at column 256 is the first with fewer rows (32,744): inside
+    the first outer block in float32 (512 columns), at the start of the second
+    in float64 (256 columns), whose outer products are the first on short
+    slices.  R is checked by R^T R = (SA)^T (SA) on sampled columns, to the
+    storage precision's rounding."""
+    s, n = 33000, 1600
+    rng = np.random.default_rng(33000)
+    SAo = rng.standard_normal((s, n)) * np.geomspace(1.0, 1e3, n)[None, :]
+    if dtype == "f32":
+        SAo = SAo.astype(np.float32).astype(np.float64)
+    SA = torch.tensor(SAo, device="cuda", dtype=torch.float64 if dtype == "f64" else torch.float32)
+    P = R.rfmls_precond(handle, SA, dtype, dtype)
+    Rg = R.rfmls_precond_export_R(handle, P).cpu().numpy().astype(np.float64)
+    del SA, P
+    J = np.unique(np.concatenate([[0, 63, 64, 255, 256, 511, 512, 1023, 1024, 1599],
+                                  np.random.default_rng(6).integers(0, n, 20)]))
+    assert all(np.all(Rg[j + 1:, j] == 0.0) for j in J)
+    assert np.all(np.diag(Rg)[J] > 0)
+    lhs = Rg.T @ Rg[:, J]
+    rhs = SAo.T @ SAo[:, J]
+    err = np.linalg.norm(lhs - rhs) / (np.linalg.norm(SAo) * np.linalg.norm(SAo[:, J]))
+    u = 1.1e-16 if dtype == "f64" else 6.0e-8
+    assert err < 20 * n * u, err
+
+
 @pytest.mark.parametrize("name", SMALL)
 def test_qr_on_sketch_backward_error(handle, name):
     S, s, A = system(name)
